@@ -1,0 +1,59 @@
+"""Pins of the oracle's time integration (Sec. 5.5, App. B)."""
+import json
+import os
+
+import numpy as np
+
+import workloads as wl
+from oracle import geometry as G, ns
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_rk3_amplification_polynomial():
+    for z in (-0.3, 0.1 + 0.7j, -1.2 + 0.2j, 0.05):
+        lam = z
+        y = ns.rk3_williamson([np.array([1.0 + 0j])], lambda s, k: [lam * s[0]], 1.0)[0][0]
+        assert abs(y - (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-15
+
+
+def test_rk3_third_order_in_time():
+    f = lambda s, k: [np.cos(s[0]) + 0.3 * s[0]]
+    def run(n):
+        y = [np.array([0.4])]
+        for _ in range(n):
+            y = ns.rk3_williamson(y, f, 1.0 / n)
+        return y[0][0]
+    ref = run(4096)
+    e1, e2 = abs(run(16) - ref), abs(run(32) - ref)
+    assert 2.8 < np.log2(e1 / e2) < 3.2
+
+
+def test_dt_max_on_stability_triangle():
+    tri = json.load(open(os.path.join(GOLD, "paper_constants.json")))["rk3_stability_triangle"]
+    Cmax, rmax = tri["vertices_C_r"][1][0], tri["vertices_C_r"][2][1]
+    for h, nu, a in ((1 / 64, 0.01, 0.3536), (0.01, 1e-4, 2.0), (0.05, 0.1, 0.0)):
+        dt = ns.dt_max(h, nu, a)
+        C, r = a * dt / h, nu * dt / h ** 2
+        assert abs(C / Cmax + r / rmax - 1.0) < 1e-14
+    # the Taylor-Couette workload: C_stab = 0.5
+    w = wl.taylor_couette(128)
+    assert abs(w.dt - 0.5 * ns.dt_max(w.grid.h, w.grid.nu, np.sqrt(2) * 0.25)) < 1e-18
+    assert abs(w.dt - 3.462e-3) < 1e-6
+
+
+def test_free_space_total_circulation_stays_zero():
+    """From rest in free space, Gamma_k + h^2 sum_{outside R_k} omega = 0 for
+    all time (discrete Kelvin theorem, Sec. 5.1)."""
+    w = wl.cylinder_small()
+    geo = G.Geometry(w.grid, w.bodies)
+    st = ns.Stepper(geo)
+    om = np.zeros((geo.ny, geo.nx))
+    Gam = np.zeros(1)
+    i0, i1, j0, j1 = geo.rects[0]
+    for _ in range(4):
+        om, Gam = st.step(om, Gam, w.dt)
+        tot = Gam[0] + geo.h ** 2 * (om.sum() - om[j0:j1 + 1, i0:i1 + 1].sum())
+        assert abs(tot) < 1e-13
+    assert np.max(np.abs(om)) > 1.0          # vorticity was created at the wall
+    assert np.all(om[geo.solid] == 0.0)

@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU parity tests and
+the benchmark.
+
+This module holds no arithmetic of the method itself: it only produces
+boundary point sets (closed, ordered curves), grid descriptors, flow
+parameters and seeded vorticity fields.  Both the FP64 oracle and the HIP
+library consume these plain arrays/dicts; neither imports the other.
+
+Conventions (shared by every consumer):
+  * grid node (i, j) sits at (x0 + i*h, y0 + j*h); fields are stored [ny][nx];
+  * a body is a closed polygon of boundary points, ordered so that the fluid
+    lies to the RIGHT of the direction of travel (counter-clockwise for an
+    obstacle, clockwise for an enclosing wall), first point not repeated;
+  * rigid-motion boundary data: u_b(x) = u_rigid + omega_rigid * k x (x - center).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+EXT_BOX = "box"          # Dirichlet box (stream function zero on the box faces)
+EXT_FREE = "free"        # unbounded domain
+EXT_OUTFLOW = "outflow"  # unbounded, with an even mirror plane at the x_max face
+
+
+@dataclass
+class GridDesc:
+    nx: int
+    ny: int
+    x0: float
+    y0: float
+    h: float
+    exterior: str = EXT_FREE
+    u_inf: Tuple[float, float] = (0.0, 0.0)
+    nu: float = 0.01
+
+
+@dataclass
+class BodyDesc:
+    points: np.ndarray                 # (P, 2) float64
+    is_enclosure: bool = False
+    center: Tuple[float, float] = (0.0, 0.0)
+    u_rigid: Tuple[float, float] = (0.0, 0.0)
+    omega_rigid: float = 0.0
+    rect: Optional[Tuple[int, int, int, int]] = None   # (i0, i1, j0, j1) or None = automatic
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: GridDesc
+    bodies: List[BodyDesc]
+    dt: float
+    steps: int
+    extra: dict = field(default_factory=dict)
+
+    def describe(self) -> dict:
+        g = asdict(self.grid)
+        return {"workload": self.name, "nx": g["nx"], "ny": g["ny"], "h": g["h"],
+                "exterior": g["exterior"], "nu": g["nu"], "u_inf": list(g["u_inf"]),
+                "bodies": len(self.bodies), "dt": self.dt, "steps": self.steps}
+
+
+# ----------------------------------------------------------------------------
+# boundary point sets
+# ----------------------------------------------------------------------------
+
+def circle_points(center, radius, n, clockwise=False, phase=0.0):
+    t = phase + 2.0 * np.pi * np.arange(n) / n
+    if clockwise:
+        t = -t
+    return np.stack([center[0] + radius * np.cos(t), center[1] + radius * np.sin(t)], axis=1)
+
+
+def ellipse_points(center, a, b, angle, n, phase=0.0):
+    t = phase + 2.0 * np.pi * np.arange(n) / n
+    ca, sa = math.cos(angle), math.sin(angle)
+    x = a * np.cos(t)
+    y = b * np.sin(t)
+    return np.stack([center[0] + ca * x - sa * y, center[1] + sa * x + ca * y], axis=1)
+
+
+def c_shape_points(center, ra, rb, theta_a, theta_b, n):
+    """Counter-clockwise boundary of the set of points within rb of the circular
+    arc of radius ra about `center`, starting at angle theta_a and spanning
+    theta_b radians (round end caps).  Points are spaced uniformly in arc length.
+    """
+    cx, cy = center
+    t_end = theta_a + theta_b
+    # pieces: outer arc (ccw), end cap at t_end, inner arc (cw), start cap
+    L_outer = (ra + rb) * theta_b
+    L_inner = (ra - rb) * theta_b
+    L_cap = math.pi * rb
+    total = L_outer + L_inner + 2 * L_cap
+    s = (np.arange(n) + 0.5) * total / n
+    pts = np.empty((n, 2))
+    for k, sk in enumerate(s):
+        if sk < L_outer:
+            a = theta_a + sk / (ra + rb)
+            pts[k] = (cx + (ra + rb) * math.cos(a), cy + (ra + rb) * math.sin(a))
+            continue
+        sk -= L_outer
+        if sk < L_cap:
+            ex, ey = cx + ra * math.cos(t_end), cy + ra * math.sin(t_end)
+            a = t_end + sk / rb
+            pts[k] = (ex + rb * math.cos(a), ey + rb * math.sin(a))
+            continue
+        sk -= L_cap
+        if sk < L_inner:
+            a = t_end - sk / (ra - rb)
+            pts[k] = (cx + (ra - rb) * math.cos(a), cy + (ra - rb) * math.sin(a))
+            continue
+        sk -= L_inner
+        sx, sy = cx + ra * math.cos(theta_a), cy + ra * math.sin(theta_a)
+        a = theta_a + math.pi + sk / rb
+        pts[k] = (sx + rb * math.cos(a), sy + rb * math.sin(a))
+    return pts
+
+
+# ----------------------------------------------------------------------------
+# named workloads (shapes and parameters of the paper's flows)
+# ----------------------------------------------------------------------------
+
+def dt_from_polygon(h, nu, a_max, c_stab):
+    """Time step on the RK3 stability triangle (C, r): (0,0), (1.620,0), (0,0.314)."""
+    return c_stab / (a_max / (1.620 * h) + nu / (0.314 * h * h))
+
+
+def taylor_couette(n=128, points=256, c_stab=0.5, steps=20):
+    """Annulus between a rotating inner circle (r=0.25, omega=1) and a fixed outer
+    wall (r=0.75), cell-centred n x n grid on [-1,1]^2, Dirichlet box."""
+    h = 2.0 / n
+    grid = GridDesc(nx=n, ny=n, x0=-1.0 + 0.5 * h, y0=-1.0 + 0.5 * h, h=h,
+                    exterior=EXT_BOX, u_inf=(0.0, 0.0), nu=0.01)
+    inner = BodyDesc(points=circle_points((0.0, 0.0), 0.25, points), center=(0.0, 0.0),
+                     omega_rigid=1.0)
+    outer = BodyDesc(points=circle_points((0.0, 0.0), 0.75, points, clockwise=True),
+                     is_enclosure=True, center=(0.0, 0.0))
+    a_max = math.sqrt(2.0) * 0.25
+    dt = dt_from_polygon(h, grid.nu, a_max, c_stab)
+    return Workload("taylor_couette_%dx%d_box" % (n, n), grid, [inner, outer], dt, steps)
+
+
+def cylinder(nx=1024, ny=512, h=1.0 / 64, points=256, nu=0.01, dt=0.0025, steps=1000,
+             center=(2.0, 0.0), diameter=1.0, y_extent=None):
+    """Impulsively started cylinder in free space, u_inf = (1, 0), cell-centred grid
+    on [0, nx*h) x [-ny*h/2, ny*h/2)."""
+    y0 = -0.5 * ny * h + 0.5 * h
+    grid = GridDesc(nx=nx, ny=ny, x0=0.5 * h, y0=y0, h=h, exterior=EXT_FREE,
+                    u_inf=(1.0, 0.0), nu=nu)
+    body = BodyDesc(points=circle_points(center, 0.5 * diameter, points), center=center)
+    return Workload("cylinder_Re%d_%dx%d_free" % (round(diameter / nu), nx, ny), grid,
+                    [body], dt, steps)
+
+
+def cylinder_small():
+    """A small free-space cylinder case (D=1 at h=1/32, 128x96 nodes) that the
+    oracle solves in seconds."""
+    return cylinder(nx=128, ny=96, h=1.0 / 32, points=128, dt=0.005, steps=5,
+                    center=(1.5, 0.0))
+
+
+def two_c_shapes_lamb_oseen(n):
+    """Two C-shaped bodies of the reconstruction convergence study on the unit
+    square, x_ij = (i/n, j/n), free space."""
+    h = 1.0 / n
+    grid = GridDesc(nx=n, ny=n, x0=0.0, y0=0.0, h=h, exterior=EXT_FREE,
+                    u_inf=(0.0, 0.0), nu=0.01)
+    npts = max(256, int(8.0 / h))
+    b1 = BodyDesc(points=c_shape_points((0.309, 0.679), 0.167, 0.057, 0.5, 1.8, npts),
+                  center=(0.309, 0.679))
+    b2 = BodyDesc(points=c_shape_points((0.559, 0.451), 0.157, 0.057, 3.7, 2.0, npts),
+                  center=(0.559, 0.451))
+    return Workload("lamb_oseen_two_c_%d" % n, grid, [b1, b2], dt=0.0, steps=0,
+                    extra={"x0": (0.501, 0.501), "Gamma": 1.0, "nut": 0.0025})
+
+
+# ----------------------------------------------------------------------------
+# seeded fields
+# ----------------------------------------------------------------------------
+
+def node_coords(grid: GridDesc):
+    x = grid.x0 + grid.h * np.arange(grid.nx)
+    y = grid.y0 + grid.h * np.arange(grid.ny)
+    return np.meshgrid(x, y)   # X[j, i], Y[j, i]
+
+
+def seeded_vortices(grid: GridDesc, seed: int, count=6, box=None, amp=2.0, width=(0.05, 0.2)):
+    """Sum of seeded Gaussian vortices, stored [ny][nx].  `box` = (xmin, xmax,
+    ymin, ymax) restricts vortex centres; default: the middle of the grid."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, Y = node_coords(grid)
+    if box is None:
+        xs = grid.x0 + grid.h * (grid.nx - 1)
+        ys = grid.y0 + grid.h * (grid.ny - 1)
+        box = (grid.x0 + 0.2 * (xs - grid.x0), xs - 0.2 * (xs - grid.x0),
+               grid.y0 + 0.2 * (ys - grid.y0), ys - 0.2 * (ys - grid.y0))
+    w = np.zeros((grid.ny, grid.nx))
+    for _ in range(count):
+        cx = rng.uniform(box[0], box[1])
+        cy = rng.uniform(box[2], box[3])
+        s = rng.uniform(width[0], width[1])
+        a = rng.uniform(-amp, amp)
+        w += a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * s * s))
+    return w
+
+
+def seeded_gammas(n_bodies: int, seed: int, scale=0.5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-scale, scale, size=n_bodies)
