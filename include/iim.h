@@ -1,0 +1,196 @@
+/*
+ * iim.h -- C ABI of the MI355X (gfx950) immersed interface method library.
+ *
+ * The library advances the 2D vorticity-velocity Navier-Stokes equations with
+ * immersed bodies as described in Gabbard, Gillis, Chatelain & van Rees,
+ * "An immersed interface method for the 2D vorticity-velocity Navier-Stokes
+ * equations with multiple bodies" (arXiv:2109.13628):
+ *   - velocity reconstruction (Sec. 4.2): the 5-point Poisson problem with
+ *     IIM corrections gamma on the affected points, solved as the Schur
+ *     complement system with one circulation row per body, by GMRES whose
+ *     matrix-vector product is an FFT convolution;
+ *   - vorticity transport (Sec. 3): conservative third-order upwind advection
+ *     and centred diffusion with the IIM boundary rules, the boundary
+ *     vorticity of Sec. 5.3 and the Kelvin circulation ODE of Sec. 5.1;
+ *   - the low-storage third-order Runge-Kutta step of Sec. 5.5.
+ *
+ * Conventions
+ *   - Grid node (i, j) sits at (x0 + i h, y0 + j h); a grid field is a
+ *     contiguous double array [ny][nx] (row j, column i).
+ *   - A "ring" field is a contiguous double array [ny+2][nx+2] holding the
+ *     grid plus one node on every side: element [(j+1)*(nx+2) + (i+1)] is
+ *     node (i, j), -1 <= i <= nx, -1 <= j <= ny.
+ *   - Pointers named *_dev are device pointers (hipMalloc / torch CUDA
+ *     tensors) owned by the caller; pointers named *_host are host memory.
+ *   - Bodies are closed curves given as boundary points ordered with the
+ *     fluid on the right: counter-clockwise for obstacles, clockwise for an
+ *     enclosing wall.  Boundary data is a rigid motion
+ *     u_b(x) = u_rigid + omega_rigid * k x (x - center).
+ *   - Every call returns an int status (IIM_OK = 0, < 0 on error); nothing
+ *     throws across the ABI.  A failed call leaves a message readable with
+ *     iim_last_error().
+ *   - Compute calls are enqueued on the stream given to iim_create (a
+ *     hipStream_t passed as void*; NULL = the null stream).  Calls that
+ *     return host values (Gamma, statistics) synchronise that stream.
+ *   - One context must not be used by two host threads at once.
+ */
+#ifndef IIM_H
+#define IIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IIM_ABI_VERSION 1
+
+enum {
+  IIM_OK = 0,
+  IIM_EINVAL = -1,        /* invalid argument (sizes, NULL pointers, dt too large) */
+  IIM_ENOMEM = -2,        /* device or host allocation failed */
+  IIM_EGEOM = -3,         /* geometry cannot be discretised (message names body / node) */
+  IIM_ENOCONV = -4,       /* Krylov solver reached its iteration limit; results still written */
+  IIM_ENONFINITE = -5,    /* NaN or Inf met in an input or a residual */
+  IIM_EDEVICE = -6,       /* HIP runtime error */
+  IIM_EUNSUPPORTED = -7   /* feature not available (e.g. compute on a host-only context) */
+};
+
+/* exterior condition of the Poisson solve (Sec. 4.1 and Sec. 5.2) */
+enum {
+  IIM_EXT_BOX = 0,        /* stream function zero on the box faces half a cell outside the edge nodes */
+  IIM_EXT_FREE = 1,       /* unbounded domain: lattice Green's function convolution */
+  IIM_EXT_OUTFLOW = 2     /* unbounded, with the vorticity mirrored (even) across the face x_{nx-1/2} */
+};
+
+enum { IIM_PREC_FP64 = 0, IIM_PREC_MIXED = 1 };
+enum { IIM_GUESS_ZERO = 0, IIM_GUESS_PREVIOUS = 1 };
+
+typedef struct {
+  int32_t nx, ny;         /* grid nodes per direction (>= 16) */
+  double x0, y0, h;       /* coordinates of node (0,0) and the grid spacing */
+  int32_t exterior;       /* IIM_EXT_* */
+  double u_inf[2];        /* free stream (free-space exteriors only; ignored for the box) */
+  double nu;              /* kinematic viscosity */
+} iim_grid_desc;
+
+typedef struct {
+  int32_t n_points;       /* >= 4 */
+  const double* xy_host;  /* [n_points][2], copied at create */
+  int32_t is_enclosure;   /* 1: exterior wall (stream-function constant 0, no circulation unknown) */
+  double center[2];       /* rigid-motion centre */
+  double u_rigid[2];      /* rigid translation velocity */
+  double omega_rigid;     /* rigid angular velocity */
+  int32_t rect[4];        /* bounding region R_k as node ranges i0,i1,j0,j1 (inclusive); rect[0] < 0 = automatic */
+} iim_body_desc;
+
+typedef struct {
+  int32_t precision;      /* IIM_PREC_* */
+  double krylov_tol;      /* stop when ||r|| <= tol ||b|| (relative to b, so warm starts count) */
+  int32_t krylov_max_iter;/* total matrix-vector products per solve */
+  int32_t krylov_restart; /* GMRES restart length (<= 64) */
+  int32_t max_refine;     /* mixed precision: maximum refinement rounds */
+  int32_t guess;          /* IIM_GUESS_* initial guess of each Schur solve */
+  int32_t host_only;      /* 1: build geometry and tables only, allocate nothing on the device */
+} iim_solver_opts;
+
+typedef struct {
+  int32_t iters[3];       /* Krylov matrix-vector products of each RK stage (reconstruct: [0]) */
+  int32_t refine_rounds[3];
+  double res0[3];         /* initial relative residual of each stage */
+  double res[3];          /* final relative residual of each stage */
+  int32_t converged;      /* 1 if every stage met the tolerance */
+} iim_step_stats;
+
+typedef struct {
+  int32_t nx, ny;
+  int32_t n_control;      /* |C| */
+  int32_t n_affected;     /* |A| = |A+| + |A-| */
+  int32_t n_ghost;        /* |A-| */
+  int32_t n_circ;         /* bodies carrying a circulation unknown */
+  int32_t n_special;      /* fluid nodes handled by the boundary transport kernel */
+  int32_t fft_mx, fft_my; /* padded FFT sizes (free space) */
+  int32_t win_j0, win_j1; /* source rows / output rows of the pruned Krylov convolution */
+  int64_t device_bytes;   /* device memory held by the context */
+} iim_info;
+
+/* Host views of the geometry tables (valid until iim_destroy). */
+typedef struct {
+  int32_t n_control;
+  const double* c_xy;     /* [n_control][2] control point coordinates */
+  const double* c_theta;  /* [n_control] distance fluid node -> control point, in units of h, (0,1] */
+  const double* c_normal; /* [n_control][2] unit normal into the fluid */
+  const int32_t* c_int;   /* [n_control][5] axis (0: horizontal line), sigma (+-1: ghost = fluid + sigma),
+                             i_fluid, j_fluid, body */
+  int32_t n_affected;
+  const int32_t* a_int;   /* [n_affected][4] i, j, is_ghost, body */
+  const int8_t* cls;      /* [ny][nx] 0 fluid, 1 ghost (A-), 2 solid interior */
+  int32_t n_circ;
+  const int32_t* rects;   /* [n_circ][4] i0, i1, j0, j1 */
+  const int32_t* circ_body; /* [n_circ] body index of each circulation unknown */
+} iim_geometry_view;
+
+typedef struct iim_ctx iim_ctx;
+
+int iim_abi_version(void);
+const char* iim_status_string(int status);
+
+/* Build a context: geometry (Sec. 2.2, App. A), stencil tables, the Poisson
+ * operator of the exterior condition (Sec. 4.2) and all device workspaces.
+ * Host inputs are copied.  Errors: IIM_EINVAL, IIM_EGEOM (with the body named
+ * in the message), IIM_ENOMEM, IIM_EDEVICE.  On error *out is NULL. */
+int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc* bodies,
+               const iim_solver_opts* opts, void* hip_stream, iim_ctx** out);
+int iim_destroy(iim_ctx* ctx);
+/* Message of the last failed call on ctx; with ctx == NULL, the message of the
+ * last failed iim_create on this host thread.  The string stays valid until
+ * the next call on the same context (or thread). */
+const char* iim_last_error(const iim_ctx* ctx);
+int iim_query(const iim_ctx* ctx, iim_info* out);
+int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
+
+/* Largest stable time step on the RK3 stability triangle of App. B for a
+ * velocity bound a_max = max(|u_x| + |u_y|). */
+int iim_dt_max(const iim_ctx* ctx, double a_max, double* dt_max_out);
+
+/* Lattice Green's function g(m, n) of the 5-point Laplacian (host, for
+ * tests): out_host[n*(mx+1) + m] for 0 <= m <= mx, 0 <= n <= my. */
+int iim_lgf_table(int32_t mx, int32_t my, double* out_host);
+
+/* psi = G src with the context's exterior condition, no immersed bodies
+ * (Sec. 4.2, the FFT solution operator).  src_dev: grid field; psi_dev:
+ * ring field. */
+int iim_poisson(iim_ctx* ctx, const double* src_dev, double* psi_dev);
+
+/* Velocity reconstruction of one stage (Sec. 4.2): solves the Schur system
+ * for gamma and the body constants, recovers psi, fills the ghost values and
+ * the velocity (extended to A- at third order with u_b).
+ * omega_dev: grid field (values at solid nodes ignored); Gamma_host:
+ * [n_circ] circulations of the bounding regions R_k; psi_dev (nullable),
+ * u_dev, v_dev: ring fields.  Returns IIM_ENOCONV if the Krylov limit was
+ * hit (outputs still written). */
+int iim_reconstruct(iim_ctx* ctx, const double* omega_dev, const double* Gamma_host,
+                    double* psi_dev, double* u_dev, double* v_dev, iim_step_stats* stats);
+
+/* Right-hand side of the transport equation and of the Kelvin ODE (Sec. 3,
+ * Sec. 5.1, Sec. 5.3) for a given (extended) velocity.  u_dev, v_dev: ring
+ * fields as written by iim_reconstruct; domega_dev: grid field (zero at
+ * solid nodes); dGamma_host: [n_circ]; omega_b_dev (nullable): [n_control]. */
+int iim_rhs(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
+            double* domega_dev, double* dGamma_host, double* omega_b_dev);
+
+/* One low-storage RK3 step (Sec. 5.5) of (omega, Gamma) in place.
+ * omega_dev: grid field; Gamma_host: [n_circ]; dt > 0. */
+int iim_rk3_step(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt,
+                 iim_step_stats* stats);
+
+/* Several RK3 steps with Gamma kept on the device between steps (synchronises
+ * once at the end).  Same arguments as iim_rk3_step; stats (nullable) are
+ * those of the last step. */
+int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt, int32_t n_steps,
+                  iim_step_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IIM_H */

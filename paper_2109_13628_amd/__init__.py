@@ -1,0 +1,243 @@
+"""Python binding of the MI355X IIM library (libiim.so, C ABI in include/iim.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors on cuda:0) and the stream.
+The library must have been built (paper_2109_13628_amd/build.py); importing
+this module never falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiim.so")
+
+IIM_OK, IIM_EINVAL, IIM_ENOMEM, IIM_EGEOM, IIM_ENOCONV, IIM_ENONFINITE, IIM_EDEVICE, IIM_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+EXT = {"box": 0, "free": 1, "outflow": 2}
+PREC_FP64, PREC_MIXED = 0, 1
+GUESS_ZERO, GUESS_PREVIOUS = 0, 1
+
+# every symbol declared in include/iim.h
+EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
+           "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_reconstruct", "iim_rhs",
+           "iim_rk3_step", "iim_rk3_steps"]
+
+
+class IIMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_status_name(code), code, msg))
+        self.code = code
+
+
+def _status_name(code):
+    return {0: "IIM_OK", -1: "IIM_EINVAL", -2: "IIM_ENOMEM", -3: "IIM_EGEOM", -4: "IIM_ENOCONV",
+            -5: "IIM_ENONFINITE", -6: "IIM_EDEVICE", -7: "IIM_EUNSUPPORTED"}.get(code, "?")
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_double), ("y0", C.c_double), ("h", C.c_double),
+                ("exterior", C.c_int32), ("u_inf", C.c_double * 2), ("nu", C.c_double)]
+
+
+class BodyDesc(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("xy_host", C.POINTER(C.c_double)), ("is_enclosure", C.c_int32),
+                ("center", C.c_double * 2), ("u_rigid", C.c_double * 2), ("omega_rigid", C.c_double),
+                ("rect", C.c_int32 * 4)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_max_iter", C.c_int32),
+                ("krylov_restart", C.c_int32), ("max_refine", C.c_int32), ("guess", C.c_int32),
+                ("host_only", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 3), ("refine_rounds", C.c_int32 * 3), ("res0", C.c_double * 3),
+                ("res", C.c_double * 3), ("converged", C.c_int32)]
+
+    def as_dict(self):
+        return {"iters": list(self.iters), "refine_rounds": list(self.refine_rounds),
+                "res0": list(self.res0), "res": list(self.res), "converged": bool(self.converged)}
+
+
+class Info(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("n_control", C.c_int32), ("n_affected", C.c_int32),
+                ("n_ghost", C.c_int32), ("n_circ", C.c_int32), ("n_special", C.c_int32), ("fft_mx", C.c_int32),
+                ("fft_my", C.c_int32), ("win_j0", C.c_int32), ("win_j1", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class GeometryView(C.Structure):
+    _fields_ = [("n_control", C.c_int32), ("c_xy", C.POINTER(C.c_double)), ("c_theta", C.POINTER(C.c_double)),
+                ("c_normal", C.POINTER(C.c_double)), ("c_int", C.POINTER(C.c_int32)),
+                ("n_affected", C.c_int32), ("a_int", C.POINTER(C.c_int32)), ("cls", C.POINTER(C.c_int8)),
+                ("n_circ", C.c_int32), ("rects", C.POINTER(C.c_int32)), ("circ_body", C.POINTER(C.c_int32))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libiim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libiim.so is not built: run paper_2109_13628_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    L.iim_abi_version.restype = ip
+    L.iim_status_string.restype = C.c_char_p
+    L.iim_status_string.argtypes = [ip]
+    L.iim_create.restype = ip
+    L.iim_create.argtypes = [C.POINTER(GridDesc), C.c_int32, C.POINTER(BodyDesc), C.POINTER(SolverOpts), vp,
+                             C.POINTER(vp)]
+    L.iim_destroy.restype = ip
+    L.iim_destroy.argtypes = [vp]
+    L.iim_last_error.restype = C.c_char_p
+    L.iim_last_error.argtypes = [vp]
+    L.iim_query.restype = ip
+    L.iim_query.argtypes = [vp, C.POINTER(Info)]
+    L.iim_get_geometry.restype = ip
+    L.iim_get_geometry.argtypes = [vp, C.POINTER(GeometryView)]
+    L.iim_dt_max.restype = ip
+    L.iim_dt_max.argtypes = [vp, C.c_double, dp]
+    L.iim_lgf_table.restype = ip
+    L.iim_lgf_table.argtypes = [C.c_int32, C.c_int32, dp]
+    L.iim_poisson.restype = ip
+    L.iim_poisson.argtypes = [vp, vp, vp]
+    L.iim_reconstruct.restype = ip
+    L.iim_reconstruct.argtypes = [vp, vp, dp, vp, vp, vp, C.POINTER(StepStats)]
+    L.iim_rhs.restype = ip
+    L.iim_rhs.argtypes = [vp, vp, vp, vp, vp, dp, vp]
+    L.iim_rk3_step.restype = ip
+    L.iim_rk3_step.argtypes = [vp, vp, dp, C.c_double, C.POINTER(StepStats)]
+    L.iim_rk3_steps.restype = ip
+    L.iim_rk3_steps.argtypes = [vp, vp, dp, C.c_double, C.c_int32, C.POINTER(StepStats)]
+    _lib = L
+    return L
+
+
+def lgf_table(mx, my):
+    out = np.zeros((my + 1, mx + 1))
+    rc = lib().iim_lgf_table(mx, my, out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc:
+        raise IIMError(rc, "iim_lgf_table")
+    return out
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One IIM problem (grid + bodies) on the current device."""
+
+    def __init__(self, grid, bodies, precision=PREC_FP64, tol=1e-13, max_iter=400, restart=40,
+                 guess=GUESS_PREVIOUS, host_only=False, stream=None):
+        L = lib()
+        g = GridDesc(nx=grid.nx, ny=grid.ny, x0=grid.x0, y0=grid.y0, h=grid.h, exterior=EXT[grid.exterior],
+                     nu=grid.nu)
+        g.u_inf[0], g.u_inf[1] = grid.u_inf
+        self.grid = grid
+        self._pts = []
+        arr = (BodyDesc * max(1, len(bodies)))()
+        for k, b in enumerate(bodies):
+            p = np.ascontiguousarray(b.points, dtype=np.float64)
+            self._pts.append(p)
+            arr[k].n_points = p.shape[0]
+            arr[k].xy_host = p.ctypes.data_as(C.POINTER(C.c_double))
+            arr[k].is_enclosure = int(b.is_enclosure)
+            arr[k].center[0], arr[k].center[1] = b.center
+            arr[k].u_rigid[0], arr[k].u_rigid[1] = b.u_rigid
+            arr[k].omega_rigid = b.omega_rigid
+            r = b.rect if b.rect is not None else (-1, -1, -1, -1)
+            for q in range(4):
+                arr[k].rect[q] = r[q]
+        o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
+                       max_refine=3, guess=guess, host_only=int(host_only))
+        if stream is None and not host_only:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        rc = L.iim_create(C.byref(g), len(bodies), arr, C.byref(o), C.c_void_p(stream or 0), C.byref(h))
+        if rc:
+            raise IIMError(rc, (L.iim_last_error(None) or b"").decode())
+        self._h = h
+        self.host_only = host_only
+        info = Info()
+        L.iim_query(h, C.byref(info))
+        self.info = {f[0]: getattr(info, f[0]) for f in Info._fields_}
+        self.n_circ = info.n_circ
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what, allow=()):
+        if rc and rc not in allow:
+            raise IIMError(rc, "%s: %s" % (what, (lib().iim_last_error(self._h) or b"").decode()))
+        return rc
+
+    def geometry(self):
+        v = GeometryView()
+        self._check(lib().iim_get_geometry(self._h, C.byref(v)), "iim_get_geometry")
+        nc, na = v.n_control, v.n_affected
+        nx, ny = self.grid.nx, self.grid.ny
+        a = lambda p, n: np.ctypeslib.as_array(p, shape=(n,)).copy() if n else np.zeros(0)
+        out = {
+            "c_xy": a(v.c_xy, 2 * nc).reshape(nc, 2), "c_theta": a(v.c_theta, nc),
+            "c_normal": a(v.c_normal, 2 * nc).reshape(nc, 2), "c_int": a(v.c_int, 5 * nc).reshape(nc, 5),
+            "a_int": a(v.a_int, 4 * na).reshape(na, 4), "cls": a(v.cls, nx * ny).reshape(ny, nx),
+            "rects": a(v.rects, 4 * v.n_circ).reshape(v.n_circ, 4), "circ_body": a(v.circ_body, v.n_circ),
+        }
+        return out
+
+    def dt_max(self, a_max):
+        d = C.c_double()
+        self._check(lib().iim_dt_max(self._h, a_max, C.byref(d)), "iim_dt_max")
+        return d.value
+
+    def poisson(self, src, psi):
+        self._check(lib().iim_poisson(self._h, _ptr(src), _ptr(psi)), "iim_poisson")
+
+    def reconstruct(self, omega, Gamma, psi, u, v, allow_noconv=False):
+        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64)))
+        st = StepStats()
+        rc = lib().iim_reconstruct(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), _ptr(psi),
+                                   _ptr(u), _ptr(v), C.byref(st))
+        self._check(rc, "iim_reconstruct", allow=(IIM_ENOCONV,) if allow_noconv else ())
+        return st.as_dict()
+
+    def rhs(self, omega, u, v, domega, omega_b=None):
+        dG = np.zeros(max(1, self.n_circ))
+        self._check(lib().iim_rhs(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(domega),
+                                  dG.ctypes.data_as(C.POINTER(C.c_double)), _ptr(omega_b)), "iim_rhs")
+        return dG[:self.n_circ]
+
+    def rk3_steps(self, omega, Gamma, dt, n_steps=1):
+        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).copy()
+        if G.size == 0:
+            G = np.zeros(1)
+        st = StepStats()
+        self._check(lib().iim_rk3_steps(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
+                                        n_steps, C.byref(st)), "iim_rk3_steps")
+        return G[:self.n_circ], st.as_dict()

@@ -1,0 +1,683 @@
+// C ABI of the IIM library (declared in include/iim.h): context set-up and the
+// orchestration of one velocity reconstruction (Sec. 4.2), the transport and
+// Kelvin right-hand sides (Sec. 3, Sec. 5.1, Sec. 5.3) and the low-storage
+// RK3 step (Sec. 5.5).  All device work is enqueued on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/iim.h"
+#include "iim_dev.hpp"
+#include "iim_host.hpp"
+
+using namespace iim;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Williamson's low-storage third-order coefficients
+const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+struct HipError : std::runtime_error {
+  int code;
+  HipError(const std::string& m, int c) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess)                                                                           \
+      throw HipError(std::string(#x) + ": " + hipGetErrorString(e_),                                \
+                     e_ == hipErrorOutOfMemory ? IIM_ENOMEM : IIM_EDEVICE);                         \
+  } while (0)
+
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+struct iim_ctx {
+  std::string err;
+  Geometry geo;
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  int precision = IIM_PREC_FP64;
+  double tol = 1e-13;
+  int max_iter = 400, restart = 40, guess = IIM_GUESS_PREVIOUS, chunk = 4;
+  std::vector<void*> allocs;
+  size_t dev_bytes = 0;
+  DGeom dg{};
+  DFft df{};
+  DDst dd{};
+  DKrylov dk{};
+  bool box = false;
+  int8_t* cls_zero = nullptr;
+  double *psi = nullptr, *U = nullptr, *V = nullptr;
+  double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
+  double *Qw = nullptr, *wtmp = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
+  double* st_host = nullptr;
+  bool have_prev = false;
+  // host copies for the geometry view
+  std::vector<double> v_cxy, v_cn;
+  std::vector<int32_t> v_cint, v_aint, v_rects, v_circ;
+
+  template <class T>
+  T* dalloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    allocs.push_back(p);
+    dev_bytes += n * sizeof(T);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~iim_ctx() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+  }
+};
+
+// ---------------------------------------------------------------- helpers
+namespace {
+
+int fail(iim_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+DStencil upload_stencil(iim_ctx* c, const Stencil& s, bool with_comp) {
+  const int nx = c->geo.grid.nx, nxr = nx + 2;
+  std::vector<int> ridx(s.w.size()), gidx(s.w.size());
+  for (size_t e = 0; e < s.w.size(); ++e) {
+    ridx[e] = (s.jj[e] + 1) * nxr + s.ii[e] + 1;
+    if (with_comp && s.comp[e] == 1) ridx[e] |= (1 << 30);
+    gidx[e] = s.jj[e] * nx + s.ii[e];
+  }
+  DStencil d;
+  d.ptr = c->upload(s.ptr);
+  d.ridx = c->upload(ridx);
+  d.gidx = c->upload(gidx);
+  d.w = c->upload(s.w);
+  d.bptr = c->upload(s.bptr);
+  d.bc = c->upload(s.bc);
+  d.bw = c->upload(s.bw);
+  d.rows = s.rows();
+  return d;
+}
+
+void setup_device(iim_ctx* c) {
+  const Geometry& g = c->geo;
+  const int nx = g.grid.nx, ny = g.grid.ny, nxr = nx + 2;
+  const size_t N = (size_t)nx * ny, NR = (size_t)nxr * (ny + 2);
+  DGeom& d = c->dg;
+  d.nx = nx;
+  d.ny = ny;
+  d.nxr = nxr;
+  d.h = g.grid.h;
+  d.inv_h = 1.0 / g.grid.h;
+  d.nu = g.grid.nu;
+  const bool box = g.grid.exterior == IIM_EXT_BOX;
+  c->box = box;
+  d.uinf_x = box ? 0.0 : g.grid.u_inf[0];
+  d.uinf_y = box ? 0.0 : g.grid.u_inf[1];
+  d.nc = g.nc;
+  d.ng = g.ng;
+  d.na = g.na;
+  d.nbc = g.nbc();
+  d.nsp = (int)g.special.size();
+  d.n = g.na + g.nbc();
+  // classes: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
+  std::vector<int8_t> cls(N);
+  for (size_t q = 0; q < N; ++q) cls[q] = g.cls[q] == CLS_FLUID ? 0 : (g.cls[q] == CLS_GHOST ? 2 : 3);
+  for (int q : g.special) cls[q] = 1;
+  d.cls = c->upload(cls);
+  c->cls_zero = c->dalloc<int8_t>(N);
+  HIPCHK(hipMemset(c->cls_zero, 0, N));
+  std::vector<int> gr(g.ng), gg(g.ng);
+  for (int q = 0; q < g.ng; ++q) {
+    gr[q] = (g.g_j[q] + 1) * nxr + g.g_i[q] + 1;
+    gg[q] = g.g_j[q] * nx + g.g_i[q];
+  }
+  d.g_ridx = c->upload(gr);
+  d.g_gidx = c->upload(gg);
+  std::vector<int> col_of_body(g.bodies.size(), -1);
+  for (int k = 0; k < g.nbc(); ++k) col_of_body[g.circ_body[k]] = k;
+  std::vector<int> ag(g.na), acol(g.na);
+  for (int a = 0; a < g.na; ++a) {
+    ag[a] = g.a_j[a] * nx + g.a_i[a];
+    acol[a] = col_of_body[g.a_body[a]];
+  }
+  d.a_gidx = c->upload(ag);
+  d.a_col = c->upload(acol);
+  d.a_id = c->upload(g.a_id);
+  std::vector<int> rp(ny + 1, 0), ri, ra;
+  for (int a = 0; a < g.na; ++a) rp[g.a_j[a] + 1]++;
+  for (int j = 0; j < ny; ++j) rp[j + 1] += rp[j];
+  ri.resize(g.na);
+  ra.resize(g.na);
+  {
+    std::vector<int> fillp(rp.begin(), rp.end() - 1);
+    for (int a = 0; a < g.na; ++a) {
+      const int p = fillp[g.a_j[a]]++;
+      ri[p] = g.a_i[a];
+      ra[p] = a;
+    }
+  }
+  d.row_ptr = c->upload(rp);
+  d.row_i = c->upload(ri);
+  d.row_a = c->upload(ra);
+  d.special = c->upload(g.special);
+  std::vector<int> ccol(g.nc);
+  std::vector<double> psibt(g.nc), wbc(g.nc, 0.0);
+  for (int q = 0; q < g.nc; ++q) {
+    ccol[q] = col_of_body[g.c_body[q]];
+    psibt[q] = g.c_psib[q] - (d.uinf_x * g.c_y[q] - d.uinf_y * g.c_x[q]);
+  }
+  for (int q = 0; q < g.nc; ++q)
+    for (int e = g.wbc.bptr[q]; e < g.wbc.bptr[q + 1]; ++e)
+      wbc[q] += g.wbc.bw[e] * g.c_ub[2 * g.wbc.bc[e] + g.wbc.bcomp[e]];
+  d.c_col = c->upload(ccol);
+  d.c_psibt = c->upload(psibt);
+  d.c_ub = c->upload(g.c_ub);
+  d.wb_const = c->upload(wbc);
+  std::vector<double> bpsi(g.na, 0.0), b1((size_t)std::max(1, g.nbc()) * g.na, 0.0);
+  for (int a = 0; a < g.na; ++a)
+    for (int e = g.aop.bptr[a]; e < g.aop.bptr[a + 1]; ++e) {
+      const int cp = g.aop.bc[e];
+      bpsi[a] += g.aop.bw[e] * psibt[cp];
+      if (ccol[cp] >= 0) b1[(size_t)ccol[cp] * g.na + a] += g.aop.bw[e];
+    }
+  d.bpsi = c->upload(bpsi);
+  d.b1 = c->upload(b1);
+  std::vector<int> rects;
+  for (auto& r : g.rects) rects.insert(rects.end(), r.begin(), r.end());
+  d.rects = c->upload(rects);
+  d.ext4b = upload_stencil(c, g.ext4b, false);
+  d.ext3b = upload_stencil(c, g.ext3b, false);
+  d.ext3n = upload_stencil(c, g.ext3n, false);
+  d.aop = upload_stencil(c, g.aop, false);
+  d.wbc = upload_stencil(c, g.wbc, true);
+
+  // Poisson operator
+  const double h = g.grid.h;
+  if (box) {
+    auto phi = [](int n, std::vector<double>& P, std::vector<double>& PT) {
+      P.resize((size_t)n * n);
+      PT.resize((size_t)n * n);
+      for (int k = 0; k < n; ++k) {
+        const double ck = (k == n - 1) ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+        for (int m = 0; m < n; ++m) {
+          const double v = ck * std::sin(M_PI * (k + 1) * (2.0 * m + 1) / (2.0 * n));
+          P[(size_t)k * n + m] = v;
+          PT[(size_t)m * n + k] = v;
+        }
+      }
+    };
+    std::vector<double> px, pxt, py, pyt, lam(N);
+    phi(nx, px, pxt);
+    phi(ny, py, pyt);
+    for (int ky = 0; ky < ny; ++ky)
+      for (int kx = 0; kx < nx; ++kx) {
+        const double sy = std::sin(M_PI * (ky + 1) / (2.0 * ny)), sx = std::sin(M_PI * (kx + 1) / (2.0 * nx));
+        lam[(size_t)ky * nx + kx] = 1.0 / ((4.0 / (h * h)) * (sy * sy + sx * sx));
+      }
+    c->dd.phx = c->upload(px);
+    c->dd.phxT = c->upload(pxt);
+    c->dd.phy = c->upload(py);
+    c->dd.phyT = c->upload(pyt);
+    c->dd.lam_inv = c->upload(lam);
+    c->dd.t1 = c->dalloc<double>(N);
+    c->dd.t2 = c->dalloc<double>(N);
+    c->dd.src = c->dalloc<double>(N);
+  } else {
+    const bool outflow = g.grid.exterior == IIM_EXT_OUTFLOW;
+    const int mx = next_pow2((outflow ? 4 : 2) * nx), my = next_pow2(2 * ny);
+    if (mx / 2 > 4096 || my > 4096) throw ArgError("grid too large for the FFT plan (mx/2, my <= 4096)");
+    DFft& f = c->df;
+    f.mx = mx;
+    f.my = my;
+    f.hx = mx / 2;
+    f.ld = ny + 2;
+    f.outflow = outflow;
+    std::vector<double> tab((size_t)(mx / 2 + 1) * (my / 2 + 1));
+    lgf_table(mx / 2, my / 2, tab.data());
+    std::vector<double> ghat((size_t)(mx / 2 + 1) * (my / 2 + 1));
+    lgf_spectrum(mx, my, h, tab.data(), mx / 2, ghat.data());
+    f.ghat = c->upload(ghat);
+    auto twid = [](int n, int count) {
+      std::vector<double2> t(count);
+      for (int k = 0; k < count; ++k) {
+        const double a = -2.0 * M_PI * (double)k / n;
+        t[k] = make_double2(std::cos(a), std::sin(a));
+      }
+      return t;
+    };
+    f.tw_x = c->upload(twid(f.hx, f.hx));
+    f.tw_xr = c->upload(twid(mx, f.hx + 1));
+    f.tw_y = c->upload(twid(my, my));
+    f.spec = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
+  }
+  // Krylov state
+  DKrylov& k = c->dk;
+  k.n = d.n;
+  k.m = c->restart;
+  k.V = c->dalloc<double>((size_t)(k.m + 1) * k.n);
+  k.H = c->dalloc<double>((size_t)(k.m + 1) * k.m);
+  k.cs = c->dalloc<double>(k.m);
+  k.sn = c->dalloc<double>(k.m);
+  k.g = c->dalloc<double>(k.m + 1);
+  k.x = c->dalloc<double>(k.n);
+  k.b = c->dalloc<double>(k.n);
+  k.w = c->dalloc<double>(k.n);
+  k.st = c->dalloc<double>(KS_SIZE);
+  HIPCHK(hipMemset(k.x, 0, k.n * sizeof(double)));
+  HIPCHK(hipHostMalloc(&c->st_host, KS_SIZE * sizeof(double)));
+  // fields
+  c->psi = c->dalloc<double>(NR);
+  c->U = c->dalloc<double>(NR);
+  c->V = c->dalloc<double>(NR);
+  c->wb = c->dalloc<double>(g.nc);
+  c->w4 = c->dalloc<double>(N);
+  c->w3b = c->dalloc<double>(N);
+  c->w3n = c->dalloc<double>(N);
+  c->Qw = c->dalloc<double>(N);
+  c->wtmp = c->dalloc<double>(N);
+  c->Gd = c->dalloc<double>(std::max(1, g.nbc()));
+  c->QGd = c->dalloc<double>(std::max(1, g.nbc()));
+  c->dGd = c->dalloc<double>(std::max(1, g.nbc()));
+  HIPCHK(hipMemset(c->psi, 0, NR * sizeof(double)));
+  HIPCHK(hipMemset(c->w4, 0, N * sizeof(double)));
+  HIPCHK(hipMemset(c->w3b, 0, N * sizeof(double)));
+  HIPCHK(hipMemset(c->w3n, 0, N * sizeof(double)));
+  HIPCHK(hipDeviceSynchronize());
+}
+
+// psi (ring) = G(source), source = mask(omega) + sgn * E_a gam, rows [rj0, rj1] -> [oj0, oj1]
+void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
+             int oj0, int oj1, double* psi, const double* done) {
+  if (c->box)
+    launch_dst(dg, c->dd, omega, gam, sgn, psi, done, c->stream);
+  else
+    launch_conv(dg, c->df, omega, gam, sgn, rj0, rj1, oj0, oj1, psi, done, c->stream);
+}
+
+void read_status(iim_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->st_host, c->dk.st, KS_SIZE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+void set_status(iim_ctx* c) {
+  double st[KS_SIZE] = {0};
+  st[KS_DONE] = 0.0;
+  st[KS_RES0] = -1.0;
+  st[KS_TOL] = c->tol;
+  std::memcpy(c->st_host, st, sizeof(st));
+  HIPCHK(hipMemcpyAsync(c->dk.st, c->st_host, KS_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+}
+
+// One velocity reconstruction: returns status; fills iters/res0/res.
+int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, int& iters, double& res0,
+                      double& res) {
+  const Geometry& g = c->geo;
+  const DGeom& dg = c->dg;
+  DKrylov& k = c->dk;
+  const int ny = g.grid.ny;
+  // right-hand side: b = A G omega + B psi_b_tilde, circulation rows
+  apply_G(c, dg, omega, nullptr, 0.0, 0, ny - 1, g.out_j0, g.out_j1, c->psi, nullptr);
+  launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
+  set_status(c);
+  const bool warm = c->guess == IIM_GUESS_PREVIOUS && c->have_prev;
+  if (warm) {
+    apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
+    launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
+  }
+  launch_krylov_start(dg, k, !warm, c->stream);
+  read_status(c);
+  int total = 0;
+  bool done = c->st_host[KS_DONE] != 0.0;
+  while (!done && total < c->max_iter) {
+    int j = 0;
+    for (; j < k.m && total < c->max_iter; ++j) {
+      apply_G(c, dg, nullptr, k.V + (size_t)j * k.n, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, k.st);
+      launch_arnoldi(dg, k, c->psi, j, c->stream);
+      ++total;
+      if ((j + 1) % c->chunk == 0 || j + 1 == k.m || total >= c->max_iter) {
+        read_status(c);
+        if (c->st_host[KS_DONE] != 0.0) {
+          done = true;
+          break;
+        }
+      }
+    }
+    launch_gmres_update(k, c->stream);
+    if (done || total >= c->max_iter) break;
+    // restart from the true residual
+    apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
+    launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
+    launch_krylov_start(dg, k, false, c->stream);
+    read_status(c);
+    done = c->st_host[KS_DONE] != 0.0;
+  }
+  read_status(c);
+  iters = (int)c->st_host[KS_ITERS];
+  res0 = c->st_host[KS_RES0];
+  res = c->st_host[KS_RES];
+  c->have_prev = true;
+  // psi = G (omega - E_a gamma), ghosts, velocity
+  apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+  launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
+  if (c->st_host[KS_NFAIL] != 0.0) return IIM_ENONFINITE;
+  if (c->st_host[KS_RES] > c->tol) return IIM_ENOCONV;
+  return IIM_OK;
+}
+
+int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
+  const size_t N = (size_t)c->geo.grid.nx * c->geo.grid.ny;
+  const DGeom& dg = c->dg;
+  launch_fill(c->Qw, 0.0, N, c->stream);
+  launch_fill(c->QGd, 0.0, std::max(1, dg.nbc), c->stream);
+  double* in = omega;
+  double* out = c->wtmp;
+  int status = IIM_OK;
+  iim_step_stats st{};
+  st.converged = 1;
+  for (int s = 0; s < 3; ++s) {
+    int it;
+    double r0, r1;
+    const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1);
+    st.iters[s] = it;
+    st.res0[s] = r0;
+    st.res[s] = r1;
+    if (rc == IIM_ENONFINITE) return rc;
+    if (rc == IIM_ENOCONV) {
+      status = IIM_ENOCONV;
+      st.converged = 0;
+    }
+    launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+    launch_transport(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, RK_A[s], RK_B[s], dt, 1, c->stream);
+    launch_kelvin(dg, in, c->U, c->V, c->dGd, c->Gd, c->QGd, RK_A[s], RK_B[s], dt, 1, c->stream);
+    std::swap(in, out);
+  }
+  // three swaps: the result sits in the context buffer
+  HIPCHK(hipMemcpyAsync(omega, in, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (stats) *stats = st;
+  return status;
+}
+
+iim_ctx* as_ctx(const iim_ctx* c) { return const_cast<iim_ctx*>(c); }
+
+}  // namespace
+
+// ================================================================== ABI
+extern "C" {
+
+int iim_abi_version(void) { return IIM_ABI_VERSION; }
+
+const char* iim_status_string(int s) {
+  switch (s) {
+    case IIM_OK: return "ok";
+    case IIM_EINVAL: return "invalid argument";
+    case IIM_ENOMEM: return "out of memory";
+    case IIM_EGEOM: return "geometry error";
+    case IIM_ENOCONV: return "Krylov solver did not converge";
+    case IIM_ENONFINITE: return "non-finite value";
+    case IIM_EDEVICE: return "device error";
+    case IIM_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc* bodies, const iim_solver_opts* opts,
+               void* hip_stream, iim_ctx** out) {
+  if (!out) return IIM_EINVAL;
+  *out = nullptr;
+  if (!grid || n_bodies < 0 || (n_bodies > 0 && !bodies)) return IIM_EINVAL;
+  iim_ctx* c = new (std::nothrow) iim_ctx();
+  if (!c) return IIM_ENOMEM;
+  try {
+    GridSpec gs;
+    gs.nx = grid->nx;
+    gs.ny = grid->ny;
+    gs.x0 = grid->x0;
+    gs.y0 = grid->y0;
+    gs.h = grid->h;
+    gs.exterior = grid->exterior;
+    gs.u_inf[0] = grid->u_inf[0];
+    gs.u_inf[1] = grid->u_inf[1];
+    gs.nu = grid->nu;
+    if (gs.exterior < IIM_EXT_BOX || gs.exterior > IIM_EXT_OUTFLOW) throw ArgError("unknown exterior condition");
+    if (!(gs.nu >= 0.0)) throw ArgError("nu must be >= 0");
+    std::vector<BodySpec> bs(n_bodies);
+    for (int k = 0; k < n_bodies; ++k) {
+      const auto& b = bodies[k];
+      if (b.n_points < 4 || !b.xy_host) throw ArgError("body " + std::to_string(k) + ": bad point set");
+      bs[k].xy.assign(b.xy_host, b.xy_host + 2 * (size_t)b.n_points);
+      for (double v : bs[k].xy)
+        if (!std::isfinite(v)) throw ArgError("body " + std::to_string(k) + ": non-finite point");
+      bs[k].enclosure = b.is_enclosure != 0;
+      for (int q = 0; q < 2; ++q) {
+        bs[k].center[q] = b.center[q];
+        bs[k].u_rigid[q] = b.u_rigid[q];
+      }
+      bs[k].omega = b.omega_rigid;
+      for (int q = 0; q < 4; ++q) bs[k].rect[q] = b.rect[q];
+    }
+    if (opts) {
+      c->precision = opts->precision;
+      if (opts->krylov_tol > 0) c->tol = opts->krylov_tol;
+      if (opts->krylov_max_iter > 0) c->max_iter = opts->krylov_max_iter;
+      if (opts->krylov_restart > 0) c->restart = std::min(64, opts->krylov_restart);
+      c->guess = opts->guess;
+      c->host_only = opts->host_only != 0;
+    }
+    if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
+    build_geometry(c->geo, gs, bs);
+    c->stream = (hipStream_t)hip_stream;
+    // geometry views
+    const Geometry& g = c->geo;
+    for (int q = 0; q < g.nc; ++q) {
+      c->v_cxy.push_back(g.c_x[q]);
+      c->v_cxy.push_back(g.c_y[q]);
+      c->v_cn.push_back(g.c_nx[q]);
+      c->v_cn.push_back(g.c_ny[q]);
+      const int32_t ints[5] = {g.c_axis[q], g.c_sigma[q], g.c_if[q], g.c_jf[q], g.c_body[q]};
+      c->v_cint.insert(c->v_cint.end(), ints, ints + 5);
+    }
+    for (int a = 0; a < g.na; ++a) {
+      const int32_t ints[4] = {g.a_i[a], g.a_j[a], g.a_ghost[a], g.a_body[a]};
+      c->v_aint.insert(c->v_aint.end(), ints, ints + 4);
+    }
+    for (auto& r : g.rects) c->v_rects.insert(c->v_rects.end(), r.begin(), r.end());
+    c->v_circ = std::vector<int32_t>(g.circ_body.begin(), g.circ_body.end());
+    if (!c->host_only) setup_device(c);
+  } catch (const GeomError& e) {
+    g_create_error = e.what();
+    delete c;
+    return IIM_EGEOM;
+  } catch (const ArgError& e) {
+    g_create_error = e.what();
+    delete c;
+    return IIM_EINVAL;
+  } catch (const HipError& e) {
+    g_create_error = e.what();
+    const int code = e.code;
+    delete c;
+    return code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    delete c;
+    return IIM_ENOMEM;
+  }
+  g_create_error.clear();
+  *out = c;
+  return IIM_OK;
+}
+
+int iim_destroy(iim_ctx* c) {
+  if (!c) return IIM_EINVAL;
+  if (!c->host_only && c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return IIM_OK;
+}
+
+const char* iim_last_error(const iim_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int iim_query(const iim_ctx* c, iim_info* o) {
+  if (!c || !o) return IIM_EINVAL;
+  const Geometry& g = c->geo;
+  o->nx = g.grid.nx;
+  o->ny = g.grid.ny;
+  o->n_control = g.nc;
+  o->n_affected = g.na;
+  o->n_ghost = g.ng;
+  o->n_circ = g.nbc();
+  o->n_special = (int32_t)g.special.size();
+  o->fft_mx = c->box ? 0 : c->df.mx;
+  o->fft_my = c->box ? 0 : c->df.my;
+  o->win_j0 = g.src_j0;
+  o->win_j1 = g.src_j1;
+  o->device_bytes = (int64_t)c->dev_bytes;
+  return IIM_OK;
+}
+
+int iim_get_geometry(const iim_ctx* c, iim_geometry_view* o) {
+  if (!c || !o) return IIM_EINVAL;
+  const Geometry& g = c->geo;
+  o->n_control = g.nc;
+  o->c_xy = c->v_cxy.data();
+  o->c_theta = g.c_theta.data();
+  o->c_normal = c->v_cn.data();
+  o->c_int = c->v_cint.data();
+  o->n_affected = g.na;
+  o->a_int = c->v_aint.data();
+  o->cls = g.cls.data();
+  o->n_circ = g.nbc();
+  o->rects = c->v_rects.data();
+  o->circ_body = c->v_circ.data();
+  return IIM_OK;
+}
+
+int iim_dt_max(const iim_ctx* c, double a_max, double* dt) {
+  if (!c || !dt || !(a_max >= 0)) return IIM_EINVAL;
+  const double h = c->geo.grid.h, nu = c->geo.grid.nu;
+  const double denom = a_max / (1.620 * h) + nu / (0.314 * h * h);
+  if (!(denom > 0)) return IIM_EINVAL;
+  *dt = 1.0 / denom;
+  return IIM_OK;
+}
+
+int iim_lgf_table(int32_t mx, int32_t my, double* out) {
+  if (mx < 0 || my < 0 || !out) return IIM_EINVAL;
+  lgf_table(mx, my, out);
+  return IIM_OK;
+}
+
+int iim_poisson(iim_ctx* c, const double* src, double* psi) {
+  if (!c || !src || !psi) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    DGeom dg = c->dg;
+    dg.cls = c->cls_zero;  // no masking
+    dg.na = 0;
+    const int ny = c->geo.grid.ny;
+    apply_G(c, dg, src, nullptr, 0.0, 0, ny - 1, -1, ny, psi, nullptr);
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_reconstruct(iim_ctx* c, const double* omega, const double* Gamma_host, double* psi, double* u, double* v,
+                    iim_step_stats* stats) {
+  if (!c || !omega || !u || !v || (c->geo.nbc() > 0 && !Gamma_host)) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    const int nb = c->geo.nbc();
+    if (nb)
+      HIPCHK(hipMemcpyAsync(c->Gd, Gamma_host, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int it;
+    double r0, r1;
+    const int rc = reconstruct_stage(c, omega, c->Gd, it, r0, r1);
+    const size_t NR = (size_t)(c->geo.grid.nx + 2) * (c->geo.grid.ny + 2);
+    if (psi) HIPCHK(hipMemcpyAsync(psi, c->psi, NR * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(u, c->U, NR * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(v, c->V, NR * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipGetLastError());
+    if (stats) {
+      *stats = iim_step_stats{};
+      stats->iters[0] = it;
+      stats->res0[0] = r0;
+      stats->res[0] = r1;
+      stats->converged = rc == IIM_OK;
+    }
+    if (rc != IIM_OK) return fail(c, rc, rc == IIM_ENOCONV ? "Krylov limit reached" : "non-finite residual");
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_rhs(iim_ctx* c, const double* omega, const double* u, const double* v, double* domega, double* dGamma_host,
+            double* omega_b) {
+  if (!c || !omega || !u || !v || !domega || (c->geo.nbc() > 0 && !dGamma_host)) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    const DGeom& dg = c->dg;
+    launch_omega_bc(dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+    launch_transport(dg, omega, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, 0.0, 0.0, 0.0, 0, c->stream);
+    launch_kelvin(dg, omega, u, v, c->dGd, nullptr, nullptr, 0.0, 0.0, 0.0, 0, c->stream);
+    if (omega_b)
+      HIPCHK(hipMemcpyAsync(omega_b, c->wb, c->geo.nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    const int nb = c->geo.nbc();
+    if (nb) HIPCHK(hipMemcpyAsync(dGamma_host, c->dGd, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int32_t n_steps, iim_step_stats* stats) {
+  if (!c || !omega || (c->geo.nbc() > 0 && !Gamma_host) || !(dt > 0) || n_steps < 0) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    const int nb = c->geo.nbc();
+    if (nb) HIPCHK(hipMemcpyAsync(c->Gd, Gamma_host, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int status = IIM_OK;
+    for (int s = 0; s < n_steps; ++s) {
+      const int rc = run_step(c, omega, dt, stats);
+      if (rc == IIM_ENONFINITE) return fail(c, rc, "non-finite residual");
+      if (rc == IIM_ENOCONV) status = rc;
+    }
+    if (nb) HIPCHK(hipMemcpyAsync(Gamma_host, c->Gd, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    if (status != IIM_OK) return fail(c, status, "Krylov limit reached");
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_rk3_step(iim_ctx* c, double* omega, double* Gamma_host, double dt, iim_step_stats* stats) {
+  return iim_rk3_steps(c, omega, Gamma_host, dt, 1, stats);
+}
+
+}  // extern "C"

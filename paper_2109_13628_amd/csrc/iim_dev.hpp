@@ -1,0 +1,125 @@
+// Device-side data of one IIM context and the launch wrappers of the HIP
+// kernels (kernels.hip).  Host code (api.cpp) fills these structs; kernels
+// receive them by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace iim {
+
+// Sparse table on the device: row r reads node entries [ptr[r], ptr[r+1]) and
+// boundary entries [bptr[r], bptr[r+1]).
+struct DStencil {
+  const int* ptr = nullptr;
+  const int* ridx = nullptr;   // ring-array index (j+1)*(nx+2) + (i+1); bit 30 = component 1 (wbc only)
+  const int* gidx = nullptr;   // grid-array index j*nx + i
+  const double* w = nullptr;
+  const int* bptr = nullptr;
+  const int* bc = nullptr;     // control point
+  const double* bw = nullptr;
+  int rows = 0;
+};
+
+struct DGeom {
+  int nx, ny, nxr;             // nxr = nx + 2
+  double h, inv_h, nu;
+  double uinf_x, uinf_y;
+  int nc, ng, na, nbc, nsp;
+  int n;                       // Krylov unknowns: na + nbc
+  const int8_t* cls;           // [ny][nx]: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
+  const int* g_ridx;           // ghost -> ring index
+  const int* g_gidx;           // ghost -> grid index
+  const int* a_gidx;           // affected -> grid index
+  const int* a_id;             // [ny][nx] grid -> affected index (-1: none)
+  const int* a_col;            // affected -> circulation column (-1: none)
+  const int* row_ptr;          // per grid row: affected points of that row
+  const int* row_i;            //   column i
+  const int* row_a;            //   affected index
+  const int* special;          // boundary-kernel fluid nodes (grid index)
+  const int* c_col;            // control point -> circulation column (-1: none)
+  const double* c_psibt;       // psi_b - psi_inf at control points
+  const double* c_ub;          // [nc][2]
+  const double* wb_const;      // boundary-velocity part of omega_b
+  const double* bpsi;          // B psi_b_tilde  [na]
+  const double* b1;            // B 1_k, [nbc][na]
+  const int* rects;            // [nbc][4]
+  DStencil ext4b, ext3b, ext3n, aop, wbc;
+};
+
+// FFT convolution plan (free space / outflow)
+struct DFft {
+  int mx, my;                  // padded torus
+  int hx;                      // mx / 2 (complex length of the row transforms)
+  int ld;                      // leading dimension of the spectrum buffer (>= ny + 2)
+  const double* ghat;          // [mx/2+1][my/2+1]
+  const double2* tw_x;         // exp(-2 pi i k / hx), k < hx
+  const double2* tw_xr;        // exp(-2 pi i k / mx), k <= mx/2 (real-FFT post-processing)
+  const double2* tw_y;         // exp(-2 pi i k / my), k < my
+  double2* spec;               // [mx/2+1][ld]
+  bool outflow;
+};
+
+struct DDst {                  // box: dense orthonormal sine transforms
+  const double* phx;           // [nx][nx]   phi_x[k][n] (orthonormal DST-II)
+  const double* phxT;          // transpose
+  const double* phy;           // [ny][ny]
+  const double* phyT;
+  const double* lam_inv;       // [ny][nx]
+  double* t1;                  // [ny][nx]
+  double* t2;
+  double* src;                 // [ny][nx] assembled source
+};
+
+// Krylov state (device)
+struct DKrylov {
+  int n, m;                    // unknowns, restart length
+  double* V;                   // [(m+1)][n]
+  double* H;                   // [(m+1)][m] column-major: H[k*(m+1) + i]
+  double* cs;                  // [m]
+  double* sn;                  // [m]
+  double* g;                   // [m+1]
+  double* x;                   // [n]
+  double* b;                   // [n]
+  double* w;                   // [n] work
+  double* st;                  // status: see KS_* offsets
+};
+enum {
+  KS_DONE = 0, KS_K = 1, KS_ITERS = 2, KS_BNORM = 3, KS_BETA = 4, KS_RES = 5, KS_RES0 = 6, KS_TOL = 7,
+  KS_NFAIL = 8, KS_SIZE = 16
+};
+
+// ---------------------------------------------------------------- launchers
+// Poisson operator (free space): psi_ring rows [oj0, oj1] from sources in rows [rj0, rj1].
+// source = mask(omega) (omega may be null) + sgn * scatter(gam) (gam may be null).
+void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
+                 int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
+                 hipStream_t s);
+void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
+                double* psi_ring, const double* done_flag, hipStream_t s);
+void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,
+                          double* psi_ring, hipStream_t s);
+
+void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega,
+                       const double* Gamma, double* b, hipStream_t s);
+void launch_krylov_start(const DGeom& g, const DKrylov& k, bool x_is_zero, hipStream_t s);
+void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s);
+void launch_gmres_update(const DKrylov& k, hipStream_t s);
+void launch_matvec_finish(const DGeom& g, const DKrylov& kr, const double* psi_ring, const double* v,
+                          double* out, hipStream_t s);
+
+void launch_recover_fields(const DGeom& g, const double* x, double* psi_ring, double* U, double* V,
+                           hipStream_t s);
+void launch_omega_bc(const DGeom& g, const double* omega, const double* U, const double* V,
+                     double* wb, double* w4, double* w3b, double* w3n, hipStream_t s);
+// mode 0: out = domega/dt;  mode 1: Q = a Q + dt rhs, out = omega + b Q
+void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V,
+                      const double* w4, const double* w3b, const double* w3n, double* out, double* Q,
+                      double a, double b, double dt, int mode, hipStream_t s);
+// Kelvin: dG = -h sum (F+Q).n over dR_k; mode 1 also updates Gamma/QG in place
+void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG,
+                   double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s);
+void launch_fill(double* p, double v, size_t n, hipStream_t s);
+
+}  // namespace iim

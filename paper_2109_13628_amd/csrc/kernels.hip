@@ -1,0 +1,913 @@
+// HIP kernels of the IIM library (gfx950, wave64).
+//
+// Poisson operator (Sec. 4.2): zero-padded lattice-Green's-function
+// convolution on an mx x my torus in three passes over HBM,
+//   rows  : real-to-complex FFT of each source row (half-length complex FFT +
+//           split), IIM scatter of gamma fused into the load, spectrum written
+//           column-major spec[kx][j];
+//   cols  : per column kx: FFT, multiply by the (real) kernel spectrum, inverse
+//           FFT -- entirely in LDS, reading only the source rows and writing
+//           only the requested output rows (pruned in the Krylov loop);
+//   irows : complex-to-real inverse FFT of the requested rows, writing the
+//           grid plus the one-node ring.
+// FFTs are LDS Stockham radix-4 (one radix-2 stage when log2 N is odd) with
+// per-thread register butterflies and a twiddle table in global memory.
+//
+// Box exterior: dense orthonormal sine transforms (DST-II) as four small
+// GEMMs.
+//
+// IIM sparse kernels (Sec. 2.1-2.2): ghost values, correction rows, boundary
+// vorticity (Sec. 5.3) and the vorticity extensions read host-built tables.
+// Transport (Sec. 3): a bulk kernel for fluid nodes whose stencils are all
+// fluid, and a boundary kernel for the rest; both fuse the RK3 update.
+// GMRES (Sec. 4.2): Arnoldi with classical Gram-Schmidt applied twice, Givens
+// rotations, all in one workgroup per step, state in device memory.
+#include <hip/hip_runtime.h>
+
+#include "iim_dev.hpp"
+
+namespace iim {
+
+#define IIM_LAUNCH_CHECK() (void)0
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+
+// ------------------------------------------------------------------ FFT core
+template <int N>
+struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <>
+struct Log2<1> { static constexpr int v = 0; };
+
+// One Stockham stage of radix R on N points by TPF threads.  In place: all
+// loads to registers, barrier, all stores, barrier.
+template <int N, int TPF, int R, bool INV>
+__device__ __forceinline__ void fft_stage(double2* buf, int lt, int Ns, const double2* __restrict__ tw) {
+  constexpr int NBF = N / R;                   // butterflies
+  constexpr int NB = (NBF + TPF - 1) / TPF;    // per thread
+  double2 v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lt + b * TPF;
+    if (NBF % TPF == 0 || j < NBF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NBF];
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
+        const int step = N / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[r * k * step];
+          if (INV) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      if (R == 2) {
+        const double2 a = v[b][0], c = v[b][1];
+        v[b][0] = cadd(a, c);
+        v[b][1] = csub(a, c);
+      } else {
+        const double2 a0 = cadd(v[b][0], v[b][2]);
+        const double2 a1 = csub(v[b][0], v[b][2]);
+        const double2 a2 = cadd(v[b][1], v[b][3]);
+        const double2 d = csub(v[b][1], v[b][3]);
+        // forward: -i * d ; inverse: +i * d
+        const double2 a3 = INV ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+        v[b][0] = cadd(a0, a2);
+        v[b][2] = csub(a0, a2);
+        v[b][1] = cadd(a1, a3);
+        v[b][3] = csub(a1, a3);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lt + b * TPF;
+    if (NBF % TPF == 0 || j < NBF) {
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place FFT of N complex points in LDS; tw[k] = exp(-2 pi i k / N).
+// Forward: X_k = sum x_n e^{-2 pi i k n / N}; inverse: unnormalised, +i.
+template <int N, int TPF, bool INV>
+__device__ __forceinline__ void fft_lds(double2* buf, int lt, const double2* __restrict__ tw) {
+  int Ns = 1;
+  if (Log2<N>::v % 2 == 1) {
+    fft_stage<N, TPF, 2, INV>(buf, lt, Ns, tw);
+    Ns = 2;
+  }
+#pragma unroll 1
+  for (; Ns < N; Ns *= 4) fft_stage<N, TPF, 4, INV>(buf, lt, Ns, tw);
+}
+
+template <int N>
+struct FftCfg {
+  static constexpr int TPF = (N / 4 >= 64) ? 64 : (N / 4 >= 1 ? N / 4 : 1);
+  // FFTs per block: keep LDS <= 64 KB and the block <= 256 threads
+  static constexpr int PER_LDS = (65536 / (N * 16)) > 0 ? (65536 / (N * 16)) : 1;
+  static constexpr int PER_THR = 256 / TPF;
+  static constexpr int PER = PER_LDS < PER_THR ? (PER_LDS < 4 ? PER_LDS : 4) : (PER_THR < 4 ? PER_THR : 4);
+  static constexpr int THREADS = PER * TPF;
+};
+
+// ------------------------------------------------------------------ row pass
+// Forward real FFT of length mx = 2*HX of the source rows j in [j0, j0 + count).
+template <int HX>
+__global__ void __launch_bounds__(FftCfg<HX>::THREADS)
+k_rows_fwd(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
+           int j0, int count, const double* __restrict__ done) {
+  using C = FftCfg<HX>;
+  if (done && done[KS_DONE] != 0.0) return;
+  __shared__ double2 lds[C::PER][HX];
+  const int tid = threadIdx.x;
+  const int r = tid / C::TPF, lt = tid % C::TPF;
+  const int jrow = j0 + blockIdx.x * C::PER + r;
+  const bool valid = (jrow < j0 + count) && jrow >= 0 && jrow < g.ny;
+  double2* z = lds[r];
+  // load z_n = (x_{2n}, x_{2n+1})
+  for (int n = lt; n < HX; n += C::TPF) {
+    double2 v = make_double2(0.0, 0.0);
+    if (valid && omega) {
+      const int i0 = 2 * n, i1 = 2 * n + 1;
+      if (!f.outflow) {
+        if (i0 < g.nx && g.cls[jrow * g.nx + i0] < 2) v.x = omega[jrow * g.nx + i0];
+        if (i1 < g.nx && g.cls[jrow * g.nx + i1] < 2) v.y = omega[jrow * g.nx + i1];
+      } else {
+        const int m0 = i0 < g.nx ? i0 : 2 * g.nx - 1 - i0;
+        const int m1 = i1 < g.nx ? i1 : 2 * g.nx - 1 - i1;
+        if (m0 >= 0 && m0 < g.nx && g.cls[jrow * g.nx + m0] < 2) v.x = omega[jrow * g.nx + m0];
+        if (m1 >= 0 && m1 < g.nx && g.cls[jrow * g.nx + m1] < 2) v.y = omega[jrow * g.nx + m1];
+      }
+    }
+    z[n] = v;
+  }
+  __syncthreads();
+  if (valid && gam) {
+    for (int e = g.row_ptr[jrow] + lt; e < g.row_ptr[jrow + 1]; e += C::TPF) {
+      const int i = g.row_i[e];
+      const double val = sgn * gam[g.row_a[e]];
+      double* zz = reinterpret_cast<double*>(z);
+      zz[i] += val;
+      if (f.outflow) zz[2 * g.nx - 1 - i] += val;
+    }
+  }
+  __syncthreads();
+  fft_lds<HX, C::TPF, false>(z, lt, f.tw_x);
+  // split: X_k = E_k + W^k O_k, k in [0, HX]; write spec[k][jrow + 1]
+  const int nth = C::THREADS;
+  for (int t = tid; t < (HX + 1) * C::PER; t += nth) {
+    const int rr = t % C::PER, k = t / C::PER;
+    const int jj = j0 + blockIdx.x * C::PER + rr;
+    if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
+    const double2 zk = lds[rr][k & (HX - 1)];
+    const double2 zc = conj2(lds[rr][(HX - k) & (HX - 1)]);
+    const double2 E = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+    const double2 Od = csub(zk, zc);   // 2 i O
+    const double2 O = make_double2(0.5 * Od.y, -0.5 * Od.x);
+    const double2 X = cadd(E, cmul(f.tw_xr[k], O));
+    f.spec[(size_t)k * f.ld + jj + 1] = X;
+  }
+}
+
+// ---------------------------------------------------------------- column pass
+template <int MY>
+__global__ void __launch_bounds__(FftCfg<MY>::THREADS)
+k_cols(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
+  using C = FftCfg<MY>;
+  if (done && done[KS_DONE] != 0.0) return;
+  __shared__ double2 lds[C::PER][MY];
+  const int tid = threadIdx.x;
+  const int r = tid / C::TPF, lt = tid % C::TPF;
+  const int kx = blockIdx.x * C::PER + r;
+  const bool valid = kx <= f.hx;
+  double2* z = lds[r];
+  double2* col = f.spec + (size_t)(valid ? kx : 0) * f.ld;
+  for (int n = lt; n < MY; n += C::TPF) z[n] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (valid)
+    for (int j = rj0 + lt; j <= rj1; j += C::TPF) z[j & (MY - 1)] = col[j + 1];
+  __syncthreads();
+  fft_lds<MY, C::TPF, false>(z, lt, f.tw_y);
+  if (valid) {
+    const double* gh = f.ghat + (size_t)kx * (MY / 2 + 1);
+    for (int n = lt; n < MY; n += C::TPF) {
+      const double s = gh[n <= MY / 2 ? n : MY - n];
+      z[n].x *= s;
+      z[n].y *= s;
+    }
+  }
+  __syncthreads();
+  fft_lds<MY, C::TPF, true>(z, lt, f.tw_y);
+  if (valid)
+    for (int j = oj0 + lt; j <= oj1; j += C::TPF) col[j + 1] = z[j & (MY - 1)];
+}
+
+// ------------------------------------------------------------ inverse rows
+// Output rows jo in [j0, j0 + count) (jo may be -1 .. ny), written to the ring array.
+template <int HX>
+__global__ void __launch_bounds__(FftCfg<HX>::THREADS)
+k_rows_inv(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
+  using C = FftCfg<HX>;
+  if (done && done[KS_DONE] != 0.0) return;
+  __shared__ double2 lds[C::PER][HX + 1];
+  const int tid = threadIdx.x;
+  const int nth = C::THREADS;
+  // gather X_k, k in [0, HX]
+  for (int t = tid; t < (HX + 1) * C::PER; t += nth) {
+    const int rr = t % C::PER, k = t / C::PER;
+    const int jo = j0 + blockIdx.x * C::PER + rr;
+    double2 v = make_double2(0.0, 0.0);
+    if (jo < j0 + count) v = f.spec[(size_t)k * f.ld + jo + 1];
+    lds[rr][k] = v;
+  }
+  __syncthreads();
+  // Z_k = (X_k + conj X_{HX-k}) + i (X_k - conj X_{HX-k}) / W^k, k < HX (in registers, then store)
+  const int r = tid / C::TPF, lt = tid % C::TPF;
+  double2* z = lds[r];
+  constexpr int NPT = (HX + C::TPF - 1) / C::TPF;
+  double2 tmp[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int k = lt + q * C::TPF;
+    if (k < HX) {
+      const double2 xk = z[k];
+      const double2 xc = conj2(z[HX - k]);
+      const double2 E = cadd(xk, xc);
+      const double2 D = csub(xk, xc);
+      const double2 O = cmul(D, conj2(f.tw_xr[k]));   // divide by W^k = multiply by conj
+      tmp[q] = make_double2(E.x - O.y, E.y + O.x);      // E + i O
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int k = lt + q * C::TPF;
+    if (k < HX) z[k] = tmp[q];
+  }
+  __syncthreads();
+  fft_lds<HX, C::TPF, true>(z, lt, f.tw_x);
+  const int nxr = g.nx + 2;
+  for (int t = tid; t < (g.nx + 2) * C::PER; t += nth) {
+    const int rr = t / (g.nx + 2), ii = t % (g.nx + 2) - 1;   // ii in [-1, nx]
+    const int jo = j0 + blockIdx.x * C::PER + rr;
+    if (jo >= j0 + count) continue;
+    const int i = ii < 0 ? 2 * HX - 1 : ii;
+    const double2 zz = lds[rr][i >> 1];
+    psi[(size_t)(jo + 1) * nxr + (ii + 1)] = (i & 1) ? zz.y : zz.x;
+  }
+}
+
+template <int HX>
+static void rows_fwd_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
+                            int j0, int count, const double* done, hipStream_t s) {
+  using C = FftCfg<HX>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0) k_rows_fwd<HX><<<blocks, C::THREADS, 0, s>>>(g, f, omega, gam, sgn, j0, count, done);
+}
+template <int MY>
+static void cols_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
+                        hipStream_t s) {
+  using C = FftCfg<MY>;
+  const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
+  k_cols<MY><<<blocks, C::THREADS, 0, s>>>(g, f, rj0, rj1, oj0, oj1, done);
+}
+template <int HX>
+static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
+                            hipStream_t s) {
+  using C = FftCfg<HX>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0) k_rows_inv<HX><<<blocks, C::THREADS, 0, s>>>(g, f, j0, count, psi, done);
+}
+
+#define IIM_POW2_SWITCH(VAL, FN, ...)                     \
+  switch (VAL) {                                          \
+    case 16: FN<16>(__VA_ARGS__); break;                  \
+    case 32: FN<32>(__VA_ARGS__); break;                  \
+    case 64: FN<64>(__VA_ARGS__); break;                  \
+    case 128: FN<128>(__VA_ARGS__); break;                \
+    case 256: FN<256>(__VA_ARGS__); break;                \
+    case 512: FN<512>(__VA_ARGS__); break;                \
+    case 1024: FN<1024>(__VA_ARGS__); break;              \
+    case 2048: FN<2048>(__VA_ARGS__); break;              \
+    case 4096: FN<4096>(__VA_ARGS__); break;              \
+    default: break;                                       \
+  }
+
+void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
+                 int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s) {
+  IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, rj0, rj1 - rj0 + 1, done, s);
+  IIM_POW2_SWITCH(f.my, cols_launch, g, f, rj0, rj1, oj0, oj1, done, s);
+  IIM_POW2_SWITCH(f.hx, rows_inv_launch, g, f, oj0, oj1 - oj0 + 1, psi_ring, done, s);
+}
+
+// ------------------------------------------------------------------ box DST
+// C[M][N] (ldc, possibly scaled elementwise by S[M][N]) = A[M][K] * B[K][N]
+template <int TS>
+__global__ void __launch_bounds__(TS * TS / 4)
+k_gemm(int M, int N, int K, const double* __restrict__ A, int lda, bool transA, const double* __restrict__ B,
+       int ldb, double* __restrict__ Cm, int ldc, const double* __restrict__ S, const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  __shared__ double As[TS][TS + 1];
+  __shared__ double Bs[TS][TS + 1];
+  const int tx = threadIdx.x % TS, ty4 = threadIdx.x / TS;   // each thread: 4 rows
+  const int row0 = blockIdx.y * TS, col0 = blockIdx.x * TS;
+  double acc[4] = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += TS) {
+    for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+      const int rr = q / TS, cc = q % TS;
+      const int ar = row0 + rr, ak = k0 + cc;
+      double av = 0.0;
+      if (ar < M && ak < K) av = transA ? A[(size_t)ak * lda + ar] : A[(size_t)ar * lda + ak];
+      As[rr][cc] = av;
+      const int bk = k0 + rr, bc = col0 + cc;
+      Bs[rr][cc] = (bk < K && bc < N) ? B[(size_t)bk * ldb + bc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < TS; ++kk) {
+      const double b = Bs[kk][tx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += As[ty4 * 4 + q][kk] * b;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = row0 + ty4 * 4 + q, cc = col0 + tx;
+    if (rr < M && cc < N) Cm[(size_t)rr * ldc + cc] = S ? acc[q] * S[(size_t)rr * N + cc] : acc[q];
+  }
+}
+
+__global__ void k_build_source(DGeom g, const double* __restrict__ omega, const double* __restrict__ gam,
+                               double sgn, const int* __restrict__ a_id, double* __restrict__ src,
+                               const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.nx * g.ny) return;
+  double v = (omega && g.cls[q] < 2) ? omega[q] : 0.0;
+  if (gam) {
+    const int a = a_id[q];
+    if (a >= 0) v += sgn * gam[a];
+  }
+  src[q] = v;
+}
+
+__global__ void k_ring_reflect(DGeom g, double* __restrict__ psi, const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nxr = g.nx + 2;
+  if (t < g.nx) {
+    psi[t + 1] = -psi[nxr + t + 1];
+    psi[(size_t)(g.ny + 1) * nxr + t + 1] = -psi[(size_t)g.ny * nxr + t + 1];
+  }
+  if (t < g.ny) {
+    psi[(size_t)(t + 1) * nxr] = -psi[(size_t)(t + 1) * nxr + 1];
+    psi[(size_t)(t + 1) * nxr + g.nx + 1] = -psi[(size_t)(t + 1) * nxr + g.nx];
+  }
+  if (t == 0) {
+    psi[0] = psi[nxr + 1];
+    psi[g.nx + 1] = psi[nxr + g.nx];
+    psi[(size_t)(g.ny + 1) * nxr] = psi[(size_t)g.ny * nxr + 1];
+    psi[(size_t)(g.ny + 1) * nxr + g.nx + 1] = psi[(size_t)g.ny * nxr + g.nx];
+  }
+}
+
+static void gemm(int M, int N, int K, const double* A, int lda, bool tA, const double* B, int ldb, double* Cm,
+                 int ldc, const double* S, const double* done, hipStream_t s) {
+  constexpr int TS = 32;
+  dim3 grid((N + TS - 1) / TS, (M + TS - 1) / TS);
+  k_gemm<TS><<<grid, TS * TS / 4, 0, s>>>(M, N, K, A, lda, tA, B, ldb, Cm, ldc, S, done);
+}
+
+// psi_ring = G src (box): src assembled from omega / gamma, then
+// T1 = src phx^T, T2 = (phy T1) .* lam^-1, T1 = T2 phx, psi = phy^T T1.
+void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
+                double* psi_ring, const double* done, hipStream_t s) {
+  const int nx = g.nx, ny = g.ny, nxr = nx + 2;
+  const int n = nx * ny;
+  k_build_source<<<(n + 255) / 256, 256, 0, s>>>(g, omega, gam, sgn, g.a_id, d.src, done);
+  gemm(ny, nx, nx, d.src, nx, false, d.phxT, nx, d.t1, nx, nullptr, done, s);
+  gemm(ny, nx, ny, d.phy, ny, false, d.t1, nx, d.t2, nx, d.lam_inv, done, s);
+  gemm(ny, nx, nx, d.t2, nx, false, d.phx, nx, d.t1, nx, nullptr, done, s);
+  gemm(ny, nx, ny, d.phyT, ny, false, d.t1, nx, psi_ring + nxr + 1, nxr, nullptr, done, s);
+  const int m = nx > ny ? nx : ny;
+  k_ring_reflect<<<(m + 255) / 256, 256, 0, s>>>(g, psi_ring, done);
+}
+
+}  // namespace iim
+
+namespace iim {
+
+// ============================================================ small helpers
+__global__ void k_fill(double* p, double v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+void launch_fill(double* p, double v, size_t n, hipStream_t s) {
+  if (n) k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+}
+
+// Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in all threads.
+__device__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  double t = 0.0;
+  for (int q = 0; q < nw; ++q) t += red[q];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ============================================================ Schur system
+// y_gamma = v_gamma + A psi - sum_k psibar_k B 1_k ;  y_k = sum_{B_k} v_gamma
+// (computed by one workgroup so the circulation rows need no atomics)
+__device__ void matvec_finish_block(const DGeom& g, const double* __restrict__ psi, const double* __restrict__ v,
+                                    double* __restrict__ out, double* red) {
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
+    double acc = 0.0;
+    for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
+    double y = v[a] + acc;
+    for (int k = 0; k < g.nbc; ++k) y -= g.b1[(size_t)k * g.na + a] * v[g.na + k];
+    out[a] = y;
+    const int c = g.a_col[a];
+    if (c >= 0 && c < 8) part[c] += v[a];
+  }
+  for (int k = 0; k < g.nbc && k < 8; ++k) {
+    const double s = block_sum(part[k], red);
+    if (threadIdx.x == 0) out[g.na + k] = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_matvec_finish(DGeom g, const double* psi, const double* v, double* out) {
+  __shared__ double red[16];
+  matvec_finish_block(g, psi, v, out, red);
+}
+void launch_matvec_finish(const DGeom& g, const DKrylov&, const double* psi_ring, const double* v, double* out,
+                          hipStream_t s) {
+  k_matvec_finish<<<1, 1024, 0, s>>>(g, psi_ring, v, out);
+}
+
+// b_gamma = A (G omega) + B psi_b_tilde ; b_k = sum_{R_k} omega - Gamma_k / h^2
+__global__ void __launch_bounds__(256) k_rhs_vector(DGeom g, const double* __restrict__ psi,
+                                                    const double* __restrict__ omega,
+                                                    const double* __restrict__ Gamma, double* __restrict__ b) {
+  __shared__ double red[16];
+  if ((int)blockIdx.x < g.nbc) {
+    const int k = blockIdx.x;
+    const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
+    const int w = i1 - i0 + 1, cnt = w * (j1 - j0 + 1);
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+      const int i = i0 + q % w, j = j0 + q / w;
+      const int idx = j * g.nx + i;
+      if (g.cls[idx] < 2) acc += omega[idx];
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) b[g.na + k] = s - Gamma[k] * g.inv_h * g.inv_h;
+    return;
+  }
+  const int a = (blockIdx.x - g.nbc) * blockDim.x + threadIdx.x;
+  if (a >= g.na) return;
+  double acc = 0.0;
+  for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
+  b[a] = acc + g.bpsi[a];
+}
+void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma, double* b,
+                       hipStream_t s) {
+  const int blocks = g.nbc + (g.na + 255) / 256;
+  k_rhs_vector<<<blocks, 256, 0, s>>>(g, psi_ring, omega, Gamma, b);
+}
+
+// ============================================================ GMRES (device)
+// start: r = b - w (or b when x = 0), V0 = r / |r|, g = (|r|, 0, ...)
+__global__ void __launch_bounds__(1024) k_krylov_start(DKrylov k, int x_is_zero) {
+  __shared__ double red[16];
+  const int n = k.n;
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double bi = k.b[i];
+    const double ri = x_is_zero ? bi : bi - k.w[i];
+    if (x_is_zero) k.x[i] = 0.0;
+    k.V[i] = ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  const double beta = sqrt(block_sum(rr, red));
+  const double bnorm = sqrt(block_sum(bb, red));
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) k.V[i] *= inv;
+  if (threadIdx.x == 0) {
+    k.g[0] = beta;
+    k.st[KS_BETA] = beta;
+    k.st[KS_BNORM] = bnorm;
+    const double rel = bnorm > 0.0 ? beta / bnorm : 0.0;
+    k.st[KS_RES] = rel;
+    if (k.st[KS_RES0] < 0.0) k.st[KS_RES0] = rel;
+    k.st[KS_K] = 0.0;
+    if (!(beta == beta) || !(bnorm == bnorm)) k.st[KS_NFAIL] = 1.0;
+    k.st[KS_DONE] = (beta <= k.st[KS_TOL] * bnorm || !(beta == beta)) ? 1.0 : 0.0;
+  }
+}
+void launch_krylov_start(const DGeom&, const DKrylov& k, bool x_is_zero, hipStream_t s) {
+  k_krylov_start<<<1, 1024, 0, s>>>(k, x_is_zero ? 1 : 0);
+}
+
+// One Arnoldi step: w = S V_j (psi = G E_a V_j,gamma already in the ring buffer),
+// CGS2 against V_0..V_j, new Givens rotation, residual estimate.
+__global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const double* __restrict__ psi, int j) {
+  __shared__ double red[16];
+  __shared__ double hcol[72];
+  __shared__ double hacc[72];
+  if (k.st[KS_DONE] != 0.0) return;
+  const int n = k.n, m = k.m;
+  const double* vj = k.V + (size_t)j * n;
+  double* w = k.V + (size_t)(j + 1) * n;
+  matvec_finish_block(g, psi, vj, w, red);   // ends with a barrier; w visible block-wide
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) hacc[i] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int pass = 0; pass < 2; ++pass) {
+    // dots: wave wid handles basis vectors i = wid, wid + nw, ...
+    for (int i = wid; i <= j; i += nw) {
+      const double* vi = k.V + (size_t)i * n;
+      double acc = 0.0;
+      for (int e = lane; e < n; e += 64) acc += vi[e] * w[e];
+      acc = wave_sum(acc);
+      if (lane == 0) hcol[i] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      double we = w[e];
+      for (int i = 0; i <= j; ++i) we -= hcol[i] * k.V[(size_t)i * n + e];
+      w[e] = we;
+    }
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) hacc[i] += hcol[i];
+    __syncthreads();
+  }
+  double nn = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) nn += w[e] * w[e];
+  const double hn = sqrt(block_sum(nn, red));
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) w[e] *= inv;
+  if (threadIdx.x == 0) {
+    double* H = k.H + (size_t)j * (m + 1);
+    for (int i = 0; i <= j; ++i) H[i] = hacc[i];
+    H[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = k.cs[i] * H[i] + k.sn[i] * H[i + 1];
+      H[i + 1] = -k.sn[i] * H[i] + k.cs[i] * H[i + 1];
+      H[i] = t;
+    }
+    const double den = hypot(H[j], H[j + 1]);
+    const double c = den > 0.0 ? H[j] / den : 1.0, s = den > 0.0 ? H[j + 1] / den : 0.0;
+    k.cs[j] = c;
+    k.sn[j] = s;
+    H[j] = den;
+    H[j + 1] = 0.0;
+    k.g[j + 1] = -s * k.g[j];
+    k.g[j] = c * k.g[j];
+    k.st[KS_K] = (double)(j + 1);
+    k.st[KS_ITERS] += 1.0;
+    const double bnorm = k.st[KS_BNORM];
+    const double rel = bnorm > 0.0 ? fabs(k.g[j + 1]) / bnorm : 0.0;
+    k.st[KS_RES] = rel;
+    if (!(rel == rel)) k.st[KS_NFAIL] = 1.0;
+    if (rel <= k.st[KS_TOL] || !(rel == rel) || hn == 0.0) k.st[KS_DONE] = 1.0;
+  }
+}
+void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s) {
+  k_arnoldi<<<1, 1024, 0, s>>>(g, k, psi_ring, j);
+}
+
+// x += V y with H(0:kk, 0:kk) y = g(0:kk)
+__global__ void __launch_bounds__(1024) k_gmres_update(DKrylov k) {
+  __shared__ double y[72];
+  const int kk = (int)k.st[KS_K];
+  const int n = k.n, m = k.m;
+  if (kk <= 0) return;
+  if (threadIdx.x == 0) {
+    for (int i = kk - 1; i >= 0; --i) {
+      double s = k.g[i];
+      for (int q = i + 1; q < kk; ++q) s -= k.H[(size_t)q * (m + 1) + i] * y[q];
+      y[i] = s / k.H[(size_t)i * (m + 1) + i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double xe = k.x[e];
+    for (int i = 0; i < kk; ++i) xe += y[i] * k.V[(size_t)i * n + e];
+    k.x[e] = xe;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) k.st[KS_K] = 0.0;
+}
+void launch_gmres_update(const DKrylov& k, hipStream_t s) { k_gmres_update<<<1, 1024, 0, s>>>(k); }
+
+// ============================================================ recovery
+// psi ghosts (fourth order with psi_b_tilde + psibar_k)
+__global__ void k_ghost_psi(DGeom g, const double* __restrict__ x, double* __restrict__ psi) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.ng) return;
+  double acc = 0.0;
+  for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) acc += g.ext4b.w[e] * psi[g.ext4b.ridx[e]];
+  for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) {
+    const int c = g.ext4b.bc[e];
+    const int col = g.c_col[c];
+    const double bcv = g.c_psibt[c] + (col >= 0 ? x[g.na + col] : 0.0);
+    acc += g.ext4b.bw[e] * bcv;
+  }
+  psi[g.g_ridx[q]] = acc;
+}
+
+// velocity at fluid nodes and the normal components on the ring
+__global__ void k_velocity(DGeom g, const double* __restrict__ psi, double* __restrict__ U, double* __restrict__ V) {
+  const int nxr = g.nx + 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxr * (g.ny + 2)) return;
+  const int ir = t % nxr, jr = t / nxr;   // ring coordinates
+  const int i = ir - 1, j = jr - 1;
+  const double c = 0.5 * g.inv_h;
+  double u = 0.0, v = 0.0;
+  if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+    if (g.cls[j * g.nx + i] < 2) {
+      u = g.uinf_x + c * (psi[t + nxr] - psi[t - nxr]);
+      v = g.uinf_y - c * (psi[t + 1] - psi[t - 1]);
+    }
+  } else {
+    const bool side = (i == -1 || i == g.nx) && j >= 0 && j < g.ny;
+    const bool topbot = (j == -1 || j == g.ny) && i >= 0 && i < g.nx;
+    if (side) u = g.uinf_x + c * (psi[t + nxr] - psi[t - nxr]);
+    if (topbot) v = g.uinf_y - c * (psi[t + 1] - psi[t - 1]);
+  }
+  U[t] = u;
+  V[t] = v;
+}
+
+// velocity extension to A- (third order with u_b)
+__global__ void k_vel_ext(DGeom g, double* __restrict__ U, double* __restrict__ V) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.ng) return;
+  double au = 0.0, av = 0.0;
+  for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) {
+    const int r = g.ext3b.ridx[e];
+    au += g.ext3b.w[e] * U[r];
+    av += g.ext3b.w[e] * V[r];
+  }
+  for (int e = g.ext3b.bptr[q]; e < g.ext3b.bptr[q + 1]; ++e) {
+    const int c = g.ext3b.bc[e];
+    au += g.ext3b.bw[e] * g.c_ub[2 * c];
+    av += g.ext3b.bw[e] * g.c_ub[2 * c + 1];
+  }
+  U[g.g_ridx[q]] = au;
+  V[g.g_ridx[q]] = av;
+}
+
+void launch_recover_fields(const DGeom& g, const double* x, double* psi, double* U, double* V, hipStream_t s) {
+  if (g.ng) k_ghost_psi<<<(g.ng + 127) / 128, 128, 0, s>>>(g, x, psi);
+  const int nr = (g.nx + 2) * (g.ny + 2);
+  k_velocity<<<(nr + 255) / 256, 256, 0, s>>>(g, psi, U, V);
+  if (g.ng) k_vel_ext<<<(g.ng + 127) / 128, 128, 0, s>>>(g, U, V);
+}
+
+// ============================================================ boundary vorticity
+__global__ void k_omega_b(DGeom g, const double* __restrict__ U, const double* __restrict__ V, double* __restrict__ wb) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.nc) return;
+  double acc = g.wb_const[c];
+  for (int e = g.wbc.ptr[c]; e < g.wbc.ptr[c + 1]; ++e) {
+    const int r = g.wbc.ridx[e];
+    const double val = (r & (1 << 30)) ? V[r & ((1 << 30) - 1)] : U[r];
+    acc += g.wbc.w[e] * val;
+  }
+  wb[c] = acc;
+}
+
+__global__ void k_omega_ext(DGeom g, const double* __restrict__ omega, const double* __restrict__ wb,
+                            double* __restrict__ w4, double* __restrict__ w3b, double* __restrict__ w3n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.ng) return;
+  double a4 = 0.0, a3 = 0.0, an = 0.0;
+  for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) a4 += g.ext4b.w[e] * omega[g.ext4b.gidx[e]];
+  for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) a4 += g.ext4b.bw[e] * wb[g.ext4b.bc[e]];
+  for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) a3 += g.ext3b.w[e] * omega[g.ext3b.gidx[e]];
+  for (int e = g.ext3b.bptr[q]; e < g.ext3b.bptr[q + 1]; ++e) a3 += g.ext3b.bw[e] * wb[g.ext3b.bc[e]];
+  for (int e = g.ext3n.ptr[q]; e < g.ext3n.ptr[q + 1]; ++e) an += g.ext3n.w[e] * omega[g.ext3n.gidx[e]];
+  const int gi = g.g_gidx[q];
+  w4[gi] = a4;
+  w3b[gi] = a3;
+  w3n[gi] = an;
+}
+
+void launch_omega_bc(const DGeom& g, const double* omega, const double* U, const double* V, double* wb, double* w4,
+                     double* w3b, double* w3n, hipStream_t s) {
+  if (g.nc) k_omega_b<<<(g.nc + 127) / 128, 128, 0, s>>>(g, U, V, wb);
+  if (g.ng) k_omega_ext<<<(g.ng + 127) / 128, 128, 0, s>>>(g, omega, wb, w4, w3b, w3n);
+}
+
+// ============================================================ transport
+// Face flux core: advective bracket of f values on the chosen stencil plus the
+// diffusive flux.  use_left: stencil (-1, 0, 1) with (-1/6, 5/6, 1/3); else
+// (0, 1, 2) with (1/3, 5/6, -1/6).
+__device__ __forceinline__ double flux_core(bool use_left, double fm1, double f0, double f1, double f2,
+                                            double wl, double wr, double nu_inv_h) {
+  const double c6 = 1.0 / 6.0, c56 = 5.0 / 6.0, c3 = 1.0 / 3.0;
+  const double F = use_left ? (-c6 * fm1 + c56 * f0 + c3 * f1) : (c3 * f0 + c56 * f1 - c6 * f2);
+  return F - nu_inv_h * (wr - wl);
+}
+
+// Standard face (all four nodes fluid): upwind side by the face velocity sign.
+__device__ __forceinline__ double flux_std(double um1, double u0, double u1, double u2, double wm1, double w0,
+                                           double w1, double w2, double nu_inv_h) {
+  const double uf = 0.5 * (u0 + u1);
+  return flux_core(uf >= 0.0, um1 * wm1, u0 * w0, u1 * w1, u2 * w2, w0, w1, nu_inv_h);
+}
+
+enum { NK_FLUID = 0, NK_GHOST = 1, NK_SOLID = 2, NK_OUT = 3 };
+
+// General face between node (i, j) and (i, j) + e_axis (axis 0: x, 1: y).
+__device__ double flux_general(const DGeom& g, const double* __restrict__ omega, const double* __restrict__ U,
+                               const double* __restrict__ V, const double* __restrict__ w4,
+                               const double* __restrict__ w3b, const double* __restrict__ w3n, int i, int j,
+                               int axis) {
+  const int di = axis == 0 ? 1 : 0, dj = axis == 0 ? 0 : 1;
+  const double* vel = axis == 0 ? U : V;
+  int kind[4];
+  double u[4], w[4], w4v[4], wb[4], wn[4];
+  const int nxr = g.nx + 2;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int ii = i + (t - 1) * di, jj = j + (t - 1) * dj;
+    const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
+    const bool ring = ii >= -1 && jj >= -1 && ii <= g.nx && jj <= g.ny;
+    u[t] = ring ? vel[(jj + 1) * nxr + ii + 1] : 0.0;
+    if (!in) {
+      kind[t] = NK_OUT;
+      w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
+    } else {
+      const int q = jj * g.nx + ii;
+      const int c = g.cls[q];
+      kind[t] = c < 2 ? NK_FLUID : (c == 2 ? NK_GHOST : NK_SOLID);
+      if (kind[t] == NK_FLUID) {
+        w[t] = w4v[t] = wb[t] = wn[t] = omega[q];
+      } else if (kind[t] == NK_GHOST) {
+        w[t] = 0.0;
+        w4v[t] = w4[q];
+        wb[t] = w3b[q];
+        wn[t] = w3n[q];
+      } else {
+        w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
+      }
+    }
+  }
+  const bool fl0 = kind[1] == NK_FLUID || kind[1] == NK_OUT;
+  const bool fl1 = kind[2] == NK_FLUID || kind[2] == NK_OUT;
+  const double uf = 0.5 * (u[1] + u[2]);
+  const bool up_left = uf >= 0.0;
+  const bool use_left = (fl0 && fl1) ? up_left : fl0;
+  double f[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    double om;
+    if (kind[t] == NK_GHOST) {
+      const bool on_left = t <= 1;
+      om = (on_left == up_left) ? wb[t] : wn[t];
+    } else {
+      om = w[t];
+    }
+    f[t] = u[t] * om;
+  }
+  return flux_core(use_left, f[0], f[1], f[2], f[3], w4v[1], w4v[2], g.nu * g.inv_h);
+}
+
+// Bulk nodes (cls 0): all stencil nodes are fluid and inside the grid.
+__global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* __restrict__ omega,
+                                                        const double* __restrict__ U, const double* __restrict__ V,
+                                                        double* __restrict__ out, double* __restrict__ Q, double a,
+                                                        double b, double dt, int mode) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= g.nx) return;
+  const int q = j * g.nx + i;
+  const int8_t c = g.cls[q];
+  if (c == 1) return;   // boundary kernel
+  if (c >= 2) {         // solid: vorticity stays zero
+    out[q] = 0.0;
+    if (mode == 1) Q[q] = 0.0;
+    return;
+  }
+  const int nx = g.nx, nxr = nx + 2;
+  const int r = (j + 1) * nxr + i + 1;
+  const double nih = g.nu * g.inv_h;
+  const double wc = omega[q];
+  // x faces
+  const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
+  const double uxm2 = U[r - 2], uxm1 = U[r - 1], uc = U[r], uxp1 = U[r + 1], uxp2 = U[r + 2];
+  const double fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
+  const double fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
+  // y faces
+  const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
+  const double vym2 = V[r - 2 * nxr], vym1 = V[r - nxr], vc = V[r], vyp1 = V[r + nxr], vyp2 = V[r + 2 * nxr];
+  const double fyt = flux_std(vym1, vc, vyp1, vyp2, wym1, wc, wyp1, wyp2, nih);
+  const double fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
+  const double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
+  if (mode == 0) {
+    out[q] = rhs;
+  } else {
+    const double qn = a * Q[q] + dt * rhs;
+    Q[q] = qn;
+    out[q] = wc + b * qn;
+  }
+}
+
+__global__ void __launch_bounds__(128) k_transport_special(DGeom g, const double* __restrict__ omega,
+                                                           const double* __restrict__ U, const double* __restrict__ V,
+                                                           const double* __restrict__ w4, const double* __restrict__ w3b,
+                                                           const double* __restrict__ w3n, double* __restrict__ out,
+                                                           double* __restrict__ Q, double a, double b, double dt,
+                                                           int mode) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.nsp) return;
+  const int q = g.special[s];
+  const int i = q % g.nx, j = q / g.nx;
+  const double fxr = flux_general(g, omega, U, V, w4, w3b, w3n, i, j, 0);
+  const double fxl = flux_general(g, omega, U, V, w4, w3b, w3n, i - 1, j, 0);
+  const double fyt = flux_general(g, omega, U, V, w4, w3b, w3n, i, j, 1);
+  const double fyb = flux_general(g, omega, U, V, w4, w3b, w3n, i, j - 1, 1);
+  const double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
+  if (mode == 0) {
+    out[q] = rhs;
+  } else {
+    const double qn = a * Q[q] + dt * rhs;
+    Q[q] = qn;
+    out[q] = omega[q] + b * qn;
+  }
+}
+
+void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
+                      const double* w3b, const double* w3n, double* out, double* Q, double a, double b, double dt,
+                      int mode, hipStream_t s) {
+  dim3 grid((g.nx + 255) / 256, g.ny);
+  k_transport_bulk<<<grid, 256, 0, s>>>(g, omega, U, V, out, Q, a, b, dt, mode);
+  if (g.nsp) k_transport_special<<<(g.nsp + 127) / 128, 128, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
+}
+
+// Kelvin: one block per circulating body
+__global__ void __launch_bounds__(256) k_kelvin(DGeom g, const double* __restrict__ omega, const double* __restrict__ U,
+                                                const double* __restrict__ V, double* __restrict__ dG,
+                                                double* __restrict__ Gamma, double* __restrict__ QG, double a,
+                                                double b, double dt, int mode) {
+  __shared__ double red[16];
+  const int k = blockIdx.x;
+  const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
+  const int nv = j1 - j0 + 1, nh = i1 - i0 + 1;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < 2 * (nv + nh); t += blockDim.x) {
+    if (t < nv) {
+      acc += flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i1, j0 + t, 0);           // right (+)
+    } else if (t < 2 * nv) {
+      acc -= flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 - 1, j0 + t - nv, 0);  // left (-)
+    } else if (t < 2 * nv + nh) {
+      acc += flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 + t - 2 * nv, j1, 1);  // top (+)
+    } else {
+      acc -= flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 + t - 2 * nv - nh, j0 - 1, 1);  // bottom
+    }
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    const double rate = -g.h * tot;
+    dG[k] = rate;
+    if (mode == 1) {
+      const double qn = a * QG[k] + dt * rate;
+      QG[k] = qn;
+      Gamma[k] += b * qn;
+    }
+  }
+}
+
+void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG, double* Gamma,
+                   double* QG, double a, double b, double dt, int mode, hipStream_t s) {
+  if (g.nbc) k_kelvin<<<g.nbc, 256, 0, s>>>(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode);
+}
+
+}  // namespace iim

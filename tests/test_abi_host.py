@@ -1,0 +1,91 @@
+"""Host-side checks of the C-ABI library (no GPU needed): symbol exports,
+geometry and lattice Green's function against the oracle, error paths."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+import paper_2109_13628_amd as iim
+from oracle import geometry as OG, lgf as OL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "iim.h")).read()
+    return sorted(set(re.findall(r"\b(iim_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = iim.lib()
+    names = _declared()
+    assert set(names) == set(iim.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.iim_abi_version() == 1
+
+
+def test_lgf_matches_closed_forms_and_oracle():
+    g = iim.lgf_table(40, 24)
+    pi = np.pi
+    assert abs(-2 * g[0, 1] - 0.5) < 1e-15
+    assert abs(-2 * g[1, 1] - 2 / pi) < 1e-15
+    assert abs(-2 * g[2, 2] - 8 / (3 * pi)) < 1e-15
+    ref = OL.lgf_table(40, 24)
+    assert np.max(np.abs(g - ref)) < 2e-15
+    big = iim.lgf_table(300, 300)
+    f = np.concatenate([big[:, :0:-1], big], axis=1)
+    f = np.concatenate([f[:0:-1, :], f], axis=0)
+    lap = f[1:-1, 2:] + f[1:-1, :-2] + f[2:, 1:-1] + f[:-2, 1:-1] - 4 * f[1:-1, 1:-1]
+    c = 299
+    lap[c, c] += 1.0
+    assert np.max(np.abs(lap)) < 1e-14
+
+
+CASES = [lambda: wl.taylor_couette(128), wl.cylinder_small, lambda: wl.two_c_shapes_lamb_oseen(128)]
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_geometry_matches_oracle(make):
+    w = make()
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    geo = ctx.geometry()
+    ref = OG.Geometry(w.grid, w.bodies)
+    assert np.array_equal(geo["cls"], ref.cls)
+    ci = geo["c_int"]
+    assert ci.shape[0] == ref.nc
+    assert np.array_equal(ci[:, 0], ref.c_axis)
+    assert np.array_equal(ci[:, 1], ref.c_sigma)
+    assert np.array_equal(ci[:, 2], ref.c_if)
+    assert np.array_equal(ci[:, 3], ref.c_jf)
+    assert np.array_equal(ci[:, 4], ref.c_body)
+    assert np.max(np.abs(geo["c_xy"][:, 0] - ref.c_x)) < 1e-13
+    assert np.max(np.abs(geo["c_xy"][:, 1] - ref.c_y)) < 1e-13
+    assert np.max(np.abs(geo["c_theta"] - ref.c_theta)) < 1e-11
+    assert np.max(np.abs(geo["c_normal"][:, 0] - ref.c_nx)) < 1e-12
+    ai = geo["a_int"]
+    assert np.array_equal(ai[:, 0], ref.a_i) and np.array_equal(ai[:, 1], ref.a_j)
+    assert np.array_equal(ai[:, 2].astype(bool), ref.a_is_ghost)
+    assert np.array_equal(ai[:, 3], ref.a_body)
+    assert [tuple(r) for r in geo["rects"]] == ref.rects
+    ctx.close()
+
+
+def test_error_paths():
+    w = wl.taylor_couette(64)
+    bad = [wl.BodyDesc(points=w.bodies[0].points[::-1].copy())]
+    with pytest.raises(iim.IIMError) as e:
+        iim.Context(w.grid, bad, host_only=True)
+    assert e.value.code == iim.IIM_EGEOM and "counter-clockwise" in str(e.value)
+    g = wl.GridDesc(nx=8, ny=8, x0=0, y0=0, h=0.1)
+    with pytest.raises(iim.IIMError) as e:
+        iim.Context(g, [], host_only=True)
+    assert e.value.code == iim.IIM_EINVAL
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    rc = iim.lib().iim_poisson(ctx._h, C.c_void_p(1), C.c_void_p(1))
+    assert rc == iim.IIM_EUNSUPPORTED
+    assert abs(ctx.dt_max(np.sqrt(2) * 0.25) - w.dt / 0.5) < 1e-15
+    ctx.close()
