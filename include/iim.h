@@ -65,6 +65,10 @@ enum {
 
 enum { IIM_PREC_FP64 = 0, IIM_PREC_MIXED = 1 };
 enum { IIM_GUESS_ZERO = 0, IIM_GUESS_PREVIOUS = 1 };
+/* Schur-system solver: GMRES with the FFT matrix-vector product (the paper's
+ * iterative solve), or the dense inverse of the Schur matrix built once at
+ * create (bodies are fixed, so the matrix is too). */
+enum { IIM_SOLVER_KRYLOV = 0, IIM_SOLVER_DIRECT = 1 };
 
 typedef struct {
   int32_t nx, ny;         /* grid nodes per direction (>= 16) */
@@ -92,6 +96,7 @@ typedef struct {
   int32_t max_refine;     /* mixed precision: maximum refinement rounds */
   int32_t guess;          /* IIM_GUESS_* initial guess of each Schur solve */
   int32_t host_only;      /* 1: build geometry and tables only, allocate nothing on the device */
+  int32_t solver;         /* IIM_SOLVER_*; DIRECT stores (|A| + n_circ)^2 doubles on the device */
 } iim_solver_opts;
 
 typedef struct {
@@ -189,6 +194,18 @@ int iim_rk3_step(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt,
  * those of the last step. */
 int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt, int32_t n_steps,
                   iim_step_stats* stats);
+
+/* ---- instrumentation (measurement of the kernels above; not part of the method) ----
+ * iim_profile: drop collected timings and time every later launch of the
+ * kernels whose id bit is set in kernel_mask with a pair of HIP events on the
+ * context's stream (ids: 0 row FFT pass, 1 column FFT + kernel-multiply pass,
+ * 2 inverse row FFT pass, 3 bulk transport + RK update, 4 Arnoldi step).
+ * iim_profile_read: summed event time (ms), launch count and summed
+ * algorithmic bytes of one kernel id since the last iim_profile.
+ * iim_krylov_totals: Schur solves and Krylov matrix-vector products so far. */
+int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
+int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
+int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
 
 #ifdef __cplusplus
 }

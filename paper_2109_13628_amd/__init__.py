@@ -22,11 +22,13 @@ IIM_OK, IIM_EINVAL, IIM_ENOMEM, IIM_EGEOM, IIM_ENOCONV, IIM_ENONFINITE, IIM_EDEV
 EXT = {"box": 0, "free": 1, "outflow": 2}
 PREC_FP64, PREC_MIXED = 0, 1
 GUESS_ZERO, GUESS_PREVIOUS = 0, 1
+SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_reconstruct", "iim_rhs",
-           "iim_rk3_step", "iim_rk3_steps"]
+           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals"]
+KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport_bulk", "arnoldi"]
 
 
 class IIMError(RuntimeError):
@@ -54,7 +56,7 @@ class BodyDesc(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_max_iter", C.c_int32),
                 ("krylov_restart", C.c_int32), ("max_refine", C.c_int32), ("guess", C.c_int32),
-                ("host_only", C.c_int32)]
+                ("host_only", C.c_int32), ("solver", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -119,6 +121,12 @@ def lib():
     L.iim_rk3_step.argtypes = [vp, vp, dp, C.c_double, C.POINTER(StepStats)]
     L.iim_rk3_steps.restype = ip
     L.iim_rk3_steps.argtypes = [vp, vp, dp, C.c_double, C.c_int32, C.POINTER(StepStats)]
+    L.iim_profile.restype = ip
+    L.iim_profile.argtypes = [vp, C.c_int32]
+    L.iim_profile_read.restype = ip
+    L.iim_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
+    L.iim_krylov_totals.restype = ip
+    L.iim_krylov_totals.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -145,7 +153,7 @@ class Context:
     """One IIM problem (grid + bodies) on the current device."""
 
     def __init__(self, grid, bodies, precision=PREC_FP64, tol=1e-13, max_iter=400, restart=40,
-                 guess=GUESS_PREVIOUS, host_only=False, stream=None):
+                 guess=GUESS_PREVIOUS, host_only=False, stream=None, solver=SOLVER_KRYLOV):
         L = lib()
         g = GridDesc(nx=grid.nx, ny=grid.ny, x0=grid.x0, y0=grid.y0, h=grid.h, exterior=EXT[grid.exterior],
                      nu=grid.nu)
@@ -166,7 +174,7 @@ class Context:
             for q in range(4):
                 arr[k].rect[q] = r[q]
         o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
-                       max_refine=3, guess=guess, host_only=int(host_only))
+                       max_refine=3, guess=guess, host_only=int(host_only), solver=solver)
         if stream is None and not host_only:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -232,6 +240,27 @@ class Context:
         self._check(lib().iim_rhs(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(domega),
                                   dG.ctypes.data_as(C.POINTER(C.c_double)), _ptr(omega_b)), "iim_rhs")
         return dG[:self.n_circ]
+
+    def profile(self, mask):
+        self._check(lib().iim_profile(self._h, int(mask)), "iim_profile")
+
+    def profile_read(self):
+        out = {}
+        for kid, name in enumerate(KERNEL_NAMES):
+            ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+            self._check(lib().iim_profile_read(self._h, kid, C.byref(ms), C.byref(n), C.byref(b)),
+                        "iim_profile_read")
+            if n.value:
+                avg = ms.value / n.value
+                out[name] = {"launches": n.value, "total_ms": ms.value, "avg_us": 1e3 * avg,
+                             "bytes_per_launch": b.value / n.value,
+                             "GBps": (b.value / n.value) / (avg * 1e-3) / 1e9 if avg > 0 else None}
+        return out
+
+    def krylov_totals(self):
+        s, m = C.c_int64(), C.c_int64()
+        self._check(lib().iim_krylov_totals(self._h, C.byref(s), C.byref(m)), "iim_krylov_totals")
+        return s.value, m.value
 
     def rk3_steps(self, omega, Gamma, dt, n_steps=1):
         G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).copy()

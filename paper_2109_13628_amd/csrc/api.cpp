@@ -67,6 +67,10 @@ struct iim_ctx {
   double *Qw = nullptr, *wtmp = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
   bool have_prev = false;
+  int solver = IIM_SOLVER_KRYLOV;
+  double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
+  long n_solves = 0, n_matvecs = 0;
+  Prof prof;
   // host copies for the geometry view
   std::vector<double> v_cxy, v_cn;
   std::vector<int32_t> v_cint, v_aint, v_rects, v_circ;
@@ -313,7 +317,8 @@ void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam
   if (c->box)
     launch_dst(dg, c->dd, omega, gam, sgn, psi, done, c->stream);
   else
-    launch_conv(dg, c->df, omega, gam, sgn, rj0, rj1, oj0, oj1, psi, done, c->stream);
+    launch_conv(dg, c->df, omega, gam, sgn, rj0, rj1, oj0, oj1, psi, done, c->stream,
+                c->prof.mask ? &c->prof : nullptr);
 }
 
 void read_status(iim_ctx* c) {
@@ -330,6 +335,33 @@ void set_status(iim_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->dk.st, c->st_host, KS_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream));
 }
 
+// Dense Schur matrix, column by column through the same operator as the
+// Krylov matrix-vector product (columns S e_q), then inverted on the device.
+void build_direct(iim_ctx* c) {
+  const Geometry& g = c->geo;
+  DKrylov& k = c->dk;
+  const int n = k.n;
+  if (n == 0) return;
+  c->Sinv_t = c->dalloc<double>((size_t)n * n);
+  double* e = c->dalloc<double>(n);
+  for (int q = 0; q < n; ++q) {
+    launch_unit(e, n, q, c->stream);
+    apply_G(c, c->dg, nullptr, e, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
+    launch_matvec_finish(c->dg, k, c->psi, e, c->Sinv_t + (size_t)q * n, c->stream);
+  }
+  // the buffer holds S^T (row q = column q of S); its inverse is (S^-1)^T
+  int* perm = c->dalloc<int>(n);
+  double* fcol = c->dalloc<double>(n);
+  double* info = c->dalloc<double>(1);
+  HIPCHK(hipMemsetAsync(info, 0, sizeof(double), c->stream));
+  launch_gj_invert(c->Sinv_t, n, perm, fcol, info, c->stream);
+  double h_info = 0.0;
+  HIPCHK(hipMemcpyAsync(&h_info, info, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipGetLastError());
+  if (h_info != 0.0) throw GeomError("the Schur matrix is singular");
+}
+
 // One velocity reconstruction: returns status; fills iters/res0/res.
 int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, int& iters, double& res0,
                       double& res) {
@@ -340,6 +372,15 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   // right-hand side: b = A G omega + B psi_b_tilde, circulation rows
   apply_G(c, dg, omega, nullptr, 0.0, 0, ny - 1, g.out_j0, g.out_j1, c->psi, nullptr);
   launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
+  if (c->solver == IIM_SOLVER_DIRECT) {
+    launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->stream);
+    iters = 0;
+    res0 = res = 0.0;
+    c->n_solves += 1;
+    apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+    launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
+    return IIM_OK;
+  }
   set_status(c);
   const bool warm = c->guess == IIM_GUESS_PREVIOUS && c->have_prev;
   if (warm) {
@@ -354,7 +395,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
     int j = 0;
     for (; j < k.m && total < c->max_iter; ++j) {
       apply_G(c, dg, nullptr, k.V + (size_t)j * k.n, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, k.st);
-      launch_arnoldi(dg, k, c->psi, j, c->stream);
+      launch_arnoldi(dg, k, c->psi, j, c->stream, c->prof.mask ? &c->prof : nullptr);
       ++total;
       if ((j + 1) % c->chunk == 0 || j + 1 == k.m || total >= c->max_iter) {
         read_status(c);
@@ -375,6 +416,8 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   }
   read_status(c);
   iters = (int)c->st_host[KS_ITERS];
+  c->n_solves += 1;
+  c->n_matvecs += iters;
   res0 = c->st_host[KS_RES0];
   res = c->st_host[KS_RES];
   c->have_prev = true;
@@ -409,7 +452,8 @@ int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
       st.converged = 0;
     }
     launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
-    launch_transport(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, RK_A[s], RK_B[s], dt, 1, c->stream);
+    launch_transport(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, RK_A[s], RK_B[s], dt, 1, c->stream,
+                     c->prof.mask ? &c->prof : nullptr);
     launch_kelvin(dg, in, c->U, c->V, c->dGd, c->Gd, c->QGd, RK_A[s], RK_B[s], dt, 1, c->stream);
     std::swap(in, out);
   }
@@ -484,8 +528,10 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       if (opts->krylov_restart > 0) c->restart = std::min(64, opts->krylov_restart);
       c->guess = opts->guess;
       c->host_only = opts->host_only != 0;
+      c->solver = opts->solver;
     }
     if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
+    if (c->solver != IIM_SOLVER_KRYLOV && c->solver != IIM_SOLVER_DIRECT) throw ArgError("unknown solver");
     build_geometry(c->geo, gs, bs);
     c->stream = (hipStream_t)hip_stream;
     // geometry views
@@ -504,7 +550,10 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
     }
     for (auto& r : g.rects) c->v_rects.insert(c->v_rects.end(), r.begin(), r.end());
     c->v_circ = std::vector<int32_t>(g.circ_body.begin(), g.circ_body.end());
-    if (!c->host_only) setup_device(c);
+    if (!c->host_only) {
+      setup_device(c);
+      if (c->solver == IIM_SOLVER_DIRECT) build_direct(c);
+    }
   } catch (const GeomError& e) {
     g_create_error = e.what();
     delete c;
@@ -673,6 +722,34 @@ int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int3
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
   }
+  return IIM_OK;
+}
+
+int iim_profile(iim_ctx* c, int32_t kernel_mask) {
+  if (!c) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->prof.collect();
+  c->prof.reset();
+  c->prof.mask = (unsigned)kernel_mask;
+  return IIM_OK;
+}
+
+int iim_profile_read(iim_ctx* c, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes) {
+  if (!c || kernel_id < 0 || kernel_id >= KID_N || !total_ms || !launches || !bytes) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  (void)hipStreamSynchronize(c->stream);
+  c->prof.collect();
+  *total_ms = c->prof.total_ms[kernel_id];
+  *launches = c->prof.count[kernel_id];
+  *bytes = c->prof.bytes[kernel_id];
+  return IIM_OK;
+}
+
+int iim_krylov_totals(const iim_ctx* c, int64_t* solves, int64_t* matvecs) {
+  if (!c || !solves || !matvecs) return IIM_EINVAL;
+  *solves = c->n_solves;
+  *matvecs = c->n_matvecs;
   return IIM_OK;
 }
 

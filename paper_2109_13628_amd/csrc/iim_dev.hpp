@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace iim {
 
@@ -90,12 +91,69 @@ enum {
   KS_NFAIL = 8, KS_SIZE = 16
 };
 
+// ---------------------------------------------------------------- profiling
+// Event pairs around selected kernel launches (kernel ids below); read back
+// with Prof::collect after the stream has drained.
+enum KId { KID_ROWS_FWD = 0, KID_COLS = 1, KID_ROWS_INV = 2, KID_TRANSPORT = 3, KID_ARNOLDI = 4, KID_GEMM = 5,
+           KID_N = 6 };
+struct Prof {
+  unsigned mask = 0;
+  struct Rec { int id; int ea, eb; double bytes; };
+  std::vector<hipEvent_t> pool;
+  int used = 0;
+  std::vector<Rec> recs;
+  double total_ms[KID_N] = {0};
+  double bytes[KID_N] = {0};
+  long count[KID_N] = {0};
+  int ev(hipStream_t s) {
+    if (used == (int)pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+    (void)hipEventRecord(pool[used], s);
+    return used++;
+  }
+  int begin(int id, hipStream_t s) {
+    if (!((mask >> id) & 1u) || recs.size() > 200000) return -1;
+    Rec r{id, ev(s), -1, 0.0};
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int h, double b, hipStream_t s) {
+    if (h < 0) return;
+    recs[h].eb = ev(s);
+    recs[h].bytes = b;
+  }
+  void collect() {
+    for (auto& r : recs) {
+      if (r.ea < 0 || r.eb < 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pool[r.ea], pool[r.eb]) == hipSuccess) {
+        total_ms[r.id] += ms;
+        bytes[r.id] += r.bytes;
+        count[r.id] += 1;
+      }
+    }
+    recs.clear();
+    used = 0;
+  }
+  void reset() {
+    recs.clear();
+    used = 0;
+    for (int i = 0; i < KID_N; ++i) total_ms[i] = bytes[i] = 0.0, count[i] = 0;
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // ---------------------------------------------------------------- launchers
 // Poisson operator (free space): psi_ring rows [oj0, oj1] from sources in rows [rj0, rj1].
 // source = mask(omega) (omega may be null) + sgn * scatter(gam) (gam may be null).
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
-                 hipStream_t s);
+                 hipStream_t s, Prof* prof = nullptr);
 void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
                 double* psi_ring, const double* done_flag, hipStream_t s);
 void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,
@@ -104,7 +162,8 @@ void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const do
 void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega,
                        const double* Gamma, double* b, hipStream_t s);
 void launch_krylov_start(const DGeom& g, const DKrylov& k, bool x_is_zero, hipStream_t s);
-void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s);
+void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s,
+                    Prof* prof = nullptr);
 void launch_gmres_update(const DKrylov& k, hipStream_t s);
 void launch_matvec_finish(const DGeom& g, const DKrylov& kr, const double* psi_ring, const double* v,
                           double* out, hipStream_t s);
@@ -116,10 +175,14 @@ void launch_omega_bc(const DGeom& g, const double* omega, const double* U, const
 // mode 0: out = domega/dt;  mode 1: Q = a Q + dt rhs, out = omega + b Q
 void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V,
                       const double* w4, const double* w3b, const double* w3n, double* out, double* Q,
-                      double a, double b, double dt, int mode, hipStream_t s);
+                      double a, double b, double dt, int mode, hipStream_t s, Prof* prof = nullptr);
 // Kelvin: dG = -h sum (F+Q).n over dR_k; mode 1 also updates Gamma/QG in place
 void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG,
                    double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s);
 void launch_fill(double* p, double v, size_t n, hipStream_t s);
+// dense Schur complement: in-place Gauss-Jordan inverse, transposed GEMV, unit vector
+void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s);
+void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s);
+void launch_unit(double* v, int n, int q, hipStream_t s);
 
 }  // namespace iim

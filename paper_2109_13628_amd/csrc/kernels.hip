@@ -305,10 +305,18 @@ static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, do
   }
 
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
-                 int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s) {
-  IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, rj0, rj1 - rj0 + 1, done, s);
+                 int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+  int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
+  IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, rj0, nin, done, s);
+  // algorithmic bytes: source rows read (omega) + half spectrum written
+  if (prof) prof->end(h, (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
+  h = prof ? prof->begin(KID_COLS, s) : -1;
   IIM_POW2_SWITCH(f.my, cols_launch, g, f, rj0, rj1, oj0, oj1, done, s);
-  IIM_POW2_SWITCH(f.hx, rows_inv_launch, g, f, oj0, oj1 - oj0 + 1, psi_ring, done, s);
+  if (prof) prof->end(h, (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
+  h = prof ? prof->begin(KID_ROWS_INV, s) : -1;
+  IIM_POW2_SWITCH(f.hx, rows_inv_launch, g, f, oj0, nout, psi_ring, done, s);
+  if (prof) prof->end(h, (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2)), s);
 }
 
 // ------------------------------------------------------------------ box DST
@@ -596,8 +604,10 @@ __global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const doub
     if (rel <= k.st[KS_TOL] || !(rel == rel) || hn == 0.0) k.st[KS_DONE] = 1.0;
   }
 }
-void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s) {
+void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s, Prof* prof) {
+  const int h = prof ? prof->begin(KID_ARNOLDI, s) : -1;
   k_arnoldi<<<1, 1024, 0, s>>>(g, k, psi_ring, j);
+  if (prof) prof->end(h, 8.0 * k.n * (2.0 * (j + 1) + 3.0), s);
 }
 
 // x += V y with H(0:kk, 0:kk) y = g(0:kk)
@@ -866,9 +876,12 @@ __global__ void __launch_bounds__(128) k_transport_special(DGeom g, const double
 
 void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
                       const double* w3b, const double* w3n, double* out, double* Q, double a, double b, double dt,
-                      int mode, hipStream_t s) {
+                      int mode, hipStream_t s, Prof* prof) {
   dim3 grid((g.nx + 255) / 256, g.ny);
+  const int h = prof ? prof->begin(KID_TRANSPORT, s) : -1;
   k_transport_bulk<<<grid, 256, 0, s>>>(g, omega, U, V, out, Q, a, b, dt, mode);
+  // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
+  if (prof) prof->end(h, 48.0 * g.nx * g.ny, s);
   if (g.nsp) k_transport_special<<<(g.nsp + 127) / 128, 128, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
 }
 
@@ -909,5 +922,114 @@ void launch_kelvin(const DGeom& g, const double* omega, const double* U, const d
                    double* QG, double a, double b, double dt, int mode, hipStream_t s) {
   if (g.nbc) k_kelvin<<<g.nbc, 256, 0, s>>>(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode);
 }
+
+}  // namespace iim
+
+namespace iim {
+
+// ============================================================ dense Schur inverse
+// In-place Gauss-Jordan inversion with partial pivoting of an n x n row-major
+// matrix M (device).  Step k: pick the pivot row, swap it into row k, scale
+// row k, save column k; then eliminate column k from every other row.
+__global__ void __launch_bounds__(1024) k_gj_pivot(double* M, int n, int k, int* perm, double* fcol, double* info) {
+  __shared__ double vbest[16];
+  __shared__ int ibest[16];
+  double best = -1.0;
+  int bi = k;
+  for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+    const double v = fabs(M[(size_t)i * n + k]);
+    if (v > best) { best = v; bi = i; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { vbest[wid] = best; ibest[wid] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+      if (vbest[q] > vbest[0] || (vbest[q] == vbest[0] && ibest[q] < ibest[0])) { vbest[0] = vbest[q]; ibest[0] = ibest[q]; }
+    perm[k] = ibest[0];
+    if (!(vbest[0] > 0.0)) info[0] = 1.0;   // singular
+  }
+  __syncthreads();
+  const int p = ibest[0];
+  if (p != k)
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double a = M[(size_t)k * n + j];
+      M[(size_t)k * n + j] = M[(size_t)p * n + j];
+      M[(size_t)p * n + j] = a;
+    }
+  __syncthreads();
+  const double piv = M[(size_t)k * n + k];
+  const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double a = (j == k) ? 1.0 : M[(size_t)k * n + j];
+    M[(size_t)k * n + j] = a * inv;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) fcol[i] = (i == k) ? 0.0 : M[(size_t)i * n + k];
+}
+
+__global__ void k_gj_elim(double* M, int n, int k, const double* __restrict__ fcol) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n || i == k) return;
+  const double f = fcol[i];
+  const double rk = M[(size_t)k * n + j];
+  const double a = (j == k) ? 0.0 : M[(size_t)i * n + j];
+  M[(size_t)i * n + j] = a - f * rk;
+}
+
+// undo the row interchanges as column interchanges, last first
+__global__ void k_gj_colswap(double* M, int n, const int* __restrict__ perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* row = M + (size_t)i * n;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k) {
+      const double a = row[k];
+      row[k] = row[p];
+      row[p] = a;
+    }
+  }
+}
+
+void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    k_gj_pivot<<<1, 1024, 0, s>>>(M, n, k, perm, fcol, info);
+    dim3 grid((n + 255) / 256, n);
+    k_gj_elim<<<grid, 256, 0, s>>>(M, n, k, fcol);
+  }
+  k_gj_colswap<<<(n + 255) / 256, 256, 0, s>>>(M, n, perm);
+}
+
+// x[p] = sum_q Mt[q][p] b[q]   (Mt = transpose of the inverse, row-major)
+__global__ void __launch_bounds__(256) k_gemv_t(const double* __restrict__ Mt, int n, const double* __restrict__ b,
+                                                double* __restrict__ x) {
+  // each block: 64 outputs x 4 slices of q, reduced through LDS
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (p < n)
+    for (int q = sl; q < n; q += 4) acc += Mt[(size_t)q * n + p] * b[q];
+  part[sl][lane] = acc;
+  __syncthreads();
+  if (sl == 0 && p < n) x[p] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+}
+
+void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s) {
+  k_gemv_t<<<(n + 63) / 64, 256, 0, s>>>(Mt, n, b, x);
+}
+
+__global__ void k_unit(double* v, int n, int q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (i == q) ? 1.0 : 0.0;
+}
+void launch_unit(double* v, int n, int q, hipStream_t s) { k_unit<<<(n + 255) / 256, 256, 0, s>>>(v, n, q); }
 
 }  // namespace iim

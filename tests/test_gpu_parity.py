@@ -41,14 +41,15 @@ def test_poisson_operator(name):
     assert rel(got, ref) < 1e-13, rel(got, ref)
 
 
+@pytest.mark.parametrize("solver", [iim.SOLVER_KRYLOV, iim.SOLVER_DIRECT])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_reconstruct(name):
+def test_reconstruct(name, solver):
     w = SMALL[name]()
     geo = OG.Geometry(w.grid, w.bodies)
     R = Reconstructor(geo)
     om, G = seeded_state(w, geo, 11)
     ref = R.reconstruct(om, G)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-14, guess=iim.GUESS_ZERO)
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-14, guess=iim.GUESS_ZERO, solver=solver)
     psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
     st = ctx.reconstruct(to_dev(om), G, psi, U, V)
     torch.cuda.synchronize()
@@ -80,15 +81,16 @@ def test_rhs(name):
     assert np.max(np.abs(dG - dG_ref)) < 1e-12 * (np.abs(dG_ref).max() + 1e-3)
 
 
+@pytest.mark.parametrize("solver", [iim.SOLVER_KRYLOV, iim.SOLVER_DIRECT])
 @pytest.mark.parametrize("name", ["tc128", "cyl_small", "two_c_128"])
-def test_rk3_step(name):
+def test_rk3_step(name, solver):
     w = SMALL[name]()
     geo = OG.Geometry(w.grid, w.bodies)
     om, G = seeded_state(w, geo, 3)
     dt = w.dt if w.dt > 0 else 0.5 * ONS.dt_max(w.grid.h, w.grid.nu, 3.0)
     st = ONS.Stepper(geo)
     om_ref, G_ref = st.step(om, G, dt)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-14)
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-14, solver=solver)
     omd = to_dev(om)
     G_gpu, stats = ctx.rk3_steps(omd, G, dt, 1)
     torch.cuda.synchronize()
