@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -258,6 +259,7 @@ void setup_device(iim_ctx* c) {
     f.hx = mx / 2;
     f.ld = ny + 2;
     f.outflow = outflow;
+    f.use_reg = std::getenv("IIM_FFT_LDS_ONLY") == nullptr;
     std::vector<double> tab((size_t)(mx / 2 + 1) * (my / 2 + 1));
     lgf_table(mx / 2, my / 2, tab.data());
     std::vector<double> ghat((size_t)(mx / 2 + 1) * (my / 2 + 1));
@@ -390,29 +392,33 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   launch_krylov_start(dg, k, !warm, c->stream);
   read_status(c);
   int total = 0;
+  // Restarted GMRES.  Every cycle ends by recomputing the true residual
+  // b - S x; the solve stops only when that residual meets the tolerance, or
+  // when the iteration limit is reached.
   bool done = c->st_host[KS_DONE] != 0.0;
+  double last_true = c->st_host[KS_RES];
+  int stalls = 0;
   while (!done && total < c->max_iter) {
-    int j = 0;
-    for (; j < k.m && total < c->max_iter; ++j) {
+    for (int j = 0; j < k.m && total < c->max_iter; ++j) {
       apply_G(c, dg, nullptr, k.V + (size_t)j * k.n, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, k.st);
       launch_arnoldi(dg, k, c->psi, j, c->stream, c->prof.mask ? &c->prof : nullptr);
       ++total;
       if ((j + 1) % c->chunk == 0 || j + 1 == k.m || total >= c->max_iter) {
         read_status(c);
-        if (c->st_host[KS_DONE] != 0.0) {
-          done = true;
-          break;
-        }
+        if (c->st_host[KS_DONE] != 0.0) break;
       }
     }
     launch_gmres_update(k, c->stream);
-    if (done || total >= c->max_iter) break;
-    // restart from the true residual
+    // true residual and restart
     apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
     launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
     launch_krylov_start(dg, k, false, c->stream);
     read_status(c);
-    done = c->st_host[KS_DONE] != 0.0;
+    done = c->st_host[KS_DONE] != 0.0 || c->st_host[KS_NFAIL] != 0.0;
+    const double now = c->st_host[KS_RES];
+    // stop when restarts no longer reduce the true residual (rounding floor)
+    if (!done && now > 0.5 * last_true && ++stalls >= 2) break;
+    last_true = now;
   }
   read_status(c);
   iters = (int)c->st_host[KS_ITERS];

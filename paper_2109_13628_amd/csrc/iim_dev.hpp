@@ -60,6 +60,7 @@ struct DFft {
   const double2* tw_y;         // exp(-2 pi i k / my), k < my
   double2* spec;               // [mx/2+1][ld]
   bool outflow;
+  bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
 };
 
 struct DDst {                  // box: dense orthonormal sine transforms

@@ -304,8 +304,16 @@ static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, do
     default: break;                                       \
   }
 
+bool conv_reg_supported(int hx, int my);
+void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
+                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof);
+
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                  int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
+  if (f.use_reg && conv_reg_supported(f.hx, f.my)) {
+    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof);
+    return;
+  }
   const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
   int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
   IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, rj0, nin, done, s);
@@ -1031,5 +1039,404 @@ __global__ void k_unit(double* v, int n, int q) {
   if (i < n) v[i] = (i == q) ? 1.0 : 0.0;
 }
 void launch_unit(double* v, int n, int q, hipStream_t s) { k_unit<<<(n + 255) / 256, 256, 0, s>>>(v, n, q); }
+
+}  // namespace iim
+
+namespace iim {
+
+// ============================================================ register FFT
+// FFT of N >= 256 points by T threads; thread t holds E = N / T points in
+// registers in the layout x[t + T m].  Every Stockham pass of radix R reads its
+// butterfly inputs x[j + r N/R] (j = t + T b) straight from registers, applies
+// the twiddles W_{Ns R}^{r k}, does the radix-R DFT in registers and writes the
+// outputs to LDS in Stockham order; the next pass reloads the [t + T m] layout.
+// The last pass leaves its output in registers, again in the [t + T m] layout.
+template <int N>
+struct RP;
+template <> struct RP<256> { static constexpr int T = 64, E = 4; };
+template <> struct RP<512> { static constexpr int T = 64, E = 8; };
+template <> struct RP<1024> { static constexpr int T = 64, E = 16; };
+template <> struct RP<2048> { static constexpr int T = 128, E = 16; };
+template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
+
+template <int N>
+struct RegCfg {
+  static constexpr int T = RP<N>::T;
+  static constexpr int PER = 256 / T;              // FFTs per block
+  static constexpr int THREADS = PER * T;
+  static constexpr int LDSN = N + N / 16 + 1;      // padded length (one pad slot per 16 points)
+};
+
+__device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 s0 = cadd(a0, a2), d0 = csub(a0, a2), s1 = cadd(a1, a3), d1 = csub(a1, a3);
+  const double2 e = INV ? make_double2(-d1.y, d1.x) : make_double2(d1.y, -d1.x);
+  a0 = cadd(s0, s1);
+  a2 = csub(s0, s1);
+  a1 = cadd(d0, e);
+  a3 = csub(d0, e);
+}
+
+// exp(-2 pi i e / 16) (forward) for e = 0..15
+__device__ __forceinline__ double2 w16(int e, bool inv) {
+  const double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173, R2 = 0.70710678118654752440;
+  double c, s;
+  switch (e & 15) {
+    case 0: c = 1.0; s = 0.0; break;
+    case 1: c = C1; s = S1; break;
+    case 2: c = R2; s = R2; break;
+    case 3: c = S1; s = C1; break;
+    case 4: c = 0.0; s = 1.0; break;
+    case 5: c = -S1; s = C1; break;
+    case 6: c = -R2; s = R2; break;
+    case 7: c = -C1; s = S1; break;
+    case 8: c = -1.0; s = 0.0; break;
+    case 9: c = -C1; s = -S1; break;
+    case 10: c = -R2; s = -R2; break;
+    case 11: c = -S1; s = -C1; break;
+    case 12: c = 0.0; s = -1.0; break;
+    case 13: c = S1; s = -C1; break;
+    case 14: c = R2; s = -R2; break;
+    default: c = C1; s = -S1; break;
+  }
+  return make_double2(c, inv ? s : -s);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(double2 (&u)[R]) {
+  if constexpr (R == 2) {
+    const double2 a = u[0];
+    u[0] = cadd(a, u[1]);
+    u[1] = csub(a, u[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(u[0], u[1], u[2], u[3]);
+  } else if constexpr (R == 8) {
+    // n = q + 2 m: inner DFT4 over m, twiddle W8^{q s}, outer DFT2 over q
+    dft4<INV>(u[0], u[2], u[4], u[6]);
+    dft4<INV>(u[1], u[3], u[5], u[7]);
+    double2 o[8];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double2 a = u[2 * s];
+      const double2 b = cmul(u[2 * s + 1], w16(2 * s, INV));
+      o[s] = cadd(a, b);
+      o[s + 4] = csub(a, b);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = o[q];
+  } else {
+    static_assert(R == 16, "radix");
+    // n = q + 4 m: inner DFT4 over m (elements q, q+4, q+8, q+12), twiddle W16^{q s}, outer DFT4 over q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dft4<INV>(u[q], u[q + 4], u[q + 8], u[q + 12]);
+    // after the inner DFT, element q + 4 s holds A[q][s]
+    double2 o[16];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double2 b0 = u[0 + 4 * s];
+      double2 b1 = cmul(u[1 + 4 * s], w16(1 * s, INV));
+      double2 b2 = cmul(u[2 + 4 * s], w16(2 * s, INV));
+      double2 b3 = cmul(u[3 + 4 * s], w16(3 * s, INV));
+      dft4<INV>(b0, b1, b2, b3);
+      o[s] = b0;
+      o[s + 4] = b1;
+      o[s + 8] = b2;
+      o[s + 12] = b3;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) u[q] = o[q];
+  }
+}
+
+template <int N, int T, int E, int R, int NS, bool INV, bool LAST>
+__device__ __forceinline__ void reg_pass(double2 (&v)[E], double2* lds, int t, const double2* __restrict__ tw) {
+  constexpr int B = E / R;
+  double2 u[B][R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + T * b;
+    const int k = j & (NS - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[b][r] = v[b + r * B];
+    if (NS > 1) {
+      constexpr int step = N / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        double2 w = tw[r * k * step];
+        if (INV) w.y = -w.y;
+        u[b][r] = cmul(u[b][r], w);
+      }
+    }
+    dftR<R, INV>(u[b]);
+  }
+  if (LAST) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * B] = u[b][r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + T * b;
+      const int k = j & (NS - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[padi(base + r * NS)] = u[b][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = lds[padi(t + T * m)];
+    __syncthreads();
+  }
+}
+
+template <int N, bool INV>
+__device__ __forceinline__ void fft_reg(double2 (&v)[RP<N>::E], double2* lds, int t, const double2* __restrict__ tw) {
+  constexpr int T = RP<N>::T, E = RP<N>::E;
+  if constexpr (N == 256) {
+    reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 4, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 64, INV, true>(v, lds, t, tw);
+  } else if constexpr (N == 512) {
+    reg_pass<N, T, E, 8, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 8, 8, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 8, 64, INV, true>(v, lds, t, tw);
+  } else if constexpr (N == 1024) {
+    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 256, INV, true>(v, lds, t, tw);
+  } else if constexpr (N == 2048) {
+    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 8, 256, INV, true>(v, lds, t, tw);
+  } else {
+    static_assert(N == 4096, "size");
+    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 16, 256, INV, true>(v, lds, t, tw);
+  }
+}
+
+// ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
+template <int MY>
+__global__ void __launch_bounds__(RegCfg<MY>::THREADS)
+k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
+  using C = RegCfg<MY>;
+  constexpr int T = RP<MY>::T, E = RP<MY>::E;
+  __shared__ double2 lds[C::PER][C::LDSN];
+  if (done && done[KS_DONE] != 0.0) return;
+  const int w = threadIdx.x / T, t = threadIdx.x % T;
+  const int kx = blockIdx.x * C::PER + w;
+  const bool valid = kx <= f.hx;
+  double2* col = f.spec + (size_t)(valid ? kx : 0) * f.ld;
+  double2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = t + T * m;
+    v[m] = (valid && n >= rj0 && n <= rj1) ? col[n + 1] : make_double2(0.0, 0.0);
+  }
+  fft_reg<MY, false>(v, lds[w], t, f.tw_y);
+  const double* gh = f.ghat + (size_t)(valid ? kx : 0) * (MY / 2 + 1);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = t + T * m;
+    const double s = gh[n <= MY / 2 ? n : MY - n];
+    v[m].x *= s;
+    v[m].y *= s;
+  }
+  fft_reg<MY, true>(v, lds[w], t, f.tw_y);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      const int jo = (n == MY - 1) ? -1 : n;
+      if (jo >= oj0 && jo <= oj1) col[jo + 1] = v[m];
+    }
+  }
+}
+
+// ---- forward rows: real FFT of length 2 HX (half-length complex FFT + split)
+template <int HX>
+__device__ __forceinline__ void add_at(double2 (&v)[RP<HX>::E], int t, int i, double val) {
+  constexpr int T = RP<HX>::T, E = RP<HX>::E;
+  const int n = i >> 1;
+  if ((n % T) != t) return;
+  const int mm = n / T;
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    if (m == mm) {
+      if (i & 1) v[m].y += val; else v[m].x += val;
+    }
+}
+
+template <int HX>
+__global__ void __launch_bounds__(RegCfg<HX>::THREADS)
+k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
+               int j0, int count, const double* __restrict__ done) {
+  using C = RegCfg<HX>;
+  constexpr int T = RP<HX>::T, E = RP<HX>::E;
+  __shared__ double2 lds[C::PER][C::LDSN];
+  if (done && done[KS_DONE] != 0.0) return;
+  const int w = threadIdx.x / T, t = threadIdx.x % T;
+  const int jrow = j0 + blockIdx.x * C::PER + w;
+  const bool valid = (jrow < j0 + count) && jrow >= 0 && jrow < g.ny;
+  double2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = t + T * m;
+    double2 z = make_double2(0.0, 0.0);
+    if (valid && omega) {
+      const int i0 = 2 * n, i1 = 2 * n + 1;
+      int m0 = i0, m1 = i1;
+      if (f.outflow) {
+        m0 = i0 < g.nx ? i0 : 2 * g.nx - 1 - i0;
+        m1 = i1 < g.nx ? i1 : 2 * g.nx - 1 - i1;
+      }
+      const size_t rb = (size_t)jrow * g.nx;
+      if (m0 >= 0 && m0 < g.nx && g.cls[rb + m0] < 2) z.x = omega[rb + m0];
+      if (m1 >= 0 && m1 < g.nx && g.cls[rb + m1] < 2) z.y = omega[rb + m1];
+    }
+    v[m] = z;
+  }
+  if (valid && gam) {
+    for (int e = g.row_ptr[jrow]; e < g.row_ptr[jrow + 1]; ++e) {
+      const int i = g.row_i[e];
+      const double val = sgn * gam[g.row_a[e]];
+      add_at<HX>(v, t, i, val);
+      if (f.outflow) add_at<HX>(v, t, 2 * g.nx - 1 - i, val);
+    }
+  }
+  fft_reg<HX, false>(v, lds[w], t, f.tw_x);
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[w][padi(t + T * m)] = v[m];
+  // split twiddles of this thread's bins, loaded before the barrier
+  constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
+  double2 wk[IT];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
+    wk[q] = idx < (HX + 1) * C::PER ? f.tw_xr[idx / C::PER] : make_double2(1.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
+    if (idx >= (HX + 1) * C::PER) break;
+    const int rr = idx % C::PER, k = idx / C::PER;
+    const int jj = j0 + blockIdx.x * C::PER + rr;
+    if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
+    const double2 zk = lds[rr][padi(k & (HX - 1))];
+    const double2 zc = conj2(lds[rr][padi((HX - k) & (HX - 1))]);
+    const double2 E2 = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+    const double2 Od = csub(zk, zc);
+    const double2 O = make_double2(0.5 * Od.y, -0.5 * Od.x);
+    f.spec[(size_t)k * f.ld + jj + 1] = cadd(E2, cmul(wk[q], O));
+  }
+}
+
+// ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
+template <int HX>
+__global__ void __launch_bounds__(RegCfg<HX>::THREADS)
+k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
+  using C = RegCfg<HX>;
+  constexpr int T = RP<HX>::T, E = RP<HX>::E;
+  __shared__ double2 lds[C::PER][C::LDSN];
+  if (done && done[KS_DONE] != 0.0) return;
+  {
+    // all loads of this thread in flight before the LDS stores
+    constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
+    double2 tmp[IT];
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int idx = threadIdx.x + q * C::THREADS;
+      const int rr = idx % C::PER, k = idx / C::PER;
+      const int jo = j0 + blockIdx.x * C::PER + rr;
+      tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? f.spec[(size_t)k * f.ld + jo + 1]
+                                                             : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int idx = threadIdx.x + q * C::THREADS;
+      if (idx < (HX + 1) * C::PER) lds[idx % C::PER][padi(idx / C::PER)] = tmp[q];
+    }
+  }
+  __syncthreads();
+  const int w = threadIdx.x / T, t = threadIdx.x % T;
+  double2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const double2 xk = lds[w][padi(k)];
+    const double2 xc = conj2(lds[w][padi(HX - k)]);
+    const double2 Ev = cadd(xk, xc);
+    const double2 Ov = cmul(csub(xk, xc), conj2(f.tw_xr[k]));
+    v[m] = make_double2(Ev.x - Ov.y, Ev.y + Ov.x);
+  }
+  __syncthreads();
+  fft_reg<HX, true>(v, lds[w], t, f.tw_x);
+  const int jo = j0 + blockIdx.x * C::PER + w;
+  if (jo >= j0 + count) return;
+  const int nxr = g.nx + 2;
+  double* row = psi + (size_t)(jo + 1) * nxr;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = t + T * m;
+    const int i0 = 2 * n, i1 = 2 * n + 1;
+    if (i0 <= g.nx) row[i0 + 1] = v[m].x;
+    if (i1 <= g.nx) row[i1 + 1] = v[m].y;
+    if (i1 == 2 * HX - 1) row[0] = v[m].y;
+  }
+}
+
+template <int HX>
+void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0,
+                         int count, const double* done, hipStream_t s) {
+  using C = RegCfg<HX>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0) k_rows_fwd_reg<HX><<<blocks, C::THREADS, 0, s>>>(g, f, omega, gam, sgn, j0, count, done);
+}
+template <int MY>
+void cols_reg_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
+                     hipStream_t s) {
+  using C = RegCfg<MY>;
+  const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
+  k_cols_reg<MY><<<blocks, C::THREADS, 0, s>>>(g, f, rj0, rj1, oj0, oj1, done);
+}
+template <int HX>
+void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
+                         hipStream_t s) {
+  using C = RegCfg<HX>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0) k_rows_inv_reg<HX><<<blocks, C::THREADS, 0, s>>>(g, f, j0, count, psi, done);
+}
+
+#define IIM_REG_SWITCH(VAL, FN, ...)                \
+  switch (VAL) {                                    \
+    case 256: FN<256>(__VA_ARGS__); break;          \
+    case 512: FN<512>(__VA_ARGS__); break;          \
+    case 1024: FN<1024>(__VA_ARGS__); break;        \
+    case 2048: FN<2048>(__VA_ARGS__); break;        \
+    case 4096: FN<4096>(__VA_ARGS__); break;        \
+    default: break;                                 \
+  }
+
+bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
+
+void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
+                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+  int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
+  IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, g, f, omega, gam, sgn, rj0, nin, done, s);
+  if (prof) prof->end(h, (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
+  h = prof ? prof->begin(KID_COLS, s) : -1;
+  IIM_REG_SWITCH(f.my, cols_reg_launch, g, f, rj0, rj1, oj0, oj1, done, s);
+  if (prof) prof->end(h, (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
+  h = prof ? prof->begin(KID_ROWS_INV, s) : -1;
+  IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, g, f, oj0, nout, psi_ring, done, s);
+  if (prof) prof->end(h, (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2)), s);
+}
 
 }  // namespace iim

@@ -119,23 +119,28 @@ void lgf_table(int mx, int my, double* out, int threads) {
 void lgf_spectrum(int mx, int my, double h, const double* table, int tab_mx, double* out) {
   // K(i, j) = h^2 g(min(i, mx-i), min(j, my-j)) is real and even in both
   // directions; its DFT is real:  sum_i sum_j K cos(2 pi kx i / mx) cos(2 pi ky j / my).
+  // The kernel grows like log r, so the high-frequency coefficients are small
+  // differences of large sums: both cosine sums accumulate in 80-bit long
+  // double, which keeps the result accurate to double rounding.
+  typedef long double LD;
   const int hx = mx / 2, hy = my / 2;
-  std::vector<double> cx(mx), cy(my);
-  for (int i = 0; i < mx; ++i) cx[i] = std::cos(2.0 * M_PI * i / mx);
-  for (int j = 0; j < my; ++j) cy[j] = std::cos(2.0 * M_PI * j / my);
+  const LD two_pi = 6.283185307179586476925286766559005768L;
+  std::vector<LD> cx(mx), cy(my);
+  for (int i = 0; i < mx; ++i) cx[i] = std::cos(two_pi * (LD)i / (LD)mx);
+  for (int j = 0; j < my; ++j) cy[j] = std::cos(two_pi * (LD)j / (LD)my);
   // first along x: C1[j][kx] for j in [0, hy]
-  std::vector<double> C1((size_t)(hy + 1) * (hx + 1));
+  std::vector<LD> C1((size_t)(hy + 1) * (hx + 1));
   int threads = (int)std::thread::hardware_concurrency();
   if (threads <= 0) threads = 1;
   if (threads > 16) threads = 16;
-  auto kern = [&](int i, int j) { return h * h * table[(size_t)j * (tab_mx + 1) + i]; };
+  const LD h2 = (LD)h * (LD)h;
+  auto kern = [&](int i, int j) { return h2 * (LD)table[(size_t)j * (tab_mx + 1) + i]; };
   auto passx = [&](int tid) {
     for (int j = tid; j <= hy; j += threads)
       for (int kx = 0; kx <= hx; ++kx) {
-        double s = kern(0, j) + ((kx & 1) ? -1.0 : 1.0) * kern(hx, j);
-        double acc = 0.0;
+        LD acc = 0.0L;
         for (int i = 1; i < hx; ++i) acc += kern(i, j) * cx[((size_t)kx * i) % mx];
-        C1[(size_t)j * (hx + 1) + kx] = s + 2.0 * acc;
+        C1[(size_t)j * (hx + 1) + kx] = kern(0, j) + ((kx & 1) ? -1.0L : 1.0L) * kern(hx, j) + 2.0L * acc;
       }
   };
   {
@@ -143,14 +148,14 @@ void lgf_spectrum(int mx, int my, double h, const double* table, int tab_mx, dou
     for (int t = 0; t < threads; ++t) pool.emplace_back(passx, t);
     for (auto& th : pool) th.join();
   }
-  const double scale = 1.0 / ((double)mx * (double)my);
+  const LD scale = 1.0L / ((LD)mx * (LD)my);
   auto passy = [&](int tid) {
     for (int kx = tid; kx <= hx; kx += threads)
       for (int ky = 0; ky <= hy; ++ky) {
-        double s = C1[kx] + ((ky & 1) ? -1.0 : 1.0) * C1[(size_t)hy * (hx + 1) + kx];
-        double acc = 0.0;
+        LD acc = 0.0L;
         for (int j = 1; j < hy; ++j) acc += C1[(size_t)j * (hx + 1) + kx] * cy[((size_t)ky * j) % my];
-        out[(size_t)kx * (hy + 1) + ky] = (s + 2.0 * acc) * scale;
+        const LD v = C1[kx] + ((ky & 1) ? -1.0L : 1.0L) * C1[(size_t)hy * (hx + 1) + kx] + 2.0L * acc;
+        out[(size_t)kx * (hy + 1) + ky] = (double)(v * scale);
       }
   };
   {

@@ -20,8 +20,18 @@ def ring_zeros(grid):
     return torch.zeros((grid.ny + 2, grid.nx + 2), dtype=torch.float64, device=DEV)
 
 
-def seeded_state(w, geo, seed):
-    """Seeded vorticity (zero in the solid) and circulations of the workload's shape."""
+def seeded_state(w, geo, seed, body_scale=None):
+    """Seeded vorticity (zero in the solid) and circulations of the workload's
+    shape.  body_scale: place vortices of the body's size within a few body
+    sizes of the first body (a wake-like state) instead of domain-sized blobs."""
+    if body_scale is not None:
+        cx, cy = np.mean(w.bodies[0].points, axis=0)
+        D = body_scale
+        om = wl.seeded_vortices(w.grid, seed, count=8, amp=3.0,
+                                box=(cx - 1.0 * D, cx + 4.0 * D, cy - 1.5 * D, cy + 1.5 * D),
+                                width=(0.05 * D, 0.25 * D))
+        om = np.where(geo.fluid, om, 0.0)
+        return om, wl.seeded_gammas(geo.nbc, seed + 1, scale=0.5)
     xs = w.grid.x0 + w.grid.h * (w.grid.nx - 1)
     ys = w.grid.y0 + w.grid.h * (w.grid.ny - 1)
     om = wl.seeded_vortices(w.grid, seed, count=8, amp=3.0,

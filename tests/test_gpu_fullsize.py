@@ -1,0 +1,57 @@
+"""GPU vs oracle at the benchmark size (1024 x 512 free-space cylinder, FFT
+torus 2048 x 1024), in the launch configuration bench.py times."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+import paper_2109_13628_amd as iim
+from oracle import geometry as OG
+from oracle import poisson as OP
+from oracle.reconstruct import Reconstructor
+from oracle import ns as ONS
+from gpu_util import DEV, to_dev, ring_zeros, seeded_state, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def _setup(name):
+    w = wl.cylinder() if name == "cyl1024" else wl.cylinder(nx=512, ny=256, h=1.0 / 32, points=256, dt=0.005)
+    geo = OG.Geometry(w.grid, w.bodies)
+    return w, geo, ONS.Stepper(geo)
+
+
+@pytest.mark.parametrize("name", ["cyl512", "cyl1024"])
+def test_poisson_fullsize(name):
+    w, geo, st = _setup(name)
+    rng = np.random.default_rng(2)
+    src = rng.standard_normal((w.grid.ny, w.grid.nx))
+    ctx = iim.Context(w.grid, w.bodies)
+    psi = ring_zeros(w.grid)
+    ctx.poisson(to_dev(src), psi)
+    torch.cuda.synchronize()
+    ref = st.rec._fs(src)
+    assert rel(psi.cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("solver", [iim.SOLVER_DIRECT, iim.SOLVER_KRYLOV])
+@pytest.mark.parametrize("name", ["cyl512", "cyl1024"])
+def test_step_fullsize(name, solver):
+    w, geo, st = _setup(name)
+    om, G = seeded_state(w, geo, 21, body_scale=1.0)
+    om_ref, G_ref = st.step(om, G, w.dt)
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-13, solver=solver)
+    d = to_dev(om)
+    G2, stats = ctx.rk3_steps(d, G, w.dt, 1)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    assert rel(got, om_ref) < 1e-11, stats
+    assert np.max(np.abs(G2 - G_ref)) < 1e-11 * (1 + np.abs(G_ref).max())
+    # velocity reconstructed from the GPU state vs from the oracle state
+    a = st.rec.reconstruct(got, G2)
+    b = st.rec.reconstruct(om_ref, G_ref)
+    fl = np.pad(geo.fluid, 1)
+    assert rel(np.stack([a.U[fl], a.V[fl]]), np.stack([b.U[fl], b.V[fl]])) < 1e-11

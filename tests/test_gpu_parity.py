@@ -49,7 +49,7 @@ def test_reconstruct(name, solver):
     R = Reconstructor(geo)
     om, G = seeded_state(w, geo, 11)
     ref = R.reconstruct(om, G)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-14, guess=iim.GUESS_ZERO, solver=solver)
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-13, guess=iim.GUESS_ZERO, solver=solver)
     psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
     st = ctx.reconstruct(to_dev(om), G, psi, U, V)
     torch.cuda.synchronize()
@@ -90,7 +90,7 @@ def test_rk3_step(name, solver):
     dt = w.dt if w.dt > 0 else 0.5 * ONS.dt_max(w.grid.h, w.grid.nu, 3.0)
     st = ONS.Stepper(geo)
     om_ref, G_ref = st.step(om, G, dt)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-14, solver=solver)
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-13, solver=solver)
     omd = to_dev(om)
     G_gpu, stats = ctx.rk3_steps(omd, G, dt, 1)
     torch.cuda.synchronize()
