@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libiim.so")
+LIB_PATH = os.environ.get("IIM_LIBRARY") or os.path.join(HERE, "libiim.so")
 
 IIM_OK, IIM_EINVAL, IIM_ENOMEM, IIM_EGEOM, IIM_ENOCONV, IIM_ENONFINITE, IIM_EDEVICE, IIM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/iim.h"
+#include "iim.h"
 #include "iim_dev.hpp"
 #include "iim_host.hpp"
 
@@ -70,6 +70,13 @@ struct iim_ctx {
   bool have_prev = false;
   int solver = IIM_SOLVER_KRYLOV;
   double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
+  // one RK3 step captured as a HIP graph (direct solver): replayed while the
+  // omega buffer and dt stay the same
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* g_omega = nullptr;
+  double g_dt = 0.0;
+  bool use_graph = true;
   long n_solves = 0, n_matvecs = 0;
   Prof prof;
   // host copies for the geometry view
@@ -92,6 +99,8 @@ struct iim_ctx {
     return p;
   }
   ~iim_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
   }
@@ -469,6 +478,54 @@ int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
   return status;
 }
 
+// Direct solver: the whole step is a fixed kernel sequence without host
+// synchronisation; capture it once on an internal stream and replay it.
+int run_step_graph(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
+  if (!c->gexec || c->g_omega != omega || c->g_dt != dt) {
+    if (c->gexec) {
+      HIPCHK(hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+    if (!c->gstream) HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    // order the capture after the work already queued on the user stream
+    HIPCHK(hipStreamSynchronize(c->stream));
+    hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    hipGraph_t graph = nullptr;
+    int rc = IIM_OK;
+    const long solves0 = c->n_solves;
+    HIPCHK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+    try {
+      rc = run_step(c, omega, dt, nullptr);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->gstream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      c->stream = user;
+      throw;
+    }
+    const hipError_t ec = hipStreamEndCapture(c->gstream, &graph);
+    c->stream = user;
+    HIPCHK(ec);
+    if (rc != IIM_OK) {
+      (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(ei);
+    c->g_omega = omega;
+    c->g_dt = dt;
+    c->n_solves = solves0;
+  }
+  HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  c->n_solves += 3;
+  if (stats) {
+    *stats = iim_step_stats{};
+    stats->converged = 1;
+  }
+  return IIM_OK;
+}
+
 iim_ctx* as_ctx(const iim_ctx* c) { return const_cast<iim_ctx*>(c); }
 
 }  // namespace
@@ -535,6 +592,7 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       c->guess = opts->guess;
       c->host_only = opts->host_only != 0;
       c->solver = opts->solver;
+      c->use_graph = std::getenv("IIM_NO_GRAPH") == nullptr;
     }
     if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
     if (c->solver != IIM_SOLVER_KRYLOV && c->solver != IIM_SOLVER_DIRECT) throw ArgError("unknown solver");
@@ -716,8 +774,9 @@ int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int3
     const int nb = c->geo.nbc();
     if (nb) HIPCHK(hipMemcpyAsync(c->Gd, Gamma_host, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
     int status = IIM_OK;
+    const bool graph = c->use_graph && c->solver == IIM_SOLVER_DIRECT && c->prof.mask == 0;
     for (int s = 0; s < n_steps; ++s) {
-      const int rc = run_step(c, omega, dt, stats);
+      const int rc = graph ? run_step_graph(c, omega, dt, stats) : run_step(c, omega, dt, stats);
       if (rc == IIM_ENONFINITE) return fail(c, rc, "non-finite residual");
       if (rc == IIM_ENOCONV) status = rc;
     }

@@ -613,14 +613,17 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
     }
   }
 
-  // ---- transport: fluid nodes whose stencils meet a non-fluid node or the grid edge
+  // ---- transport: fluid nodes whose stencils meet a solid or ghost node
+  // (nodes near the grid edge whose stencils are otherwise fluid stay in the
+  // bulk kernel, which treats nodes outside the grid as vorticity-free fluid)
+  auto solid_in_grid = [&](int i, int j) { return i >= 0 && j >= 0 && i < nx && j < ny && is_solid(i, j); };
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       if (is_solid(i, j)) continue;
       bool sp = false;
       for (int d = -2; d <= 2 && !sp; ++d) {
         if (d == 0) continue;
-        if (!fluid_at(i + d, j) || !fluid_at(i, j + d)) sp = true;
+        if (solid_in_grid(i + d, j) || solid_in_grid(i, j + d)) sp = true;
       }
       if (sp) g.special.push_back(j * nx + i);
     }

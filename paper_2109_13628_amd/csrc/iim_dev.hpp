@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <vector>
@@ -115,6 +116,24 @@ struct Prof {
     (void)hipEventRecord(pool[used], s);
     return used++;
   }
+  bool on(int id) const { return ((mask >> id) & 1u) && recs.size() <= 200000; }
+  // Two pooled events for a launch made with hipExtLaunchKernelGGL, which
+  // records them in the dispatch packet around the kernel itself.
+  void pair(int id, double b, hipEvent_t& ea, hipEvent_t& eb) {
+    auto get = [&]() -> int {
+      if (used == (int)pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        pool.push_back(e);
+      }
+      return used++;
+    };
+    const int a = get(), c = get();
+    if (a < 0 || c < 0) { ea = eb = nullptr; return; }
+    recs.push_back(Rec{id, a, c, b});
+    ea = pool[a];
+    eb = pool[c];
+  }
   int begin(int id, hipStream_t s) {
     if (!((mask >> id) & 1u) || recs.size() > 200000) return -1;
     Rec r{id, ev(s), -1, 0.0};
@@ -148,6 +167,18 @@ struct Prof {
     for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
+
+// Launch `kern` on stream s; when prof times kernel id, bracket it with
+// dispatch-packet events (hipExtLaunchKernelGGL).
+#define IIM_LAUNCH(prof, id, bytes, kern, grid, block, s, ...)                       \
+  do {                                                                               \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                         \
+    if ((prof) && (prof)->on(id)) (prof)->pair((id), (bytes), ea_, eb_);             \
+    if (ea_)                                                                         \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, ea_, eb_, 0, __VA_ARGS__); \
+    else                                                                             \
+      kern<<<(grid), (block), 0, s>>>(__VA_ARGS__);                                  \
+  } while (0)
 
 // ---------------------------------------------------------------- launchers
 // Poisson operator (free space): psi_ring rows [oj0, oj1] from sources in rows [rj0, rj1].

@@ -461,6 +461,7 @@ __device__ void matvec_finish_block(const DGeom& g, const double* __restrict__ p
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
     double acc = 0.0;
+#pragma unroll 4
     for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
     double y = v[a] + acc;
     for (int k = 0; k < g.nbc; ++k) y -= g.b1[(size_t)k * g.na + a] * v[g.na + k];
@@ -506,6 +507,7 @@ __global__ void __launch_bounds__(256) k_rhs_vector(DGeom g, const double* __res
   const int a = (blockIdx.x - g.nbc) * blockDim.x + threadIdx.x;
   if (a >= g.na) return;
   double acc = 0.0;
+#pragma unroll 4
   for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
   b[a] = acc + g.bpsi[a];
 }
@@ -613,9 +615,7 @@ __global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const doub
   }
 }
 void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s, Prof* prof) {
-  const int h = prof ? prof->begin(KID_ARNOLDI, s) : -1;
-  k_arnoldi<<<1, 1024, 0, s>>>(g, k, psi_ring, j);
-  if (prof) prof->end(h, 8.0 * k.n * (2.0 * (j + 1) + 3.0), s);
+  IIM_LAUNCH(prof, KID_ARNOLDI, 8.0 * k.n * (2.0 * (j + 1) + 3.0), k_arnoldi, 1, 1024, s, g, k, psi_ring, j);
 }
 
 // x += V y with H(0:kk, 0:kk) y = g(0:kk)
@@ -648,6 +648,7 @@ __global__ void k_ghost_psi(DGeom g, const double* __restrict__ x, double* __res
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.ng) return;
   double acc = 0.0;
+#pragma unroll 4
   for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) acc += g.ext4b.w[e] * psi[g.ext4b.ridx[e]];
   for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) {
     const int c = g.ext4b.bc[e];
@@ -687,6 +688,7 @@ __global__ void k_vel_ext(DGeom g, double* __restrict__ U, double* __restrict__ 
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.ng) return;
   double au = 0.0, av = 0.0;
+#pragma unroll 4
   for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) {
     const int r = g.ext3b.ridx[e];
     au += g.ext3b.w[e] * U[r];
@@ -713,6 +715,7 @@ __global__ void k_omega_b(DGeom g, const double* __restrict__ U, const double* _
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.nc) return;
   double acc = g.wb_const[c];
+#pragma unroll 4
   for (int e = g.wbc.ptr[c]; e < g.wbc.ptr[c + 1]; ++e) {
     const int r = g.wbc.ridx[e];
     const double val = (r & (1 << 30)) ? V[r & ((1 << 30) - 1)] : U[r];
@@ -726,10 +729,13 @@ __global__ void k_omega_ext(DGeom g, const double* __restrict__ omega, const dou
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.ng) return;
   double a4 = 0.0, a3 = 0.0, an = 0.0;
+#pragma unroll 4
   for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) a4 += g.ext4b.w[e] * omega[g.ext4b.gidx[e]];
   for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) a4 += g.ext4b.bw[e] * wb[g.ext4b.bc[e]];
+#pragma unroll 4
   for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) a3 += g.ext3b.w[e] * omega[g.ext3b.gidx[e]];
   for (int e = g.ext3b.bptr[q]; e < g.ext3b.bptr[q + 1]; ++e) a3 += g.ext3b.bw[e] * wb[g.ext3b.bc[e]];
+#pragma unroll 4
   for (int e = g.ext3n.ptr[q]; e < g.ext3n.ptr[q + 1]; ++e) an += g.ext3n.w[e] * omega[g.ext3n.gidx[e]];
   const int gi = g.g_gidx[q];
   w4[gi] = a4;
@@ -834,20 +840,36 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
     if (mode == 1) Q[q] = 0.0;
     return;
   }
-  const int nx = g.nx, nxr = nx + 2;
+  const int nx = g.nx, ny = g.ny, nxr = nx + 2;
   const int r = (j + 1) * nxr + i + 1;
   const double nih = g.nu * g.inv_h;
   const double wc = omega[q];
-  // x faces
-  const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
-  const double uxm2 = U[r - 2], uxm1 = U[r - 1], uc = U[r], uxp1 = U[r + 1], uxp2 = U[r + 2];
-  const double fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
-  const double fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
-  // y faces
-  const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
-  const double vym2 = V[r - 2 * nxr], vym1 = V[r - nxr], vc = V[r], vyp1 = V[r + nxr], vyp2 = V[r + 2 * nxr];
-  const double fyt = flux_std(vym1, vc, vyp1, vyp2, wym1, wc, wyp1, wyp2, nih);
-  const double fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
+  double fxr, fxl, fyt, fyb;
+  if (i >= 2 && i < nx - 2 && j >= 2 && j < ny - 2) {
+    // x faces
+    const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
+    const double uxm2 = U[r - 2], uxm1 = U[r - 1], uc = U[r], uxp1 = U[r + 1], uxp2 = U[r + 2];
+    fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
+    fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
+    // y faces
+    const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
+    const double vym2 = V[r - 2 * nxr], vym1 = V[r - nxr], vc = V[r], vyp1 = V[r + nxr], vyp2 = V[r + 2 * nxr];
+    fyt = flux_std(vym1, vc, vyp1, vyp2, wym1, wc, wyp1, wyp2, nih);
+    fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
+  } else {
+    // near the grid edge: nodes outside carry omega = 0; velocities come from the ring
+    auto W = [&](int ii, int jj) { return (ii >= 0 && jj >= 0 && ii < nx && jj < ny) ? omega[jj * nx + ii] : 0.0; };
+    auto UU = [&](int ii, int jj) {
+      return (ii >= -1 && jj >= -1 && ii <= nx && jj <= ny) ? U[(jj + 1) * nxr + ii + 1] : 0.0;
+    };
+    auto VV = [&](int ii, int jj) {
+      return (ii >= -1 && jj >= -1 && ii <= nx && jj <= ny) ? V[(jj + 1) * nxr + ii + 1] : 0.0;
+    };
+    fxr = flux_std(UU(i - 1, j), UU(i, j), UU(i + 1, j), UU(i + 2, j), W(i - 1, j), wc, W(i + 1, j), W(i + 2, j), nih);
+    fxl = flux_std(UU(i - 2, j), UU(i - 1, j), UU(i, j), UU(i + 1, j), W(i - 2, j), W(i - 1, j), wc, W(i + 1, j), nih);
+    fyt = flux_std(VV(i, j - 1), VV(i, j), VV(i, j + 1), VV(i, j + 2), W(i, j - 1), wc, W(i, j + 1), W(i, j + 2), nih);
+    fyb = flux_std(VV(i, j - 2), VV(i, j - 1), VV(i, j), VV(i, j + 1), W(i, j - 2), W(i, j - 1), wc, W(i, j + 1), nih);
+  }
   const double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
   if (mode == 0) {
     out[q] = rhs;
@@ -886,10 +908,9 @@ void launch_transport(const DGeom& g, const double* omega, const double* U, cons
                       const double* w3b, const double* w3n, double* out, double* Q, double a, double b, double dt,
                       int mode, hipStream_t s, Prof* prof) {
   dim3 grid((g.nx + 255) / 256, g.ny);
-  const int h = prof ? prof->begin(KID_TRANSPORT, s) : -1;
-  k_transport_bulk<<<grid, 256, 0, s>>>(g, omega, U, V, out, Q, a, b, dt, mode);
   // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
-  if (prof) prof->end(h, 48.0 * g.nx * g.ny, s);
+  IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_bulk, grid, 256, s, g, omega, U, V, out, Q, a, b,
+             dt, mode);
   if (g.nsp) k_transport_special<<<(g.nsp + 127) / 128, 128, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
 }
 
@@ -1018,20 +1039,33 @@ void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, h
 // x[p] = sum_q Mt[q][p] b[q]   (Mt = transpose of the inverse, row-major)
 __global__ void __launch_bounds__(256) k_gemv_t(const double* __restrict__ Mt, int n, const double* __restrict__ b,
                                                 double* __restrict__ x) {
-  // each block: 64 outputs x 4 slices of q, reduced through LDS
-  __shared__ double part[4][64];
-  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int p = blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (p < n)
-    for (int q = sl; q < n; q += 4) acc += Mt[(size_t)q * n + p] * b[q];
-  part[sl][lane] = acc;
+  // 16 outputs per block, 16 slices of the sum per output, reduced through LDS
+  __shared__ double part[16][17];
+  const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int p = blockIdx.x * 16 + lo;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (p < n) {
+    int q = sl;
+    for (; q + 48 < n; q += 64) {
+      a0 += Mt[(size_t)q * n + p] * b[q];
+      a1 += Mt[(size_t)(q + 16) * n + p] * b[q + 16];
+      a2 += Mt[(size_t)(q + 32) * n + p] * b[q + 32];
+      a3 += Mt[(size_t)(q + 48) * n + p] * b[q + 48];
+    }
+    for (; q < n; q += 16) a0 += Mt[(size_t)q * n + p] * b[q];
+  }
+  part[sl][lo] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (sl == 0 && p < n) x[p] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+  if (sl == 0 && p < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += part[k][lo];
+    x[p] = t;
+  }
 }
 
 void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s) {
-  k_gemv_t<<<(n + 63) / 64, 256, 0, s>>>(Mt, n, b, x);
+  k_gemv_t<<<(n + 15) / 16, 256, 0, s>>>(Mt, n, b, x);
 }
 
 __global__ void k_unit(double* v, int n, int q) {
@@ -1055,14 +1089,25 @@ template <int N>
 struct RP;
 template <> struct RP<256> { static constexpr int T = 64, E = 4; };
 template <> struct RP<512> { static constexpr int T = 64, E = 8; };
-template <> struct RP<1024> { static constexpr int T = 64, E = 16; };
+#ifndef IIM_FFT1024_THREADS
+#define IIM_FFT1024_THREADS 128
+#endif
+template <> struct RP<1024> { static constexpr int T = IIM_FFT1024_THREADS, E = 1024 / IIM_FFT1024_THREADS; };
 template <> struct RP<2048> { static constexpr int T = 128, E = 16; };
 template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
 
-template <int N>
+#ifndef IIM_ROW_FFTS_PER_BLOCK
+#define IIM_ROW_FFTS_PER_BLOCK 4
+#endif
+#ifndef IIM_COL_FFTS_PER_BLOCK
+#define IIM_COL_FFTS_PER_BLOCK 4
+#endif
+// FFTs per block: ROWS for the row passes, otherwise the column pass
+template <int N, bool ROWS = false>
 struct RegCfg {
   static constexpr int T = RP<N>::T;
-  static constexpr int PER = 256 / T;              // FFTs per block
+  static constexpr int WANT = ROWS ? IIM_ROW_FFTS_PER_BLOCK : IIM_COL_FFTS_PER_BLOCK;
+  static constexpr int PER = (WANT * T > 256) ? (256 / T > 0 ? 256 / T : 1) : WANT;
   static constexpr int THREADS = PER * T;
   static constexpr int LDSN = N + N / 16 + 1;      // padded length (one pad slot per 16 points)
 };
@@ -1204,9 +1249,20 @@ __device__ __forceinline__ void fft_reg(double2 (&v)[RP<N>::E], double2* lds, in
     reg_pass<N, T, E, 8, 1, INV, false>(v, lds, t, tw);
     reg_pass<N, T, E, 8, 8, INV, false>(v, lds, t, tw);
     reg_pass<N, T, E, 8, 64, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 1024) {
+  } else if constexpr (N == 1024 && E == 16) {
     reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
     reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 256, INV, true>(v, lds, t, tw);
+  } else if constexpr (N == 1024 && E == 8) {
+    reg_pass<N, T, E, 8, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 8, 8, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 8, 64, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 2, 512, INV, true>(v, lds, t, tw);
+  } else if constexpr (N == 1024 && E == 4) {
+    reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 4, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 16, INV, false>(v, lds, t, tw);
+    reg_pass<N, T, E, 4, 64, INV, false>(v, lds, t, tw);
     reg_pass<N, T, E, 4, 256, INV, true>(v, lds, t, tw);
   } else if constexpr (N == 2048) {
     reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
@@ -1273,10 +1329,10 @@ __device__ __forceinline__ void add_at(double2 (&v)[RP<HX>::E], int t, int i, do
 }
 
 template <int HX>
-__global__ void __launch_bounds__(RegCfg<HX>::THREADS)
+__global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
 k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
                int j0, int count, const double* __restrict__ done) {
-  using C = RegCfg<HX>;
+  using C = RegCfg<HX, true>;
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
   __shared__ double2 lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
@@ -1339,9 +1395,9 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
 
 // ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
 template <int HX>
-__global__ void __launch_bounds__(RegCfg<HX>::THREADS)
+__global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
 k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
-  using C = RegCfg<HX>;
+  using C = RegCfg<HX, true>;
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
   __shared__ double2 lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
@@ -1393,24 +1449,27 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
 
 template <int HX>
 void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0,
-                         int count, const double* done, hipStream_t s) {
-  using C = RegCfg<HX>;
+                         int count, const double* done, hipStream_t s, Prof* prof, double bytes) {
+  using C = RegCfg<HX, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
-  if (blocks > 0) k_rows_fwd_reg<HX><<<blocks, C::THREADS, 0, s>>>(g, f, omega, gam, sgn, j0, count, done);
+  if (blocks > 0)
+    IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX>, blocks, C::THREADS, s, g, f, omega, gam, sgn, j0,
+               count, done);
 }
 template <int MY>
 void cols_reg_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
-                     hipStream_t s) {
+                     hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<MY>;
   const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  k_cols_reg<MY><<<blocks, C::THREADS, 0, s>>>(g, f, rj0, rj1, oj0, oj1, done);
+  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY>, blocks, C::THREADS, s, g, f, rj0, rj1, oj0, oj1, done);
 }
 template <int HX>
 void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
-                         hipStream_t s) {
-  using C = RegCfg<HX>;
+                         hipStream_t s, Prof* prof, double bytes) {
+  using C = RegCfg<HX, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
-  if (blocks > 0) k_rows_inv_reg<HX><<<blocks, C::THREADS, 0, s>>>(g, f, j0, count, psi, done);
+  if (blocks > 0)
+    IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX>, blocks, C::THREADS, s, g, f, j0, count, psi, done);
 }
 
 #define IIM_REG_SWITCH(VAL, FN, ...)                \
@@ -1428,15 +1487,14 @@ bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
   const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
-  int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
-  IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, g, f, omega, gam, sgn, rj0, nin, done, s);
-  if (prof) prof->end(h, (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
-  h = prof ? prof->begin(KID_COLS, s) : -1;
-  IIM_REG_SWITCH(f.my, cols_reg_launch, g, f, rj0, rj1, oj0, oj1, done, s);
-  if (prof) prof->end(h, (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
-  h = prof ? prof->begin(KID_ROWS_INV, s) : -1;
-  IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, g, f, oj0, nout, psi_ring, done, s);
-  if (prof) prof->end(h, (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2)), s);
+  // algorithmic bytes: source rows read (omega) + half spectrum written;
+  // spectrum rows in + kernel spectrum + rows out; half spectrum in + ring rows out
+  const double b_fwd = (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1));
+  const double b_col = (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout);
+  const double b_inv = (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2));
+  IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
+  IIM_REG_SWITCH(f.my, cols_reg_launch, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
+  IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
 }
 
 }  // namespace iim

@@ -90,7 +90,9 @@ def test_rk3_step(name, solver):
     dt = w.dt if w.dt > 0 else 0.5 * ONS.dt_max(w.grid.h, w.grid.nu, 3.0)
     st = ONS.Stepper(geo)
     om_ref, G_ref = st.step(om, G, dt)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-13, solver=solver)
+    # GMRES stops at a true relative residual of 1e-12 here: the nonconvex
+    # two-body Schur system reaches its rounding floor near 1e-13
+    ctx = iim.Context(w.grid, w.bodies, tol=1e-12, solver=solver)
     omd = to_dev(om)
     G_gpu, stats = ctx.rk3_steps(omd, G, dt, 1)
     torch.cuda.synchronize()
