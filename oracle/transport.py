@@ -24,7 +24,9 @@ Boundary treatment (Sec. 3.2):
 
 Domain edges in free space (our reading): nodes outside the grid carry
 omega = 0 and count as fluid for the choice of stencil; the face velocity
-at the outermost face uses the exact ring velocity.
+at the outermost face uses the exact ring velocity.  With an outflow plane
+at the face x_{nx-1/2} (Sec. 5.2) the two nodes past it carry the mirrored
+vorticity and x-velocity instead.
 
 Boundary vorticity omega_b at each control point: the stencil of
 Geometry.vorticity_bc_stencil applied to the extended velocity.
@@ -79,6 +81,12 @@ def _padded(geom, omega, U, V, e4b, e3b, e3n):
     u, v = P(0.0), P(0.0)
     u[1:-1, 1:-1] = U
     v[1:-1, 1:-1] = V
+    if geom.grid.exterior == "outflow":
+        # even mirror of the vorticity and of u_x across the face x_{nx-1/2} (Sec. 5.2):
+        # node nx+m carries the values of node nx-1-m; the outflow faces use them
+        w[2:-2, nx + 2] = w[2:-2, nx + 1]
+        w[2:-2, nx + 3] = w[2:-2, nx]
+        u[2:-2, nx + 3] = u[2:-2, nx]
     return cls, w, w4, w3b, w3n, u, v
 
 

@@ -155,6 +155,7 @@ void setup_device(iim_ctx* c) {
   d.nbc = g.nbc();
   d.nsp = (int)g.special.size();
   d.n = g.na + g.nbc();
+  d.outflow = g.grid.exterior == IIM_EXT_OUTFLOW ? 1 : 0;
   // classes: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
   std::vector<int8_t> cls(N);
   for (size_t q = 0; q < N; ++q) cls[q] = g.cls[q] == CLS_FLUID ? 0 : (g.cls[q] == CLS_GHOST ? 2 : 3);

@@ -30,6 +30,7 @@ struct DGeom {
   double uinf_x, uinf_y;
   int nc, ng, na, nbc, nsp;
   int n;                       // Krylov unknowns: na + nbc
+  int outflow;                 // 1: even mirror plane at the face x_{nx-1/2}
   const int8_t* cls;           // [ny][nx]: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
   const int* g_ridx;           // ghost -> ring index
   const int* g_gidx;           // ghost -> grid index

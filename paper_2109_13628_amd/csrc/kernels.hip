@@ -788,6 +788,11 @@ __device__ double flux_general(const DGeom& g, const double* __restrict__ omega,
     if (!in) {
       kind[t] = NK_OUT;
       w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
+      if (g.outflow && ii >= g.nx && ii <= g.nx + 1 && jj >= 0 && jj < g.ny) {
+        const int im = 2 * g.nx - 1 - ii;   // mirror across the outflow face
+        w[t] = w4v[t] = wb[t] = wn[t] = omega[jj * g.nx + im];
+        if (axis == 0 && ii == g.nx + 1) u[t] = vel[(jj + 1) * nxr + im + 1];
+      }
     } else {
       const int q = jj * g.nx + ii;
       const int c = g.cls[q];
@@ -858,8 +863,14 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
     fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
   } else {
     // near the grid edge: nodes outside carry omega = 0; velocities come from the ring
-    auto W = [&](int ii, int jj) { return (ii >= 0 && jj >= 0 && ii < nx && jj < ny) ? omega[jj * nx + ii] : 0.0; };
+    // with an outflow plane at x_{nx-1/2}, nodes nx, nx+1 mirror nx-1, nx-2 (omega and u_x even)
+    const bool mir = g.outflow != 0;
+    auto W = [&](int ii, int jj) {
+      if (mir && ii >= nx && ii <= nx + 1 && jj >= 0 && jj < ny) ii = 2 * nx - 1 - ii;
+      return (ii >= 0 && jj >= 0 && ii < nx && jj < ny) ? omega[jj * nx + ii] : 0.0;
+    };
     auto UU = [&](int ii, int jj) {
+      if (mir && ii == nx + 1) ii = nx - 2;
       return (ii >= -1 && jj >= -1 && ii <= nx && jj <= ny) ? U[(jj + 1) * nxr + ii + 1] : 0.0;
     };
     auto VV = [&](int ii, int jj) {

@@ -21,10 +21,11 @@ SMALL = {
     "tc128": lambda: wl.taylor_couette(128),
     "cyl_small": wl.cylinder_small,
     "two_c_128": lambda: wl.two_c_shapes_lamb_oseen(128),
+    "cyl_outflow": wl.cylinder_outflow_small,
 }
 
 
-@pytest.mark.parametrize("name", ["tc64", "cyl_small", "two_c_128"])
+@pytest.mark.parametrize("name", ["tc64", "cyl_small", "two_c_128", "cyl_outflow"])
 def test_poisson_operator(name):
     w = SMALL[name]()
     ctx = iim.Context(w.grid, w.bodies)
@@ -36,7 +37,7 @@ def test_poisson_operator(name):
     if w.grid.exterior == "box":
         ref = OP.box_dirichlet(src, w.grid.h)
     else:
-        ref = OP.FreeSpace(w.grid.nx, w.grid.ny, w.grid.h)(src)
+        ref = OP.FreeSpace(w.grid.nx, w.grid.ny, w.grid.h, outflow=w.grid.exterior == "outflow")(src)
     got = psi.cpu().numpy()
     assert rel(got, ref) < 1e-13, rel(got, ref)
 
@@ -82,7 +83,7 @@ def test_rhs(name):
 
 
 @pytest.mark.parametrize("solver", [iim.SOLVER_KRYLOV, iim.SOLVER_DIRECT])
-@pytest.mark.parametrize("name", ["tc128", "cyl_small", "two_c_128"])
+@pytest.mark.parametrize("name", ["tc128", "cyl_small", "two_c_128", "cyl_outflow"])
 def test_rk3_step(name, solver):
     w = SMALL[name]()
     geo = OG.Geometry(w.grid, w.bodies)

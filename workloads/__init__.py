@@ -211,3 +211,57 @@ def seeded_vortices(grid: GridDesc, seed: int, count=6, box=None, amp=2.0, width
 def seeded_gammas(n_bodies: int, seed: int, scale=0.5):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-scale, scale, size=n_bodies)
+
+
+def cylinder_outflow_small():
+    """The small free-space cylinder with an outflow plane at the x_max face."""
+    w = cylinder_small()
+    w.grid.exterior = EXT_OUTFLOW
+    w.name = w.name.replace("_free", "_outflow")
+    return w
+
+
+def multi_body(n=2048, seed=3, steps=500):
+    """Four seeded nonconvex/elongated bodies in a uniform stream on [0,1]^2
+    with an outflow plane at x = 1: two ellipses (aspect 1.5-3) and two
+    C-shaped arcs (gap angle 60-120 degrees), outer sizes 0.05-0.15, centres in
+    [0.1,0.55] x [0.15,0.85], kept apart by rejection on their bounding
+    circles.  Re ~ U[200, 1000] with nu = 0.1/Re (length scale 0.1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 1.0 / n
+    re = rng.uniform(200.0, 1000.0)
+    nu = 0.1 / re
+    grid = GridDesc(nx=n, ny=n, x0=0.5 * h, y0=0.5 * h, h=h, exterior=EXT_OUTFLOW,
+                    u_inf=(1.0, 0.0), nu=nu)
+    placed = []          # (cx, cy, R)
+    bodies = []
+    kinds = ["ellipse", "ellipse", "c", "c"]
+    for kind in kinds:
+        for _ in range(1000):
+            size = rng.uniform(0.05, 0.15)          # outer extent (diameter)
+            R = 0.5 * size
+            cx = rng.uniform(0.1, 0.55)
+            cy = rng.uniform(0.15, 0.85)
+            if all(np.hypot(cx - px, cy - py) > R + pR + 0.03 for (px, py, pR) in placed):
+                break
+        placed.append((cx, cy, R))
+        if kind == "ellipse":
+            aspect = rng.uniform(1.5, 3.0)
+            a, b = R, R / aspect
+            ang = rng.uniform(0.0, np.pi)
+            per = np.pi * (3 * (a + b) - np.sqrt((3 * a + b) * (a + 3 * b)))
+            pts = ellipse_points((cx, cy), a, b, ang, max(256, int(np.ceil(2 * per / h))))
+        else:
+            thick = rng.uniform(0.2, 0.35)           # thickness / centre-line radius
+            ra = R / (1.0 + 0.5 * thick)             # outer radius = ra + rb = R
+            rb = 0.5 * thick * ra
+            gap = np.deg2rad(rng.uniform(60.0, 120.0))
+            theta_a = rng.uniform(0.0, 2 * np.pi)
+            theta_b = 2 * np.pi - gap
+            per = 2 * np.pi * ra * 2 + 2 * np.pi * rb
+            pts = c_shape_points((cx, cy), ra, rb, theta_a, theta_b, max(256, int(np.ceil(2 * per / h))))
+        bodies.append(BodyDesc(points=pts, center=(cx, cy)))
+    a_max = 2.0 * np.sqrt(2.0)
+    dt = dt_from_polygon(h, nu, a_max, 0.5)
+    return Workload("multi_body_%d_outflow_seed%d" % (n, seed), grid, bodies, dt, steps,
+                    extra={"Re": re})
