@@ -64,7 +64,18 @@ enum {
 };
 
 enum { IIM_PREC_FP64 = 0, IIM_PREC_MIXED = 1 };
-enum { IIM_GUESS_ZERO = 0, IIM_GUESS_PREVIOUS = 1 };
+/* Initial guess of each Schur solve:
+ *   ZERO        x = 0;
+ *   PREVIOUS    the solution of the previous solve (previous RK stage);
+ *   EXTRAPOLATE the line through the last two solutions extended to the
+ *               current stage time (stages at t + c dt, c = 0, 1/3, 3/4; needs
+ *               two earlier solves of the same run at a fixed dt);
+ *   NETWORK     EXTRAPOLATE plus the correction predicted by a trained
+ *               network (iim_set_warm_start), kept only when its residual is
+ *               below that of PREVIOUS; needs three earlier solves.
+ * Modes that lack their history fall back to PREVIOUS (ZERO on the first
+ * solve).  With IIM_SOLVER_DIRECT the guess is not used. */
+enum { IIM_GUESS_ZERO = 0, IIM_GUESS_PREVIOUS = 1, IIM_GUESS_EXTRAPOLATE = 2, IIM_GUESS_NETWORK = 3 };
 /* Schur-system solver: GMRES with the FFT matrix-vector product (the paper's
  * iterative solve), or the dense inverse of the Schur matrix built once at
  * create (bodies are fixed, so the matrix is too). */
@@ -206,6 +217,80 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
 int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
 int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
+
+/* ---- learned initial guess ----
+ * A stack of circular 1D convolutions (kernel 5) with tanh-approximated GELU
+ * between layers; the last layer has one output channel.  Layer l maps
+ * lin[l] -> lout[l] channels with weights W_l[(tap*lin + ci)*lout + co] and
+ * bias b_l[co]; output position p reads input positions (p + tap - 2) mod L
+ * of its own sequence.  The flat parameter array is W_0, b_0, W_1, b_1, ...
+ * Products run on the matrix cores with BF16 operands and FP32 accumulation
+ * (bf16 = 1) or with FP32 operands (bf16 = 0).
+ *
+ * Ragged sequence batches: x_dev is float [batch][P][in_channels]; seq_dev is
+ * int32 [3][P] on the device: for position p, the start of its sequence, the
+ * sequence length and p's index inside it.  Outputs are float [batch][P]. */
+typedef struct iim_net iim_net;
+#define IIM_NET_FEATURES 10   /* input channels of the initial-guess network */
+typedef struct {
+  int32_t in_channels;    /* IIM_NET_FEATURES for use with iim_set_warm_start */
+  int32_t width;          /* hidden channels */
+  int32_t layers;         /* number of convolutions (>= 1) */
+  int32_t bf16;           /* 1: BF16 operands, FP32 accumulation; 0: FP32 operands */
+  uint64_t seed;          /* He-uniform initialisation of the weights, zero biases */
+} iim_net_desc;
+
+/* Create / destroy a network; work is enqueued on hip_stream. */
+int iim_net_create(const iim_net_desc* desc, void* hip_stream, iim_net** out);
+int iim_net_destroy(iim_net* net);
+int64_t iim_net_num_params(const iim_net* net);
+/* which = 0: parameters, 1: gradients of the last iim_net_grad_mse; n must
+ * equal iim_net_num_params.  Synchronises the network's stream. */
+int iim_net_get_params(const iim_net* net, int32_t which, float* host, int64_t n);
+/* Replace the parameters (and reset the Adam moments). */
+int iim_net_set_params(iim_net* net, const float* host, int64_t n);
+int iim_net_forward(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                    float* y_dev);
+/* Gradients of mean((y - target)^2) over batch*P outputs; loss_host
+ * (nullable) receives the loss. */
+int iim_net_grad_mse(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                     const float* target_dev, float* loss_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * current gradients. */
+int iim_net_adam_step(iim_net* net, float lr);
+int iim_net_save(const iim_net* net, const char* path);
+int iim_net_load(iim_net* net, const char* path);
+
+/* Select the initial guess (IIM_GUESS_*) of the context's Krylov solves;
+ * net is required for IIM_GUESS_NETWORK (in_channels IIM_NET_FEATURES, one
+ * output channel) and must outlive its use.  Not owned. */
+int iim_set_warm_start(iim_ctx* ctx, int32_t guess, iim_net* net);
+/* Record the right-hand side and the solution of every solve made inside an
+ * RK step (up to capacity solves, device memory 2 * capacity * (|A| + n_circ)
+ * doubles); capacity 0 stops recording.  Restarts the record. */
+int iim_record_solves(iim_ctx* ctx, int32_t capacity);
+/* Train net on the recorded solves: each sample is a recorded solve with
+ * three predecessors of the same run; the loss is the mean square, over the
+ * affected points, of the network output minus (x - x_base) / s_r, where x
+ * is the recorded solution, x_base the extrapolated guess and s_r the RMS of
+ * its residual over the corrections.  iters Adam steps with `batch` samples
+ * drawn with the seed; loss_host (nullable, [iters]) receives the loss of
+ * every step.  Errors: IIM_EINVAL when no recorded solve qualifies. */
+int iim_warm_start_train(iim_ctx* ctx, iim_net* net, int32_t iters, int32_t batch, float lr, uint64_t seed,
+                         float* loss_host);
+/* Start a new run: the next solves do not extrapolate from, and recorded
+ * samples do not reach back to, the solves made so far (call when the state
+ * is replaced by one that does not continue the previous steps). */
+int iim_reset_history(iim_ctx* ctx);
+/* Counters: solves recorded; network guesses kept and rejected; matrix-vector
+ * products spent on initial residuals (not counted as Krylov iterations). */
+int iim_warm_start_stats(const iim_ctx* ctx, int64_t* recorded, int64_t* net_used, int64_t* net_rejected,
+                         int64_t* extra_matvecs);
+/* The network's input ordering for this context: P positions, perm_host[P]
+ * (affected index of each position), seq_host[3][P] (as seq_dev above) and
+ * geo_host[P][4] (ghost flag, boundary tangent x, y, signed distance / h).
+ * Any output pointer may be NULL. */
+int iim_warm_start_sequences(iim_ctx* ctx, int32_t* P, int32_t* perm_host, int32_t* seq_host, float* geo_host);
 
 #ifdef __cplusplus
 }

@@ -83,3 +83,29 @@ def loss_and_grads(params, X, T):
         grads[li] = (dW, db)
         dY = dX
     return loss, grads
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) at step t >= 1; returns the
+    new (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def flatten(params):
+    """Parameters as one array: W_0, b_0, W_1, b_1, ... (row-major W)."""
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params])
+
+
+def unflatten(flat, sizes):
+    params, off = [], 0
+    for cin, cout in zip(sizes[:-1], sizes[1:]):
+        W = flat[off:off + TAPS * cin * cout].reshape(TAPS * cin, cout)
+        off += TAPS * cin * cout
+        b = flat[off:off + cout]
+        off += cout
+        params.append((W, b))
+    return params

@@ -21,13 +21,18 @@ IIM_OK, IIM_EINVAL, IIM_ENOMEM, IIM_EGEOM, IIM_ENOCONV, IIM_ENONFINITE, IIM_EDEV
     0, -1, -2, -3, -4, -5, -6, -7
 EXT = {"box": 0, "free": 1, "outflow": 2}
 PREC_FP64, PREC_MIXED = 0, 1
-GUESS_ZERO, GUESS_PREVIOUS = 0, 1
+GUESS_ZERO, GUESS_PREVIOUS, GUESS_EXTRAPOLATE, GUESS_NETWORK = 0, 1, 2, 3
+NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_reconstruct", "iim_rhs",
-           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals"]
+           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals",
+           "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
+           "iim_net_forward", "iim_net_grad_mse", "iim_net_adam_step", "iim_net_save", "iim_net_load",
+           "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
+           "iim_warm_start_sequences", "iim_reset_history"]
 KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport_bulk", "arnoldi"]
 
 
@@ -66,6 +71,11 @@ class StepStats(C.Structure):
     def as_dict(self):
         return {"iters": list(self.iters), "refine_rounds": list(self.refine_rounds),
                 "res0": list(self.res0), "res": list(self.res), "converged": bool(self.converged)}
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("in_channels", C.c_int32), ("width", C.c_int32), ("layers", C.c_int32), ("bf16", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class Info(C.Structure):
@@ -127,6 +137,39 @@ def lib():
     L.iim_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
     L.iim_krylov_totals.restype = ip
     L.iim_krylov_totals.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    i64p = C.POINTER(C.c_int64)
+    L.iim_net_create.restype = ip
+    L.iim_net_create.argtypes = [C.POINTER(NetDesc), vp, C.POINTER(vp)]
+    L.iim_net_destroy.restype = ip
+    L.iim_net_destroy.argtypes = [vp]
+    L.iim_net_num_params.restype = C.c_int64
+    L.iim_net_num_params.argtypes = [vp]
+    L.iim_net_get_params.restype = ip
+    L.iim_net_get_params.argtypes = [vp, C.c_int32, vp, C.c_int64]
+    L.iim_net_set_params.restype = ip
+    L.iim_net_set_params.argtypes = [vp, vp, C.c_int64]
+    L.iim_net_forward.restype = ip
+    L.iim_net_forward.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp]
+    L.iim_net_grad_mse.restype = ip
+    L.iim_net_grad_mse.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_float)]
+    L.iim_net_adam_step.restype = ip
+    L.iim_net_adam_step.argtypes = [vp, C.c_float]
+    L.iim_net_save.restype = ip
+    L.iim_net_save.argtypes = [vp, C.c_char_p]
+    L.iim_net_load.restype = ip
+    L.iim_net_load.argtypes = [vp, C.c_char_p]
+    L.iim_set_warm_start.restype = ip
+    L.iim_set_warm_start.argtypes = [vp, C.c_int32, vp]
+    L.iim_record_solves.restype = ip
+    L.iim_record_solves.argtypes = [vp, C.c_int32]
+    L.iim_warm_start_train.restype = ip
+    L.iim_warm_start_train.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp]
+    L.iim_warm_start_stats.restype = ip
+    L.iim_warm_start_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
+    L.iim_reset_history.restype = ip
+    L.iim_reset_history.argtypes = [vp]
+    L.iim_warm_start_sequences.restype = ip
+    L.iim_warm_start_sequences.argtypes = [vp, C.POINTER(C.c_int32), vp, vp, vp]
     _lib = L
     return L
 
@@ -270,3 +313,110 @@ class Context:
         self._check(lib().iim_rk3_steps(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                         n_steps, C.byref(st)), "iim_rk3_steps")
         return G[:self.n_circ], st.as_dict()
+
+    # ---- learned initial guess
+    def set_warm_start(self, guess, net=None):
+        self._check(lib().iim_set_warm_start(self._h, int(guess), net._h if net is not None else None),
+                    "iim_set_warm_start")
+        self._net = net   # keep the network alive while the context uses it
+
+    def reset_history(self):
+        self._check(lib().iim_reset_history(self._h), "iim_reset_history")
+
+    def record_solves(self, capacity):
+        self._check(lib().iim_record_solves(self._h, int(capacity)), "iim_record_solves")
+
+    def warm_start_train(self, net, iters, batch, lr, seed=0):
+        losses = np.zeros(iters, dtype=np.float32)
+        self._check(lib().iim_warm_start_train(self._h, net._h, iters, batch, lr, seed,
+                                               losses.ctypes.data_as(C.c_void_p)), "iim_warm_start_train")
+        return losses
+
+    def warm_start_stats(self):
+        v = [C.c_int64() for _ in range(4)]
+        self._check(lib().iim_warm_start_stats(self._h, *[C.byref(x) for x in v]), "iim_warm_start_stats")
+        return dict(zip(("recorded", "net_used", "net_rejected", "extra_matvecs"), (x.value for x in v)))
+
+    def warm_start_sequences(self):
+        P = C.c_int32()
+        self._check(lib().iim_warm_start_sequences(self._h, C.byref(P), None, None, None), "iim_warm_start_sequences")
+        n = P.value
+        perm = np.zeros(n, dtype=np.int32)
+        seq = np.zeros(3 * n, dtype=np.int32)
+        geo = np.zeros(4 * n, dtype=np.float32)
+        self._check(lib().iim_warm_start_sequences(self._h, C.byref(P), perm.ctypes.data_as(C.c_void_p),
+                                                    seq.ctypes.data_as(C.c_void_p), geo.ctypes.data_as(C.c_void_p)),
+                    "iim_warm_start_sequences")
+        return perm, seq.reshape(3, n), geo.reshape(n, 4)
+
+
+def _fptr(t, dtype_name="float32"):
+    import torch
+    want = {"float32": torch.float32, "int32": torch.int32}[dtype_name]
+    if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise ValueError("expected a contiguous %s CUDA tensor" % dtype_name)
+    return C.c_void_p(t.data_ptr())
+
+
+class Network:
+    """Stack of circular 1D convolutions (kernel 5, GELU between layers, one
+    output channel) run by the library's matrix-core kernels."""
+
+    def __init__(self, in_channels=NET_FEATURES, width=128, layers=4, bf16=True, seed=0, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        d = NetDesc(in_channels=in_channels, width=width, layers=layers, bf16=int(bf16), seed=seed)
+        h = C.c_void_p()
+        rc = lib().iim_net_create(C.byref(d), C.c_void_p(stream or 0), C.byref(h))
+        if rc:
+            raise IIMError(rc, "iim_net_create")
+        self._h = h
+        self.shape = (in_channels, width, layers)
+        self.nparam = lib().iim_net_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iim_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            raise IIMError(rc, what)
+
+    def get(self, which=0):
+        out = np.zeros(self.nparam, dtype=np.float32)
+        self._check(lib().iim_net_get_params(self._h, which, out.ctypes.data_as(C.c_void_p), self.nparam),
+                    "iim_net_get_params")
+        return out
+
+    def set(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(lib().iim_net_set_params(self._h, flat.ctypes.data_as(C.c_void_p), flat.size),
+                    "iim_net_set_params")
+
+    def forward(self, x, seq, y):
+        B, P = x.shape[0], x.shape[1]
+        self._check(lib().iim_net_forward(self._h, _fptr(x), B, P, _fptr(seq, "int32"), _fptr(y)), "iim_net_forward")
+
+    def grad_mse(self, x, seq, target):
+        B, P = x.shape[0], x.shape[1]
+        loss = C.c_float()
+        self._check(lib().iim_net_grad_mse(self._h, _fptr(x), B, P, _fptr(seq, "int32"), _fptr(target),
+                                           C.byref(loss)), "iim_net_grad_mse")
+        return loss.value
+
+    def adam_step(self, lr):
+        self._check(lib().iim_net_adam_step(self._h, lr), "iim_net_adam_step")
+
+    def save(self, path):
+        self._check(lib().iim_net_save(self._h, path.encode()), "iim_net_save")
+
+    def load(self, path):
+        self._check(lib().iim_net_load(self._h, path.encode()), "iim_net_load")

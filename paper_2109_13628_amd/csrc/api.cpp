@@ -15,6 +15,7 @@
 #include "iim.h"
 #include "iim_dev.hpp"
 #include "iim_host.hpp"
+#include "ctx.hpp"
 
 using namespace iim;
 
@@ -26,19 +27,6 @@ thread_local std::string g_create_error;
 const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-struct HipError : std::runtime_error {
-  int code;
-  HipError(const std::string& m, int c) : std::runtime_error(m), code(c) {}
-};
-
-#define HIPCHK(x)                                                                                   \
-  do {                                                                                              \
-    hipError_t e_ = (x);                                                                            \
-    if (e_ != hipSuccess)                                                                           \
-      throw HipError(std::string(#x) + ": " + hipGetErrorString(e_),                                \
-                     e_ == hipErrorOutOfMemory ? IIM_ENOMEM : IIM_EDEVICE);                         \
-  } while (0)
-
 int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -46,65 +34,6 @@ int next_pow2(int v) {
 }
 
 }  // namespace
-
-struct iim_ctx {
-  std::string err;
-  Geometry geo;
-  bool host_only = false;
-  hipStream_t stream = nullptr;
-  int precision = IIM_PREC_FP64;
-  double tol = 1e-13;
-  int max_iter = 400, restart = 40, guess = IIM_GUESS_PREVIOUS, chunk = 4;
-  std::vector<void*> allocs;
-  size_t dev_bytes = 0;
-  DGeom dg{};
-  DFft df{};
-  DDst dd{};
-  DKrylov dk{};
-  bool box = false;
-  int8_t* cls_zero = nullptr;
-  double *psi = nullptr, *U = nullptr, *V = nullptr;
-  double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
-  double *Qw = nullptr, *wtmp = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
-  double* st_host = nullptr;
-  bool have_prev = false;
-  int solver = IIM_SOLVER_KRYLOV;
-  double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
-  // one RK3 step captured as a HIP graph (direct solver): replayed while the
-  // omega buffer and dt stay the same
-  hipStream_t gstream = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double* g_omega = nullptr;
-  double g_dt = 0.0;
-  bool use_graph = true;
-  long n_solves = 0, n_matvecs = 0;
-  Prof prof;
-  // host copies for the geometry view
-  std::vector<double> v_cxy, v_cn;
-  std::vector<int32_t> v_cint, v_aint, v_rects, v_circ;
-
-  template <class T>
-  T* dalloc(size_t n) {
-    if (n == 0) n = 1;
-    void* p = nullptr;
-    HIPCHK(hipMalloc(&p, n * sizeof(T)));
-    allocs.push_back(p);
-    dev_bytes += n * sizeof(T);
-    return (T*)p;
-  }
-  template <class T>
-  T* upload(const std::vector<T>& v) {
-    T* p = dalloc<T>(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return p;
-  }
-  ~iim_ctx() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (gstream) (void)hipStreamDestroy(gstream);
-    for (void* p : allocs) (void)hipFree(p);
-    if (st_host) (void)hipHostFree(st_host);
-  }
-};
 
 // ---------------------------------------------------------------- helpers
 namespace {
@@ -323,8 +252,10 @@ void setup_device(iim_ctx* c) {
   HIPCHK(hipDeviceSynchronize());
 }
 
+}  // namespace
+
 // psi (ring) = G(source), source = mask(omega) + sgn * E_a gam, rows [rj0, rj1] -> [oj0, oj1]
-void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
+void iim::apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
              int oj0, int oj1, double* psi, const double* done) {
   if (c->box)
     launch_dst(dg, c->dd, omega, gam, sgn, psi, done, c->stream);
@@ -333,12 +264,13 @@ void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam
                 c->prof.mask ? &c->prof : nullptr);
 }
 
-void read_status(iim_ctx* c) {
+
+void iim::read_status(iim_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->st_host, c->dk.st, KS_SIZE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
-void set_status(iim_ctx* c) {
+void iim::set_status(iim_ctx* c) {
   double st[KS_SIZE] = {0};
   st[KS_DONE] = 0.0;
   st[KS_RES0] = -1.0;
@@ -348,20 +280,29 @@ void set_status(iim_ctx* c) {
 }
 
 // Dense Schur matrix, column by column through the same operator as the
-// Krylov matrix-vector product (columns S e_q), then inverted on the device.
-void build_direct(iim_ctx* c) {
+// Krylov matrix-vector product: St[q] = S e_q (so St holds S^T, row-major).
+void iim::build_schur_t(iim_ctx* c, double* St) {
   const Geometry& g = c->geo;
   DKrylov& k = c->dk;
   const int n = k.n;
-  if (n == 0) return;
-  c->Sinv_t = c->dalloc<double>((size_t)n * n);
-  double* e = c->dalloc<double>(n);
+  if ((size_t)n > (size_t)g.grid.nx * g.grid.ny) throw ArgError("more Schur unknowns than grid nodes");
+  double* e = c->wtmp;  // unit vectors (n <= nx * ny)
   for (int q = 0; q < n; ++q) {
     launch_unit(e, n, q, c->stream);
     apply_G(c, c->dg, nullptr, e, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
-    launch_matvec_finish(c->dg, k, c->psi, e, c->Sinv_t + (size_t)q * n, c->stream);
+    launch_matvec_finish(c->dg, k, c->psi, e, St + (size_t)q * n, c->stream);
   }
-  // the buffer holds S^T (row q = column q of S); its inverse is (S^-1)^T
+}
+
+namespace {
+
+// Dense inverse of the Schur matrix (bodies are fixed), built once.
+void build_direct(iim_ctx* c) {
+  const int n = c->dk.n;
+  if (n == 0) return;
+  c->Sinv_t = c->dalloc<double>((size_t)n * n);
+  build_schur_t(c, c->Sinv_t);
+  // the buffer holds S^T; its inverse is (S^-1)^T
   int* perm = c->dalloc<int>(n);
   double* fcol = c->dalloc<double>(n);
   double* info = c->dalloc<double>(1);
@@ -389,18 +330,39 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
     iters = 0;
     res0 = res = 0.0;
     c->n_solves += 1;
+    push_history(c);
     apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
     launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
     return IIM_OK;
   }
   set_status(c);
-  const bool warm = c->guess == IIM_GUESS_PREVIOUS && c->have_prev;
+  // initial guess: zero, the previous solve, its extrapolation in time, or
+  // the extrapolation corrected by the network
+  const int mode = prepare_guess(c);
+  const bool warm = mode != IIM_GUESS_ZERO;
   if (warm) {
     apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
     launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
   }
   launch_krylov_start(dg, k, !warm, c->stream);
   read_status(c);
+  int extra = warm ? 1 : 0;
+  if (mode == IIM_GUESS_NETWORK) {
+    // the residual judges the network: keep its guess only if it beats the
+    // previous-stage guess, whose residual norm is |b - b_previous|
+    if (c->st_host[KS_BETA] > c->st_host[KS_PREVRES]) {
+      ++c->n_net_rejected;
+      restore_previous(c);
+      set_status(c);
+      apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
+      launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
+      launch_krylov_start(dg, k, false, c->stream);
+      read_status(c);
+      ++extra;
+    } else {
+      ++c->n_net_used;
+    }
+  }
   int total = 0;
   // Restarted GMRES.  Every cycle ends by recomputing the true residual
   // b - S x; the solve stops only when that residual meets the tolerance, or
@@ -434,9 +396,11 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   iters = (int)c->st_host[KS_ITERS];
   c->n_solves += 1;
   c->n_matvecs += iters;
+  c->n_extra_matvecs += extra;
   res0 = c->st_host[KS_RES0];
   res = c->st_host[KS_RES];
   c->have_prev = true;
+  push_history(c);
   // psi = G (omega - E_a gamma), ghosts, velocity
   apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
   launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
@@ -455,10 +419,17 @@ int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
   int status = IIM_OK;
   iim_step_stats st{};
   st.converged = 1;
+  if (dt != c->hist_dt) {
+    c->hist_dt = dt;
+    c->hist_count = 0;
+    ++c->run_id;
+  }
   for (int s = 0; s < 3; ++s) {
     int it;
     double r0, r1;
+    c->cur_stage = s;
     const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1);
+    c->cur_stage = -1;
     st.iters[s] = it;
     st.res0[s] = r0;
     st.res[s] = r1;
@@ -597,6 +568,7 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
     }
     if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
     if (c->solver != IIM_SOLVER_KRYLOV && c->solver != IIM_SOLVER_DIRECT) throw ArgError("unknown solver");
+    if (c->guess < IIM_GUESS_ZERO || c->guess > IIM_GUESS_NETWORK) throw ArgError("unknown initial guess");
     build_geometry(c->geo, gs, bs);
     c->stream = (hipStream_t)hip_stream;
     // geometry views
@@ -775,7 +747,7 @@ int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int3
     const int nb = c->geo.nbc();
     if (nb) HIPCHK(hipMemcpyAsync(c->Gd, Gamma_host, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
     int status = IIM_OK;
-    const bool graph = c->use_graph && c->solver == IIM_SOLVER_DIRECT && c->prof.mask == 0;
+    const bool graph = c->use_graph && c->solver == IIM_SOLVER_DIRECT && c->prof.mask == 0 && c->rec_cap == 0;
     for (int s = 0; s < n_steps; ++s) {
       const int rc = graph ? run_step_graph(c, omega, dt, stats) : run_step(c, omega, dt, stats);
       if (rc == IIM_ENONFINITE) return fail(c, rc, "non-finite residual");

@@ -1,0 +1,157 @@
+// The IIM context (an opaque iim_ctx at the ABI) and the network object
+// (iim_net), shared by the C ABI files.  Host-only declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "iim.h"
+#include "iim_dev.hpp"
+#include "iim_host.hpp"
+#include "net_dev.hpp"
+
+namespace iim {
+
+struct HipError : std::runtime_error {
+  int code;
+  HipError(const std::string& m, int c) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess)                                                                           \
+      throw iim::HipError(std::string(#x) + ": " + hipGetErrorString(e_),                           \
+                          e_ == hipErrorOutOfMemory ? IIM_ENOMEM : IIM_EDEVICE);                    \
+  } while (0)
+
+// status slot written by the guess preparation: norm of b - b_previous
+constexpr int KS_PREVRES = 9;
+
+}  // namespace iim
+
+struct iim_net {
+  std::string err;
+  int cin = iim::NET_FEATURES, width = 128, layers = 4;
+  bool bf16 = true;
+  hipStream_t stream = nullptr;
+  std::vector<int> lin, lout;          // channels of each layer
+  std::vector<size_t> offW, offb;      // offsets in the flat parameter array
+  size_t nparam = 0;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  int t = 0;                           // Adam steps taken
+  float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  // activations (grown on demand): Z[l], H[l] = [rows][lout[l]]
+  size_t cap_rows = 0;
+  std::vector<float*> Z, H;
+  float *dA = nullptr, *dB = nullptr;  // [rows][max width]
+  float* part = nullptr;               // weight-gradient partial sums
+  size_t part_cap = 0;
+  float* dY = nullptr;                 // [rows]
+  float* lossbuf = nullptr;            // [1]
+  std::vector<void*> allocs, act_allocs;
+  ~iim_net();
+};
+
+struct iim_ctx {
+  std::string err;
+  iim::Geometry geo;
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  int precision = IIM_PREC_FP64;
+  double tol = 1e-13;
+  int max_iter = 400, restart = 40, guess = IIM_GUESS_PREVIOUS, chunk = 4;
+  std::vector<void*> allocs;
+  size_t dev_bytes = 0;
+  iim::DGeom dg{};
+  iim::DFft df{};
+  iim::DDst dd{};
+  iim::DKrylov dk{};
+  bool box = false;
+  int8_t* cls_zero = nullptr;
+  double *psi = nullptr, *U = nullptr, *V = nullptr;
+  double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
+  double *Qw = nullptr, *wtmp = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
+  double* st_host = nullptr;
+  bool have_prev = false;
+  int solver = IIM_SOLVER_KRYLOV;
+  double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
+  // one RK3 step captured as a HIP graph (direct solver): replayed while the
+  // omega buffer and dt stay the same
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* g_omega = nullptr;
+  double g_dt = 0.0;
+  bool use_graph = true;
+  long n_solves = 0, n_matvecs = 0;
+  iim::Prof prof;
+  // host copies for the geometry view
+  std::vector<double> v_cxy, v_cn;
+  std::vector<int32_t> v_cint, v_aint, v_rects, v_circ;
+
+  // ---- initial guesses from the solve history (extrapolated / network)
+  int cur_stage = -1;             // RK stage of the solve in progress; -1 outside an RK step
+  double hist_dt = 0.0;
+  int hist_count = 0;             // consecutive solves of the current run held in the ring
+  long hist_next = 0;             // ring position of the next solve
+  double *hb = nullptr, *hx = nullptr;  // [4][n] right-hand sides and solutions
+  int* hs_ring = nullptr;         // [3 stages][4 positions][8] slot tables for the feature kernel
+  iim_net* net = nullptr;         // not owned
+  long n_net_used = 0, n_net_rejected = 0, n_extra_matvecs = 0;
+  // sequences of affected points around each body (network input order)
+  int seq_P = 0;
+  int *perm = nullptr, *seq = nullptr;  // perm[P]; seq = seg0[P], segl[P], pos[P]
+  float* seq_geo = nullptr;             // [P][4]
+  float *inf_F = nullptr, *inf_scale = nullptr;
+  // recording of solves for training
+  int rec_cap = 0, rec_count = 0, run_id = 0;
+  double *rb = nullptr, *rx = nullptr;  // [cap][n]
+  std::vector<int> rec_stage, rec_run;
+
+  template <class T>
+  T* dalloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    allocs.push_back(p);
+    dev_bytes += n * sizeof(T);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~iim_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    for (void* p : allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+  }
+};
+
+namespace iim {
+
+// api.cpp
+void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
+             int oj0, int oj1, double* psi, const double* done);
+void build_schur_t(iim_ctx* c, double* St);   // St[q][i] = (S e_q)_i
+void read_status(iim_ctx* c);
+void set_status(iim_ctx* c);
+
+// warm_start.cpp
+// Prepare the initial guess of the Krylov solve whose right-hand side is in
+// dk.b: returns the mode used (IIM_GUESS_*), after writing dk.x for the
+// extrapolated and network modes.
+int prepare_guess(iim_ctx* c);
+// after a Krylov solve: push (b, x) into the history ring and the recording
+void push_history(iim_ctx* c);
+// previous-stage solution, for the fallback of a rejected network guess
+void restore_previous(iim_ctx* c);
+void net_forward(iim_net* net, const Seq& s, int B, const float* X, bool keep_pre, hipStream_t st);
+
+}  // namespace iim

@@ -1,0 +1,208 @@
+"""Initial-guess network: the matrix-core kernels (BF16 and FP32 operands)
+against the FP64 oracle network, and the learned guess inside the Krylov
+solve of the cylinder workload (iterations saved, results unchanged)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+import paper_2109_13628_amd as iim
+from oracle import network as N
+from oracle import geometry as OG
+from oracle import ns as ONS
+from gpu_util import DEV, to_dev, seeded_state, rel
+
+pytestmark = pytest.mark.gpu
+
+# FP32 operands: rounding of FP32 products through a few layers.  BF16
+# operands: each product rounds both operands to 8 significant bits
+# (relative 2^-9 each), about 4e-3 per layer, compounded over 4 layers
+# forward and 4 backward.
+TOL_F32_FWD, TOL_F32_GRAD = 1e-5, 1e-4
+TOL_BF16_FWD, TOL_BF16_GRAD = 3e-2, 6e-2
+
+
+def _segments(lengths):
+    seg0, segl, pos, start = [], [], [], 0
+    for L in lengths:
+        for q in range(L):
+            seg0.append(start)
+            segl.append(L)
+            pos.append(q)
+        start += L
+    return np.array([seg0, segl, pos], dtype=np.int32)
+
+
+def _dev32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def _case(sizes, lengths, B, seed):
+    rng = np.random.default_rng(seed)
+    P = sum(lengths)
+    X = rng.standard_normal((B, P, sizes[0]))
+    T = rng.standard_normal((B, P))
+    params = N.init_params(sizes, seed=seed + 1)
+    # non-zero biases so that the bias paths are exercised
+    params = [(W, 0.1 * rng.standard_normal(b.shape)) for W, b in params]
+    # round the oracle's inputs to FP32 so both sides see the same numbers
+    X = X.astype(np.float32).astype(np.float64)
+    T = T.astype(np.float32).astype(np.float64)
+    flat = N.flatten(params).astype(np.float32)
+    params = N.unflatten(flat.astype(np.float64), sizes)
+    return X, T, params, flat
+
+
+def _oracle(params, X, T, lengths):
+    ys, grads, start = [], None, 0
+    B, P = X.shape[:2]
+    loss = 0.0
+    for L in lengths:
+        sl = slice(start, start + L)
+        y, _ = N.forward(params, X[:, sl])
+        ys.append(y[..., 0])
+        l, g = N.loss_and_grads(params, X[:, sl], T[:, sl])
+        w = (B * L) / (B * P)          # the batch loss is the mean over all B*P outputs
+        loss += w * l
+        gf = N.flatten([(gw * w, gb * w) for gw, gb in g])
+        grads = gf if grads is None else grads + gf
+        start += L
+    return np.concatenate(ys, 1), loss, grads
+
+
+SIZES = {"small": [10, 16, 16, 1], "paper": [10, 128, 128, 128, 1]}
+LENGTHS = [37, 50, 3, 1, 70]
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("arch", list(SIZES))
+def test_forward_and_gradients_match_oracle(arch, bf16):
+    sizes = SIZES[arch]
+    X, T, params, flat = _case(sizes, LENGTHS, B=3, seed=7)
+    net = iim.Network(in_channels=sizes[0], width=sizes[1], layers=len(sizes) - 1, bf16=bf16)
+    net.set(flat)
+    seq = torch.as_tensor(_segments(LENGTHS), device=DEV)
+    x, t = _dev32(X), _dev32(T)
+    y = torch.zeros((X.shape[0], X.shape[1]), dtype=torch.float32, device=DEV)
+    net.forward(x, seq, y)
+    loss = net.grad_mse(x, seq, t)
+    torch.cuda.synchronize()
+    g = net.get(1).astype(np.float64)
+    y_ref, loss_ref, g_ref = _oracle(params, X, T, LENGTHS)
+    ey = rel(y.cpu().numpy(), y_ref)
+    tf, tg = (TOL_BF16_FWD, TOL_BF16_GRAD) if bf16 else (TOL_F32_FWD, TOL_F32_GRAD)
+    assert ey < tf, ey
+    assert abs(loss - loss_ref) / loss_ref < tf, (loss, loss_ref)
+    # every layer's weight and bias gradient
+    off = 0
+    for cin, cout in zip(sizes[:-1], sizes[1:]):
+        for n in (N.TAPS * cin * cout, cout):
+            e = rel(g[off:off + n], g_ref[off:off + n])
+            assert e < tg, (off, n, e)
+            off += n
+
+
+def test_adam_step_matches_oracle():
+    sizes = SIZES["small"]
+    X, T, params, flat = _case(sizes, [40, 24], B=2, seed=3)
+    net = iim.Network(in_channels=sizes[0], width=sizes[1], layers=len(sizes) - 1, bf16=False)
+    net.set(flat)
+    seq = torch.as_tensor(_segments([40, 24]), device=DEV)
+    x, t = _dev32(X), _dev32(T)
+    p = flat.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in range(1, 4):
+        net.grad_mse(x, seq, t)
+        g = net.get(1).astype(np.float64)
+        net.adam_step(1e-2)
+        p, m, v = N.adam_step(p, g, m, v, step, lr=1e-2)
+        got = net.get(0).astype(np.float64)
+        # the update itself (lr-sized) must agree to FP32 rounding
+        assert np.max(np.abs(got - p)) < 1e-5, (step, np.max(np.abs(got - p)))
+        p = got
+
+
+def test_sequences_cover_affected_points():
+    w = wl.cylinder_small()
+    ctx = iim.Context(w.grid, w.bodies)
+    perm, seq, geo = ctx.warm_start_sequences()
+    na = ctx.info["n_affected"]
+    assert sorted(perm.tolist()) == list(range(na))
+    a_int = ctx.geometry()["a_int"]
+    assert np.array_equal(geo[:, 0], a_int[perm, 2].astype(np.float32))
+    assert np.all((seq[2] >= 0) & (seq[2] < seq[1]))
+
+
+def _run(ctx, omega0, G0, dt, steps):
+    om = to_dev(omega0)
+    ctx.reset_history()
+    G = np.array(G0, dtype=np.float64)
+    iters, res0 = [], []
+    for _ in range(steps):
+        G, st = ctx.rk3_steps(om, G, dt, 1)
+        iters += st["iters"]
+        res0 += st["res0"]
+    torch.cuda.synchronize()
+    return om.cpu().numpy(), G, np.array(iters), np.array(res0)
+
+
+def _state(w, geo, seed):
+    """Seed 0: the impulsive start from rest; otherwise mild domain-scale
+    vortices added to it (the training runs)."""
+    if seed == 0:
+        return np.zeros((w.grid.ny, w.grid.nx)), np.zeros(geo.nbc)
+    return np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, seed, count=8), 0.0), np.zeros(geo.nbc)
+
+
+def test_learned_guess_in_the_krylov_solve():
+    """Trains the network on recorded solves of perturbed runs, then solves
+    the held-out impulsive start to 1e-10 with each initial guess.  Asserted:
+    the network lowers the initial residual below the extrapolated guess it
+    corrects; the extrapolated guess takes fewer Krylov iterations than the
+    previous-stage guess; the network guess is not worse than the
+    previous-stage guess in iterations (it does not beat the extrapolation:
+    the iterations follow the error in the slowly converging directions,
+    which the network does not reduce); the results do not depend on the
+    guess."""
+    w = wl.cylinder_small()
+    geo = OG.Geometry(w.grid, w.bodies)
+    rec = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    rec.record_solves(4000)
+    for seed in range(1, 9):
+        om, G = _state(w, geo, seed)
+        _run(rec, om, G, w.dt, 60)
+    assert rec.warm_start_stats()["recorded"] == 8 * 60 * 3
+    net = iim.Network(bf16=True, seed=0)
+    losses = rec.warm_start_train(net, iters=2000, batch=64, lr=1e-3, seed=1)
+    assert np.all(np.isfinite(losses))
+    assert losses[-100:].mean() < 0.25 * losses[:100].mean(), (losses[:100].mean(), losses[-100:].mean())
+
+    om0, G0 = _state(w, geo, 0)
+    steps = 20
+    out = {}
+    for name, mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE),
+                       ("network", iim.GUESS_NETWORK)):
+        ctx = iim.Context(w.grid, w.bodies, tol=1e-10, guess=mode)
+        if mode == iim.GUESS_NETWORK:
+            ctx.set_warm_start(mode, net)
+        out[name] = _run(ctx, om0, G0, w.dt, steps) + (ctx.warm_start_stats(),)
+    # from the fourth solve on, every mode has its history
+    it = {k: v[2][3:].mean() for k, v in out.items()}
+    r0 = {k: np.median(v[3][3:]) for k, v in out.items()}
+    print("iterations", it, "initial residuals", r0, "network", out["network"][4])
+    assert r0["extrapolate"] < 0.5 * r0["previous"], r0
+    assert r0["network"] < 0.8 * r0["extrapolate"], r0
+    assert it["extrapolate"] < it["previous"] - 1.0, it
+    assert it["network"] < it["previous"] + 1.0, it
+    st = out["network"][4]
+    assert st["net_used"] > 10 * st["net_rejected"], st
+    # the guess changes the iterations, not the answer
+    ref = ONS.Stepper(geo)
+    om = np.where(geo.fluid, om0, 0.0)
+    G = np.array(G0, dtype=np.float64)
+    for _ in range(steps):
+        om, G = ref.step(om, G, w.dt)
+    for k, v in out.items():
+        e = rel(v[0], om, mask=geo.fluid)
+        assert e < 1e-8, (k, e)

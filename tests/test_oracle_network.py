@@ -57,3 +57,22 @@ def test_gelu_derivative():
     z = np.linspace(-4, 4, 101)
     fd = (N.gelu(z + 1e-6) - N.gelu(z - 1e-6)) / 2e-6
     assert np.max(np.abs(fd - N.gelu_grad(z))) < 1e-8
+
+
+def test_adam_first_step_is_signed_lr():
+    # with zero moments, the bias-corrected first step is lr * g / (|g| + eps)
+    g = np.array([3.0, -0.5, 1e-3, -2e2])
+    p, m, v = N.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01, eps=0.0)
+    assert np.allclose(p, -0.01 * np.sign(g), rtol=0, atol=1e-15)
+    # a constant gradient keeps the step at lr (bias corrections cancel)
+    for t in range(2, 6):
+        p2, m, v = N.adam_step(p, g, m, v, t, lr=0.01, eps=0.0)
+        assert np.allclose(p2 - p, -0.01 * np.sign(g), rtol=1e-12, atol=0)
+        p = p2
+
+
+def test_flatten_roundtrip():
+    params = N.init_params([10, 16, 16, 1], seed=3)
+    back = N.unflatten(N.flatten(params), [10, 16, 16, 1])
+    for (W, b), (W2, b2) in zip(params, back):
+        assert np.array_equal(W, W2) and np.array_equal(b, b2)
