@@ -32,6 +32,13 @@ def _parse():
     p.add_argument("--krylov-steps", type=int, default=5, help="steps of the GMRES path timed for 'paths'")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10)
+    p.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
+                   help="write the text summary of a rocprofv3 --kernel-trace --stats run and exit")
+    p.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                   help="write the HBM traffic summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    p.add_argument("--command", default="", help="command line recorded in a summary")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="end with one plain device copy of 256 MiB (scale reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -67,8 +74,120 @@ def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profil
     return ctx, omega, Gamma, res, pre
 
 
+# library kernel names of the instrumented kernel ids
+HIP_NAMES = {"fft_rows_fwd": "k_rows_fwd_reg", "fft_cols_conv": "k_cols_reg", "fft_rows_inv": "k_rows_inv_reg",
+             "transport_bulk": "k_transport_bulk", "arnoldi": "k_arnoldi"}
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "paper_2109_13628_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_cylinder_1024x512.txt")
+
+
+def _src_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _summarize_trace(trace_dir, out, command):
+    """Top kernels of a --kernel-trace --stats run, and for the instrumented
+    kernels the average duration per launch shape (the full-size launches of
+    the RK3 steps are the largest grid)."""
+    import glob
+    stats = _read_csv(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0])
+    trace = _read_csv(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])
+    lines = ["# rocprofv3 kernel trace: RK3 steps of the 1024x512 free-space cylinder workload", "",
+             "command: " + command, "", "kernel | calls | avg us | total ms | share %", "---|---|---|---|---"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append("%s | %s | %.2f | %.3f | %.2f" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                      float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    # launches inside the RK steps: from the first transport launch on (the
+    # set-up before it builds the dense Schur matrix with pruned convolutions)
+    t0 = min(int(r["Start_Timestamp"]) for r in trace if "k_transport_bulk" in r["Kernel_Name"])
+    lines += ["", "launches inside the RK steps, per launch shape (grid size): calls, avg us", ""]
+    for short, hip in HIP_NAMES.items():
+        by = {}
+        for r in trace:
+            if (hip + "<" in r["Kernel_Name"] or hip + "(" in r["Kernel_Name"]) and int(r["Start_Timestamp"]) >= t0:
+                by.setdefault(int(r["Grid_Size_X"]), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        for grid in sorted(by, reverse=True):
+            v = by[grid]
+            lines.append("%s (%s) grid %d: %d calls, avg %.2f us" % (short, hip, grid, len(v), sum(v) / len(v) / 1e3))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _summarize_pmc(fetch_dir, write_dir, out, command):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the full-size
+    launches of every instrumented kernel, and the scale that turns each
+    counter into bytes: the counter reading of one plain 256 MiB device copy
+    (the last copy dispatch of the run) against 256 MiB."""
+    import glob
+    res = {}
+    for tag, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _read_csv(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        probe = max(copies, key=lambda r: int(r["Dispatch_Id"]))
+        res[tag + "_scale"] = (256 * 1024) / float(probe["Counter_Value"])
+        # dispatches inside the RK steps (from the first transport launch on)
+        d0 = min(int(r["Dispatch_Id"]) for r in rows if "k_transport_bulk" in r["Kernel_Name"])
+        for short, hip in HIP_NAMES.items():
+            ks = [r for r in rows if (hip + "<" in r["Kernel_Name"] or hip + "(" in r["Kernel_Name"])
+                  and int(r["Dispatch_Id"]) >= d0]
+            if not ks:
+                continue
+            gmax = max(int(r["Grid_Size"]) for r in ks)
+            v = [float(r["Counter_Value"]) for r in ks if int(r["Grid_Size"]) == gmax]
+            res["%s_%s_kib" % (short, tag)] = sum(v) / len(v)
+            res["%s_grid" % short] = gmax
+    lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE), full-size launches",
+             "# inside the RK steps of the 1024x512 free-space cylinder workload; bytes = KiB * 1024 * scale, where scale is",
+             "# 256 MiB over the counter's reading for one plain 256 MiB device copy in the same run.", "",
+             "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE"),
+             "command_write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_f", "pmc_w"),
+             "kernel_source_sha256_16: " + _src_hash()]
+    for k in sorted(res):
+        lines.append("%s: %s" % (k, res[k]))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _traffic(kernel):
+    """HBM bytes per full-size launch of `kernel` from the committed counter
+    summary, or None when it is missing or the kernel source has changed
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != _src_hash():
+        return None
+    try:
+        fb = float(kv[kernel + "_fetch_kib"]) * 1024 * float(kv["fetch_scale"])
+        wb = float(kv[kernel + "_write_kib"]) * 1024 * float(kv["write_scale"])
+    except KeyError:
+        return None
+    return {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb, "source": os.path.relpath(TRAFFIC_FILE, HERE)}
+
+
 def main():
     args = _parse()
+    if args.summarize_trace:
+        _summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        return
+    if args.summarize_pmc:
+        _summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2], args.command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -94,19 +213,32 @@ def main():
     shares = {n: round(v["total_ms"] / total, 4) for n, v in pre.items()}
 
     # roofline of the dominant kernel: HIP events around each of its launches on
-    # the context stream, over the same number of steps continuing the run
+    # the context stream, over the same number of steps continuing the run;
+    # then its largest launch repeated back to back between one event pair
+    # (per-launch events also time the dispatch latency that back-to-back
+    # launches hide, which a kernel profiler does not count)
     ctx.profile(1 << iim.KERNEL_NAMES.index(dominant))
     Gamma, _ = ctx.rk3_steps(omega, Gamma, w.dt, args.steps)
     torch.cuda.synchronize()
     prof = ctx.profile_read().get(dominant, {})
+    rep = None
+    if dominant in ("fft_rows_fwd", "fft_cols_conv", "fft_rows_inv"):
+        rep = ctx.profile_replay(dominant, 200)
+        torch.cuda.synchronize()
     ctx.profile(0)
-    achieved = prof.get("GBps")
+    achieved = rep["GBps"] if rep else prof.get("GBps")
+    tr = _traffic(dominant)
     roof = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-            "frac": (achieved / 8000.0) if achieved else None, "traffic": None,
-            "avg_us": prof.get("avg_us"), "launches": prof.get("launches"),
-            "algorithmic_bytes_per_launch": prof.get("bytes_per_launch"),
-            "timing": "HIP events around every launch of this kernel over %d eager steps continuing the "
-                      "timed run" % args.steps}
+            "frac": (achieved / 8000.0) if achieved else None,
+            "traffic": tr["bytes_per_launch"] if tr else None, "traffic_detail": tr,
+            "avg_us": rep["avg_us"] if rep else prof.get("avg_us"),
+            "algorithmic_bytes_per_launch": rep["bytes_per_launch"] if rep else prof.get("bytes_per_launch"),
+            "timing": ("HIP event pair around 200 back-to-back repeats of the kernel's full-size launch"
+                       if rep else "HIP events around every launch"),
+            "events_per_launch": {"avg_us": prof.get("avg_us"), "launches": prof.get("launches"),
+                                  "GBps": prof.get("GBps"),
+                                  "timing": "HIP events around every launch of this kernel over %d eager steps "
+                                            "continuing the timed run" % args.steps}}
 
     paths = {tag + "_" + args.solver: head}
     if args.krylov_steps and solver != iim.SOLVER_KRYLOV:
@@ -137,6 +269,15 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(w, args.cpu_steps)
+    if args.copy_probe:
+        # one copy kernel that reads and writes exactly 256 MiB: the reference
+        # for converting FETCH_SIZE / WRITE_SIZE counters into bytes
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 4
     print(json.dumps(out))
 
 

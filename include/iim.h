@@ -217,6 +217,15 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
 int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
 int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
+/* Repeat the largest launch of kernel id 0, 1 or 2 (the FFT passes; made
+ * while it was timed) reps times back to back between one pair of HIP events
+ * on the context's stream: average duration (ms) and algorithmic bytes of
+ * that launch.  The repeats overwrite only the context's spectrum and
+ * stream-function workspaces, which every reconstruction rebuilds before
+ * reading them.  Per-launch event pairs also time the dispatch latency that
+ * back-to-back launches hide; this is the duration a kernel profiler
+ * reports. */
+int iim_profile_replay(iim_ctx* ctx, int32_t kernel_id, int32_t reps, double* avg_ms, double* bytes);
 
 /* ---- learned initial guess ----
  * A stack of circular 1D convolutions (kernel 5) with tanh-approximated GELU

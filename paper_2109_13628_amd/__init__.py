@@ -28,7 +28,7 @@ SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_reconstruct", "iim_rhs",
-           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals",
+           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
            "iim_net_forward", "iim_net_grad_mse", "iim_net_adam_step", "iim_net_save", "iim_net_load",
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
@@ -135,6 +135,8 @@ def lib():
     L.iim_profile.argtypes = [vp, C.c_int32]
     L.iim_profile_read.restype = ip
     L.iim_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
+    L.iim_profile_replay.restype = ip
+    L.iim_profile_replay.argtypes = [vp, C.c_int32, C.c_int32, dp, dp]
     L.iim_krylov_totals.restype = ip
     L.iim_krylov_totals.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     i64p = C.POINTER(C.c_int64)
@@ -299,6 +301,13 @@ class Context:
                              "bytes_per_launch": b.value / n.value,
                              "GBps": (b.value / n.value) / (avg * 1e-3) / 1e9 if avg > 0 else None}
         return out
+
+    def profile_replay(self, name, reps=200):
+        ms, b = C.c_double(), C.c_double()
+        self._check(lib().iim_profile_replay(self._h, KERNEL_NAMES.index(name), reps, C.byref(ms), C.byref(b)),
+                    "iim_profile_replay")
+        return {"avg_us": 1e3 * ms.value, "bytes_per_launch": b.value, "reps": reps,
+                "GBps": b.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else None}
 
     def krylov_totals(self):
         s, m = C.c_int64(), C.c_int64()

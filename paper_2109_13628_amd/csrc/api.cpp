@@ -784,6 +784,37 @@ int iim_profile_read(iim_ctx* c, int32_t kernel_id, double* total_ms, int64_t* l
   return IIM_OK;
 }
 
+int iim_profile_replay(iim_ctx* c, int32_t kernel_id, int32_t reps, double* avg_ms, double* bytes) {
+  if (!c || reps < 1 || !avg_ms || !bytes) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  // the FFT passes write only the spectrum / stream-function workspaces,
+  // which every convolution rebuilds before it reads them
+  if (kernel_id != KID_ROWS_FWD && kernel_id != KID_COLS && kernel_id != KID_ROWS_INV)
+    return fail(c, IIM_EUNSUPPORTED, "kernel not replayable");
+  if (!c->prof.replay[kernel_id]) return fail(c, IIM_EINVAL, "kernel not launched while timed");
+  try {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->prof.replay[kernel_id](c->stream);  // warm
+    HIPCHK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) c->prof.replay[kernel_id](c->stream);
+    HIPCHK(hipEventRecord(b, c->stream));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    HIPCHK(hipGetLastError());
+    *avg_ms = ms / reps;
+    *bytes = c->prof.replay_bytes[kernel_id];
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
 int iim_krylov_totals(const iim_ctx* c, int64_t* solves, int64_t* matvecs) {
   if (!c || !solves || !matvecs) return IIM_EINVAL;
   *solves = c->n_solves;

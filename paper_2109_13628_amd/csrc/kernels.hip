@@ -66,7 +66,7 @@ __device__ __forceinline__ void fft_stage(double2* buf, int lt, int Ns, const do
           v[b][r] = cmul(v[b][r], w);
         }
       }
-      if (R == 2) {
+      if constexpr (R == 2) {
         const double2 a = v[b][0], c = v[b][1];
         v[b][0] = cadd(a, c);
         v[b][1] = csub(a, c);
@@ -486,7 +486,7 @@ void launch_matvec_finish(const DGeom& g, const DKrylov&, const double* psi_ring
 }
 
 // b_gamma = A (G omega) + B psi_b_tilde ; b_k = sum_{R_k} omega - Gamma_k / h^2
-__global__ void __launch_bounds__(256) k_rhs_vector(DGeom g, const double* __restrict__ psi,
+__global__ void __launch_bounds__(1024) k_rhs_vector(DGeom g, const double* __restrict__ psi,
                                                     const double* __restrict__ omega,
                                                     const double* __restrict__ Gamma, double* __restrict__ b) {
   __shared__ double red[16];
@@ -495,10 +495,24 @@ __global__ void __launch_bounds__(256) k_rhs_vector(DGeom g, const double* __res
     const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
     const int w = i1 - i0 + 1, cnt = w * (j1 - j0 + 1);
     double acc = 0.0;
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-      const int i = i0 + q % w, j = j0 + q / w;
-      const int idx = j * g.nx + i;
-      if (g.cls[idx] < 2) acc += omega[idx];
+    // four independent loads in flight per thread and iteration
+    for (int q0 = threadIdx.x; q0 < cnt; q0 += 4 * blockDim.x) {
+      double v[4];
+      int8_t cl[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * blockDim.x;
+        cl[u] = 3;
+        v[u] = 0.0;
+        if (q < cnt) {
+          const int idx = (j0 + q / w) * g.nx + i0 + q % w;
+          cl[u] = g.cls[idx];
+          v[u] = omega[idx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cl[u] < 2) acc += v[u];
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) b[g.na + k] = s - Gamma[k] * g.inv_h * g.inv_h;
@@ -513,8 +527,8 @@ __global__ void __launch_bounds__(256) k_rhs_vector(DGeom g, const double* __res
 }
 void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma, double* b,
                        hipStream_t s) {
-  const int blocks = g.nbc + (g.na + 255) / 256;
-  k_rhs_vector<<<blocks, 256, 0, s>>>(g, psi_ring, omega, Gamma, b);
+  const int blocks = g.nbc + (g.na + 1023) / 1024;
+  k_rhs_vector<<<blocks, 1024, 0, s>>>(g, psi_ring, omega, Gamma, b);
 }
 
 // ============================================================ GMRES (device)
@@ -891,20 +905,29 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
   }
 }
 
-__global__ void __launch_bounds__(128) k_transport_special(DGeom g, const double* __restrict__ omega,
+// One group of 4 lanes per boundary-kernel node: lane f computes the flux on
+// face f (right, left, top, bottom); lane 0 of the group combines them.
+__global__ void __launch_bounds__(256) k_transport_special(DGeom g, const double* __restrict__ omega,
                                                            const double* __restrict__ U, const double* __restrict__ V,
                                                            const double* __restrict__ w4, const double* __restrict__ w3b,
                                                            const double* __restrict__ w3n, double* __restrict__ out,
                                                            double* __restrict__ Q, double a, double b, double dt,
                                                            int mode) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.nsp) return;
-  const int q = g.special[s];
-  const int i = q % g.nx, j = q / g.nx;
-  const double fxr = flux_general(g, omega, U, V, w4, w3b, w3n, i, j, 0);
-  const double fxl = flux_general(g, omega, U, V, w4, w3b, w3n, i - 1, j, 0);
-  const double fyt = flux_general(g, omega, U, V, w4, w3b, w3n, i, j, 1);
-  const double fyb = flux_general(g, omega, U, V, w4, w3b, w3n, i, j - 1, 1);
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sp = tid >> 2, face = tid & 3;
+  const bool act = sp < g.nsp;
+  int q = 0;
+  double fl = 0.0;
+  if (act) {
+    q = g.special[sp];
+    const int i = q % g.nx, j = q / g.nx;
+    const int fi = face == 1 ? i - 1 : i, fj = face == 3 ? j - 1 : j;
+    fl = flux_general(g, omega, U, V, w4, w3b, w3n, fi, fj, face >> 1);
+  }
+  const int base = (threadIdx.x & 63) & ~3;
+  const double fxr = __shfl(fl, base, 64), fxl = __shfl(fl, base + 1, 64);
+  const double fyt = __shfl(fl, base + 2, 64), fyb = __shfl(fl, base + 3, 64);
+  if (!act || face != 0) return;
   const double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
   if (mode == 0) {
     out[q] = rhs;
@@ -922,11 +945,11 @@ void launch_transport(const DGeom& g, const double* omega, const double* U, cons
   // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
   IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_bulk, grid, 256, s, g, omega, U, V, out, Q, a, b,
              dt, mode);
-  if (g.nsp) k_transport_special<<<(g.nsp + 127) / 128, 128, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
+  if (g.nsp) k_transport_special<<<(4 * g.nsp + 255) / 256, 256, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
 }
 
 // Kelvin: one block per circulating body
-__global__ void __launch_bounds__(256) k_kelvin(DGeom g, const double* __restrict__ omega, const double* __restrict__ U,
+__global__ void __launch_bounds__(512) k_kelvin(DGeom g, const double* __restrict__ omega, const double* __restrict__ U,
                                                 const double* __restrict__ V, double* __restrict__ dG,
                                                 double* __restrict__ Gamma, double* __restrict__ QG, double a,
                                                 double b, double dt, int mode) {
@@ -960,7 +983,7 @@ __global__ void __launch_bounds__(256) k_kelvin(DGeom g, const double* __restric
 
 void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG, double* Gamma,
                    double* QG, double a, double b, double dt, int mode, hipStream_t s) {
-  if (g.nbc) k_kelvin<<<g.nbc, 256, 0, s>>>(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode);
+  if (g.nbc) k_kelvin<<<g.nbc, 512, 0, s>>>(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode);
 }
 
 }  // namespace iim
@@ -1124,6 +1147,18 @@ struct RegCfg {
 };
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
+
+// The hardware deals consecutive workgroups round-robin to the 8 XCDs, each
+// with its own L2.  Row passes give consecutive spectrum rows to consecutive
+// logical blocks, and 128-byte lines of the spectrum span several of them:
+// hand each XCD a contiguous range of logical blocks so that the blocks
+// sharing a line meet in one L2 (otherwise every XCD fetches, and writes
+// back, its own partial copy of the line).
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 template <bool INV>
 __device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
@@ -1348,7 +1383,8 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
   __shared__ double2 lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int w = threadIdx.x / T, t = threadIdx.x % T;
-  const int jrow = j0 + blockIdx.x * C::PER + w;
+  const int lb = xcd_block();
+  const int jrow = j0 + lb * C::PER + w;
   const bool valid = (jrow < j0 + count) && jrow >= 0 && jrow < g.ny;
   double2 v[E];
 #pragma unroll
@@ -1393,7 +1429,7 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
     const int idx = threadIdx.x + q * C::THREADS;
     if (idx >= (HX + 1) * C::PER) break;
     const int rr = idx % C::PER, k = idx / C::PER;
-    const int jj = j0 + blockIdx.x * C::PER + rr;
+    const int jj = j0 + lb * C::PER + rr;
     if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
     const double2 zk = lds[rr][padi(k & (HX - 1))];
     const double2 zc = conj2(lds[rr][padi((HX - k) & (HX - 1))]);
@@ -1412,6 +1448,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
   __shared__ double2 lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
+  const int lb = xcd_block();
   {
     // all loads of this thread in flight before the LDS stores
     constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
@@ -1420,7 +1457,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
     for (int q = 0; q < IT; ++q) {
       const int idx = threadIdx.x + q * C::THREADS;
       const int rr = idx % C::PER, k = idx / C::PER;
-      const int jo = j0 + blockIdx.x * C::PER + rr;
+      const int jo = j0 + lb * C::PER + rr;
       tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? f.spec[(size_t)k * f.ld + jo + 1]
                                                              : make_double2(0.0, 0.0);
     }
@@ -1444,7 +1481,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   }
   __syncthreads();
   fft_reg<HX, true>(v, lds[w], t, f.tw_x);
-  const int jo = j0 + blockIdx.x * C::PER + w;
+  const int jo = j0 + lb * C::PER + w;
   if (jo >= j0 + count) return;
   const int nxr = g.nx + 2;
   double* row = psi + (size_t)(jo + 1) * nxr;
