@@ -29,7 +29,11 @@ def _parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--solver", choices=["krylov", "direct"], default="direct")
-    p.add_argument("--krylov-steps", type=int, default=5, help="steps of the GMRES path timed for 'paths'")
+    p.add_argument("--krylov-steps", type=int, default=10, help="timed steps of each GMRES path in 'paths' (0: none)")
+    p.add_argument("--krylov-tol", type=float, default=1e-10, help="relative residual of the GMRES paths")
+    p.add_argument("--train-runs", type=int, default=10, help="recorded runs for the network (0: no network path)")
+    p.add_argument("--train-steps", type=int, default=600, help="RK3 steps per recorded run")
+    p.add_argument("--train-iters", type=int, default=2000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10)
     p.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
@@ -42,9 +46,12 @@ def _parse():
     return p.parse_args()
 
 
-def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profile_kernels=None):
+def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profile_kernels=None, tol=1e-13,
+              net=None, per_step=False):
     g = w.grid
-    ctx = iim.Context(g, w.bodies, precision=precision, tol=1e-13, guess=guess, solver=solver)
+    ctx = iim.Context(g, w.bodies, precision=precision, tol=tol, guess=guess, solver=solver)
+    if net is not None:
+        ctx.set_warm_start(iim.GUESS_NETWORK, net)
     omega = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
     Gamma = np.zeros(ctx.n_circ)
     pre = {}
@@ -61,17 +68,66 @@ def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profil
     if warmup - n_prof:
         Gamma, _ = ctx.rk3_steps(omega, Gamma, w.dt, warmup - n_prof)
     torch.cuda.synchronize()
-    s0, m0 = ctx.krylov_totals()
+    c0 = ctx.counters()
+    iters, rounds, res0 = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Gamma, stats = ctx.rk3_steps(omega, Gamma, w.dt, steps)
+    if per_step:
+        # Krylov paths synchronise inside every solve anyway: one call per step
+        # to collect the statistics of every stage
+        for _ in range(steps):
+            Gamma, st = ctx.rk3_steps(omega, Gamma, w.dt, 1)
+            iters += st["iters"]
+            rounds += st["refine_rounds"]
+            res0 += st["res0"]
+    else:
+        Gamma, st = ctx.rk3_steps(omega, Gamma, w.dt, steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    s1, m1 = ctx.krylov_totals()
+    c1 = ctx.counters()
+    d = {k: c1[k] - c0[k] for k in c1}
     res = {"value": g.nx * g.ny * steps / secs, "ms_per_step": 1e3 * secs / steps, "steps": steps,
-           "krylov": {"solves": s1 - s0, "matvecs": m1 - m0, "matvecs_per_solve": (m1 - m0) / max(1, s1 - s0),
-                      "last_step": stats}}
+           "krylov": {"tol": tol, "solves": d["solves"], "iterations": d["krylov_iterations"],
+                      "iterations_per_solve": d["krylov_iterations"] / max(1, d["solves"]),
+                      "fp32_products": d["fp32_products"],
+                      "initial_residual_matvecs": d["initial_residual_matvecs"]}}
+    if per_step:
+        res["krylov"]["refine_rounds_per_solve"] = float(np.mean(rounds)) if rounds else 0.0
+        res["krylov"]["median_initial_residual"] = float(np.median(res0)) if res0 else None
+        if net is not None:
+            res["krylov"]["network_guesses_kept"] = d["network_kept"]
+            res["krylov"]["network_guesses_rejected"] = d["network_rejected"]
     return ctx, omega, Gamma, res, pre
+
+
+def _train_network(iim, w, torch, np, runs, steps, iters):
+    """Record the solves of `runs` perturbed runs of the workload with the
+    dense solver, then train the initial-guess network on them (on the GPU,
+    the library's own kernels)."""
+    import workloads as wl
+    g = w.grid
+    rec = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
+    rec.record_solves(runs * steps * 3)
+    t0 = time.perf_counter()
+    for seed in range(1, runs + 1):
+        om = torch.as_tensor(0.5 * wl.seeded_vortices(g, seed, count=8), device="cuda:0")
+        rec.reset_history()
+        rec.rk3_steps(om, np.zeros(rec.n_circ), w.dt, steps)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    net = iim.Network(bf16=True, seed=0)
+    t0 = time.perf_counter()
+    losses = rec.warm_start_train(net, iters=iters, batch=64, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    info = {"recorded_solves": rec.warm_start_stats()["recorded"], "runs": runs, "steps_per_run": steps,
+            "record_s": t_rec, "train_s": t_train, "adam_steps": iters, "batch": 64,
+            "loss_first100": float(losses[:100].mean()), "loss_last100": float(losses[-100:].mean()),
+            "network": "4 circular conv1d layers, kernel 5, width 128, GELU; BF16 matrix-core products, FP32 accumulation",
+            "data": "runs started from mild seeded vortices (0.5 x seeded_vortices, 8 vortices, seeds 1..%d); "
+                    "evaluated on the impulsive start from rest" % runs}
+    rec.close()
+    return net, info
 
 
 # library kernel names of the instrumented kernel ids
@@ -241,10 +297,26 @@ def main():
                                             "continuing the timed run" % args.steps}}
 
     paths = {tag + "_" + args.solver: head}
-    if args.krylov_steps and solver != iim.SOLVER_KRYLOV:
-        _, _, _, kry, _ = _run_path(iim, w, torch, np, prec, iim.SOLVER_KRYLOV, iim.GUESS_PREVIOUS,
-                                    args.warmup, args.krylov_steps)
-        paths[tag + "_krylov_plain"] = kry
+    warm = None
+    net = None
+    if args.krylov_steps:
+        kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True)
+        for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+            for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
+                c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
+                paths["%s_krylov_%s" % (p_name, g_name)] = r_
+                c_.close()
+        if args.train_runs:
+            net, warm = _train_network(iim, w, torch, np, args.train_runs, args.train_steps, args.train_iters)
+            for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+                c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, iim.GUESS_NETWORK,
+                                            net=net, **kw)
+                paths["%s_krylov_network" % p_name] = r_
+                c_.close()
+        base = paths["fp64_krylov_previous"]["ms_per_step"]
+        warm = warm or {}
+        warm["speedup_vs_fp64_krylov_previous"] = {k: base / v["ms_per_step"] for k, v in paths.items()
+                                                  if "krylov" in k}
 
     out = {
         "metric": "RK3 step cell-updates/s at 1e-8 rel. error; FP64 plain vs mixed+learned warm-start",
@@ -261,14 +333,20 @@ def main():
         "data": "synthetic (impulsively started flow from rest)",
         "config": {"workload": w.name, "nx": g.nx, "ny": g.ny, "h": g.h,
                    "fft": [ctx.info["fft_mx"], ctx.info["fft_my"]], "Re": 100, "dt": w.dt,
-                   "precision": args.precision, "solver": args.solver, "guess": "previous-stage",
-                   "krylov_tol": 1e-13, "t_start": args.warmup * w.dt},
+                   "precision": args.precision, "solver": args.solver, "krylov_tol_headline": 1e-13,
+                   "t_start": args.warmup * w.dt},
         "paths": paths,
+        "warm_start": warm,
         "roofline": roof,
         "kernel_time_share_warmup": shares,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(w, args.cpu_steps)
+        cpu, ref_state = _cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu
+        # the state after the same steps from rest on the mixed-precision
+        # network path (GMRES to the same tolerance as 'paths') against the
+        # FP64 oracle: vorticity and velocity relative errors
+        out["accuracy_vs_oracle"] = _accuracy(iim, w, torch, np, ref_state, net, args.krylov_tol)
     if args.copy_probe:
         # one copy kernel that reads and writes exactly 256 MiB: the reference
         # for converting FETCH_SIZE / WRITE_SIZE counters into bytes
@@ -281,9 +359,40 @@ def main():
     print(json.dumps(out))
 
 
+def _accuracy(iim, w, torch, np, ref, net, tol):
+    om_ref, G_ref, n_steps, R, geo = ref
+    g = w.grid
+    res = {}
+    for name, prec, guess in (("fp64_direct", iim.PREC_FP64, iim.GUESS_PREVIOUS),
+                              ("mixed_krylov_network" if net is not None else "mixed_krylov_extrapolate",
+                               iim.PREC_MIXED, iim.GUESS_NETWORK if net is not None else iim.GUESS_EXTRAPOLATE)):
+        solver = iim.SOLVER_DIRECT if name == "fp64_direct" else iim.SOLVER_KRYLOV
+        ctx = iim.Context(g, w.bodies, precision=prec, tol=tol, guess=guess, solver=solver)
+        if guess == iim.GUESS_NETWORK:
+            ctx.set_warm_start(guess, net)
+        om = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
+        G, _ = ctx.rk3_steps(om, np.zeros(ctx.n_circ), w.dt, n_steps)
+        U = torch.zeros((g.ny + 2, g.nx + 2), dtype=torch.float64, device="cuda:0")
+        V = torch.zeros_like(U)
+        ctx.reconstruct(om, G, None, U, V)
+        torch.cuda.synchronize()
+        a = R.reconstruct(om_ref, G_ref)
+        fl = np.pad(geo.fluid, 1)
+        uv = np.stack([U.cpu().numpy()[fl], V.cpu().numpy()[fl]])
+        uv_ref = np.stack([a.U[fl], a.V[fl]])
+        om_gpu = om.cpu().numpy()[geo.fluid]
+        res[name] = {"steps": n_steps, "krylov_tol": tol if solver == iim.SOLVER_KRYLOV else None,
+                     "velocity_rel_error": float(np.linalg.norm(uv - uv_ref) / np.linalg.norm(uv_ref)),
+                     "vorticity_rel_error": float(np.linalg.norm(om_gpu - om_ref[geo.fluid]) /
+                                                  np.linalg.norm(om_ref[geo.fluid]))}
+        ctx.close()
+    return res
+
+
 def _cpu_baseline(w, steps):
     """The FP64 oracle, timed on this host's cores over a bounded sample of the
-    same workload (a few RK3 steps from rest; set-up excluded)."""
+    same workload (a few RK3 steps from rest; set-up excluded).  Also returns
+    its final state for the accuracy check."""
     import numpy as np
     import scipy.fft as sfft
     from oracle import geometry as OG, ns as ONS
@@ -299,10 +408,11 @@ def _cpu_baseline(w, steps):
         for _ in range(steps):
             om, G = st.step(om, G, w.dt)
         secs = time.perf_counter() - t0
-    return {"value": w.grid.nx * w.grid.ny * steps / secs, "unit": "cell-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d RK3 steps of the same 1024x512 cylinder workload after one set-up step from rest "
-                      "(FP64 NumPy/SciPy, dense Schur LU, scipy.fft workers=%d)" % (steps, cores)}
+    cpu = {"value": w.grid.nx * w.grid.ny * steps / secs, "unit": "cell-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "%d RK3 steps of the same 1024x512 cylinder workload after one set-up step from rest "
+                     "(FP64 NumPy/SciPy, dense Schur LU, scipy.fft workers=%d)" % (steps, cores)}
+    return cpu, (om, G, steps + 1, st.rec, geo)
 
 
 if __name__ == "__main__":

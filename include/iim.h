@@ -63,6 +63,17 @@ enum {
   IIM_EXT_OUTFLOW = 2     /* unbounded, with the vorticity mirrored (even) across the face x_{nx-1/2} */
 };
 
+/* Precision of the Krylov solve.  MIXED: once the GMRES residual estimate
+ * has fallen below tol / 2e-6 (relative), the matrix-vector products apply
+ * the Poisson operator with FP32 FFTs and an FP32 kernel spectrum (inexact
+ * Krylov with relaxation: the FP32 operator's ~2e-7 relative error, times a
+ * safety factor 10, stays below tol / |r_k|).  Free-space exteriors with FFT
+ * sizes >= 256; otherwise FP64.  Every GMRES cycle ends with the FP64
+ * residual b - S x, which alone decides convergence; cycles repeat until it
+ * does (iterative refinement, at most max_refine cycles).  The right-hand
+ * side, the psi recovery, the velocity, the IIM stencils, the transport and
+ * the circulation sums stay FP64, so results meet the same tolerance as FP64.
+ * The dense solver ignores the setting. */
 enum { IIM_PREC_FP64 = 0, IIM_PREC_MIXED = 1 };
 /* Initial guess of each Schur solve:
  *   ZERO        x = 0;
@@ -104,7 +115,7 @@ typedef struct {
   double krylov_tol;      /* stop when ||r|| <= tol ||b|| (relative to b, so warm starts count) */
   int32_t krylov_max_iter;/* total matrix-vector products per solve */
   int32_t krylov_restart; /* GMRES restart length (<= 64) */
-  int32_t max_refine;     /* mixed precision: maximum refinement rounds */
+  int32_t max_refine;     /* mixed precision: maximum refinement rounds (<= 0: 8) */
   int32_t guess;          /* IIM_GUESS_* initial guess of each Schur solve */
   int32_t host_only;      /* 1: build geometry and tables only, allocate nothing on the device */
   int32_t solver;         /* IIM_SOLVER_*; DIRECT stores (|A| + n_circ)^2 doubles on the device */
@@ -178,6 +189,12 @@ int iim_lgf_table(int32_t mx, int32_t my, double* out_host);
  * ring field. */
 int iim_poisson(iim_ctx* ctx, const double* src_dev, double* psi_dev);
 
+/* iim_poisson with FP32 FFTs and kernel spectrum (the operator of the inner
+ * products of the mixed-precision solve; inputs and output FP64).  Needs a
+ * mixed-precision free-space context with FFT sizes >= 256, else
+ * IIM_EUNSUPPORTED. */
+int iim_poisson_fp32(iim_ctx* ctx, const double* src_dev, double* psi_dev);
+
 /* Velocity reconstruction of one stage (Sec. 4.2): solves the Schur system
  * for gamma and the body constants, recovers psi, fills the ghost values and
  * the velocity (extended to A- at third order with u_b).
@@ -217,6 +234,16 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
 int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
 int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
+/* All solver counters since create. */
+typedef struct {
+  int64_t solves;                   /* Schur solves */
+  int64_t krylov_iterations;        /* Arnoldi steps (one product each) */
+  int64_t fp32_products;            /* of which applied in FP32 (mixed precision) */
+  int64_t initial_residual_matvecs; /* FP64 products for initial residuals of warm starts */
+  int64_t network_kept, network_rejected;
+  int64_t recorded;                 /* solves held by iim_record_solves */
+} iim_counters;
+int iim_solver_counters(const iim_ctx* ctx, iim_counters* out);
 /* Repeat the largest launch of kernel id 0, 1 or 2 (the FFT passes; made
  * while it was timed) reps times back to back between one pair of HIP events
  * on the context's stream: average duration (ms) and algorithmic bytes of

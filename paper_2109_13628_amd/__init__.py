@@ -27,8 +27,8 @@ SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
-           "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_reconstruct", "iim_rhs",
-           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay",
+           "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_poisson_fp32", "iim_reconstruct", "iim_rhs",
+           "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay", "iim_solver_counters",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
            "iim_net_forward", "iim_net_grad_mse", "iim_net_adam_step", "iim_net_save", "iim_net_load",
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
@@ -78,6 +78,12 @@ class NetDesc(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class Counters(C.Structure):
+    _fields_ = [("solves", C.c_int64), ("krylov_iterations", C.c_int64), ("fp32_products", C.c_int64),
+                ("initial_residual_matvecs", C.c_int64), ("network_kept", C.c_int64),
+                ("network_rejected", C.c_int64), ("recorded", C.c_int64)]
+
+
 class Info(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("n_control", C.c_int32), ("n_affected", C.c_int32),
                 ("n_ghost", C.c_int32), ("n_circ", C.c_int32), ("n_special", C.c_int32), ("fft_mx", C.c_int32),
@@ -123,6 +129,8 @@ def lib():
     L.iim_lgf_table.argtypes = [C.c_int32, C.c_int32, dp]
     L.iim_poisson.restype = ip
     L.iim_poisson.argtypes = [vp, vp, vp]
+    L.iim_poisson_fp32.restype = ip
+    L.iim_poisson_fp32.argtypes = [vp, vp, vp]
     L.iim_reconstruct.restype = ip
     L.iim_reconstruct.argtypes = [vp, vp, dp, vp, vp, vp, C.POINTER(StepStats)]
     L.iim_rhs.restype = ip
@@ -137,6 +145,8 @@ def lib():
     L.iim_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
     L.iim_profile_replay.restype = ip
     L.iim_profile_replay.argtypes = [vp, C.c_int32, C.c_int32, dp, dp]
+    L.iim_solver_counters.restype = ip
+    L.iim_solver_counters.argtypes = [vp, C.POINTER(Counters)]
     L.iim_krylov_totals.restype = ip
     L.iim_krylov_totals.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     i64p = C.POINTER(C.c_int64)
@@ -219,7 +229,7 @@ class Context:
             for q in range(4):
                 arr[k].rect[q] = r[q]
         o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
-                       max_refine=3, guess=guess, host_only=int(host_only), solver=solver)
+                       max_refine=8, guess=guess, host_only=int(host_only), solver=solver)
         if stream is None and not host_only:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -272,6 +282,9 @@ class Context:
     def poisson(self, src, psi):
         self._check(lib().iim_poisson(self._h, _ptr(src), _ptr(psi)), "iim_poisson")
 
+    def poisson_fp32(self, src, psi):
+        self._check(lib().iim_poisson_fp32(self._h, _ptr(src), _ptr(psi)), "iim_poisson_fp32")
+
     def reconstruct(self, omega, Gamma, psi, u, v, allow_noconv=False):
         G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64)))
         st = StepStats()
@@ -308,6 +321,11 @@ class Context:
                     "iim_profile_replay")
         return {"avg_us": 1e3 * ms.value, "bytes_per_launch": b.value, "reps": reps,
                 "GBps": b.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else None}
+
+    def counters(self):
+        o = Counters()
+        self._check(lib().iim_solver_counters(self._h, C.byref(o)), "iim_solver_counters")
+        return {f[0]: getattr(o, f[0]) for f in Counters._fields_}
 
     def krylov_totals(self):
         s, m = C.c_int64(), C.c_int64()

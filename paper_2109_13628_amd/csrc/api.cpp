@@ -216,6 +216,20 @@ void setup_device(iim_ctx* c) {
     f.tw_xr = c->upload(twid(mx, f.hx + 1));
     f.tw_y = c->upload(twid(my, my));
     f.spec = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
+    if (c->precision == IIM_PREC_MIXED && conv_reg_supported(f.hx, f.my)) {
+      // FP32 tables for the inner matrix-vector products
+      auto to32 = [](const std::vector<double2>& t) {
+        std::vector<float2> o(t.size());
+        for (size_t q = 0; q < t.size(); ++q) o[q] = make_float2((float)t[q].x, (float)t[q].y);
+        return o;
+      };
+      std::vector<float> gh32(ghat.begin(), ghat.end());
+      f.ghat32 = c->upload(gh32);
+      f.tw_x32 = c->upload(to32(twid(f.hx, f.hx)));
+      f.tw_xr32 = c->upload(to32(twid(mx, f.hx + 1)));
+      f.tw_y32 = c->upload(to32(twid(my, my)));
+      f.spec32 = c->dalloc<float2>((size_t)(f.hx + 1) * f.ld);
+    }
   }
   // Krylov state
   DKrylov& k = c->dk;
@@ -256,12 +270,12 @@ void setup_device(iim_ctx* c) {
 
 // psi (ring) = G(source), source = mask(omega) + sgn * E_a gam, rows [rj0, rj1] -> [oj0, oj1]
 void iim::apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
-             int oj0, int oj1, double* psi, const double* done) {
+             int oj0, int oj1, double* psi, const double* done, bool fp32) {
   if (c->box)
     launch_dst(dg, c->dd, omega, gam, sgn, psi, done, c->stream);
   else
     launch_conv(dg, c->df, omega, gam, sgn, rj0, rj1, oj0, oj1, psi, done, c->stream,
-                c->prof.mask ? &c->prof : nullptr);
+                c->prof.mask ? &c->prof : nullptr, fp32);
 }
 
 
@@ -369,10 +383,23 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   // when the iteration limit is reached.
   bool done = c->st_host[KS_DONE] != 0.0;
   double last_true = c->st_host[KS_RES];
-  int stalls = 0;
+  int stalls = 0, rounds = 0;
+  // Mixed precision (inexact Krylov with relaxation): a product may carry an
+  // error of about tol / |r_k| relative to the current residual r_k without
+  // spoiling convergence to tol, so once the residual estimate has fallen to
+  // tol / eps32 (eps32: the FP32 operator's relative error, with a safety
+  // factor) the Arnoldi products apply G in FP32.  Every cycle ends with the
+  // FP64 residual b - S x, which alone decides convergence; a cycle whose
+  // estimate met tol while the true residual did not is followed by another
+  // (iterative refinement).
+  const bool mixed = c->precision == IIM_PREC_MIXED && c->df.spec32 != nullptr;
+  const double fp32_below = c->tol / c->eps32;
   while (!done && total < c->max_iter) {
     for (int j = 0; j < k.m && total < c->max_iter; ++j) {
-      apply_G(c, dg, nullptr, k.V + (size_t)j * k.n, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, k.st);
+      const bool fp32 = mixed && c->st_host[KS_RES] <= fp32_below;
+      c->n_fp32_products += fp32 ? 1 : 0;
+      apply_G(c, dg, nullptr, k.V + (size_t)j * k.n, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, k.st,
+              fp32);
       launch_arnoldi(dg, k, c->psi, j, c->stream, c->prof.mask ? &c->prof : nullptr);
       ++total;
       if ((j + 1) % c->chunk == 0 || j + 1 == k.m || total >= c->max_iter) {
@@ -381,19 +408,22 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
       }
     }
     launch_gmres_update(k, c->stream);
-    // true residual and restart
+    // true residual (FP64) and restart
     apply_G(c, dg, nullptr, k.x, 1.0, g.src_j0, g.src_j1, g.out_j0, g.out_j1, c->psi, nullptr);
     launch_matvec_finish(dg, k, c->psi, k.x, k.w, c->stream);
     launch_krylov_start(dg, k, false, c->stream);
     read_status(c);
+    ++rounds;
     done = c->st_host[KS_DONE] != 0.0 || c->st_host[KS_NFAIL] != 0.0;
     const double now = c->st_host[KS_RES];
     // stop when restarts no longer reduce the true residual (rounding floor)
     if (!done && now > 0.5 * last_true && ++stalls >= 2) break;
+    if (mixed && rounds >= c->max_refine) break;
     last_true = now;
   }
   read_status(c);
   iters = (int)c->st_host[KS_ITERS];
+  c->last_rounds = rounds;
   c->n_solves += 1;
   c->n_matvecs += iters;
   c->n_extra_matvecs += extra;
@@ -431,6 +461,7 @@ int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
     const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1);
     c->cur_stage = -1;
     st.iters[s] = it;
+    st.refine_rounds[s] = c->last_rounds;
     st.res0[s] = r0;
     st.res[s] = r1;
     if (rc == IIM_ENONFINITE) return rc;
@@ -561,6 +592,7 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       if (opts->krylov_tol > 0) c->tol = opts->krylov_tol;
       if (opts->krylov_max_iter > 0) c->max_iter = opts->krylov_max_iter;
       if (opts->krylov_restart > 0) c->restart = std::min(64, opts->krylov_restart);
+      if (opts->max_refine > 0) c->max_refine = opts->max_refine;
       c->guess = opts->guess;
       c->host_only = opts->host_only != 0;
       c->solver = opts->solver;
@@ -689,6 +721,23 @@ int iim_poisson(iim_ctx* c, const double* src, double* psi) {
   return IIM_OK;
 }
 
+int iim_poisson_fp32(iim_ctx* c, const double* src, double* psi) {
+  if (!c || !src || !psi) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  if (!c->df.spec32) return fail(c, IIM_EUNSUPPORTED, "no FP32 convolution (mixed precision, free space, FFT sizes >= 256)");
+  try {
+    DGeom dg = c->dg;
+    dg.cls = c->cls_zero;
+    dg.na = 0;
+    const int ny = c->geo.grid.ny;
+    apply_G(c, dg, src, nullptr, 0.0, 0, ny - 1, -1, ny, psi, nullptr, true);
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
 int iim_reconstruct(iim_ctx* c, const double* omega, const double* Gamma_host, double* psi, double* u, double* v,
                     iim_step_stats* stats) {
   if (!c || !omega || !u || !v || (c->geo.nbc() > 0 && !Gamma_host)) return IIM_EINVAL;
@@ -708,6 +757,7 @@ int iim_reconstruct(iim_ctx* c, const double* omega, const double* Gamma_host, d
     if (stats) {
       *stats = iim_step_stats{};
       stats->iters[0] = it;
+      stats->refine_rounds[0] = c->last_rounds;
       stats->res0[0] = r0;
       stats->res[0] = r1;
       stats->converged = rc == IIM_OK;
@@ -812,6 +862,18 @@ int iim_profile_replay(iim_ctx* c, int32_t kernel_id, int32_t reps, double* avg_
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
   }
+  return IIM_OK;
+}
+
+int iim_solver_counters(const iim_ctx* c, iim_counters* o) {
+  if (!c || !o) return IIM_EINVAL;
+  o->solves = c->n_solves;
+  o->krylov_iterations = c->n_matvecs;
+  o->fp32_products = c->n_fp32_products;
+  o->initial_residual_matvecs = c->n_extra_matvecs;
+  o->network_kept = c->n_net_used;
+  o->network_rejected = c->n_net_rejected;
+  o->recorded = c->rec_count;
   return IIM_OK;
 }
 

@@ -64,6 +64,10 @@ struct iim_ctx {
   int precision = IIM_PREC_FP64;
   double tol = 1e-13;
   int max_iter = 400, restart = 40, guess = IIM_GUESS_PREVIOUS, chunk = 4;
+  double eps32 = 2e-6;            // mixed precision: FP32 operator error (measured ~2e-7) x 10
+  long n_fp32_products = 0;       // Arnoldi products applied in FP32
+  int max_refine = 8;             // mixed precision: FP64 residual evaluations per solve
+  int last_rounds = 0;            // GMRES cycles (FP64 residual evaluations) of the last solve
   std::vector<void*> allocs;
   size_t dev_bytes = 0;
   iim::DGeom dg{};
@@ -138,7 +142,7 @@ namespace iim {
 
 // api.cpp
 void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
-             int oj0, int oj1, double* psi, const double* done);
+             int oj0, int oj1, double* psi, const double* done, bool fp32 = false);
 void build_schur_t(iim_ctx* c, double* St);   // St[q][i] = (S e_q)_i
 void read_status(iim_ctx* c);
 void set_status(iim_ctx* c);

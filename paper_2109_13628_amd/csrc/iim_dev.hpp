@@ -62,6 +62,13 @@ struct DFft {
   const double2* tw_xr;        // exp(-2 pi i k / mx), k <= mx/2 (real-FFT post-processing)
   const double2* tw_y;         // exp(-2 pi i k / my), k < my
   double2* spec;               // [mx/2+1][ld]
+  // FP32 copies for the inner products of the mixed-precision solve (null
+  // unless the context is mixed precision)
+  const float* ghat32 = nullptr;
+  const float2* tw_x32 = nullptr;
+  const float2* tw_xr32 = nullptr;
+  const float2* tw_y32 = nullptr;
+  float2* spec32 = nullptr;
   bool outflow;
   bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
 };
@@ -203,9 +210,12 @@ inline long grid_size(dim3 g) { return (long)g.x * g.y * g.z; }
 // ---------------------------------------------------------------- launchers
 // Poisson operator (free space): psi_ring rows [oj0, oj1] from sources in rows [rj0, rj1].
 // source = mask(omega) (omega may be null) + sgn * scatter(gam) (gam may be null).
+// fp32: FFTs and kernel multiply in FP32 (inputs and psi stay FP64); needs the
+// FP32 tables and FFT sizes >= 256 (otherwise FP64).
+bool conv_reg_supported(int hx, int my);
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
-                 hipStream_t s, Prof* prof = nullptr);
+                 hipStream_t s, Prof* prof = nullptr, bool fp32 = false);
 void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
                 double* psi_ring, const double* done_flag, hipStream_t s);
 void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,

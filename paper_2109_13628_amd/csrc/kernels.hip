@@ -36,6 +36,27 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+
+// complex type -> its real type; complex from two reals
+template <class CX>
+struct Real;
+template <>
+struct Real<double2> { using t = double; };
+template <>
+struct Real<float2> { using t = float; };
+template <class CX, class A, class B>
+__device__ __forceinline__ CX mkc(A x, B y) {
+  CX r;
+  r.x = (typename Real<CX>::t)x;
+  r.y = (typename Real<CX>::t)y;
+  return r;
+}
 
 // ------------------------------------------------------------------ FFT core
 template <int N>
@@ -304,14 +325,15 @@ static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, do
     default: break;                                       \
   }
 
-bool conv_reg_supported(int hx, int my);
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
-                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof);
+                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
+                     bool fp32);
 
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
-                 int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
+                 int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
+                 bool fp32) {
   if (f.use_reg && conv_reg_supported(f.hx, f.my)) {
-    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof);
+    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof, fp32 && f.spec32);
     return;
   }
   const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
@@ -1148,6 +1170,30 @@ struct RegCfg {
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
 
+// Typed view of the convolution tables: FP64, or the FP32 copies used by the
+// inner matrix-vector products of the mixed-precision solve.
+template <class CX>
+struct FftT {
+  CX* spec;
+  const CX* tw_x;
+  const CX* tw_xr;
+  const CX* tw_y;
+  const typename Real<CX>::t* ghat;
+};
+template <class CX>
+__device__ __forceinline__ FftT<CX> fft_view(const DFft& f);
+template <>
+__device__ __forceinline__ FftT<double2> fft_view<double2>(const DFft& f) {
+  return FftT<double2>{f.spec, f.tw_x, f.tw_xr, f.tw_y, f.ghat};
+}
+template <>
+__device__ __forceinline__ FftT<float2> fft_view<float2>(const DFft& f) {
+  return FftT<float2>{f.spec32, f.tw_x32, f.tw_xr32, f.tw_y32, f.ghat32};
+}
+
+// a comma inside a macro argument (template arguments of a launched kernel)
+#define IIM_COMMA ,
+
 // The hardware deals consecutive workgroups round-robin to the 8 XCDs, each
 // with its own L2.  Row passes give consecutive spectrum rows to consecutive
 // logical blocks, and 128-byte lines of the spectrum span several of them:
@@ -1160,10 +1206,10 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
-  const double2 s0 = cadd(a0, a2), d0 = csub(a0, a2), s1 = cadd(a1, a3), d1 = csub(a1, a3);
-  const double2 e = INV ? make_double2(-d1.y, d1.x) : make_double2(d1.y, -d1.x);
+template <bool INV, class CX>
+__device__ __forceinline__ void dft4(CX& a0, CX& a1, CX& a2, CX& a3) {
+  const CX s0 = cadd(a0, a2), d0 = csub(a0, a2), s1 = cadd(a1, a3), d1 = csub(a1, a3);
+  const CX e = INV ? mkc<CX>(-d1.y, d1.x) : mkc<CX>(d1.y, -d1.x);
   a0 = cadd(s0, s1);
   a2 = csub(s0, s1);
   a1 = cadd(d0, e);
@@ -1171,9 +1217,11 @@ __device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, doub
 }
 
 // exp(-2 pi i e / 16) (forward) for e = 0..15
-__device__ __forceinline__ double2 w16(int e, bool inv) {
-  const double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173, R2 = 0.70710678118654752440;
-  double c, s;
+template <class CX>
+__device__ __forceinline__ CX w16(int e, bool inv) {
+  using S = typename Real<CX>::t;
+  const S C1 = (S)0.92387953251128675613, S1 = (S)0.38268343236508977173, R2 = (S)0.70710678118654752440;
+  S c, s;
   switch (e & 15) {
     case 0: c = 1.0; s = 0.0; break;
     case 1: c = C1; s = S1; break;
@@ -1192,13 +1240,13 @@ __device__ __forceinline__ double2 w16(int e, bool inv) {
     case 14: c = R2; s = -R2; break;
     default: c = C1; s = -S1; break;
   }
-  return make_double2(c, inv ? s : -s);
+  return mkc<CX>(c, inv ? s : -s);
 }
 
-template <int R, bool INV>
-__device__ __forceinline__ void dftR(double2 (&u)[R]) {
+template <int R, bool INV, class CX>
+__device__ __forceinline__ void dftR(CX (&u)[R]) {
   if constexpr (R == 2) {
-    const double2 a = u[0];
+    const CX a = u[0];
     u[0] = cadd(a, u[1]);
     u[1] = csub(a, u[1]);
   } else if constexpr (R == 4) {
@@ -1207,11 +1255,11 @@ __device__ __forceinline__ void dftR(double2 (&u)[R]) {
     // n = q + 2 m: inner DFT4 over m, twiddle W8^{q s}, outer DFT2 over q
     dft4<INV>(u[0], u[2], u[4], u[6]);
     dft4<INV>(u[1], u[3], u[5], u[7]);
-    double2 o[8];
+    CX o[8];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const double2 a = u[2 * s];
-      const double2 b = cmul(u[2 * s + 1], w16(2 * s, INV));
+      const CX a = u[2 * s];
+      const CX b = cmul(u[2 * s + 1], w16<CX>(2 * s, INV));
       o[s] = cadd(a, b);
       o[s + 4] = csub(a, b);
     }
@@ -1223,13 +1271,13 @@ __device__ __forceinline__ void dftR(double2 (&u)[R]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) dft4<INV>(u[q], u[q + 4], u[q + 8], u[q + 12]);
     // after the inner DFT, element q + 4 s holds A[q][s]
-    double2 o[16];
+    CX o[16];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      double2 b0 = u[0 + 4 * s];
-      double2 b1 = cmul(u[1 + 4 * s], w16(1 * s, INV));
-      double2 b2 = cmul(u[2 + 4 * s], w16(2 * s, INV));
-      double2 b3 = cmul(u[3 + 4 * s], w16(3 * s, INV));
+      CX b0 = u[0 + 4 * s];
+      CX b1 = cmul(u[1 + 4 * s], w16<CX>(1 * s, INV));
+      CX b2 = cmul(u[2 + 4 * s], w16<CX>(2 * s, INV));
+      CX b3 = cmul(u[3 + 4 * s], w16<CX>(3 * s, INV));
       dft4<INV>(b0, b1, b2, b3);
       o[s] = b0;
       o[s + 4] = b1;
@@ -1241,10 +1289,10 @@ __device__ __forceinline__ void dftR(double2 (&u)[R]) {
   }
 }
 
-template <int N, int T, int E, int R, int NS, bool INV, bool LAST>
-__device__ __forceinline__ void reg_pass(double2 (&v)[E], double2* lds, int t, const double2* __restrict__ tw) {
+template <int N, int T, int E, int R, int NS, bool INV, bool LAST, class CX>
+__device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
   constexpr int B = E / R;
-  double2 u[B][R];
+  CX u[B][R];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + T * b;
@@ -1255,7 +1303,7 @@ __device__ __forceinline__ void reg_pass(double2 (&v)[E], double2* lds, int t, c
       constexpr int step = N / (NS * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        double2 w = tw[r * k * step];
+        CX w = tw[r * k * step];
         if (INV) w.y = -w.y;
         u[b][r] = cmul(u[b][r], w);
       }
@@ -1283,8 +1331,8 @@ __device__ __forceinline__ void reg_pass(double2 (&v)[E], double2* lds, int t, c
   }
 }
 
-template <int N, bool INV>
-__device__ __forceinline__ void fft_reg(double2 (&v)[RP<N>::E], double2* lds, int t, const double2* __restrict__ tw) {
+template <int N, bool INV, class CX>
+__device__ __forceinline__ void fft_reg(CX (&v)[RP<N>::E], CX* lds, int t, const CX* __restrict__ tw) {
   constexpr int T = RP<N>::T, E = RP<N>::E;
   if constexpr (N == 256) {
     reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
@@ -1323,33 +1371,35 @@ __device__ __forceinline__ void fft_reg(double2 (&v)[RP<N>::E], double2* lds, in
 }
 
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
-template <int MY>
+template <int MY, class CX>
 __global__ void __launch_bounds__(RegCfg<MY>::THREADS)
 k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
   using C = RegCfg<MY>;
+  using S = typename Real<CX>::t;
+  const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<MY>::T, E = RP<MY>::E;
-  __shared__ double2 lds[C::PER][C::LDSN];
+  __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int w = threadIdx.x / T, t = threadIdx.x % T;
   const int kx = blockIdx.x * C::PER + w;
   const bool valid = kx <= f.hx;
-  double2* col = f.spec + (size_t)(valid ? kx : 0) * f.ld;
-  double2 v[E];
+  CX* col = ft.spec + (size_t)(valid ? kx : 0) * f.ld;
+  CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    v[m] = (valid && n >= rj0 && n <= rj1) ? col[n + 1] : make_double2(0.0, 0.0);
+    v[m] = (valid && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
   }
-  fft_reg<MY, false>(v, lds[w], t, f.tw_y);
-  const double* gh = f.ghat + (size_t)(valid ? kx : 0) * (MY / 2 + 1);
+  fft_reg<MY, false>(v, lds[w], t, ft.tw_y);
+  const S* gh = ft.ghat + (size_t)(valid ? kx : 0) * (MY / 2 + 1);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    const double s = gh[n <= MY / 2 ? n : MY - n];
+    const S s = gh[n <= MY / 2 ? n : MY - n];
     v[m].x *= s;
     v[m].y *= s;
   }
-  fft_reg<MY, true>(v, lds[w], t, f.tw_y);
+  fft_reg<MY, true>(v, lds[w], t, ft.tw_y);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -1361,8 +1411,8 @@ k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __
 }
 
 // ---- forward rows: real FFT of length 2 HX (half-length complex FFT + split)
-template <int HX>
-__device__ __forceinline__ void add_at(double2 (&v)[RP<HX>::E], int t, int i, double val) {
+template <int HX, class CX>
+__device__ __forceinline__ void add_at(CX (&v)[RP<HX>::E], int t, int i, double val) {
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
   const int n = i >> 1;
   if ((n % T) != t) return;
@@ -1374,23 +1424,25 @@ __device__ __forceinline__ void add_at(double2 (&v)[RP<HX>::E], int t, int i, do
     }
 }
 
-template <int HX>
+template <int HX, class CX>
 __global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
 k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
                int j0, int count, const double* __restrict__ done) {
   using C = RegCfg<HX, true>;
+  using S = typename Real<CX>::t;
+  const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
-  __shared__ double2 lds[C::PER][C::LDSN];
+  __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int w = threadIdx.x / T, t = threadIdx.x % T;
   const int lb = xcd_block();
   const int jrow = j0 + lb * C::PER + w;
   const bool valid = (jrow < j0 + count) && jrow >= 0 && jrow < g.ny;
-  double2 v[E];
+  CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    double2 z = make_double2(0.0, 0.0);
+    CX z = mkc<CX>(0, 0);
     if (valid && omega) {
       const int i0 = 2 * n, i1 = 2 * n + 1;
       int m0 = i0, m1 = i1;
@@ -1412,16 +1464,16 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
       if (f.outflow) add_at<HX>(v, t, 2 * g.nx - 1 - i, val);
     }
   }
-  fft_reg<HX, false>(v, lds[w], t, f.tw_x);
+  fft_reg<HX, false>(v, lds[w], t, ft.tw_x);
 #pragma unroll
   for (int m = 0; m < E; ++m) lds[w][padi(t + T * m)] = v[m];
   // split twiddles of this thread's bins, loaded before the barrier
   constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
-  double2 wk[IT];
+  CX wk[IT];
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
-    wk[q] = idx < (HX + 1) * C::PER ? f.tw_xr[idx / C::PER] : make_double2(1.0, 0.0);
+    wk[q] = idx < (HX + 1) * C::PER ? ft.tw_xr[idx / C::PER] : mkc<CX>(1, 0);
   }
   __syncthreads();
 #pragma unroll
@@ -1431,35 +1483,36 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
     const int rr = idx % C::PER, k = idx / C::PER;
     const int jj = j0 + lb * C::PER + rr;
     if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
-    const double2 zk = lds[rr][padi(k & (HX - 1))];
-    const double2 zc = conj2(lds[rr][padi((HX - k) & (HX - 1))]);
-    const double2 E2 = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-    const double2 Od = csub(zk, zc);
-    const double2 O = make_double2(0.5 * Od.y, -0.5 * Od.x);
-    f.spec[(size_t)k * f.ld + jj + 1] = cadd(E2, cmul(wk[q], O));
+    const CX zk = lds[rr][padi(k & (HX - 1))];
+    const CX zc = conj2(lds[rr][padi((HX - k) & (HX - 1))]);
+    const CX E2 = mkc<CX>(S(0.5) * (zk.x + zc.x), S(0.5) * (zk.y + zc.y));
+    const CX Od = csub(zk, zc);
+    const CX O = mkc<CX>(S(0.5) * Od.y, S(-0.5) * Od.x);
+    ft.spec[(size_t)k * f.ld + jj + 1] = cadd(E2, cmul(wk[q], O));
   }
 }
 
 // ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
-template <int HX>
+template <int HX, class CX>
 __global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
 k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
   using C = RegCfg<HX, true>;
+  const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
-  __shared__ double2 lds[C::PER][C::LDSN];
+  __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int lb = xcd_block();
   {
     // all loads of this thread in flight before the LDS stores
     constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
-    double2 tmp[IT];
+    CX tmp[IT];
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
       const int idx = threadIdx.x + q * C::THREADS;
       const int rr = idx % C::PER, k = idx / C::PER;
       const int jo = j0 + lb * C::PER + rr;
-      tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? f.spec[(size_t)k * f.ld + jo + 1]
-                                                             : make_double2(0.0, 0.0);
+      tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? ft.spec[(size_t)k * f.ld + jo + 1]
+                                                             : mkc<CX>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
@@ -1469,18 +1522,18 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   }
   __syncthreads();
   const int w = threadIdx.x / T, t = threadIdx.x % T;
-  double2 v[E];
+  CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
-    const double2 xk = lds[w][padi(k)];
-    const double2 xc = conj2(lds[w][padi(HX - k)]);
-    const double2 Ev = cadd(xk, xc);
-    const double2 Ov = cmul(csub(xk, xc), conj2(f.tw_xr[k]));
-    v[m] = make_double2(Ev.x - Ov.y, Ev.y + Ov.x);
+    const CX xk = lds[w][padi(k)];
+    const CX xc = conj2(lds[w][padi(HX - k)]);
+    const CX Ev = cadd(xk, xc);
+    const CX Ov = cmul(csub(xk, xc), conj2(ft.tw_xr[k]));
+    v[m] = mkc<CX>(Ev.x - Ov.y, Ev.y + Ov.x);
   }
   __syncthreads();
-  fft_reg<HX, true>(v, lds[w], t, f.tw_x);
+  fft_reg<HX, true>(v, lds[w], t, ft.tw_x);
   const int jo = j0 + lb * C::PER + w;
   if (jo >= j0 + count) return;
   const int nxr = g.nx + 2;
@@ -1495,54 +1548,62 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   }
 }
 
-template <int HX>
+template <int HX, class CX>
 void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0,
                          int count, const double* done, hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<HX, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
   if (blocks > 0)
-    IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX>, blocks, C::THREADS, s, g, f, omega, gam, sgn, j0,
+    IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX IIM_COMMA CX>, blocks, C::THREADS, s, g, f, omega, gam, sgn, j0,
                count, done);
 }
-template <int MY>
+template <int MY, class CX>
 void cols_reg_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
                      hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<MY>;
   const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY>, blocks, C::THREADS, s, g, f, rj0, rj1, oj0, oj1, done);
+  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX>, blocks, C::THREADS, s, g, f, rj0, rj1, oj0, oj1, done);
 }
-template <int HX>
+template <int HX, class CX>
 void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
                          hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<HX, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
   if (blocks > 0)
-    IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX>, blocks, C::THREADS, s, g, f, j0, count, psi, done);
+    IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX IIM_COMMA CX>, blocks, C::THREADS, s, g, f, j0, count, psi, done);
 }
 
-#define IIM_REG_SWITCH(VAL, FN, ...)                \
+#define IIM_REG_SWITCH(VAL, FN, CXT, ...)           \
   switch (VAL) {                                    \
-    case 256: FN<256>(__VA_ARGS__); break;          \
-    case 512: FN<512>(__VA_ARGS__); break;          \
-    case 1024: FN<1024>(__VA_ARGS__); break;        \
-    case 2048: FN<2048>(__VA_ARGS__); break;        \
-    case 4096: FN<4096>(__VA_ARGS__); break;        \
+    case 256: FN<256, CXT>(__VA_ARGS__); break;     \
+    case 512: FN<512, CXT>(__VA_ARGS__); break;     \
+    case 1024: FN<1024, CXT>(__VA_ARGS__); break;   \
+    case 2048: FN<2048, CXT>(__VA_ARGS__); break;   \
+    case 4096: FN<4096, CXT>(__VA_ARGS__); break;   \
     default: break;                                 \
   }
 
 bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
-                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof) {
+                     int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
+                     bool fp32) {
   const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
   // algorithmic bytes: source rows read (omega) + half spectrum written;
   // spectrum rows in + kernel spectrum + rows out; half spectrum in + ring rows out
-  const double b_fwd = (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1));
-  const double b_col = (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout);
-  const double b_inv = (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2));
-  IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
-  IIM_REG_SWITCH(f.my, cols_reg_launch, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
-  IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
+  const double cb = fp32 ? 8.0 : 16.0, rb = fp32 ? 4.0 : 8.0;
+  const double b_fwd = (double)nin * ((omega ? 8.0 * g.nx : 0.0) + cb * (f.hx + 1));
+  const double b_col = (double)(f.hx + 1) * (cb * nin + rb * (f.my / 2 + 1) + cb * nout);
+  const double b_inv = (double)nout * (cb * (f.hx + 1) + 8.0 * (g.nx + 2));
+  if (fp32) {
+    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.my, cols_reg_launch, float2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
+    IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, float2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
+  } else {
+    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.my, cols_reg_launch, double2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
+    IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, double2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
+  }
 }
 
 }  // namespace iim

@@ -163,6 +163,13 @@ def cylinder_small():
                     center=(1.5, 0.0))
 
 
+def cylinder_mid():
+    """A free-space cylinder case (D=1 at h=1/32, 256x128 nodes) whose FFT
+    sizes (512 x 256) take the register FFT kernels."""
+    return cylinder(nx=256, ny=128, h=1.0 / 32, points=128, dt=0.005, steps=5,
+                    center=(2.0, 0.0))
+
+
 def two_c_shapes_lamb_oseen(n):
     """Two C-shaped bodies of the reconstruction convergence study on the unit
     square, x_ij = (i/n, j/n), free space."""
