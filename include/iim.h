@@ -234,6 +234,19 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
 int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
 int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
+/* FFT tile autotuner: times one full Poisson convolution of this context
+ * (reps repeats) with every instantiated number of FFTs per workgroup of
+ * the row passes and of the column pass (1, 2, 4; shapes over 1024 threads
+ * or 128 KiB of LDS fall back to the default) and keeps the fastest.
+ * Outputs (nullable): the chosen counts (0 = default), the default's and the
+ * best time per convolution in microseconds.  The shapes change only the
+ * work per workgroup, not the arithmetic: results are bitwise the same.
+ * No-op (zeros) for the box exterior and FFT sizes below 256. */
+int iim_autotune(iim_ctx* ctx, int32_t reps, int32_t* row_per, int32_t* col_per, double* us_default,
+                 double* us_best);
+/* Set the FFTs per workgroup directly (0 = default), e.g. from another
+ * context's autotune of the same FFT size. */
+int iim_set_fft_shape(iim_ctx* ctx, int32_t row_per, int32_t col_per);
 /* All solver counters since create. */
 typedef struct {
   int64_t solves;                   /* Schur solves */
@@ -327,6 +340,48 @@ int iim_warm_start_stats(const iim_ctx* ctx, int64_t* recorded, int64_t* net_use
  * geo_host[P][4] (ghost flag, boundary tangent x, y, signed distance / h).
  * Any output pointer may be NULL. */
 int iim_warm_start_sequences(iim_ctx* ctx, int32_t* P, int32_t* perm_host, int32_t* seq_host, float* geo_host);
+
+/* ---- batched serving ----
+ * Many independent simulations (each a grid with its own bodies, as for
+ * iim_create) advanced together: every simulation uses the dense Schur
+ * solver in FP64 (opts->solver and opts->precision are overridden), and one
+ * batch step is one HIP graph holding the RK3 steps of all simulations,
+ * spread over parallel branches.  At create, the FFT tile autotuner runs
+ * once per FFT size and the number of branches (1, 2, 4, 8) is chosen by
+ * timing batch steps on scratch states; iim_batch_info reports both. */
+typedef struct iim_batch iim_batch;
+typedef struct {
+  int32_t fft_mx, fft_my;   /* FFT size this choice applies to */
+  int32_t tuned_on;         /* simulation it was timed on */
+  int32_t row_per, col_per; /* FFTs per workgroup (0 = default) */
+  double us_default, us_best; /* one full convolution, microseconds */
+} iim_batch_tuning;
+typedef struct {
+  int32_t steps;
+  int64_t cells_per_step;   /* grid nodes of all simulations */
+  double ms_total;          /* sum of the batch-step times */
+  double ms_p50, ms_p99, ms_max; /* batch-step time percentiles (HIP events around every graph launch) */
+} iim_batch_stats;
+
+/* grids[n_sims]; n_bodies[n_sims]; bodies[s] = the n_bodies[s] bodies of
+ * simulation s.  Errors as iim_create (the message, from
+ * iim_batch_last_error(NULL), names the simulation). */
+int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* n_bodies,
+                     const iim_body_desc* const* bodies, const iim_solver_opts* opts, void* hip_stream,
+                     iim_batch** out);
+int iim_batch_destroy(iim_batch* batch);
+const char* iim_batch_last_error(const iim_batch* batch);
+/* n_steps RK3 steps of every simulation: omega_dev[s] grid field of
+ * simulation s (in place), Gamma_host[s] its circulations (in place), dt[s]
+ * its step.  The graph is captured on the first call and again whenever a
+ * pointer or a dt changes.  stats (nullable). */
+int iim_batch_step(iim_batch* batch, double* const* omega_dev, double* const* Gamma_host, const double* dt,
+                   int32_t n_steps, iim_batch_stats* stats);
+/* Chosen branch count; the autotuner's choices (tunings: room for n_sims
+ * entries, nullable) and their count; batch-step time (ms) of each branch
+ * count tried, 1, 2, 4, 8 in that order (branch_ms: room for 4, nullable). */
+int iim_batch_info(const iim_batch* batch, int32_t* n_branches, int32_t* n_tunings, iim_batch_tuning* tunings,
+                   double* branch_ms);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,8 @@ EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", 
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
            "iim_net_forward", "iim_net_grad_mse", "iim_net_adam_step", "iim_net_save", "iim_net_load",
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
-           "iim_warm_start_sequences", "iim_reset_history"]
+           "iim_warm_start_sequences", "iim_reset_history", "iim_autotune", "iim_set_fft_shape",
+           "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info"]
 KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport_bulk", "arnoldi"]
 
 
@@ -82,6 +83,16 @@ class Counters(C.Structure):
     _fields_ = [("solves", C.c_int64), ("krylov_iterations", C.c_int64), ("fp32_products", C.c_int64),
                 ("initial_residual_matvecs", C.c_int64), ("network_kept", C.c_int64),
                 ("network_rejected", C.c_int64), ("recorded", C.c_int64)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("fft_mx", C.c_int32), ("fft_my", C.c_int32), ("tuned_on", C.c_int32), ("row_per", C.c_int32),
+                ("col_per", C.c_int32), ("us_default", C.c_double), ("us_best", C.c_double)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("cells_per_step", C.c_int64), ("ms_total", C.c_double),
+                ("ms_p50", C.c_double), ("ms_p99", C.c_double), ("ms_max", C.c_double)]
 
 
 class Info(C.Structure):
@@ -178,6 +189,22 @@ def lib():
     L.iim_warm_start_train.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp]
     L.iim_warm_start_stats.restype = ip
     L.iim_warm_start_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
+    L.iim_autotune.restype = ip
+    L.iim_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp]
+    L.iim_set_fft_shape.restype = ip
+    L.iim_set_fft_shape.argtypes = [vp, C.c_int32, C.c_int32]
+    L.iim_batch_create.restype = ip
+    L.iim_batch_create.argtypes = [C.c_int32, C.POINTER(GridDesc), C.POINTER(C.c_int32),
+                                   C.POINTER(C.POINTER(BodyDesc)), C.POINTER(SolverOpts), vp, C.POINTER(vp)]
+    L.iim_batch_destroy.restype = ip
+    L.iim_batch_destroy.argtypes = [vp]
+    L.iim_batch_last_error.restype = C.c_char_p
+    L.iim_batch_last_error.argtypes = [vp]
+    L.iim_batch_step.restype = ip
+    L.iim_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(C.POINTER(C.c_double)), dp, C.c_int32,
+                                 C.POINTER(BatchStats)]
+    L.iim_batch_info.restype = ip
+    L.iim_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(BatchTuning), dp]
     L.iim_reset_history.restype = ip
     L.iim_reset_history.argtypes = [vp]
     L.iim_warm_start_sequences.restype = ip
@@ -322,6 +349,15 @@ class Context:
         return {"avg_us": 1e3 * ms.value, "bytes_per_launch": b.value, "reps": reps,
                 "GBps": b.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else None}
 
+    def autotune(self, reps=5):
+        r, c, d, b = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+        self._check(lib().iim_autotune(self._h, reps, C.byref(r), C.byref(c), C.byref(d), C.byref(b)),
+                    "iim_autotune")
+        return {"row_per": r.value, "col_per": c.value, "us_default": d.value, "us_best": b.value}
+
+    def set_fft_shape(self, row_per, col_per):
+        self._check(lib().iim_set_fft_shape(self._h, row_per, col_per), "iim_set_fft_shape")
+
     def counters(self):
         o = Counters()
         self._check(lib().iim_solver_counters(self._h, C.byref(o)), "iim_solver_counters")
@@ -447,3 +483,91 @@ class Network:
 
     def load(self, path):
         self._check(lib().iim_net_load(self._h, path.encode()), "iim_net_load")
+
+
+def _grid_desc(grid):
+    g = GridDesc(nx=grid.nx, ny=grid.ny, x0=grid.x0, y0=grid.y0, h=grid.h, exterior=EXT[grid.exterior], nu=grid.nu)
+    g.u_inf[0], g.u_inf[1] = grid.u_inf
+    return g
+
+
+def _body_array(bodies, keep):
+    arr = (BodyDesc * max(1, len(bodies)))()
+    for k, b in enumerate(bodies):
+        p = np.ascontiguousarray(b.points, dtype=np.float64)
+        keep.append(p)
+        arr[k].n_points = p.shape[0]
+        arr[k].xy_host = p.ctypes.data_as(C.POINTER(C.c_double))
+        arr[k].is_enclosure = int(b.is_enclosure)
+        arr[k].center[0], arr[k].center[1] = b.center
+        arr[k].u_rigid[0], arr[k].u_rigid[1] = b.u_rigid
+        arr[k].omega_rigid = b.omega_rigid
+        r = b.rect if b.rect is not None else (-1, -1, -1, -1)
+        for q in range(4):
+            arr[k].rect[q] = r[q]
+    return arr
+
+
+class Batch:
+    """Independent simulations advanced together, one HIP graph per batch
+    step (dense FP64 Schur solver in every simulation)."""
+
+    def __init__(self, workloads, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = len(workloads)
+        grids = (GridDesc * n)(*[_grid_desc(w.grid) for w in workloads])
+        self._keep = []
+        arrs = [_body_array(w.bodies, self._keep) for w in workloads]
+        self._arrs = arrs
+        ptrs = (C.POINTER(BodyDesc) * n)(*[C.cast(a, C.POINTER(BodyDesc)) for a in arrs])
+        nb = (C.c_int32 * n)(*[len(w.bodies) for w in workloads])
+        o = SolverOpts(precision=PREC_FP64, krylov_tol=1e-13, krylov_max_iter=400, krylov_restart=40,
+                       max_refine=8, guess=GUESS_PREVIOUS, host_only=0, solver=SOLVER_DIRECT)
+        h = C.c_void_p()
+        rc = lib().iim_batch_create(n, grids, nb, ptrs, C.byref(o), C.c_void_p(stream or 0), C.byref(h))
+        if rc:
+            raise IIMError(rc, (lib().iim_batch_last_error(None) or b"").decode())
+        self._h = h
+        self.n = n
+        self.workloads = workloads
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iim_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        nbr, nt = C.c_int32(), C.c_int32()
+        tun = (BatchTuning * self.n)()
+        bms = (C.c_double * 4)()
+        rc = lib().iim_batch_info(self._h, C.byref(nbr), C.byref(nt), tun, bms)
+        if rc:
+            raise IIMError(rc, "iim_batch_info")
+        tuning = [{f[0]: getattr(tun[i], f[0]) for f in BatchTuning._fields_} for i in range(nt.value)]
+        tried = [1, 2, 4, 8][:sum(1 for v in bms if v > 0)]
+        return {"branches": nbr.value, "tuning": tuning, "branch_ms": dict(zip(tried, list(bms)[:len(tried)]))}
+
+    def step(self, omegas, gammas, dts, n_steps=1):
+        """omegas: contiguous float64 CUDA tensors [ny][nx] (in place);
+        gammas: list of float64 numpy arrays (in place); dts: per simulation."""
+        n = self.n
+        om = (C.c_void_p * n)(*[_ptr(t) for t in omegas])
+        gs = [np.ascontiguousarray(g, dtype=np.float64) if np.size(g) else np.zeros(1) for g in gammas]
+        gp = (C.POINTER(C.c_double) * n)(*[g.ctypes.data_as(C.POINTER(C.c_double)) for g in gs])
+        dt = (C.c_double * n)(*dts)
+        st = BatchStats()
+        rc = lib().iim_batch_step(self._h, om, gp, dt, n_steps, C.byref(st))
+        if rc:
+            raise IIMError(rc, (lib().iim_batch_last_error(self._h) or b"").decode())
+        for g_in, g_out in zip(gammas, gs):
+            if np.size(g_in):
+                g_in[...] = g_out[:np.size(g_in)]
+        return {f[0]: getattr(st, f[0]) for f in BatchStats._fields_}

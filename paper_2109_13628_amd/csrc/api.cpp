@@ -9,6 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +34,32 @@ int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;
   return p;
+}
+
+// Kernel spectrum of the lattice Green's function on an mx x my torus for
+// h = 1 (the spectrum for spacing h is h^2 times it), computed once per torus
+// size in this process: contexts of equal FFT size share it.
+std::vector<double> kernel_spectrum(int mx, int my, double h) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::shared_ptr<const std::vector<double>>> cache;
+  std::shared_ptr<const std::vector<double>> unit;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({mx, my});
+    if (it != cache.end()) unit = it->second;
+  }
+  if (!unit) {
+    std::vector<double> tab((size_t)(mx / 2 + 1) * (my / 2 + 1));
+    lgf_table(mx / 2, my / 2, tab.data());
+    auto spec = std::make_shared<std::vector<double>>((size_t)(mx / 2 + 1) * (my / 2 + 1));
+    lgf_spectrum(mx, my, 1.0, tab.data(), mx / 2, spec->data());
+    std::lock_guard<std::mutex> lk(mu);
+    unit = cache.emplace(std::make_pair(mx, my), spec).first->second;
+  }
+  std::vector<double> out(unit->size());
+  const double h2 = h * h;
+  for (size_t q = 0; q < out.size(); ++q) out[q] = h2 * (*unit)[q];
+  return out;
 }
 
 }  // namespace
@@ -199,10 +228,7 @@ void setup_device(iim_ctx* c) {
     f.ld = ny + 2;
     f.outflow = outflow;
     f.use_reg = std::getenv("IIM_FFT_LDS_ONLY") == nullptr;
-    std::vector<double> tab((size_t)(mx / 2 + 1) * (my / 2 + 1));
-    lgf_table(mx / 2, my / 2, tab.data());
-    std::vector<double> ghat((size_t)(mx / 2 + 1) * (my / 2 + 1));
-    lgf_spectrum(mx, my, h, tab.data(), mx / 2, ghat.data());
+    const std::vector<double> ghat = kernel_spectrum(mx, my, h);
     f.ghat = c->upload(ghat);
     auto twid = [](int n, int count) {
       std::vector<double2> t(count);
@@ -439,7 +465,9 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   return IIM_OK;
 }
 
-int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
+}  // namespace
+
+int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
   const size_t N = (size_t)c->geo.grid.nx * c->geo.grid.ny;
   const DGeom& dg = c->dg;
   launch_fill(c->Qw, 0.0, N, c->stream);
@@ -480,6 +508,8 @@ int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
   if (stats) *stats = st;
   return status;
 }
+
+namespace {
 
 // Direct solver: the whole step is a fixed kernel sequence without host
 // synchronisation; capture it once on an internal stream and replay it.
@@ -874,6 +904,68 @@ int iim_solver_counters(const iim_ctx* c, iim_counters* o) {
   o->network_kept = c->n_net_used;
   o->network_rejected = c->n_net_rejected;
   o->recorded = c->rec_count;
+  return IIM_OK;
+}
+
+int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, double* us_default,
+                 double* us_best) {
+  if (!c || reps < 1) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    int br = 0, bc = 0;
+    double best = 0.0, def = 0.0;
+    if (!c->box && conv_reg_supported(c->df.hx, c->df.my)) {
+      const int nx = c->geo.grid.nx, ny = c->geo.grid.ny;
+      if (c->gexec) {  // a captured step graph keeps the old shapes
+        HIPCHK(hipGraphExecDestroy(c->gexec));
+        c->gexec = nullptr;
+      }
+      launch_fill(c->wtmp, 0.0, (size_t)nx * ny, c->stream);
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      const int opts[3] = {1, 2, 4};
+      best = 1e300;
+      for (int r = -1; r < 3; ++r)
+        for (int q = -1; q < 3; ++q) {
+          if ((r < 0) != (q < 0)) continue;        // (-1, -1): the defaults
+          c->df.row_per = r < 0 ? 0 : opts[r];
+          c->df.col_per = q < 0 ? 0 : opts[q];
+          for (int w = 0; w < 2; ++w) apply_G(c, c->dg, c->wtmp, nullptr, 0.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+          HIPCHK(hipEventRecord(a, c->stream));
+          for (int w = 0; w < reps; ++w) apply_G(c, c->dg, c->wtmp, nullptr, 0.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+          HIPCHK(hipEventRecord(b, c->stream));
+          HIPCHK(hipEventSynchronize(b));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, a, b));
+          const double us = 1e3 * ms / reps;
+          if (r < 0) def = us;
+          if (us < best) best = us, br = c->df.row_per, bc = c->df.col_per;
+        }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      c->df.row_per = br;
+      c->df.col_per = bc;
+      HIPCHK(hipGetLastError());
+    }
+    if (row_per) *row_per = br;
+    if (col_per) *col_per = bc;
+    if (us_default) *us_default = def;
+    if (us_best) *us_best = best;
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_set_fft_shape(iim_ctx* c, int32_t row_per, int32_t col_per) {
+  if (!c || row_per < 0 || col_per < 0) return IIM_EINVAL;
+  c->df.row_per = row_per;
+  c->df.col_per = col_per;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
   return IIM_OK;
 }
 

@@ -146,6 +146,8 @@ void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam
 void build_schur_t(iim_ctx* c, double* St);   // St[q][i] = (S e_q)_i
 void read_status(iim_ctx* c);
 void set_status(iim_ctx* c);
+// one RK3 step of the context's state (kernels enqueued on c->stream)
+int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats);
 
 // warm_start.cpp
 // Prepare the initial guess of the Krylov solve whose right-hand side is in

@@ -71,6 +71,7 @@ struct DFft {
   float2* spec32 = nullptr;
   bool outflow;
   bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
+  int row_per = 0, col_per = 0; // FFTs per workgroup of the row / column passes (0: default; tuned)
 };
 
 struct DDst {                  // box: dense orthonormal sine transforms

@@ -24,6 +24,8 @@
 // rotations, all in one workgroup per step, state in device memory.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "iim_dev.hpp"
 
 namespace iim {
@@ -1158,15 +1160,26 @@ template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
 #ifndef IIM_COL_FFTS_PER_BLOCK
 #define IIM_COL_FFTS_PER_BLOCK 4
 #endif
-// FFTs per block: ROWS for the row passes, otherwise the column pass
+// FFTs per block: the default of the row passes (ROWS) and of the column
+// pass; a tuned value (DFft::row_per / col_per) selects another instantiation
 template <int N, bool ROWS = false>
-struct RegCfg {
+struct RegDef {
   static constexpr int T = RP<N>::T;
   static constexpr int WANT = ROWS ? IIM_ROW_FFTS_PER_BLOCK : IIM_COL_FFTS_PER_BLOCK;
   static constexpr int PER = (WANT * T > 256) ? (256 / T > 0 ? 256 / T : 1) : WANT;
+};
+template <int N, int PER_>
+struct RegCfg {
+  static constexpr int T = RP<N>::T;
+  static constexpr int PER = PER_;
   static constexpr int THREADS = PER * T;
   static constexpr int LDSN = N + N / 16 + 1;      // padded length (one pad slot per 16 points)
 };
+// instantiated tile shapes: at most 1024 threads and 128 KiB of LDS per block
+template <int N, int PER, class CX>
+constexpr bool per_ok() {
+  return PER * RP<N>::T <= 1024 && (size_t)PER * (N + N / 16 + 1) * sizeof(CX) <= 131072;
+}
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
 
@@ -1371,10 +1384,10 @@ __device__ __forceinline__ void fft_reg(CX (&v)[RP<N>::E], CX* lds, int t, const
 }
 
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
-template <int MY, class CX>
-__global__ void __launch_bounds__(RegCfg<MY>::THREADS)
+template <int MY, class CX, int PER>
+__global__ void __launch_bounds__((RegCfg<MY, PER>::THREADS))
 k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
-  using C = RegCfg<MY>;
+  using C = RegCfg<MY, PER>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<MY>::T, E = RP<MY>::E;
@@ -1424,11 +1437,11 @@ __device__ __forceinline__ void add_at(CX (&v)[RP<HX>::E], int t, int i, double 
     }
 }
 
-template <int HX, class CX>
-__global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
+template <int HX, class CX, int PER>
+__global__ void __launch_bounds__((RegCfg<HX, PER>::THREADS))
 k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
                int j0, int count, const double* __restrict__ done) {
-  using C = RegCfg<HX, true>;
+  using C = RegCfg<HX, PER>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
@@ -1493,10 +1506,10 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
 }
 
 // ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
-template <int HX, class CX>
-__global__ void __launch_bounds__((RegCfg<HX, true>::THREADS))
+template <int HX, class CX, int PER>
+__global__ void __launch_bounds__((RegCfg<HX, PER>::THREADS))
 k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
-  using C = RegCfg<HX, true>;
+  using C = RegCfg<HX, PER>;
   const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RP<HX>::T, E = RP<HX>::E;
   __shared__ CX lds[C::PER][C::LDSN];
@@ -1548,29 +1561,62 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   }
 }
 
+template <int HX, class CX, int PER>
+void rows_fwd_go(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0, int count,
+                 const double* done, hipStream_t s, Prof* prof, double bytes) {
+  using C = RegCfg<HX, PER>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0)
+    IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f,
+               omega, gam, sgn, j0, count, done);
+}
+template <int MY, class CX, int PER>
+void cols_go(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done, hipStream_t s,
+             Prof* prof, double bytes) {
+  using C = RegCfg<MY, PER>;
+  const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
+  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f, rj0, rj1,
+             oj0, oj1, done);
+}
+template <int HX, class CX, int PER>
+void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done, hipStream_t s,
+                 Prof* prof, double bytes) {
+  using C = RegCfg<HX, PER>;
+  const int blocks = (count + C::PER - 1) / C::PER;
+  if (blocks > 0)
+    IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f,
+               j0, count, psi, done);
+}
+
+// Dispatch on the tuned FFTs-per-block (FP64 only; the FP32 inner products
+// keep the default shape).  0 or an unavailable value: the default.
+#define IIM_PER_DISPATCH(N, CX, PER_RUNTIME, ROWS, GO, ...)                            \
+  do {                                                                                 \
+    constexpr int D_ = RegDef<N, ROWS>::PER;                                           \
+    if constexpr (std::is_same<CX, double2>::value) {                                  \
+      if ((PER_RUNTIME) == 1 && per_ok<N, 1, CX>()) { GO<N, CX, 1>(__VA_ARGS__); break; } \
+      if constexpr (per_ok<N, 2, CX>())                                                \
+        if ((PER_RUNTIME) == 2) { GO<N, CX, 2>(__VA_ARGS__); break; }                  \
+      if constexpr (per_ok<N, 4, CX>())                                                \
+        if ((PER_RUNTIME) == 4) { GO<N, CX, 4>(__VA_ARGS__); break; }                  \
+    }                                                                                  \
+    GO<N, CX, D_>(__VA_ARGS__);                                                        \
+  } while (0)
+
 template <int HX, class CX>
 void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0,
                          int count, const double* done, hipStream_t s, Prof* prof, double bytes) {
-  using C = RegCfg<HX, true>;
-  const int blocks = (count + C::PER - 1) / C::PER;
-  if (blocks > 0)
-    IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX IIM_COMMA CX>, blocks, C::THREADS, s, g, f, omega, gam, sgn, j0,
-               count, done);
+  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_fwd_go, g, f, omega, gam, sgn, j0, count, done, s, prof, bytes);
 }
 template <int MY, class CX>
 void cols_reg_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
                      hipStream_t s, Prof* prof, double bytes) {
-  using C = RegCfg<MY>;
-  const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX>, blocks, C::THREADS, s, g, f, rj0, rj1, oj0, oj1, done);
+  IIM_PER_DISPATCH(MY, CX, f.col_per, false, cols_go, g, f, rj0, rj1, oj0, oj1, done, s, prof, bytes);
 }
 template <int HX, class CX>
 void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
                          hipStream_t s, Prof* prof, double bytes) {
-  using C = RegCfg<HX, true>;
-  const int blocks = (count + C::PER - 1) / C::PER;
-  if (blocks > 0)
-    IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX IIM_COMMA CX>, blocks, C::THREADS, s, g, f, j0, count, psi, done);
+  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_inv_go, g, f, j0, count, psi, done, s, prof, bytes);
 }
 
 #define IIM_REG_SWITCH(VAL, FN, CXT, ...)           \

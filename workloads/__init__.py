@@ -272,3 +272,42 @@ def multi_body(n=2048, seed=3, steps=500):
     dt = dt_from_polygon(h, nu, a_max, 0.5)
     return Workload("multi_body_%d_outflow_seed%d" % (n, seed), grid, bodies, dt, steps,
                     extra={"Re": re})
+
+
+def batch_serving(n_sims=64, seed=5, nmin=256, nmax=1024, length=4.0):
+    """Independent free-space simulations: square grids of N x N nodes with
+    N uniform in [nmin, nmax] on a domain of side `length`, 1-6 seeded
+    circles or ellipses each (semi-axes 0.12-0.3, aspect 1-2, placed apart),
+    uniform inflow U = 1, Reynolds number uniform in [50, 500] on the mean
+    body diameter, dt from the stability triangle."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for s in range(n_sims):
+        n = int(rng.integers(nmin, nmax + 1))
+        h = length / n
+        nb = int(rng.integers(1, 7))
+        bodies, placed = [], []
+        tries = 0
+        while len(bodies) < nb and tries < 2000:
+            tries += 1
+            a = rng.uniform(0.12, 0.3)
+            b = a / rng.uniform(1.0, 2.0) if rng.uniform() < 0.5 else a
+            cx = rng.uniform(0.7, length - 0.7)
+            cy = rng.uniform(-length / 2 + 0.7, length / 2 - 0.7)
+            if any(np.hypot(cx - px, cy - py) < a + pa + 0.3 for px, py, pa in placed):
+                continue
+            npts = max(64, int(2.5 * np.pi * a / h))
+            if b == a:
+                pts = circle_points((cx, cy), a, npts, phase=rng.uniform(0, 2 * np.pi))
+            else:
+                pts = ellipse_points((cx, cy), a, b, rng.uniform(0, np.pi), npts, phase=rng.uniform(0, 2 * np.pi))
+            bodies.append(BodyDesc(points=pts, center=(cx, cy)))
+            placed.append((cx, cy, a))
+        D = 2.0 * float(np.mean([p[2] for p in placed]))
+        re = rng.uniform(50.0, 500.0)
+        nu = 1.0 * D / re
+        grid = GridDesc(nx=n, ny=n, x0=0.0, y0=-length / 2, h=h, exterior=EXT_FREE, u_inf=(1.0, 0.0), nu=nu)
+        dt = dt_from_polygon(h, nu, 3.0, 0.5)
+        out.append(Workload(name="batch%d_%dx%d_%dbodies" % (s, n, n, len(bodies)), grid=grid, bodies=bodies,
+                            dt=dt, steps=10, extra={"Re": re, "D": D}))
+    return out
