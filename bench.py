@@ -34,6 +34,9 @@ def _parse():
     p.add_argument("--train-runs", type=int, default=10, help="recorded runs for the network (0: no network path)")
     p.add_argument("--train-steps", type=int, default=600, help="RK3 steps per recorded run")
     p.add_argument("--train-iters", type=int, default=2000)
+    p.add_argument("--batch-sims", type=int, default=64, help="simulations of the batched-serving measurement (0: none)")
+    p.add_argument("--batch-steps", type=int, default=20)
+    p.add_argument("--no-autotune", action="store_true", help="keep the default FFT tile shapes on the headline path")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10)
     p.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
@@ -47,11 +50,13 @@ def _parse():
 
 
 def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profile_kernels=None, tol=1e-13,
-              net=None, per_step=False):
+              net=None, per_step=False, tiles=None):
     g = w.grid
     ctx = iim.Context(g, w.bodies, precision=precision, tol=tol, guess=guess, solver=solver)
     if net is not None:
         ctx.set_warm_start(iim.GUESS_NETWORK, net)
+    if tiles is not None:
+        ctx.set_fft_shape(tiles["row_per"], tiles["col_per"])
     omega = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
     Gamma = np.zeros(ctx.n_circ)
     pre = {}
@@ -260,10 +265,17 @@ def main():
     all_kernels = (1 << len(iim.KERNEL_NAMES)) - 1
     tag = "fp64" if prec == iim.PREC_FP64 else "mixed"
 
+    # FFT tile shapes for this FFT size from the library's autotuner (timed on
+    # a scratch context, outside every measurement)
+    tiles = None
+    if not args.no_autotune:
+        tctx = iim.Context(g, w.bodies, precision=prec, solver=iim.SOLVER_KRYLOV)
+        tiles = tctx.autotune(reps=10)
+        tctx.close()
     # headline path: warm-up (kernels timed with events only to find the dominant
     # one), then exactly `steps` timed steps without instrumentation
     ctx, omega, Gamma, head, pre = _run_path(iim, w, torch, np, prec, solver, iim.GUESS_PREVIOUS,
-                                             args.warmup, args.steps, profile_kernels=all_kernels)
+                                             args.warmup, args.steps, profile_kernels=all_kernels, tiles=tiles)
     dominant = max(pre, key=lambda k: pre[k]["total_ms"]) if pre else "fft_cols_conv"
     total = sum(x["total_ms"] for x in pre.values()) or 1.0
     shares = {n: round(v["total_ms"] / total, 4) for n, v in pre.items()}
@@ -300,7 +312,7 @@ def main():
     warm = None
     net = None
     if args.krylov_steps:
-        kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True)
+        kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles)
         for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
             for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
                 c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
@@ -334,12 +346,15 @@ def main():
         "config": {"workload": w.name, "nx": g.nx, "ny": g.ny, "h": g.h,
                    "fft": [ctx.info["fft_mx"], ctx.info["fft_my"]], "Re": 100, "dt": w.dt,
                    "precision": args.precision, "solver": args.solver, "krylov_tol_headline": 1e-13,
+                   "fft_tiles": tiles,
                    "t_start": args.warmup * w.dt},
         "paths": paths,
         "warm_start": warm,
         "roofline": roof,
         "kernel_time_share_warmup": shares,
     }
+    if args.batch_sims:
+        out["batch"] = _batch(iim, wl, torch, np, args.batch_sims, args.batch_steps)
     if not args.no_cpu_baseline:
         cpu, ref_state = _cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"] = cpu
@@ -357,6 +372,33 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = src.numel() * 4
     print(json.dumps(out))
+
+
+def _batch(iim, wl, torch, np, n_sims, steps):
+    """Batched serving: n_sims independent simulations advanced by one HIP
+    graph per batch step; aggregate throughput and batch-step latency."""
+    ws = wl.batch_serving(n_sims, seed=5)
+    t0 = time.perf_counter()
+    b = iim.Batch(ws)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    info = b.info()
+    oms = [torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device="cuda:0") for w in ws]
+    Gs = [np.zeros(len(w.bodies)) for w in ws]
+    dts = [w.dt for w in ws]
+    b.step(oms, Gs, dts, 3)                  # graph capture + warm-up
+    st = b.step(oms, Gs, dts, steps)
+    torch.cuda.synchronize()
+    finite = all(bool(torch.isfinite(o).all()) for o in oms)
+    b.close()
+    return {"metric": "aggregate RK3 step cell-updates/s", "value": st["cells_per_step"] * steps / (st["ms_total"] * 1e-3),
+            "unit": "cell-updates/s", "sims": n_sims, "steps": steps, "cells_per_step": st["cells_per_step"],
+            "step_ms_p50": st["ms_p50"], "step_ms_p99": st["ms_p99"], "step_ms_max": st["ms_max"],
+            "setup_s": setup, "branches": info["branches"], "branch_ms_tried": info["branch_ms"],
+            "fft_tiles": info["tuning"], "finite": finite, "dtype": "f64",
+            "workload": "%d free-space simulations from rest, N x N nodes with N uniform in [256, 1024] on a 4 x 4 "
+                        "domain, 1-6 seeded circles/ellipses each, u_inf = 1, Re uniform in [50, 500]" % n_sims,
+            "timing": "HIP events around every batch-step graph launch"}
 
 
 def _accuracy(iim, w, torch, np, ref, net, tol):
