@@ -421,6 +421,13 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   const bool mixed = c->precision == IIM_PREC_MIXED && c->df.spec32 != nullptr;
   const double fp32_below = c->tol / c->eps32;
   while (!done && total < c->max_iter) {
+    // The status is read back (a host synchronisation) when the residual
+    // estimate is expected to reach the tolerance at the convergence rate
+    // seen since the previous read, at least 2 and at most 12 products
+    // later; products issued after convergence return at once.
+    int next_read = std::min(k.m, c->chunk);
+    double r_last = c->st_host[KS_RES];
+    int j_last = 0;
     for (int j = 0; j < k.m && total < c->max_iter; ++j) {
       const bool fp32 = mixed && c->st_host[KS_RES] <= fp32_below;
       c->n_fp32_products += fp32 ? 1 : 0;
@@ -428,9 +435,18 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
               fp32);
       launch_arnoldi(dg, k, c->psi, j, c->stream, c->prof.mask ? &c->prof : nullptr);
       ++total;
-      if ((j + 1) % c->chunk == 0 || j + 1 == k.m || total >= c->max_iter) {
+      if (j + 1 >= next_read || j + 1 == k.m || total >= c->max_iter) {
         read_status(c);
         if (c->st_host[KS_DONE] != 0.0) break;
+        const double r = c->st_host[KS_RES];
+        int ahead = c->chunk;
+        if (r > 0.0 && r_last > r) {
+          const double rate = std::log(r_last / r) / (double)(j + 1 - j_last);
+          ahead = (int)std::ceil(std::log(r / c->tol) / rate);
+        }
+        r_last = r;
+        j_last = j + 1;
+        next_read = j + 1 + std::max(2, std::min(12, ahead));
       }
     }
     launch_gmres_update(k, c->stream);

@@ -484,9 +484,23 @@ __device__ void matvec_finish_block(const DGeom& g, const double* __restrict__ p
                                     double* __restrict__ out, double* red) {
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
+    // the row's indices and weights in flight together, then its psi values
     double acc = 0.0;
-#pragma unroll 4
-    for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
+    const int e1 = g.aop.ptr[a + 1];
+    for (int e0 = g.aop.ptr[a]; e0 < e1; e0 += 8) {
+      int ri[8];
+      double wv[8], pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = e0 + u < e1;
+        ri[u] = ok ? g.aop.ridx[e0 + u] : -1;
+        wv[u] = ok ? g.aop.w[e0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = ri[u] >= 0 ? psi[ri[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += wv[u] * pv[u];
+    }
     double y = v[a] + acc;
     for (int k = 0; k < g.nbc; ++k) y -= g.b1[(size_t)k * g.na + a] * v[g.na + k];
     out[a] = y;
@@ -595,27 +609,53 @@ __global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const doub
   __shared__ double red[16];
   __shared__ double hcol[72];
   __shared__ double hacc[72];
+  __shared__ double lcs[72], lsn[72];
   if (k.st[KS_DONE] != 0.0) return;
   const int n = k.n, m = k.m;
+  // previous Givens rotations to LDS now, read by one thread at the end
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    lcs[i] = k.cs[i];
+    lsn[i] = k.sn[i];
+  }
   const double* vj = k.V + (size_t)j * n;
   double* w = k.V + (size_t)(j + 1) * n;
   matvec_finish_block(g, psi, vj, w, red);   // ends with a barrier; w visible block-wide
   for (int i = threadIdx.x; i <= j; i += blockDim.x) hacc[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // One workgroup does the whole step, so its loads must overlap: the loops
+  // below issue groups of independent loads before using any of them.
+  constexpr int G = 8;
   for (int pass = 0; pass < 2; ++pass) {
     // dots: wave wid handles basis vectors i = wid, wid + nw, ...
     for (int i = wid; i <= j; i += nw) {
       const double* vi = k.V + (size_t)i * n;
       double acc = 0.0;
-      for (int e = lane; e < n; e += 64) acc += vi[e] * w[e];
+      for (int e0 = lane; e0 < n; e0 += 64 * G) {
+        double a[G], b[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int e = e0 + 64 * u;
+          a[u] = e < n ? vi[e] : 0.0;
+          b[u] = e < n ? w[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) acc += a[u] * b[u];
+      }
       acc = wave_sum(acc);
       if (lane == 0) hcol[i] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
       double we = w[e];
-      for (int i = 0; i <= j; ++i) we -= hcol[i] * k.V[(size_t)i * n + e];
+      for (int i0 = 0; i0 <= j; i0 += G) {
+        double vv[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) vv[u] = i0 + u <= j ? k.V[(size_t)(i0 + u) * n + e] : 0.0;
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+          if (i0 + u <= j) we -= hcol[i0 + u] * vv[u];
+      }
       w[e] = we;
     }
     for (int i = threadIdx.x; i <= j; i += blockDim.x) hacc[i] += hcol[i];
@@ -626,21 +666,20 @@ __global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const doub
   const double hn = sqrt(block_sum(nn, red));
   const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) w[e] *= inv;
+  // the new column of H, rotated in LDS by one thread, then written out
   if (threadIdx.x == 0) {
-    double* H = k.H + (size_t)j * (m + 1);
-    for (int i = 0; i <= j; ++i) H[i] = hacc[i];
-    H[j + 1] = hn;
+    hacc[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-      const double t = k.cs[i] * H[i] + k.sn[i] * H[i + 1];
-      H[i + 1] = -k.sn[i] * H[i] + k.cs[i] * H[i + 1];
-      H[i] = t;
+      const double t = lcs[i] * hacc[i] + lsn[i] * hacc[i + 1];
+      hacc[i + 1] = -lsn[i] * hacc[i] + lcs[i] * hacc[i + 1];
+      hacc[i] = t;
     }
-    const double den = hypot(H[j], H[j + 1]);
-    const double c = den > 0.0 ? H[j] / den : 1.0, s = den > 0.0 ? H[j + 1] / den : 0.0;
+    const double den = hypot(hacc[j], hacc[j + 1]);
+    const double c = den > 0.0 ? hacc[j] / den : 1.0, s = den > 0.0 ? hacc[j + 1] / den : 0.0;
     k.cs[j] = c;
     k.sn[j] = s;
-    H[j] = den;
-    H[j + 1] = 0.0;
+    hacc[j] = den;
+    hacc[j + 1] = 0.0;
     k.g[j + 1] = -s * k.g[j];
     k.g[j] = c * k.g[j];
     k.st[KS_K] = (double)(j + 1);
@@ -651,6 +690,9 @@ __global__ void __launch_bounds__(1024) k_arnoldi(DGeom g, DKrylov k, const doub
     if (!(rel == rel)) k.st[KS_NFAIL] = 1.0;
     if (rel <= k.st[KS_TOL] || !(rel == rel) || hn == 0.0) k.st[KS_DONE] = 1.0;
   }
+  __syncthreads();
+  double* H = k.H + (size_t)j * (m + 1);
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) H[i] = hacc[i];
 }
 void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, int j, hipStream_t s, Prof* prof) {
   IIM_LAUNCH(prof, KID_ARNOLDI, 8.0 * k.n * (2.0 * (j + 1) + 3.0), k_arnoldi, 1, 1024, s, g, k, psi_ring, j);
@@ -659,20 +701,38 @@ void launch_arnoldi(const DGeom& g, const DKrylov& k, const double* psi_ring, in
 // x += V y with H(0:kk, 0:kk) y = g(0:kk)
 __global__ void __launch_bounds__(1024) k_gmres_update(DKrylov k) {
   __shared__ double y[72];
+  __shared__ double Hs[64][65];   // Hs[i][q] = H(i, q), restart length <= 64
   const int kk = (int)k.st[KS_K];
   const int n = k.n, m = k.m;
   if (kk <= 0) return;
-  if (threadIdx.x == 0) {
+  for (int t = threadIdx.x; t < kk * kk; t += blockDim.x) {
+    const int i = t % kk, q = t / kk;
+    Hs[i][q] = k.H[(size_t)q * (m + 1) + i];
+  }
+  __syncthreads();
+  // back substitution by one wave: lane l keeps g_l minus the terms of the
+  // unknowns solved so far; lane i's value is final when y_i is formed
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double s = l < kk ? k.g[l] : 0.0;
     for (int i = kk - 1; i >= 0; --i) {
-      double s = k.g[i];
-      for (int q = i + 1; q < kk; ++q) s -= k.H[(size_t)q * (m + 1) + i] * y[q];
-      y[i] = s / k.H[(size_t)i * (m + 1) + i];
+      const double yi = __shfl(s, i, 64) / Hs[i][i];
+      if (l < i) s -= Hs[l][i] * yi;
+      if (l == i) y[i] = yi;
     }
   }
   __syncthreads();
+  constexpr int G = 8;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     double xe = k.x[e];
-    for (int i = 0; i < kk; ++i) xe += y[i] * k.V[(size_t)i * n + e];
+    for (int i0 = 0; i0 < kk; i0 += G) {
+      double vv[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) vv[u] = i0 + u < kk ? k.V[(size_t)(i0 + u) * n + e] : 0.0;
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (i0 + u < kk) xe += y[i0 + u] * vv[u];
+    }
     k.x[e] = xe;
   }
   __syncthreads();
@@ -876,30 +936,38 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
   const int j = blockIdx.y;
   if (i >= g.nx) return;
   const int q = j * g.nx + i;
-  const int8_t c = g.cls[q];
-  if (c == 1) return;   // boundary kernel
-  if (c >= 2) {         // solid: vorticity stays zero
-    out[q] = 0.0;
-    if (mode == 1) Q[q] = 0.0;
-    return;
-  }
   const int nx = g.nx, ny = g.ny, nxr = nx + 2;
   const int r = (j + 1) * nxr + i + 1;
   const double nih = g.nu * g.inv_h;
-  const double wc = omega[q];
-  double fxr, fxl, fyt, fyb;
+  double fxr, fxl, fyt, fyb, wc;
   if (i >= 2 && i < nx - 2 && j >= 2 && j < ny - 2) {
-    // x faces
+    // interior: every stencil address is valid, so the node class is loaded
+    // together with the stencil values instead of in front of them
+    const int8_t c = g.cls[q];
+    wc = omega[q];
     const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
     const double uxm2 = U[r - 2], uxm1 = U[r - 1], uc = U[r], uxp1 = U[r + 1], uxp2 = U[r + 2];
-    fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
-    fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
-    // y faces
     const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
     const double vym2 = V[r - 2 * nxr], vym1 = V[r - nxr], vc = V[r], vyp1 = V[r + nxr], vyp2 = V[r + 2 * nxr];
+    if (c == 1) return;   // boundary kernel
+    if (c >= 2) {         // solid: vorticity stays zero
+      out[q] = 0.0;
+      if (mode == 1) Q[q] = 0.0;
+      return;
+    }
+    fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
+    fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
     fyt = flux_std(vym1, vc, vyp1, vyp2, wym1, wc, wyp1, wyp2, nih);
     fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
   } else {
+    const int8_t c = g.cls[q];
+    if (c == 1) return;
+    if (c >= 2) {
+      out[q] = 0.0;
+      if (mode == 1) Q[q] = 0.0;
+      return;
+    }
+    wc = omega[q];
     // near the grid edge: nodes outside carry omega = 0; velocities come from the ring
     // with an outflow plane at x_{nx-1/2}, nodes nx, nx+1 mirror nx-1, nx-2 (omega and u_x even)
     const bool mir = g.outflow != 0;
@@ -1207,6 +1275,7 @@ __device__ __forceinline__ FftT<float2> fft_view<float2>(const DFft& f) {
 // a comma inside a macro argument (template arguments of a launched kernel)
 #define IIM_COMMA ,
 
+
 // The hardware deals consecutive workgroups round-robin to the 8 XCDs, each
 // with its own L2.  Row passes give consecutive spectrum rows to consecutive
 // logical blocks, and 128-byte lines of the spectrum span several of them:
@@ -1403,14 +1472,19 @@ k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __
     const int n = t + T * m;
     v[m] = (valid && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
   }
-  fft_reg<MY, false>(v, lds[w], t, ft.tw_y);
+  // kernel spectrum of this thread's bins, loaded before the forward FFT
   const S* gh = ft.ghat + (size_t)(valid ? kx : 0) * (MY / 2 + 1);
+  S gk[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    const S s = gh[n <= MY / 2 ? n : MY - n];
-    v[m].x *= s;
-    v[m].y *= s;
+    gk[m] = gh[n <= MY / 2 ? n : MY - n];
+  }
+  fft_reg<MY, false>(v, lds[w], t, ft.tw_y);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    v[m].x *= gk[m];
+    v[m].y *= gk[m];
   }
   fft_reg<MY, true>(v, lds[w], t, ft.tw_y);
   if (valid) {
@@ -1464,8 +1538,12 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
         m1 = i1 < g.nx ? i1 : 2 * g.nx - 1 - i1;
       }
       const size_t rb = (size_t)jrow * g.nx;
-      if (m0 >= 0 && m0 < g.nx && g.cls[rb + m0] < 2) z.x = omega[rb + m0];
-      if (m1 >= 0 && m1 < g.nx && g.cls[rb + m1] < 2) z.y = omega[rb + m1];
+      // class and vorticity loaded together (both addresses are valid), then selected
+      const bool in0 = m0 >= 0 && m0 < g.nx, in1 = m1 >= 0 && m1 < g.nx;
+      const int8_t c0 = in0 ? g.cls[rb + m0] : (int8_t)3, c1 = in1 ? g.cls[rb + m1] : (int8_t)3;
+      const double o0 = in0 ? omega[rb + m0] : 0.0, o1 = in1 ? omega[rb + m1] : 0.0;
+      z.x = c0 < 2 ? (S)o0 : (S)0;
+      z.y = c1 < 2 ? (S)o1 : (S)0;
     }
     v[m] = z;
   }

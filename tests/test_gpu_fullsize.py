@@ -48,9 +48,13 @@ def test_step_fullsize(name, solver):
     w, geo, st = _setup(name)
     om, G = seeded_state(w, geo, 21, body_scale=1.0 if name.startswith("cyl") else 0.1)
     om_ref, G_ref = st.step(om, G, w.dt)
-    ctx = iim.Context(w.grid, w.bodies, tol=1e-13, solver=solver)
+    # GMRES to 1e-13 on one body; the four-body system (nonconvex C-shapes)
+    # has its rounding floor near 1e-13, so its solves stop at 1e-12
+    tol = 1e-12 if name == "multi512" else 1e-13
+    ctx = iim.Context(w.grid, w.bodies, tol=tol, solver=solver)
     d = to_dev(om)
     G2, stats = ctx.rk3_steps(d, G, w.dt, 1)
+    print(name, solver, stats)
     torch.cuda.synchronize()
     got = d.cpu().numpy()
     # The gate of the FP64 path: relative L2 velocity error over fluid nodes
