@@ -520,8 +520,9 @@ class Geometry:
                         rb = rb - inv_h2 * self.E4b_b[g]
             Arows.append(ra)
             Brows.append(rb)
-        self.Aop = sp.vstack(Arows).tocsr()
-        self.Bop = sp.vstack(Brows).tocsr()
+        # (no affected points: no bodies; empty operators)
+        self.Aop = sp.vstack(Arows).tocsr() if Arows else sp.csr_matrix((0, N))
+        self.Bop = sp.vstack(Brows).tocsr() if Brows else sp.csr_matrix((0, self.nc))
         # E_a: V_A -> V_G inclusion
         self.Ea = sp.csr_matrix((np.ones(self.na), (self.a_lin, np.arange(self.na))),
                                 shape=(N, self.na))

@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(1024) k_rhs_vector(DGeom g, const double* __re
 void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma, double* b,
                        hipStream_t s) {
   const int blocks = g.nbc + (g.na + 1023) / 1024;
-  k_rhs_vector<<<blocks, 1024, 0, s>>>(g, psi_ring, omega, Gamma, b);
+  if (blocks > 0) k_rhs_vector<<<blocks, 1024, 0, s>>>(g, psi_ring, omega, Gamma, b);
 }
 
 // ============================================================ GMRES (device)
@@ -1191,14 +1191,16 @@ __global__ void __launch_bounds__(256) k_gemv_t(const double* __restrict__ Mt, i
 }
 
 void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s) {
-  k_gemv_t<<<(n + 15) / 16, 256, 0, s>>>(Mt, n, b, x);
+  if (n > 0) k_gemv_t<<<(n + 15) / 16, 256, 0, s>>>(Mt, n, b, x);
 }
 
 __global__ void k_unit(double* v, int n, int q) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = (i == q) ? 1.0 : 0.0;
 }
-void launch_unit(double* v, int n, int q, hipStream_t s) { k_unit<<<(n + 255) / 256, 256, 0, s>>>(v, n, q); }
+void launch_unit(double* v, int n, int q, hipStream_t s) {
+  if (n > 0) k_unit<<<(n + 255) / 256, 256, 0, s>>>(v, n, q);
+}
 
 }  // namespace iim
 

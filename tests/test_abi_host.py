@@ -89,3 +89,40 @@ def test_error_paths():
     assert rc == iim.IIM_EUNSUPPORTED
     assert abs(ctx.dt_max(np.sqrt(2) * 0.25) - w.dt / 0.5) < 1e-15
     ctx.close()
+
+
+def test_argument_errors_of_the_additions():
+    """Argument checks of the network, warm-start, mixed-precision, tuning and
+    batch entry points (none of these reach the device)."""
+    L = iim.lib()
+    w = wl.cylinder_small()
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    h = ctx._h
+    one = C.c_void_p(1)
+    assert L.iim_poisson_fp32(h, one, one) == iim.IIM_EUNSUPPORTED
+    assert L.iim_record_solves(h, 10) == iim.IIM_EUNSUPPORTED
+    assert L.iim_record_solves(h, -1) == iim.IIM_EINVAL
+    assert L.iim_set_warm_start(h, iim.GUESS_NETWORK, None) == iim.IIM_EINVAL
+    assert L.iim_set_warm_start(h, 7, None) == iim.IIM_EINVAL
+    assert L.iim_set_warm_start(h, iim.GUESS_EXTRAPOLATE, None) == iim.IIM_OK
+    assert L.iim_autotune(h, 1, None, None, None, None) == iim.IIM_EUNSUPPORTED
+    assert L.iim_profile_replay(h, 0, 1, C.byref(C.c_double()), C.byref(C.c_double())) == iim.IIM_EUNSUPPORTED
+    assert L.iim_warm_start_train(h, None, 1, 1, 1e-3, 0, None) == iim.IIM_EINVAL
+    ctx.close()
+    # network descriptors
+    out = C.c_void_p()
+    for bad in (dict(in_channels=0, width=8, layers=2), dict(in_channels=4, width=0, layers=2),
+                dict(in_channels=4, width=8, layers=0)):
+        d = iim.NetDesc(bf16=1, seed=0, **bad)
+        assert L.iim_net_create(C.byref(d), None, C.byref(out)) == iim.IIM_EINVAL
+        assert not out.value
+    assert L.iim_net_forward(None, None, 1, 1, None, None) == iim.IIM_EINVAL
+    # batches
+    assert L.iim_batch_create(0, None, None, None, None, None, C.byref(out)) == iim.IIM_EINVAL
+    assert L.iim_batch_step(None, None, None, None, 1, None) == iim.IIM_EINVAL
+    # an unknown initial guess is refused at create
+    o = iim.SolverOpts(guess=9, host_only=1)
+    g = iim._grid_desc(w.grid)
+    keep = []
+    arr = iim._body_array(w.bodies, keep)
+    assert L.iim_create(C.byref(g), 1, arr, C.byref(o), None, C.byref(out)) == iim.IIM_EINVAL

@@ -57,3 +57,24 @@ def test_free_space_total_circulation_stays_zero():
         assert abs(tot) < 1e-13
     assert np.max(np.abs(om)) > 1.0          # vorticity was created at the wall
     assert np.all(om[geo.solid] == 0.0)
+
+
+def test_no_bodies_reduces_to_plain_poisson_and_conserves_circulation():
+    """With no immersed body the reconstruction is the plain free-space
+    Poisson solve (no corrections), and the conservative transport keeps the
+    total circulation while the vorticity stays clear of the grid edges."""
+    import workloads as wl
+    from oracle import geometry as OG, poisson as OP, reconstruct as ORC, ns as ONS
+    g = wl.GridDesc(nx=96, ny=80, x0=-0.48, y0=-0.4, h=0.01, exterior="free", u_inf=(0.3, 0.1), nu=0.01)
+    geo = OG.Geometry(g, [])
+    assert geo.na == 0 and geo.nbc == 0
+    X, Y = wl.node_coords(g)
+    om = np.exp(-(X ** 2 + Y ** 2) / (2 * 0.05 ** 2)) - 0.5 * np.exp(-((X - 0.1) ** 2 + Y ** 2) / (2 * 0.04 ** 2))
+    rec = ORC.Reconstructor(geo).reconstruct(om, np.zeros(0))
+    psi = OP.FreeSpace(g.nx, g.ny, g.h)(om)
+    u = (psi[2:, 1:-1] - psi[:-2, 1:-1]) / (2 * g.h) + g.u_inf[0]
+    v = -(psi[1:-1, 2:] - psi[1:-1, :-2]) / (2 * g.h) + g.u_inf[1]
+    assert np.max(np.abs(rec.U[1:-1, 1:-1] - u)) < 1e-13
+    assert np.max(np.abs(rec.V[1:-1, 1:-1] - v)) < 1e-13
+    om2, G2 = ONS.Stepper(geo).step(om, np.zeros(0), 0.002)
+    assert abs(om2.sum() - om.sum()) < 1e-12 * np.abs(om).sum()
