@@ -137,7 +137,7 @@ def _train_network(iim, w, torch, np, runs, steps, iters):
 
 # library kernel names of the instrumented kernel ids
 HIP_NAMES = {"fft_rows_fwd": "k_rows_fwd_reg", "fft_cols_conv": "k_cols_reg", "fft_rows_inv": "k_rows_inv_reg",
-             "transport_bulk": "k_transport_bulk", "arnoldi": "k_arnoldi"}
+             "transport": "k_transport_all", "arnoldi": "k_arnoldi"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "paper_2109_13628_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_cylinder_1024x512.txt")
@@ -170,7 +170,7 @@ def _summarize_trace(trace_dir, out, command):
                                                       float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     # launches inside the RK steps: from the first transport launch on (the
     # set-up before it builds the dense Schur matrix with pruned convolutions)
-    t0 = min(int(r["Start_Timestamp"]) for r in trace if "k_transport_bulk" in r["Kernel_Name"])
+    t0 = min(int(r["Start_Timestamp"]) for r in trace if "k_transport_all" in r["Kernel_Name"])
     lines += ["", "launches inside the RK steps, per launch shape (grid size): calls, avg us", ""]
     for short, hip in HIP_NAMES.items():
         by = {}
@@ -197,7 +197,7 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
         probe = max(copies, key=lambda r: int(r["Dispatch_Id"]))
         res[tag + "_scale"] = (256 * 1024) / float(probe["Counter_Value"])
         # dispatches inside the RK steps (from the first transport launch on)
-        d0 = min(int(r["Dispatch_Id"]) for r in rows if "k_transport_bulk" in r["Kernel_Name"])
+        d0 = min(int(r["Dispatch_Id"]) for r in rows if "k_transport_all" in r["Kernel_Name"])
         for short, hip in HIP_NAMES.items():
             ks = [r for r in rows if (hip + "<" in r["Kernel_Name"] or hip + "(" in r["Kernel_Name"])
                   and int(r["Dispatch_Id"]) >= d0]

@@ -227,7 +227,7 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
  * iim_profile: drop collected timings and time every later launch of the
  * kernels whose id bit is set in kernel_mask with a pair of HIP events on the
  * context's stream (ids: 0 row FFT pass, 1 column FFT + kernel-multiply pass,
- * 2 inverse row FFT pass, 3 bulk transport + RK update, 4 Arnoldi step).
+ * 2 inverse row FFT pass, 3 transport of all nodes + Kelvin + RK update, 4 Arnoldi step).
  * iim_profile_read: summed event time (ms), launch count and summed
  * algorithmic bytes of one kernel id since the last iim_profile.
  * iim_krylov_totals: Schur solves and Krylov matrix-vector products so far. */

@@ -34,7 +34,7 @@ EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", 
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
            "iim_warm_start_sequences", "iim_reset_history", "iim_autotune", "iim_set_fft_shape",
            "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info"]
-KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport_bulk", "arnoldi"]
+KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport", "arnoldi"]
 
 
 class IIMError(RuntimeError):

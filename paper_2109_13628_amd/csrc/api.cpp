@@ -282,6 +282,7 @@ void setup_device(iim_ctx* c) {
   c->w3n = c->dalloc<double>(N);
   c->Qw = c->dalloc<double>(N);
   c->wtmp = c->dalloc<double>(N);
+  c->wtmp2 = c->dalloc<double>(N);
   c->Gd = c->dalloc<double>(std::max(1, g.nbc()));
   c->QGd = c->dalloc<double>(std::max(1, g.nbc()));
   c->dGd = c->dalloc<double>(std::max(1, g.nbc()));
@@ -484,12 +485,10 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
 }  // namespace
 
 int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
-  const size_t N = (size_t)c->geo.grid.nx * c->geo.grid.ny;
   const DGeom& dg = c->dg;
-  launch_fill(c->Qw, 0.0, N, c->stream);
-  launch_fill(c->QGd, 0.0, std::max(1, dg.nbc), c->stream);
-  double* in = omega;
-  double* out = c->wtmp;
+  // stage inputs/outputs omega -> wtmp -> wtmp2 -> omega: no copy at the end;
+  // the first stage (RK_A[0] = 0) overwrites the RK registers Qw, QGd
+  double* const bufs[4] = {omega, c->wtmp, c->wtmp2, omega};
   int status = IIM_OK;
   iim_step_stats st{};
   st.converged = 1;
@@ -499,6 +498,8 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
     ++c->run_id;
   }
   for (int s = 0; s < 3; ++s) {
+    const double* in = bufs[s];
+    double* out = bufs[s + 1];
     int it;
     double r0, r1;
     c->cur_stage = s;
@@ -514,13 +515,9 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
       st.converged = 0;
     }
     launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
-    launch_transport(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, RK_A[s], RK_B[s], dt, 1, c->stream,
-                     c->prof.mask ? &c->prof : nullptr);
-    launch_kelvin(dg, in, c->U, c->V, c->dGd, c->Gd, c->QGd, RK_A[s], RK_B[s], dt, 1, c->stream);
-    std::swap(in, out);
+    launch_transport_all(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, c->dGd, c->Gd, c->QGd, RK_A[s],
+                         RK_B[s], dt, 1, c->stream, c->prof.mask ? &c->prof : nullptr);
   }
-  // three swaps: the result sits in the context buffer
-  HIPCHK(hipMemcpyAsync(omega, in, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (stats) *stats = st;
   return status;
 }
@@ -822,8 +819,8 @@ int iim_rhs(iim_ctx* c, const double* omega, const double* u, const double* v, d
   try {
     const DGeom& dg = c->dg;
     launch_omega_bc(dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
-    launch_transport(dg, omega, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, 0.0, 0.0, 0.0, 0, c->stream);
-    launch_kelvin(dg, omega, u, v, c->dGd, nullptr, nullptr, 0.0, 0.0, 0.0, 0, c->stream);
+    launch_transport_all(dg, omega, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, c->dGd, nullptr, nullptr, 0.0, 0.0,
+                         0.0, 0, c->stream);
     if (omega_b)
       HIPCHK(hipMemcpyAsync(omega_b, c->wb, c->geo.nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     const int nb = c->geo.nbc();

@@ -78,7 +78,7 @@ struct iim_ctx {
   int8_t* cls_zero = nullptr;
   double *psi = nullptr, *U = nullptr, *V = nullptr;
   double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
-  double *Qw = nullptr, *wtmp = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
+  double *Qw = nullptr, *wtmp = nullptr, *wtmp2 = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
   bool have_prev = false;
   int solver = IIM_SOLVER_KRYLOV;

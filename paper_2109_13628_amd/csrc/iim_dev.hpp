@@ -235,13 +235,14 @@ void launch_recover_fields(const DGeom& g, const double* x, double* psi_ring, do
                            hipStream_t s);
 void launch_omega_bc(const DGeom& g, const double* omega, const double* U, const double* V,
                      double* wb, double* w4, double* w3b, double* w3n, hipStream_t s);
-// mode 0: out = domega/dt;  mode 1: Q = a Q + dt rhs, out = omega + b Q
-void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V,
-                      const double* w4, const double* w3b, const double* w3n, double* out, double* Q,
-                      double a, double b, double dt, int mode, hipStream_t s, Prof* prof = nullptr);
-// Kelvin: dG = -h sum (F+Q).n over dR_k; mode 1 also updates Gamma/QG in place
-void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG,
-                   double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s);
+// Transport of every fluid node and the Kelvin circulation update, one launch.
+// mode 0: out = domega/dt, dG = dGamma/dt (Q, Gamma, QG unused);
+// mode 1: Q = a Q + dt rhs, out = omega + b Q, and the same for (Gamma, QG)
+// with dG the rate; a = 0 overwrites the registers without reading them.
+// Kelvin: dG = -h sum (F+Q).n over dR_k.
+void launch_transport_all(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
+                          const double* w3b, const double* w3n, double* out, double* Q, double* dG, double* Gamma,
+                          double* QG, double a, double b, double dt, int mode, hipStream_t s, Prof* prof = nullptr);
 void launch_fill(double* p, double v, size_t n, hipStream_t s);
 // dense Schur complement: in-place Gauss-Jordan inverse, transposed GEMV, unit vector
 void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s);

@@ -928,12 +928,12 @@ __device__ double flux_general(const DGeom& g, const double* __restrict__ omega,
 }
 
 // Bulk nodes (cls 0): all stencil nodes are fluid and inside the grid.
-__global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* __restrict__ omega,
-                                                        const double* __restrict__ U, const double* __restrict__ V,
-                                                        double* __restrict__ out, double* __restrict__ Q, double a,
-                                                        double b, double dt, int mode) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
+// Bulk part: one thread per node of grid row j, 256 nodes per block.
+__device__ __forceinline__ void transport_bulk(const DGeom& g, const double* __restrict__ omega,
+                                               const double* __restrict__ U, const double* __restrict__ V,
+                                               double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                               double dt, int mode, int bx, int j) {
+  const int i = bx * 256 + threadIdx.x;
   if (i >= g.nx) return;
   const int q = j * g.nx + i;
   const int nx = g.nx, ny = g.ny, nxr = nx + 2;
@@ -991,7 +991,8 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
   if (mode == 0) {
     out[q] = rhs;
   } else {
-    const double qn = a * Q[q] + dt * rhs;
+    const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
+    const double qn = a * qp + dt * rhs;
     Q[q] = qn;
     out[q] = wc + b * qn;
   }
@@ -999,13 +1000,13 @@ __global__ void __launch_bounds__(256) k_transport_bulk(DGeom g, const double* _
 
 // One group of 4 lanes per boundary-kernel node: lane f computes the flux on
 // face f (right, left, top, bottom); lane 0 of the group combines them.
-__global__ void __launch_bounds__(256) k_transport_special(DGeom g, const double* __restrict__ omega,
-                                                           const double* __restrict__ U, const double* __restrict__ V,
-                                                           const double* __restrict__ w4, const double* __restrict__ w3b,
-                                                           const double* __restrict__ w3n, double* __restrict__ out,
-                                                           double* __restrict__ Q, double a, double b, double dt,
-                                                           int mode) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void transport_special(const DGeom& g, const double* __restrict__ omega,
+                                                  const double* __restrict__ U, const double* __restrict__ V,
+                                                  const double* __restrict__ w4, const double* __restrict__ w3b,
+                                                  const double* __restrict__ w3n, double* __restrict__ out,
+                                                  double* __restrict__ Q, double a, double b, double dt, int mode,
+                                                  int bx) {
+  const int tid = bx * 256 + threadIdx.x;
   const int sp = tid >> 2, face = tid & 3;
   const bool act = sp < g.nsp;
   int q = 0;
@@ -1024,29 +1025,18 @@ __global__ void __launch_bounds__(256) k_transport_special(DGeom g, const double
   if (mode == 0) {
     out[q] = rhs;
   } else {
-    const double qn = a * Q[q] + dt * rhs;
+    const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
+    const double qn = a * qp + dt * rhs;
     Q[q] = qn;
     out[q] = omega[q] + b * qn;
   }
 }
 
-void launch_transport(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
-                      const double* w3b, const double* w3n, double* out, double* Q, double a, double b, double dt,
-                      int mode, hipStream_t s, Prof* prof) {
-  dim3 grid((g.nx + 255) / 256, g.ny);
-  // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
-  IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_bulk, grid, 256, s, g, omega, U, V, out, Q, a, b,
-             dt, mode);
-  if (g.nsp) k_transport_special<<<(4 * g.nsp + 255) / 256, 256, 0, s>>>(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode);
-}
-
 // Kelvin: one block per circulating body
-__global__ void __launch_bounds__(512) k_kelvin(DGeom g, const double* __restrict__ omega, const double* __restrict__ U,
-                                                const double* __restrict__ V, double* __restrict__ dG,
-                                                double* __restrict__ Gamma, double* __restrict__ QG, double a,
-                                                double b, double dt, int mode) {
-  __shared__ double red[16];
-  const int k = blockIdx.x;
+__device__ __forceinline__ void kelvin(const DGeom& g, const double* __restrict__ omega, const double* __restrict__ U,
+                                       const double* __restrict__ V, double* __restrict__ dG,
+                                       double* __restrict__ Gamma, double* __restrict__ QG, double a, double b,
+                                       double dt, int mode, int k, double* red) {
   const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
   const int nv = j1 - j0 + 1, nh = i1 - i0 + 1;
   double acc = 0.0;
@@ -1066,16 +1056,48 @@ __global__ void __launch_bounds__(512) k_kelvin(DGeom g, const double* __restric
     const double rate = -g.h * tot;
     dG[k] = rate;
     if (mode == 1) {
-      const double qn = a * QG[k] + dt * rate;
+      const double qp = a == 0.0 ? 0.0 : QG[k];
+      const double qn = a * qp + dt * rate;
       QG[k] = qn;
       Gamma[k] += b * qn;
     }
   }
 }
 
-void launch_kelvin(const DGeom& g, const double* omega, const double* U, const double* V, double* dG, double* Gamma,
-                   double* QG, double a, double b, double dt, int mode, hipStream_t s) {
-  if (g.nbc) k_kelvin<<<g.nbc, 512, 0, s>>>(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode);
+// Transport of every fluid node and the Kelvin update in one launch of
+// 256-thread blocks: first the bulk rows, then the boundary-kernel nodes (4
+// lanes each), then one block per circulating body.  The three parts read the
+// same inputs and write disjoint outputs.
+__global__ void __launch_bounds__(256) k_transport_all(DGeom g, const double* __restrict__ omega,
+                                                       const double* __restrict__ U, const double* __restrict__ V,
+                                                       const double* __restrict__ w4, const double* __restrict__ w3b,
+                                                       const double* __restrict__ w3n, double* __restrict__ out,
+                                                       double* __restrict__ Q, double* __restrict__ dG,
+                                                       double* __restrict__ Gamma, double* __restrict__ QG, double a,
+                                                       double b, double dt, int mode) {
+  __shared__ double red[16];
+  const int nbx = (g.nx + 255) / 256, nb_bulk = nbx * g.ny, nb_sp = (4 * g.nsp + 255) / 256;
+  int blk = blockIdx.x;
+  if (blk < nb_bulk) {
+    transport_bulk(g, omega, U, V, out, Q, a, b, dt, mode, blk % nbx, blk / nbx);
+    return;
+  }
+  blk -= nb_bulk;
+  if (blk < nb_sp) {
+    transport_special(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode, blk);
+    return;
+  }
+  blk -= nb_sp;
+  kelvin(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode, blk, red);
+}
+
+void launch_transport_all(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
+                          const double* w3b, const double* w3n, double* out, double* Q, double* dG, double* Gamma,
+                          double* QG, double a, double b, double dt, int mode, hipStream_t s, Prof* prof) {
+  const int blocks = ((g.nx + 255) / 256) * g.ny + (4 * g.nsp + 255) / 256 + g.nbc;
+  // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
+  IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_all, blocks, 256, s, g, omega, U, V, w4, w3b, w3n,
+             out, Q, dG, Gamma, QG, a, b, dt, mode);
 }
 
 }  // namespace iim
