@@ -92,6 +92,133 @@ DStencil upload_stencil(iim_ctx* c, const Stencil& s, bool with_comp) {
   return d;
 }
 
+// The boundary quantities of a stage composed into affine forms of psi, omega
+// and psibar (DBnd): psi at a ghost (its fourth-order extrapolation), the
+// fluid velocity by centred differences (ghost psi substituted), the ghost
+// velocity (third-order extension with u_b), omega_b (its stencil over fluid
+// and ghost velocities), the three vorticity extensions (over omega and
+// omega_b).  Each form is then one independent dot product, so one launch
+// replaces the chain ghost psi -> velocity extension -> omega_b -> omega
+// extensions.  Returns false if a stencil node is not where the composition
+// needs it (the chained kernels are used then).
+struct Form {
+  std::map<int, double> t[3];   // psi (ring index), omega (grid index), psibar (column)
+  double k = 0.0;
+  void add(const Form& o, double s) {
+    for (int q = 0; q < 3; ++q)
+      for (const auto& kv : o.t[q]) t[q][kv.first] += s * kv.second;
+    k += s * o.k;
+  }
+};
+
+bool build_boundary_forms(iim_ctx* c, const std::vector<double>& psibt, const std::vector<double>& wbconst,
+                          const std::vector<int>& ccol) {
+  const Geometry& g = c->geo;
+  const int nx = g.grid.nx, ny = g.grid.ny, nxr = nx + 2;
+  const double cc = 0.5 / g.grid.h, ux = c->dg.uinf_x, uy = c->dg.uinf_y;
+  auto ring = [&](int i, int j) { return (j + 1) * nxr + i + 1; };
+  auto in_grid = [&](int i, int j) { return i >= 0 && j >= 0 && i < nx && j < ny; };
+  auto fluid = [&](int i, int j) { return in_grid(i, j) && g.cl(i, j) == CLS_FLUID; };
+  std::vector<Form> gpsi(g.ng), gu(g.ng), gv(g.ng), wbf(g.nc);
+  for (int q = 0; q < g.ng; ++q) {
+    for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) {
+      if (!fluid(g.ext4b.ii[e], g.ext4b.jj[e])) return false;
+      gpsi[q].t[0][ring(g.ext4b.ii[e], g.ext4b.jj[e])] += g.ext4b.w[e];
+    }
+    for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) {
+      const int cp = g.ext4b.bc[e];
+      gpsi[q].k += g.ext4b.bw[e] * psibt[cp];
+      if (ccol[cp] >= 0) gpsi[q].t[2][ccol[cp]] += g.ext4b.bw[e];
+    }
+  }
+  // psi at a ring node: its own value, or the ghost's form
+  auto psi_at = [&](int i, int j, Form& f, double s) -> bool {
+    if (in_grid(i, j)) {
+      const int gq = g.ghost_id[(size_t)j * nx + i];
+      if (gq >= 0) {
+        f.add(gpsi[gq], s);
+        return true;
+      }
+      if (g.cl(i, j) != CLS_FLUID) return false;
+    } else if (i < -1 || j < -1 || i > nx || j > ny) {
+      return false;
+    }
+    f.t[0][ring(i, j)] += s;
+    return true;
+  };
+  // velocity component at a fluid node, as the velocity kernel forms it
+  auto vel_at = [&](int i, int j, int comp, Form& f, double s) -> bool {
+    if (!fluid(i, j)) return false;
+    if (comp == 0) {
+      f.k += s * ux;
+      return psi_at(i, j + 1, f, s * cc) && psi_at(i, j - 1, f, -s * cc);
+    }
+    f.k += s * uy;
+    return psi_at(i + 1, j, f, -s * cc) && psi_at(i - 1, j, f, s * cc);
+  };
+  for (int q = 0; q < g.ng; ++q) {
+    for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) {
+      if (!vel_at(g.ext3b.ii[e], g.ext3b.jj[e], 0, gu[q], g.ext3b.w[e])) return false;
+      if (!vel_at(g.ext3b.ii[e], g.ext3b.jj[e], 1, gv[q], g.ext3b.w[e])) return false;
+    }
+    for (int e = g.ext3b.bptr[q]; e < g.ext3b.bptr[q + 1]; ++e) {
+      const int cp = g.ext3b.bc[e];
+      gu[q].k += g.ext3b.bw[e] * g.c_ub[2 * cp];
+      gv[q].k += g.ext3b.bw[e] * g.c_ub[2 * cp + 1];
+    }
+  }
+  for (int cp = 0; cp < g.nc; ++cp) {
+    wbf[cp].k = wbconst[cp];
+    for (int e = g.wbc.ptr[cp]; e < g.wbc.ptr[cp + 1]; ++e) {
+      const int i = g.wbc.ii[e], j = g.wbc.jj[e], comp = g.wbc.comp[e];
+      if (!in_grid(i, j)) return false;
+      const int gq = g.ghost_id[(size_t)j * nx + i];
+      if (gq >= 0)
+        wbf[cp].add(comp ? gv[gq] : gu[gq], g.wbc.w[e]);
+      else if (!vel_at(i, j, comp, wbf[cp], g.wbc.w[e]))
+        return false;
+    }
+  }
+  std::vector<int> ptr{0}, idx, dst;
+  std::vector<double> w, kc;
+  auto emit = [&](const Form& f, int kind, int index) {
+    for (int q = 0; q < 3; ++q)
+      for (const auto& kv : f.t[q]) {
+        idx.push_back((q << 28) | kv.first);
+        w.push_back(kv.second);
+      }
+    ptr.push_back((int)idx.size());
+    kc.push_back(f.k);
+    dst.push_back((kind << 28) | index);
+  };
+  for (int q = 0; q < g.ng; ++q) emit(gpsi[q], 0, ring(g.g_i[q], g.g_j[q]));
+  for (int q = 0; q < g.ng; ++q) emit(gu[q], 1, ring(g.g_i[q], g.g_j[q]));
+  for (int q = 0; q < g.ng; ++q) emit(gv[q], 2, ring(g.g_i[q], g.g_j[q]));
+  for (int cp = 0; cp < g.nc; ++cp) emit(wbf[cp], 3, cp);
+  const Stencil* ext[3] = {&g.ext4b, &g.ext3b, &g.ext3n};
+  for (int k = 0; k < 3; ++k)
+    for (int q = 0; q < g.ng; ++q) {
+      Form f;
+      const Stencil& st = *ext[k];
+      for (int e = st.ptr[q]; e < st.ptr[q + 1]; ++e) {
+        if (!in_grid(st.ii[e], st.jj[e])) return false;
+        f.t[1][st.jj[e] * nx + st.ii[e]] += st.w[e];
+      }
+      if (k < 2)
+        for (int e = st.bptr[q]; e < st.bptr[q + 1]; ++e) f.add(wbf[st.bc[e]], st.bw[e]);
+      emit(f, 4 + k, g.g_j[q] * nx + g.g_i[q]);
+    }
+  // kinds take the top bits above 28-bit indices (ring indices < 2^28)
+  if ((size_t)(nx + 2) * (ny + 2) >= ((size_t)1 << 28)) return false;
+  c->bnd.rows = (int)kc.size();
+  c->bnd.ptr = c->upload(ptr);
+  c->bnd.idx = c->upload(idx);
+  c->bnd.w = c->upload(w);
+  c->bnd.kc = c->upload(kc);
+  c->bnd.dst = c->upload(dst);
+  return true;
+}
+
 void setup_device(iim_ctx* c) {
   const Geometry& g = c->geo;
   const int nx = g.grid.nx, ny = g.grid.ny, nxr = nx + 2;
@@ -185,6 +312,7 @@ void setup_device(iim_ctx* c) {
   d.ext3n = upload_stencil(c, g.ext3n, false);
   d.aop = upload_stencil(c, g.aop, false);
   d.wbc = upload_stencil(c, g.wbc, true);
+  c->bnd_ok = std::getenv("IIM_CHAINED_BOUNDARY") == nullptr && build_boundary_forms(c, psibt, wbc, ccol);
 
   // Poisson operator
   const double h = g.grid.h;
@@ -358,7 +486,7 @@ void build_direct(iim_ctx* c) {
 
 // One velocity reconstruction: returns status; fills iters/res0/res.
 int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, int& iters, double& res0,
-                      double& res) {
+                      double& res, bool recover = true) {
   const Geometry& g = c->geo;
   const DGeom& dg = c->dg;
   DKrylov& k = c->dk;
@@ -373,7 +501,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
     c->n_solves += 1;
     push_history(c);
     apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
-    launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
+    if (recover) launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
     return IIM_OK;
   }
   set_status(c);
@@ -476,7 +604,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   push_history(c);
   // psi = G (omega - E_a gamma), ghosts, velocity
   apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
-  launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
+  if (recover) launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
   if (c->st_host[KS_NFAIL] != 0.0) return IIM_ENONFINITE;
   if (c->st_host[KS_RES] > c->tol) return IIM_ENOCONV;
   return IIM_OK;
@@ -503,7 +631,7 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
     int it;
     double r0, r1;
     c->cur_stage = s;
-    const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1);
+    const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1, !c->bnd_ok);
     c->cur_stage = -1;
     st.iters[s] = it;
     st.refine_rounds[s] = c->last_rounds;
@@ -514,7 +642,13 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
       status = IIM_ENOCONV;
       st.converged = 0;
     }
-    launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+    if (c->bnd_ok) {
+      // all boundary quantities from their composed forms, then the other velocities
+      launch_boundary_forms(dg, c->bnd, in, c->dk.x, c->psi, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+      launch_velocity(dg, c->psi, c->U, c->V, c->stream);
+    } else {
+      launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+    }
     launch_transport_all(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, c->dGd, c->Gd, c->QGd, RK_A[s],
                          RK_B[s], dt, 1, c->stream, c->prof.mask ? &c->prof : nullptr);
   }

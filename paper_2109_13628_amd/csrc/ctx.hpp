@@ -74,6 +74,8 @@ struct iim_ctx {
   iim::DFft df{};
   iim::DDst dd{};
   iim::DKrylov dk{};
+  iim::DBnd bnd{};                // composed boundary forms of a stage
+  bool bnd_ok = false;
   bool box = false;
   int8_t* cls_zero = nullptr;
   double *psi = nullptr, *U = nullptr, *V = nullptr;

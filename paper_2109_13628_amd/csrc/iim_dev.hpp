@@ -52,6 +52,21 @@ struct DGeom {
   DStencil ext4b, ext3b, ext3n, aop, wbc;
 };
 
+// The boundary quantities of a stage as affine forms of psi (ring), omega
+// (grid) and the body constants psibar: row r = kc[r] + sum over its entries
+// of w * value, with entry idx = kind << 28 | index (kind 0: psi[index],
+// 1: omega[index], 2: psibar[index]); dst = kind << 28 | index names the
+// output (0 psi ghost (ring), 1 u (ring), 2 v (ring), 3 omega_b, 4 E4b,
+// 5 E3b, 6 E3n (grid)).  Indices stay below 2^28, kinds below 8.
+struct DBnd {
+  int rows = 0;
+  const int* ptr = nullptr;
+  const int* idx = nullptr;
+  const double* w = nullptr;
+  const double* kc = nullptr;
+  const int* dst = nullptr;
+};
+
 // FFT convolution plan (free space / outflow)
 struct DFft {
   int mx, my;                  // padded torus
@@ -235,6 +250,12 @@ void launch_recover_fields(const DGeom& g, const double* x, double* psi_ring, do
                            hipStream_t s);
 void launch_omega_bc(const DGeom& g, const double* omega, const double* U, const double* V,
                      double* wb, double* w4, double* w3b, double* w3n, hipStream_t s);
+// every boundary quantity of a stage from its composed form (DBnd); then
+// launch_velocity for the other nodes
+void launch_boundary_forms(const DGeom& g, const DBnd& b, const double* omega, const double* x, double* psi_ring,
+                           double* U, double* V, double* wb, double* w4, double* w3b, double* w3n, hipStream_t s);
+// velocity at every ring node except the ghosts
+void launch_velocity(const DGeom& g, const double* psi_ring, double* U, double* V, hipStream_t s);
 // Transport of every fluid node and the Kelvin circulation update, one launch.
 // mode 0: out = domega/dt, dG = dGamma/dt (Q, Gamma, QG unused);
 // mode 1: Q = a Q + dt rhs, out = omega + b Q, and the same for (Gamma, QG)

@@ -767,7 +767,9 @@ __global__ void k_velocity(DGeom g, const double* __restrict__ psi, double* __re
   const double c = 0.5 * g.inv_h;
   double u = 0.0, v = 0.0;
   if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-    if (g.cls[j * g.nx + i] < 2) {
+    const int8_t cl = g.cls[j * g.nx + i];
+    if (cl == 2) return;  // ghosts: set by the velocity extension
+    if (cl < 2) {
       u = g.uinf_x + c * (psi[t + nxr] - psi[t - nxr]);
       v = g.uinf_y - c * (psi[t + 1] - psi[t - 1]);
     }
@@ -803,9 +805,60 @@ __global__ void k_vel_ext(DGeom g, double* __restrict__ U, double* __restrict__ 
 
 void launch_recover_fields(const DGeom& g, const double* x, double* psi, double* U, double* V, hipStream_t s) {
   if (g.ng) k_ghost_psi<<<(g.ng + 127) / 128, 128, 0, s>>>(g, x, psi);
+  launch_velocity(g, psi, U, V, s);
+  if (g.ng) k_vel_ext<<<(g.ng + 127) / 128, 128, 0, s>>>(g, U, V);
+}
+
+void launch_velocity(const DGeom& g, const double* psi, double* U, double* V, hipStream_t s) {
   const int nr = (g.nx + 2) * (g.ny + 2);
   k_velocity<<<(nr + 255) / 256, 256, 0, s>>>(g, psi, U, V);
-  if (g.ng) k_vel_ext<<<(g.ng + 127) / 128, 128, 0, s>>>(g, U, V);
+}
+
+// Eight lanes per composed row (DBnd): lane l sums entries l, l + 8, ...;
+// the partial sums are combined by shuffles, lane 0 writes the result.  No
+// row reads psi at a ghost node, so the ghost values written here never race
+// with the reads.
+__global__ void __launch_bounds__(256) k_boundary_forms(DGeom g, DBnd b, const double* __restrict__ omega,
+                                                        const double* __restrict__ x, double* psi, double* U,
+                                                        double* V, double* wb, double* w4, double* w3b,
+                                                        double* w3n) {
+  constexpr int L = 8;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = tid / L, l = tid % L;
+  constexpr int M = (1 << 28) - 1;
+  double acc = 0.0;
+  if (r < b.rows) {
+    const int e1 = b.ptr[r + 1];
+    for (int e0 = b.ptr[r] + l; e0 < e1; e0 += 4 * L) {
+      int id[4];
+      double wv[4], val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = e0 + u * L < e1;
+        id[u] = ok ? b.idx[e0 + u * L] : -1;
+        wv[u] = ok ? b.w[e0 + u * L] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kind = id[u] >> 28, i = id[u] & M;
+        val[u] = id[u] < 0 ? 0.0 : (kind == 0 ? psi[i] : (kind == 1 ? omega[i] : x[g.na + i]));
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += wv[u] * val[u];
+    }
+  }
+  for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (r >= b.rows || l != 0) return;
+  acc += b.kc[r];
+  const int d = b.dst[r], kind = d >> 28, i = d & M;
+  double* out = kind == 0 ? psi : kind == 1 ? U : kind == 2 ? V : kind == 3 ? wb : kind == 4 ? w4 : kind == 5 ? w3b : w3n;
+  out[i] = acc;
+}
+
+void launch_boundary_forms(const DGeom& g, const DBnd& b, const double* omega, const double* x, double* psi,
+                           double* U, double* V, double* wb, double* w4, double* w3b, double* w3n, hipStream_t s) {
+  if (b.rows > 0)
+    k_boundary_forms<<<(8 * b.rows + 255) / 256, 256, 0, s>>>(g, b, omega, x, psi, U, V, wb, w4, w3b, w3n);
 }
 
 // ============================================================ boundary vorticity
