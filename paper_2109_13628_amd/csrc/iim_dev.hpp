@@ -2,6 +2,7 @@
 // kernels (kernels.hip).  Host code (api.cpp) fills these structs; kernels
 // receive them by value.
 #pragma once
+#include <climits>
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -228,10 +229,15 @@ inline long grid_size(dim3 g) { return (long)g.x * g.y * g.z; }
 // source = mask(omega) (omega may be null) + sgn * scatter(gam) (gam may be null).
 // fp32: FFTs and kernel multiply in FP32 (inputs and psi stay FP64); needs the
 // FP32 tables and FFT sizes >= 256 (otherwise FP64).
+// The row transforms are computed for rows [fj0, fj1] only (default: all of
+// [rj0, rj1]); the column pass reads rows [rj0, rj1] of the spectrum buffer,
+// so rows outside [fj0, fj1] must still hold the row transforms of the same
+// source from an earlier call (the column pass overwrites rows [oj0, oj1] in
+// place; the row pass writes only its own rows).
 bool conv_reg_supported(int hx, int my);
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
-                 hipStream_t s, Prof* prof = nullptr, bool fp32 = false);
+                 hipStream_t s, Prof* prof = nullptr, bool fp32 = false, int fj0 = INT_MIN, int fj1 = INT_MIN);
 void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
                 double* psi_ring, const double* done_flag, hipStream_t s);
 void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,

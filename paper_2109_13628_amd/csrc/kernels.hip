@@ -329,20 +329,26 @@ static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, do
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                     bool fp32);
+                     bool fp32, int fj0, int fj1);
 
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                  int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                 bool fp32) {
+                 bool fp32, int fj0, int fj1) {
+  if (fj0 == INT_MIN) {
+    fj0 = rj0;
+    fj1 = rj1;
+  }
+  fj0 = std::max(fj0, rj0);
+  fj1 = std::min(fj1, rj1);
   if (f.use_reg && conv_reg_supported(f.hx, f.my)) {
-    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof, fp32 && f.spec32);
+    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof, fp32 && f.spec32, fj0, fj1);
     return;
   }
-  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1, nfwd = fj1 - fj0 + 1;
   int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
-  IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, rj0, nin, done, s);
+  if (nfwd > 0) IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, fj0, nfwd, done, s);
   // algorithmic bytes: source rows read (omega) + half spectrum written
-  if (prof) prof->end(h, (double)nin * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
+  if (prof) prof->end(h, (double)std::max(nfwd, 0) * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
   h = prof ? prof->begin(KID_COLS, s) : -1;
   IIM_POW2_SWITCH(f.my, cols_launch, g, f, rj0, rj1, oj0, oj1, done, s);
   if (prof) prof->end(h, (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
@@ -1788,20 +1794,20 @@ bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                     bool fp32) {
-  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+                     bool fp32, int fj0, int fj1) {
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1, nfwd = std::max(fj1 - fj0 + 1, 0);
   // algorithmic bytes: source rows read (omega) + half spectrum written;
   // spectrum rows in + kernel spectrum + rows out; half spectrum in + ring rows out
   const double cb = fp32 ? 8.0 : 16.0, rb = fp32 ? 4.0 : 8.0;
-  const double b_fwd = (double)nin * ((omega ? 8.0 * g.nx : 0.0) + cb * (f.hx + 1));
+  const double b_fwd = (double)nfwd * ((omega ? 8.0 * g.nx : 0.0) + cb * (f.hx + 1));
   const double b_col = (double)(f.hx + 1) * (cb * nin + rb * (f.my / 2 + 1) + cb * nout);
   const double b_inv = (double)nout * (cb * (f.hx + 1) + 8.0 * (g.nx + 2));
   if (fp32) {
-    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, gam, sgn, fj0, nfwd, done, s, prof, b_fwd);
     IIM_REG_SWITCH(f.my, cols_reg_launch, float2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, float2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   } else {
-    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, gam, sgn, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, gam, sgn, fj0, nfwd, done, s, prof, b_fwd);
     IIM_REG_SWITCH(f.my, cols_reg_launch, double2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, double2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   }
