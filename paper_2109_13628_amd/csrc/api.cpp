@@ -370,6 +370,7 @@ void setup_device(iim_ctx* c) {
     f.tw_xr = c->upload(twid(mx, f.hx + 1));
     f.tw_y = c->upload(twid(my, my));
     f.spec = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
+    f.spec_out = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
     if (c->precision == IIM_PREC_MIXED && conv_reg_supported(f.hx, f.my)) {
       // FP32 tables for the inner matrix-vector products
       auto to32 = [](const std::vector<double2>& t) {
@@ -383,6 +384,7 @@ void setup_device(iim_ctx* c) {
       f.tw_xr32 = c->upload(to32(twid(mx, f.hx + 1)));
       f.tw_y32 = c->upload(to32(twid(my, my)));
       f.spec32 = c->dalloc<float2>((size_t)(f.hx + 1) * f.ld);
+      f.spec32_out = c->dalloc<float2>((size_t)(f.hx + 1) * f.ld);
     }
   }
   // Krylov state
@@ -425,12 +427,12 @@ void setup_device(iim_ctx* c) {
 
 // psi (ring) = G(source), source = mask(omega) + sgn * E_a gam, rows [rj0, rj1] -> [oj0, oj1]
 void iim::apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
-             int oj0, int oj1, double* psi, const double* done, bool fp32, int fj0, int fj1) {
+             int oj0, int oj1, double* psi, const double* done, bool fp32, bool rows_ready) {
   if (c->box)
     launch_dst(dg, c->dd, omega, gam, sgn, psi, done, c->stream);
   else
     launch_conv(dg, c->df, omega, gam, sgn, rj0, rj1, oj0, oj1, psi, done, c->stream,
-                c->prof.mask ? &c->prof : nullptr, fp32, fj0, fj1);
+                c->prof.mask ? &c->prof : nullptr, fp32, rows_ready);
 }
 
 
@@ -493,13 +495,9 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   const int ny = g.grid.ny;
   // right-hand side: b = A G omega + B psi_b_tilde, circulation rows
   apply_G(c, dg, omega, nullptr, 0.0, 0, ny - 1, g.out_j0, g.out_j1, c->psi, nullptr);
-  // The row transforms of omega now sit in the spectrum buffer.  Until the
-  // final product, every product of this solve writes spectrum rows of the
-  // correction sources (src band) and overwrites output rows (out band) only,
-  // and the correction adds to the source in the src band only, so the final
-  // product recomputes the row transforms of these two bands and reuses the
-  // rest.
-  const int band0 = std::min(g.src_j0, g.out_j0), band1 = std::max(g.src_j1, g.out_j1);
+  // The row transforms of omega now sit in the spectrum buffer; the solve's
+  // products have no dense source and leave them there, so the final product
+  // psi = G (omega - E gamma) reuses them.
   launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
   if (c->solver == IIM_SOLVER_DIRECT) {
     launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->stream);
@@ -507,7 +505,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
     res0 = res = 0.0;
     c->n_solves += 1;
     push_history(c);
-    apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr, false, band0, band1);
+    apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr, false, true);
     if (recover) launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
     return IIM_OK;
   }
@@ -610,7 +608,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   c->have_prev = true;
   push_history(c);
   // psi = G (omega - E_a gamma), ghosts, velocity
-  apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr, false, band0, band1);
+  apply_G(c, dg, omega, k.x, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr, false, true);
   if (recover) launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
   if (c->st_host[KS_NFAIL] != 0.0) return IIM_ENONFINITE;
   if (c->st_host[KS_RES] > c->tol) return IIM_ENOCONV;

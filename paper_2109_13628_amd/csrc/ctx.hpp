@@ -144,8 +144,7 @@ namespace iim {
 
 // api.cpp
 void apply_G(iim_ctx* c, const DGeom& dg, const double* omega, const double* gam, double sgn, int rj0, int rj1,
-             int oj0, int oj1, double* psi, const double* done, bool fp32 = false, int fj0 = INT_MIN,
-             int fj1 = INT_MIN);
+             int oj0, int oj1, double* psi, const double* done, bool fp32 = false, bool rows_ready = false);
 void build_schur_t(iim_ctx* c, double* St);   // St[q][i] = (S e_q)_i
 void read_status(iim_ctx* c);
 void set_status(iim_ctx* c);

@@ -77,7 +77,8 @@ struct DFft {
   const double2* tw_x;         // exp(-2 pi i k / hx), k < hx
   const double2* tw_xr;        // exp(-2 pi i k / mx), k <= mx/2 (real-FFT post-processing)
   const double2* tw_y;         // exp(-2 pi i k / my), k < my
-  double2* spec;               // [mx/2+1][ld]
+  double2* spec;               // [mx/2+1][ld] row transforms of the dense source
+  double2* spec_out;           // [mx/2+1][ld] column pass output
   // FP32 copies for the inner products of the mixed-precision solve (null
   // unless the context is mixed precision)
   const float* ghat32 = nullptr;
@@ -85,6 +86,7 @@ struct DFft {
   const float2* tw_xr32 = nullptr;
   const float2* tw_y32 = nullptr;
   float2* spec32 = nullptr;
+  float2* spec32_out = nullptr;
   bool outflow;
   bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
   int row_per = 0, col_per = 0; // FFTs per workgroup of the row / column passes (0: default; tuned)
@@ -229,15 +231,16 @@ inline long grid_size(dim3 g) { return (long)g.x * g.y * g.z; }
 // source = mask(omega) (omega may be null) + sgn * scatter(gam) (gam may be null).
 // fp32: FFTs and kernel multiply in FP32 (inputs and psi stay FP64); needs the
 // FP32 tables and FFT sizes >= 256 (otherwise FP64).
-// The row transforms are computed for rows [fj0, fj1] only (default: all of
-// [rj0, rj1]); the column pass reads rows [rj0, rj1] of the spectrum buffer,
-// so rows outside [fj0, fj1] must still hold the row transforms of the same
-// source from an earlier call (the column pass overwrites rows [oj0, oj1] in
-// place; the row pass writes only its own rows).
+// The row pass transforms the dense part (omega) into spec; the sparse part
+// (gam) enters the column pass directly, which writes spec_out, read by the
+// inverse row pass.  spec is written by the row pass only, so with
+// rows_ready the row pass is skipped and the row transforms that an earlier
+// call left in spec are used: they must be those of the same omega over the
+// same rows [rj0, rj1] and precision.
 bool conv_reg_supported(int hx, int my);
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
-                 hipStream_t s, Prof* prof = nullptr, bool fp32 = false, int fj0 = INT_MIN, int fj1 = INT_MIN);
+                 hipStream_t s, Prof* prof = nullptr, bool fp32 = false, bool rows_ready = false);
 void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
                 double* psi_ring, const double* done_flag, hipStream_t s);
 void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,

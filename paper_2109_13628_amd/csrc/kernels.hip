@@ -2,12 +2,14 @@
 //
 // Poisson operator (Sec. 4.2): zero-padded lattice-Green's-function
 // convolution on an mx x my torus in three passes over HBM,
-//   rows  : real-to-complex FFT of each source row (half-length complex FFT +
-//           split), IIM scatter of gamma fused into the load, spectrum written
-//           column-major spec[kx][j];
-//   cols  : per column kx: FFT, multiply by the (real) kernel spectrum, inverse
-//           FFT -- entirely in LDS, reading only the source rows and writing
-//           only the requested output rows (pruned in the Krylov loop);
+//   rows  : real-to-complex FFT of each dense source row (half-length
+//           complex FFT + split), spectrum written column-major spec[kx][j];
+//   cols  : per column kx: the dense rows' transforms plus the direct row
+//           transforms of the IIM correction sources (a few points per row),
+//           FFT, multiply by the (real) kernel spectrum, inverse FFT, reading
+//           only the source rows and writing only the requested output rows
+//           (pruned in the Krylov loop) into a second buffer, so that the row
+//           transforms of omega survive the solve's products;
 //   irows : complex-to-real inverse FFT of the requested rows, writing the
 //           grid plus the one-node ring.
 // FFTs are LDS Stockham radix-4 (one radix-2 stage when log2 N is odd) with
@@ -58,6 +60,51 @@ __device__ __forceinline__ CX mkc(A x, B y) {
   r.x = (typename Real<CX>::t)x;
   r.y = (typename Real<CX>::t)y;
   return r;
+}
+
+// Row transform, at frequency kx, of the correction sources of row n: the
+// sum over the row's entries of sgn * gam[a] * W^(kx i), W = exp(-2 pi i / mx),
+// plus the mirrored source at column 2 nx - 1 - i for the outflow exterior.
+// This is what the real row transform of length mx gives for a row that holds
+// only these point values; the column pass adds it directly, so the sparse
+// sources need no row pass.  tw_xr holds W^k for k <= mx / 2 (mx a power of two).
+// W^r for 0 <= r < mx from the table of W^k, k <= mx / 2 (one load, always in range)
+template <class CX>
+__device__ __forceinline__ CX twiddle_r(const CX* __restrict__ tw_xr, int r, int mx) {
+  const bool hi = r > mx / 2;
+  const CX w = tw_xr[hi ? mx - r : r];
+  return hi ? conj2(w) : w;
+}
+
+template <class CX>
+__device__ __forceinline__ CX sparse_row_dft(const DGeom& g, int mx, bool outflow, const CX* __restrict__ tw_xr,
+                                             const double* __restrict__ gam, double sgn, int n, int kx) {
+  using S = typename Real<CX>::t;
+  CX acc = mkc<CX>(0, 0);
+  const int e1 = g.row_ptr[n + 1];
+  for (int e0 = g.row_ptr[n]; e0 < e1; e0 += 4) {
+    int ii[4];
+    double val[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = e0 + u < e1;
+      ii[u] = ok ? g.row_i[e0 + u] : 0;
+      val[u] = ok ? sgn * gam[g.row_a[e0 + u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const CX w = twiddle_r(tw_xr, (kx * ii[u]) & (mx - 1), mx);
+      const S v = (S)val[u];
+      acc.x += v * w.x;
+      acc.y += v * w.y;
+      if (outflow) {
+        const CX w2 = twiddle_r(tw_xr, (kx * (2 * g.nx - 1 - ii[u])) & (mx - 1), mx);
+        acc.x += v * w2.x;
+        acc.y += v * w2.y;
+      }
+    }
+  }
+  return acc;
 }
 
 // ------------------------------------------------------------------ FFT core
@@ -148,8 +195,7 @@ struct FftCfg {
 // Forward real FFT of length mx = 2*HX of the source rows j in [j0, j0 + count).
 template <int HX>
 __global__ void __launch_bounds__(FftCfg<HX>::THREADS)
-k_rows_fwd(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
-           int j0, int count, const double* __restrict__ done) {
+k_rows_fwd(DGeom g, DFft f, const double* __restrict__ omega, int j0, int count, const double* __restrict__ done) {
   using C = FftCfg<HX>;
   if (done && done[KS_DONE] != 0.0) return;
   __shared__ double2 lds[C::PER][HX];
@@ -176,16 +222,6 @@ k_rows_fwd(DGeom g, DFft f, const double* __restrict__ omega, const double* __re
     z[n] = v;
   }
   __syncthreads();
-  if (valid && gam) {
-    for (int e = g.row_ptr[jrow] + lt; e < g.row_ptr[jrow + 1]; e += C::TPF) {
-      const int i = g.row_i[e];
-      const double val = sgn * gam[g.row_a[e]];
-      double* zz = reinterpret_cast<double*>(z);
-      zz[i] += val;
-      if (f.outflow) zz[2 * g.nx - 1 - i] += val;
-    }
-  }
-  __syncthreads();
   fft_lds<HX, C::TPF, false>(z, lt, f.tw_x);
   // split: X_k = E_k + W^k O_k, k in [0, HX]; write spec[k][jrow + 1]
   const int nth = C::THREADS;
@@ -206,7 +242,8 @@ k_rows_fwd(DGeom g, DFft f, const double* __restrict__ omega, const double* __re
 // ---------------------------------------------------------------- column pass
 template <int MY>
 __global__ void __launch_bounds__(FftCfg<MY>::THREADS)
-k_cols(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
+k_cols(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double sgn, int rj0, int rj1, int oj0, int oj1,
+       const double* __restrict__ done) {
   using C = FftCfg<MY>;
   if (done && done[KS_DONE] != 0.0) return;
   __shared__ double2 lds[C::PER][MY];
@@ -215,11 +252,16 @@ k_cols(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __rest
   const int kx = blockIdx.x * C::PER + r;
   const bool valid = kx <= f.hx;
   double2* z = lds[r];
-  double2* col = f.spec + (size_t)(valid ? kx : 0) * f.ld;
+  const double2* col = f.spec + (size_t)(valid ? kx : 0) * f.ld;
+  double2* out = f.spec_out + (size_t)(valid ? kx : 0) * f.ld;
   for (int n = lt; n < MY; n += C::TPF) z[n] = make_double2(0.0, 0.0);
   __syncthreads();
-  if (valid)
+  if (valid && dense)
     for (int j = rj0 + lt; j <= rj1; j += C::TPF) z[j & (MY - 1)] = col[j + 1];
+  // the same thread owns row j in both loops
+  if (valid && gam)
+    for (int j = rj0 + lt; j <= rj1 && j < g.ny; j += C::TPF)
+      z[j & (MY - 1)] = cadd(z[j & (MY - 1)], sparse_row_dft<double2>(g, f.mx, f.outflow, f.tw_xr, gam, sgn, j, kx));
   __syncthreads();
   fft_lds<MY, C::TPF, false>(z, lt, f.tw_y);
   if (valid) {
@@ -233,7 +275,7 @@ k_cols(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __rest
   __syncthreads();
   fft_lds<MY, C::TPF, true>(z, lt, f.tw_y);
   if (valid)
-    for (int j = oj0 + lt; j <= oj1; j += C::TPF) col[j + 1] = z[j & (MY - 1)];
+    for (int j = oj0 + lt; j <= oj1; j += C::TPF) out[j + 1] = z[j & (MY - 1)];
 }
 
 // ------------------------------------------------------------ inverse rows
@@ -251,7 +293,7 @@ k_rows_inv(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const d
     const int rr = t % C::PER, k = t / C::PER;
     const int jo = j0 + blockIdx.x * C::PER + rr;
     double2 v = make_double2(0.0, 0.0);
-    if (jo < j0 + count) v = f.spec[(size_t)k * f.ld + jo + 1];
+    if (jo < j0 + count) v = f.spec_out[(size_t)k * f.ld + jo + 1];
     lds[rr][k] = v;
   }
   __syncthreads();
@@ -292,18 +334,18 @@ k_rows_inv(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const d
 }
 
 template <int HX>
-static void rows_fwd_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
-                            int j0, int count, const double* done, hipStream_t s) {
+static void rows_fwd_launch(const DGeom& g, const DFft& f, const double* omega, int j0, int count,
+                            const double* done, hipStream_t s) {
   using C = FftCfg<HX>;
   const int blocks = (count + C::PER - 1) / C::PER;
-  if (blocks > 0) k_rows_fwd<HX><<<blocks, C::THREADS, 0, s>>>(g, f, omega, gam, sgn, j0, count, done);
+  if (blocks > 0) k_rows_fwd<HX><<<blocks, C::THREADS, 0, s>>>(g, f, omega, j0, count, done);
 }
 template <int MY>
-static void cols_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
-                        hipStream_t s) {
+static void cols_launch(const DGeom& g, const DFft& f, bool dense, const double* gam, double sgn, int rj0, int rj1,
+                        int oj0, int oj1, const double* done, hipStream_t s) {
   using C = FftCfg<MY>;
   const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  k_cols<MY><<<blocks, C::THREADS, 0, s>>>(g, f, rj0, rj1, oj0, oj1, done);
+  k_cols<MY><<<blocks, C::THREADS, 0, s>>>(g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done);
 }
 template <int HX>
 static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
@@ -329,29 +371,25 @@ static void rows_inv_launch(const DGeom& g, const DFft& f, int j0, int count, do
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                     bool fp32, int fj0, int fj1);
+                     bool fp32, bool rows_ready);
 
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                  int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                 bool fp32, int fj0, int fj1) {
-  if (fj0 == INT_MIN) {
-    fj0 = rj0;
-    fj1 = rj1;
-  }
-  fj0 = std::max(fj0, rj0);
-  fj1 = std::min(fj1, rj1);
+                 bool fp32, bool rows_ready) {
   if (f.use_reg && conv_reg_supported(f.hx, f.my)) {
-    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof, fp32 && f.spec32, fj0, fj1);
+    launch_conv_reg(g, f, omega, gam, sgn, rj0, rj1, oj0, oj1, psi_ring, done, s, prof, fp32 && f.spec32,
+                    rows_ready);
     return;
   }
-  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1, nfwd = fj1 - fj0 + 1;
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+  const bool dense = omega != nullptr;
   int h = prof ? prof->begin(KID_ROWS_FWD, s) : -1;
-  if (nfwd > 0) IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, gam, sgn, fj0, nfwd, done, s);
+  if (dense && !rows_ready) IIM_POW2_SWITCH(f.hx, rows_fwd_launch, g, f, omega, rj0, nin, done, s);
   // algorithmic bytes: source rows read (omega) + half spectrum written
-  if (prof) prof->end(h, (double)std::max(nfwd, 0) * ((omega ? 8.0 * g.nx : 0.0) + 16.0 * (f.hx + 1)), s);
+  if (prof) prof->end(h, (dense && !rows_ready) ? (double)nin * (8.0 * g.nx + 16.0 * (f.hx + 1)) : 0.0, s);
   h = prof ? prof->begin(KID_COLS, s) : -1;
-  IIM_POW2_SWITCH(f.my, cols_launch, g, f, rj0, rj1, oj0, oj1, done, s);
-  if (prof) prof->end(h, (double)(f.hx + 1) * (16.0 * nin + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
+  IIM_POW2_SWITCH(f.my, cols_launch, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s);
+  if (prof) prof->end(h, (double)(f.hx + 1) * ((dense ? 16.0 * nin : 0.0) + 8.0 * (f.my / 2 + 1) + 16.0 * nout), s);
   h = prof ? prof->begin(KID_ROWS_INV, s) : -1;
   IIM_POW2_SWITCH(f.hx, rows_inv_launch, g, f, oj0, nout, psi_ring, done, s);
   if (prof) prof->end(h, (double)nout * (16.0 * (f.hx + 1) + 8.0 * (g.nx + 2)), s);
@@ -1338,7 +1376,8 @@ __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
 // inner matrix-vector products of the mixed-precision solve.
 template <class CX>
 struct FftT {
-  CX* spec;
+  CX* spec;                    // row transforms (row pass output, column pass input)
+  CX* out;                     // column pass output, inverse row pass input
   const CX* tw_x;
   const CX* tw_xr;
   const CX* tw_y;
@@ -1348,11 +1387,11 @@ template <class CX>
 __device__ __forceinline__ FftT<CX> fft_view(const DFft& f);
 template <>
 __device__ __forceinline__ FftT<double2> fft_view<double2>(const DFft& f) {
-  return FftT<double2>{f.spec, f.tw_x, f.tw_xr, f.tw_y, f.ghat};
+  return FftT<double2>{f.spec, f.spec_out, f.tw_x, f.tw_xr, f.tw_y, f.ghat};
 }
 template <>
 __device__ __forceinline__ FftT<float2> fft_view<float2>(const DFft& f) {
-  return FftT<float2>{f.spec32, f.tw_x32, f.tw_xr32, f.tw_y32, f.ghat32};
+  return FftT<float2>{f.spec32, f.spec32_out, f.tw_x32, f.tw_xr32, f.tw_y32, f.ghat32};
 }
 
 // a comma inside a macro argument (template arguments of a launched kernel)
@@ -1538,7 +1577,8 @@ __device__ __forceinline__ void fft_reg(CX (&v)[RP<N>::E], CX* lds, int t, const
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
 template <int MY, class CX, int PER>
 __global__ void __launch_bounds__((RegCfg<MY, PER>::THREADS))
-k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __restrict__ done) {
+k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double sgn, int rj0, int rj1, int oj0,
+           int oj1, const double* __restrict__ done) {
   using C = RegCfg<MY, PER>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
@@ -1548,12 +1588,65 @@ k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __
   const int w = threadIdx.x / T, t = threadIdx.x % T;
   const int kx = blockIdx.x * C::PER + w;
   const bool valid = kx <= f.hx;
-  CX* col = ft.spec + (size_t)(valid ? kx : 0) * f.ld;
+  const CX* col = ft.spec + (size_t)(valid ? kx : 0) * f.ld;
+  CX* out = ft.out + (size_t)(valid ? kx : 0) * f.ld;
   CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    v[m] = (valid && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
+    v[m] = (valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
+  }
+  if (gam) {
+    // Correction sources: the column's T lanes compute the terms
+    // sgn gam[a_e] W^(kx i_e) of all entries e of rows [rj0, rj1] (a few per
+    // lane, loads batched), stage them in this FFT's LDS buffer (free until
+    // the FFT), and the lane owning a row sums the terms of its entries.
+    // Entries are grouped by row, so a row's terms are contiguous; more
+    // entries than the buffer holds are taken in chunks.  Every lane of the
+    // block runs the same chunks (the bounds depend on rj0, rj1 only).
+    const int jb = max(rj0, 0), je = min(rj1, g.ny - 1);
+    const int eb = jb <= je ? g.row_ptr[jb] : 0, ee = jb <= je ? g.row_ptr[je + 1] : 0;
+    int rb[E], re[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      const bool in = n >= jb && n <= je;
+      rb[m] = in ? g.row_ptr[n] : 0;
+      re[m] = in ? g.row_ptr[n + 1] : 0;
+    }
+    const int mx = f.mx;
+    for (int c0 = eb; c0 < ee; c0 += C::LDSN) {
+      const int c1 = min(ee, c0 + C::LDSN);
+      for (int e0 = c0 + t; e0 < c1; e0 += 4 * T) {
+        int ii[4];
+        double val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = e0 + u * T < c1;
+          ii[u] = ok ? g.row_i[e0 + u * T] : 0;
+          val[u] = ok ? sgn * gam[g.row_a[e0 + u * T]] : 0.0;
+        }
+        CX w1[4], w2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          w1[u] = twiddle_r(ft.tw_xr, (kx * ii[u]) & (mx - 1), mx);
+          w2[u] = f.outflow ? twiddle_r(ft.tw_xr, (kx * (2 * g.nx - 1 - ii[u])) & (mx - 1), mx) : mkc<CX>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (e0 + u * T >= c1) break;
+          const S vv = (S)val[u];
+          lds[w][e0 + u * T - c0] = mkc<CX>(vv * (w1[u].x + w2[u].x), vv * (w1[u].y + w2[u].y));
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int q1 = min(re[m], c1);
+        for (int q = max(rb[m], c0); q < q1; ++q) v[m] = cadd(v[m], lds[w][q - c0]);
+      }
+      __syncthreads();
+    }
   }
   // kernel spectrum of this thread's bins, loaded before the forward FFT
   const S* gh = ft.ghat + (size_t)(valid ? kx : 0) * (MY / 2 + 1);
@@ -1575,7 +1668,7 @@ k_cols_reg(DGeom g, DFft f, int rj0, int rj1, int oj0, int oj1, const double* __
     for (int m = 0; m < E; ++m) {
       const int n = t + T * m;
       const int jo = (n == MY - 1) ? -1 : n;
-      if (jo >= oj0 && jo <= oj1) col[jo + 1] = v[m];
+      if (jo >= oj0 && jo <= oj1) out[jo + 1] = v[m];
     }
   }
 }
@@ -1596,8 +1689,8 @@ __device__ __forceinline__ void add_at(CX (&v)[RP<HX>::E], int t, int i, double 
 
 template <int HX, class CX, int PER>
 __global__ void __launch_bounds__((RegCfg<HX, PER>::THREADS))
-k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* __restrict__ gam, double sgn,
-               int j0, int count, const double* __restrict__ done) {
+k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int count,
+               const double* __restrict__ done) {
   using C = RegCfg<HX, PER>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
@@ -1613,7 +1706,7 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
     CX z = mkc<CX>(0, 0);
-    if (valid && omega) {
+    if (valid) {
       const int i0 = 2 * n, i1 = 2 * n + 1;
       int m0 = i0, m1 = i1;
       if (f.outflow) {
@@ -1629,14 +1722,6 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, const double* 
       z.y = c1 < 2 ? (S)o1 : (S)0;
     }
     v[m] = z;
-  }
-  if (valid && gam) {
-    for (int e = g.row_ptr[jrow]; e < g.row_ptr[jrow + 1]; ++e) {
-      const int i = g.row_i[e];
-      const double val = sgn * gam[g.row_a[e]];
-      add_at<HX>(v, t, i, val);
-      if (f.outflow) add_at<HX>(v, t, 2 * g.nx - 1 - i, val);
-    }
   }
   fft_reg<HX, false>(v, lds[w], t, ft.tw_x);
 #pragma unroll
@@ -1685,7 +1770,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
       const int idx = threadIdx.x + q * C::THREADS;
       const int rr = idx % C::PER, k = idx / C::PER;
       const int jo = j0 + lb * C::PER + rr;
-      tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? ft.spec[(size_t)k * f.ld + jo + 1]
+      tmp[q] = (idx < (HX + 1) * C::PER && jo < j0 + count) ? ft.out[(size_t)k * f.ld + jo + 1]
                                                              : mkc<CX>(0, 0);
     }
 #pragma unroll
@@ -1723,21 +1808,21 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
 }
 
 template <int HX, class CX, int PER>
-void rows_fwd_go(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0, int count,
-                 const double* done, hipStream_t s, Prof* prof, double bytes) {
+void rows_fwd_go(const DGeom& g, const DFft& f, const double* omega, int j0, int count, const double* done,
+                 hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<HX, PER>;
   const int blocks = (count + C::PER - 1) / C::PER;
   if (blocks > 0)
     IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f,
-               omega, gam, sgn, j0, count, done);
+               omega, j0, count, done);
 }
 template <int MY, class CX, int PER>
-void cols_go(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done, hipStream_t s,
-             Prof* prof, double bytes) {
+void cols_go(const DGeom& g, const DFft& f, bool dense, const double* gam, double sgn, int rj0, int rj1, int oj0,
+             int oj1, const double* done, hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<MY, PER>;
   const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f, rj0, rj1,
-             oj0, oj1, done);
+  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f, dense, gam,
+             sgn, rj0, rj1, oj0, oj1, done);
 }
 template <int HX, class CX, int PER>
 void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done, hipStream_t s,
@@ -1765,14 +1850,15 @@ void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, 
   } while (0)
 
 template <int HX, class CX>
-void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int j0,
-                         int count, const double* done, hipStream_t s, Prof* prof, double bytes) {
-  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_fwd_go, g, f, omega, gam, sgn, j0, count, done, s, prof, bytes);
+void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, int j0, int count, const double* done,
+                         hipStream_t s, Prof* prof, double bytes) {
+  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_fwd_go, g, f, omega, j0, count, done, s, prof, bytes);
 }
 template <int MY, class CX>
-void cols_reg_launch(const DGeom& g, const DFft& f, int rj0, int rj1, int oj0, int oj1, const double* done,
-                     hipStream_t s, Prof* prof, double bytes) {
-  IIM_PER_DISPATCH(MY, CX, f.col_per, false, cols_go, g, f, rj0, rj1, oj0, oj1, done, s, prof, bytes);
+void cols_reg_launch(const DGeom& g, const DFft& f, bool dense, const double* gam, double sgn, int rj0, int rj1,
+                     int oj0, int oj1, const double* done, hipStream_t s, Prof* prof, double bytes) {
+  IIM_PER_DISPATCH(MY, CX, f.col_per, false, cols_go, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s, prof,
+                   bytes);
 }
 template <int HX, class CX>
 void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
@@ -1794,21 +1880,23 @@ bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,
-                     bool fp32, int fj0, int fj1) {
-  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1, nfwd = std::max(fj1 - fj0 + 1, 0);
+                     bool fp32, bool rows_ready) {
+  const int nin = rj1 - rj0 + 1, nout = oj1 - oj0 + 1;
+  const bool dense = omega != nullptr, rows = dense && !rows_ready;
   // algorithmic bytes: source rows read (omega) + half spectrum written;
-  // spectrum rows in + kernel spectrum + rows out; half spectrum in + ring rows out
+  // spectrum rows in (dense source) + kernel spectrum + rows out; half
+  // spectrum in + ring rows out
   const double cb = fp32 ? 8.0 : 16.0, rb = fp32 ? 4.0 : 8.0;
-  const double b_fwd = (double)nfwd * ((omega ? 8.0 * g.nx : 0.0) + cb * (f.hx + 1));
-  const double b_col = (double)(f.hx + 1) * (cb * nin + rb * (f.my / 2 + 1) + cb * nout);
+  const double b_fwd = (double)nin * (8.0 * g.nx + cb * (f.hx + 1));
+  const double b_col = (double)(f.hx + 1) * ((dense ? cb * nin : 0.0) + rb * (f.my / 2 + 1) + cb * nout);
   const double b_inv = (double)nout * (cb * (f.hx + 1) + 8.0 * (g.nx + 2));
   if (fp32) {
-    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, gam, sgn, fj0, nfwd, done, s, prof, b_fwd);
-    IIM_REG_SWITCH(f.my, cols_reg_launch, float2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
+    if (rows) IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.my, cols_reg_launch, float2, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, float2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   } else {
-    IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, gam, sgn, fj0, nfwd, done, s, prof, b_fwd);
-    IIM_REG_SWITCH(f.my, cols_reg_launch, double2, g, f, rj0, rj1, oj0, oj1, done, s, prof, b_col);
+    if (rows) IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, rj0, nin, done, s, prof, b_fwd);
+    IIM_REG_SWITCH(f.my, cols_reg_launch, double2, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, double2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   }
 }
