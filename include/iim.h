@@ -234,10 +234,12 @@ int iim_rk3_steps(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt
 int iim_profile(iim_ctx* ctx, int32_t kernel_mask);
 int iim_profile_read(iim_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
-/* FFT tile autotuner: times one full Poisson convolution of this context
- * (reps repeats) with every instantiated number of FFTs per workgroup of
- * the row passes and of the column pass (1, 2, 4; shapes over 1024 threads
- * or 128 KiB of LDS fall back to the default) and keeps the fastest.
+/* FFT tile autotuner: times the full Poisson convolution of a stage (dense
+ * source plus the correction sources; reps repeats, three interleaved rounds,
+ * the minimum of each shape) with every instantiated number of FFTs per
+ * workgroup of the row passes and of the column pass (1, 2, 4; shapes over
+ * 1024 threads or 128 KiB of LDS fall back to the default) and keeps the
+ * fastest.
  * Outputs (nullable): the chosen counts (0 = default), the default's and the
  * best time per convolution in microseconds.  The shapes change only the
  * work per workgroup, not the arithmetic: results are bitwise the same.

@@ -498,9 +498,11 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   // The row transforms of omega now sit in the spectrum buffer; the solve's
   // products have no dense source and leave them there, so the final product
   // psi = G (omega - E gamma) reuses them.
-  launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
   if (c->solver == IIM_SOLVER_DIRECT) {
-    launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->stream);
+    if (!launch_rhs_solve(dg, c->psi, omega, Gamma_dev, c->Sinv_t, k.n, k.b, k.x, c->stream)) {
+      launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
+      launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->stream);
+    }
     iters = 0;
     res0 = res = 0.0;
     c->n_solves += 1;
@@ -509,6 +511,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
     if (recover) launch_recover_fields(dg, k.x, c->psi, c->U, c->V, c->stream);
     return IIM_OK;
   }
+  launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
   set_status(c);
   // initial guess: zero, the previous solve, its extrapolation in time, or
   // the extrapolation corrected by the network
@@ -648,14 +651,15 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
       st.converged = 0;
     }
     if (c->bnd_ok) {
-      // all boundary quantities from their composed forms, then the other velocities
+      // all boundary quantities from their composed forms; the transport forms
+      // the other velocities from psi
       launch_boundary_forms(dg, c->bnd, in, c->dk.x, c->psi, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
-      launch_velocity(dg, c->psi, c->U, c->V, c->stream);
     } else {
       launch_omega_bc(dg, in, c->U, c->V, c->wb, c->w4, c->w3b, c->w3n, c->stream);
     }
-    launch_transport_all(dg, in, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw, c->dGd, c->Gd, c->QGd, RK_A[s],
-                         RK_B[s], dt, 1, c->stream, c->prof.mask ? &c->prof : nullptr);
+    launch_transport_all(dg, in, c->bnd_ok ? c->psi : nullptr, c->U, c->V, c->w4, c->w3b, c->w3n, out, c->Qw,
+                         c->dGd, c->Gd, c->QGd, RK_A[s], RK_B[s], dt, 1, c->stream,
+                         c->prof.mask ? &c->prof : nullptr);
   }
   if (stats) *stats = st;
   return status;
@@ -958,7 +962,7 @@ int iim_rhs(iim_ctx* c, const double* omega, const double* u, const double* v, d
   try {
     const DGeom& dg = c->dg;
     launch_omega_bc(dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
-    launch_transport_all(dg, omega, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, c->dGd, nullptr, nullptr, 0.0, 0.0,
+    launch_transport_all(dg, omega, nullptr, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, c->dGd, nullptr, nullptr, 0.0, 0.0,
                          0.0, 0, c->stream);
     if (omega_b)
       HIPCHK(hipMemcpyAsync(omega_b, c->wb, c->geo.nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1076,24 +1080,33 @@ int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, d
       hipEvent_t a, b;
       HIPCHK(hipEventCreate(&a));
       HIPCHK(hipEventCreate(&b));
+      // the timed operation is the stage's full product: dense source plus
+      // the correction sources (their values do not change the time)
+      const double* gam = c->dk.n > 0 ? c->dk.x : nullptr;
       const int opts[3] = {1, 2, 4};
-      best = 1e300;
-      for (int r = -1; r < 3; ++r)
-        for (int q = -1; q < 3; ++q) {
-          if ((r < 0) != (q < 0)) continue;        // (-1, -1): the defaults
-          c->df.row_per = r < 0 ? 0 : opts[r];
-          c->df.col_per = q < 0 ? 0 : opts[q];
-          for (int w = 0; w < 2; ++w) apply_G(c, c->dg, c->wtmp, nullptr, 0.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+      // (0, 0): the defaults; then every pair of tuned shapes.  Three
+      // interleaved rounds, the minimum of each shape kept.
+      std::vector<std::pair<int, int>> shapes{{0, 0}};
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) shapes.emplace_back(opts[r], opts[q]);
+      std::vector<double> us_min(shapes.size(), 1e300);
+      for (int round = 0; round < 3; ++round)
+        for (size_t k = 0; k < shapes.size(); ++k) {
+          c->df.row_per = shapes[k].first;
+          c->df.col_per = shapes[k].second;
+          for (int w = 0; w < 2; ++w) apply_G(c, c->dg, c->wtmp, gam, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
           HIPCHK(hipEventRecord(a, c->stream));
-          for (int w = 0; w < reps; ++w) apply_G(c, c->dg, c->wtmp, nullptr, 0.0, 0, ny - 1, -1, ny, c->psi, nullptr);
+          for (int w = 0; w < reps; ++w) apply_G(c, c->dg, c->wtmp, gam, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
           HIPCHK(hipEventRecord(b, c->stream));
           HIPCHK(hipEventSynchronize(b));
           float ms = 0.f;
           HIPCHK(hipEventElapsedTime(&ms, a, b));
-          const double us = 1e3 * ms / reps;
-          if (r < 0) def = us;
-          if (us < best) best = us, br = c->df.row_per, bc = c->df.col_per;
+          us_min[k] = std::min(us_min[k], 1e3 * ms / reps);
         }
+      def = us_min[0];
+      best = 1e300;
+      for (size_t k = 0; k < shapes.size(); ++k)
+        if (us_min[k] < best) best = us_min[k], br = shapes[k].first, bc = shapes[k].second;
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       c->df.row_per = br;

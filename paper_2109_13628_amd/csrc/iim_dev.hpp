@@ -270,13 +270,22 @@ void launch_velocity(const DGeom& g, const double* psi_ring, double* U, double* 
 // mode 1: Q = a Q + dt rhs, out = omega + b Q, and the same for (Gamma, QG)
 // with dG the rate; a = 0 overwrites the registers without reading them.
 // Kelvin: dG = -h sum (F+Q).n over dR_k.
-void launch_transport_all(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
-                          const double* w3b, const double* w3n, double* out, double* Q, double* dG, double* Gamma,
-                          double* QG, double a, double b, double dt, int mode, hipStream_t s, Prof* prof = nullptr);
+// Velocities: psi null: U, V on the ring; otherwise formed from psi (ring,
+// ghost values already in place) at every node but the ghosts, whose
+// extension values are read from U, V (the velocity kernel is not needed).
+void launch_transport_all(const DGeom& g, const double* omega, const double* psi, const double* U, const double* V,
+                          const double* w4, const double* w3b, const double* w3n, double* out, double* Q, double* dG,
+                          double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
+                          Prof* prof = nullptr);
 void launch_fill(double* p, double v, size_t n, hipStream_t s);
 // dense Schur complement: in-place Gauss-Jordan inverse, transposed GEMV, unit vector
 void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s);
 void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s);
+// b (right-hand side, as launch_rhs_vector) and x = Mt^T b in one launch; b is
+// stored too.  Returns false, launching nothing, when n differs from
+// na + nbc or exceeds the kernel's LDS capacity.
+bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
+                      const double* Mt, int n, double* b, double* x, hipStream_t s);
 void launch_unit(double* v, int n, int q, hipStream_t s);
 
 }  // namespace iim

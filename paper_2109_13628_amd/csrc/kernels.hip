@@ -964,29 +964,85 @@ __device__ __forceinline__ double flux_std(double um1, double u0, double u1, dou
 
 enum { NK_FLUID = 0, NK_GHOST = 1, NK_SOLID = 2, NK_OUT = 3 };
 
+// The grid data the transport kernel reads: a small argument, so that the
+// geometry's many other table pointers do not occupy scalar registers of
+// this large kernel (they spilled to scratch memory).
+struct TGeom {
+  int nx, ny, nsp, nbc, outflow;
+  double h, inv_h, nu, uinf_x, uinf_y;
+  const int8_t* __restrict__ cls;
+  const int* __restrict__ special;
+  const int* __restrict__ rects;
+};
+
+// Node velocities of the transport.  FROM_PSI = false: read from U / V on the
+// ring (zero beyond it).  FROM_PSI = true: formed from the stream function as
+// the velocity kernel forms them (central differences at fluid nodes, the
+// component normal to the grid edge on the ring, zero at solid nodes and for
+// the other ring component); ghost nodes still read the extension values in
+// U / V.  Both give the same numbers for the same psi.
+template <bool FROM_PSI>
+struct Vel {
+  const double* __restrict__ psi;
+  const double* __restrict__ U;
+  const double* __restrict__ V;
+  // ring index t of a fluid node (or of a ring node with that component)
+  __device__ __forceinline__ double u_at(const TGeom& g, int t) const {
+    if constexpr (FROM_PSI) {
+      const int nxr = g.nx + 2;
+      return g.uinf_x + 0.5 * g.inv_h * (psi[t + nxr] - psi[t - nxr]);
+    } else {
+      return U[t];
+    }
+  }
+  __device__ __forceinline__ double v_at(const TGeom& g, int t) const {
+    if constexpr (FROM_PSI)
+      return g.uinf_y - 0.5 * g.inv_h * (psi[t + 1] - psi[t - 1]);
+    else
+      return V[t];
+  }
+  // any node (ii, jj); axis 0: u, 1: v
+  __device__ __forceinline__ double node(const TGeom& g, int axis, int ii, int jj) const {
+    const int nxr = g.nx + 2;
+    if (ii < -1 || jj < -1 || ii > g.nx || jj > g.ny) return 0.0;
+    const int t = (jj + 1) * nxr + ii + 1;
+    if constexpr (FROM_PSI) {
+      if (ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny) {
+        // class, difference and extension value loaded together (all
+        // addresses lie in the ring), then selected
+        const int8_t cl = g.cls[jj * g.nx + ii];
+        const double d = axis == 0 ? u_at(g, t) : v_at(g, t);
+        const double e = axis == 0 ? U[t] : V[t];
+        return cl == 2 ? e : (cl > 2 ? 0.0 : d);
+      }
+      const bool side = (ii == -1 || ii == g.nx) && jj >= 0 && jj < g.ny;
+      const bool topbot = (jj == -1 || jj == g.ny) && ii >= 0 && ii < g.nx;
+      if (axis == 0 ? !side : !topbot) return 0.0;
+    }
+    return axis == 0 ? u_at(g, t) : v_at(g, t);
+  }
+};
+
 // General face between node (i, j) and (i, j) + e_axis (axis 0: x, 1: y).
-__device__ double flux_general(const DGeom& g, const double* __restrict__ omega, const double* __restrict__ U,
-                               const double* __restrict__ V, const double* __restrict__ w4,
-                               const double* __restrict__ w3b, const double* __restrict__ w3n, int i, int j,
-                               int axis) {
+template <bool P>
+__device__ double flux_general(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                               const double* __restrict__ w4, const double* __restrict__ w3b,
+                               const double* __restrict__ w3n, int i, int j, int axis) {
   const int di = axis == 0 ? 1 : 0, dj = axis == 0 ? 0 : 1;
-  const double* vel = axis == 0 ? U : V;
   int kind[4];
   double u[4], w[4], w4v[4], wb[4], wn[4];
-  const int nxr = g.nx + 2;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int ii = i + (t - 1) * di, jj = j + (t - 1) * dj;
     const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
-    const bool ring = ii >= -1 && jj >= -1 && ii <= g.nx && jj <= g.ny;
-    u[t] = ring ? vel[(jj + 1) * nxr + ii + 1] : 0.0;
+    u[t] = vel.node(g, axis, ii, jj);
     if (!in) {
       kind[t] = NK_OUT;
       w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
       if (g.outflow && ii >= g.nx && ii <= g.nx + 1 && jj >= 0 && jj < g.ny) {
         const int im = 2 * g.nx - 1 - ii;   // mirror across the outflow face
         w[t] = w4v[t] = wb[t] = wn[t] = omega[jj * g.nx + im];
-        if (axis == 0 && ii == g.nx + 1) u[t] = vel[(jj + 1) * nxr + im + 1];
+        if (axis == 0 && ii == g.nx + 1) u[t] = vel.node(g, 0, im, jj);
       }
     } else {
       const int q = jj * g.nx + ii;
@@ -1026,8 +1082,8 @@ __device__ double flux_general(const DGeom& g, const double* __restrict__ omega,
 
 // Bulk nodes (cls 0): all stencil nodes are fluid and inside the grid.
 // Bulk part: one thread per node of grid row j, 256 nodes per block.
-__device__ __forceinline__ void transport_bulk(const DGeom& g, const double* __restrict__ omega,
-                                               const double* __restrict__ U, const double* __restrict__ V,
+template <bool P>
+__device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
                                                double* __restrict__ out, double* __restrict__ Q, double a, double b,
                                                double dt, int mode, int bx, int j) {
   const int i = bx * 256 + threadIdx.x;
@@ -1043,9 +1099,11 @@ __device__ __forceinline__ void transport_bulk(const DGeom& g, const double* __r
     const int8_t c = g.cls[q];
     wc = omega[q];
     const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
-    const double uxm2 = U[r - 2], uxm1 = U[r - 1], uc = U[r], uxp1 = U[r + 1], uxp2 = U[r + 2];
+    const double uxm2 = vel.u_at(g, r - 2), uxm1 = vel.u_at(g, r - 1), uc = vel.u_at(g, r);
+    const double uxp1 = vel.u_at(g, r + 1), uxp2 = vel.u_at(g, r + 2);
     const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
-    const double vym2 = V[r - 2 * nxr], vym1 = V[r - nxr], vc = V[r], vyp1 = V[r + nxr], vyp2 = V[r + 2 * nxr];
+    const double vym2 = vel.v_at(g, r - 2 * nxr), vym1 = vel.v_at(g, r - nxr), vc = vel.v_at(g, r);
+    const double vyp1 = vel.v_at(g, r + nxr), vyp2 = vel.v_at(g, r + 2 * nxr);
     if (c == 1) return;   // boundary kernel
     if (c >= 2) {         // solid: vorticity stays zero
       out[q] = 0.0;
@@ -1074,11 +1132,9 @@ __device__ __forceinline__ void transport_bulk(const DGeom& g, const double* __r
     };
     auto UU = [&](int ii, int jj) {
       if (mir && ii == nx + 1) ii = nx - 2;
-      return (ii >= -1 && jj >= -1 && ii <= nx && jj <= ny) ? U[(jj + 1) * nxr + ii + 1] : 0.0;
+      return vel.node(g, 0, ii, jj);
     };
-    auto VV = [&](int ii, int jj) {
-      return (ii >= -1 && jj >= -1 && ii <= nx && jj <= ny) ? V[(jj + 1) * nxr + ii + 1] : 0.0;
-    };
+    auto VV = [&](int ii, int jj) { return vel.node(g, 1, ii, jj); };
     fxr = flux_std(UU(i - 1, j), UU(i, j), UU(i + 1, j), UU(i + 2, j), W(i - 1, j), wc, W(i + 1, j), W(i + 2, j), nih);
     fxl = flux_std(UU(i - 2, j), UU(i - 1, j), UU(i, j), UU(i + 1, j), W(i - 2, j), W(i - 1, j), wc, W(i + 1, j), nih);
     fyt = flux_std(VV(i, j - 1), VV(i, j), VV(i, j + 1), VV(i, j + 2), W(i, j - 1), wc, W(i, j + 1), W(i, j + 2), nih);
@@ -1097,8 +1153,8 @@ __device__ __forceinline__ void transport_bulk(const DGeom& g, const double* __r
 
 // One group of 4 lanes per boundary-kernel node: lane f computes the flux on
 // face f (right, left, top, bottom); lane 0 of the group combines them.
-__device__ __forceinline__ void transport_special(const DGeom& g, const double* __restrict__ omega,
-                                                  const double* __restrict__ U, const double* __restrict__ V,
+template <bool P>
+__device__ __forceinline__ void transport_special(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
                                                   const double* __restrict__ w4, const double* __restrict__ w3b,
                                                   const double* __restrict__ w3n, double* __restrict__ out,
                                                   double* __restrict__ Q, double a, double b, double dt, int mode,
@@ -1112,7 +1168,7 @@ __device__ __forceinline__ void transport_special(const DGeom& g, const double* 
     q = g.special[sp];
     const int i = q % g.nx, j = q / g.nx;
     const int fi = face == 1 ? i - 1 : i, fj = face == 3 ? j - 1 : j;
-    fl = flux_general(g, omega, U, V, w4, w3b, w3n, fi, fj, face >> 1);
+    fl = flux_general(g, omega, vel, w4, w3b, w3n, fi, fj, face >> 1);
   }
   const int base = (threadIdx.x & 63) & ~3;
   const double fxr = __shfl(fl, base, 64), fxl = __shfl(fl, base + 1, 64);
@@ -1130,8 +1186,9 @@ __device__ __forceinline__ void transport_special(const DGeom& g, const double* 
 }
 
 // Kelvin: one block per circulating body
-__device__ __forceinline__ void kelvin(const DGeom& g, const double* __restrict__ omega, const double* __restrict__ U,
-                                       const double* __restrict__ V, double* __restrict__ dG,
+template <bool P>
+__device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                       double* __restrict__ dG,
                                        double* __restrict__ Gamma, double* __restrict__ QG, double a, double b,
                                        double dt, int mode, int k, double* red) {
   const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
@@ -1139,13 +1196,13 @@ __device__ __forceinline__ void kelvin(const DGeom& g, const double* __restrict_
   double acc = 0.0;
   for (int t = threadIdx.x; t < 2 * (nv + nh); t += blockDim.x) {
     if (t < nv) {
-      acc += flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i1, j0 + t, 0);           // right (+)
+      acc += flux_general(g, omega, vel, nullptr, nullptr, nullptr, i1, j0 + t, 0);           // right (+)
     } else if (t < 2 * nv) {
-      acc -= flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 - 1, j0 + t - nv, 0);  // left (-)
+      acc -= flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 - 1, j0 + t - nv, 0);  // left (-)
     } else if (t < 2 * nv + nh) {
-      acc += flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 + t - 2 * nv, j1, 1);  // top (+)
+      acc += flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 + t - 2 * nv, j1, 1);  // top (+)
     } else {
-      acc -= flux_general(g, omega, U, V, nullptr, nullptr, nullptr, i0 + t - 2 * nv - nh, j0 - 1, 1);  // bottom
+      acc -= flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 + t - 2 * nv - nh, j0 - 1, 1);  // bottom
     }
   }
   const double tot = block_sum(acc, red);
@@ -1162,10 +1219,13 @@ __device__ __forceinline__ void kelvin(const DGeom& g, const double* __restrict_
 }
 
 // Transport of every fluid node and the Kelvin update in one launch of
-// 256-thread blocks: first the bulk rows, then the boundary-kernel nodes (4
-// lanes each), then one block per circulating body.  The three parts read the
-// same inputs and write disjoint outputs.
-__global__ void __launch_bounds__(256) k_transport_all(DGeom g, const double* __restrict__ omega,
+// 256-thread blocks: first one block per circulating body and the
+// boundary-kernel nodes (4 lanes each), whose dependent loads take longest,
+// so that they are dispatched first, then the bulk rows.  The three parts
+// read the same inputs and write disjoint outputs.
+template <bool P>
+__global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __restrict__ omega,
+                                                       const double* __restrict__ psi,
                                                        const double* __restrict__ U, const double* __restrict__ V,
                                                        const double* __restrict__ w4, const double* __restrict__ w3b,
                                                        const double* __restrict__ w3n, double* __restrict__ out,
@@ -1173,28 +1233,38 @@ __global__ void __launch_bounds__(256) k_transport_all(DGeom g, const double* __
                                                        double* __restrict__ Gamma, double* __restrict__ QG, double a,
                                                        double b, double dt, int mode) {
   __shared__ double red[16];
-  const int nbx = (g.nx + 255) / 256, nb_bulk = nbx * g.ny, nb_sp = (4 * g.nsp + 255) / 256;
+  const Vel<P> vel{psi, U, V};
+  const int nbx = (g.nx + 255) / 256, nb_sp = (4 * g.nsp + 255) / 256;
   int blk = blockIdx.x;
-  if (blk < nb_bulk) {
-    transport_bulk(g, omega, U, V, out, Q, a, b, dt, mode, blk % nbx, blk / nbx);
+  if (blk < g.nbc) {
+    kelvin(g, omega, vel, dG, Gamma, QG, a, b, dt, mode, blk, red);
     return;
   }
-  blk -= nb_bulk;
+  blk -= g.nbc;
   if (blk < nb_sp) {
-    transport_special(g, omega, U, V, w4, w3b, w3n, out, Q, a, b, dt, mode, blk);
+    transport_special(g, omega, vel, w4, w3b, w3n, out, Q, a, b, dt, mode, blk);
     return;
   }
   blk -= nb_sp;
-  kelvin(g, omega, U, V, dG, Gamma, QG, a, b, dt, mode, blk, red);
+  transport_bulk(g, omega, vel, out, Q, a, b, dt, mode, blk % nbx, blk / nbx);
 }
 
-void launch_transport_all(const DGeom& g, const double* omega, const double* U, const double* V, const double* w4,
-                          const double* w3b, const double* w3n, double* out, double* Q, double* dG, double* Gamma,
-                          double* QG, double a, double b, double dt, int mode, hipStream_t s, Prof* prof) {
+void launch_transport_all(const DGeom& g, const double* omega, const double* psi, const double* U, const double* V,
+                          const double* w4, const double* w3b, const double* w3n, double* out, double* Q, double* dG,
+                          double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
+                          Prof* prof) {
   const int blocks = ((g.nx + 255) / 256) * g.ny + (4 * g.nsp + 255) / 256 + g.nbc;
-  // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
-  IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_all, blocks, 256, s, g, omega, U, V, w4, w3b, w3n,
-             out, Q, dG, Gamma, QG, a, b, dt, mode);
+  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls, g.special,
+                 g.rects};
+  if (psi) {
+    // algorithmic bytes per cell: omega, psi, Q read; out, Q written
+    IIM_LAUNCH(prof, KID_TRANSPORT, 40.0 * g.nx * g.ny, k_transport_all<true>, blocks, 256, s, tg, omega, psi, U, V,
+               w4, w3b, w3n, out, Q, dG, Gamma, QG, a, b, dt, mode);
+  } else {
+    // algorithmic bytes per cell: omega, u, v, Q read; out, Q written
+    IIM_LAUNCH(prof, KID_TRANSPORT, 48.0 * g.nx * g.ny, k_transport_all<false>, blocks, 256, s, tg, omega, psi, U, V,
+               w4, w3b, w3n, out, Q, dG, Gamma, QG, a, b, dt, mode);
+  }
 }
 
 }  // namespace iim
@@ -1311,6 +1381,87 @@ __global__ void __launch_bounds__(256) k_gemv_t(const double* __restrict__ Mt, i
 
 void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s) {
   if (n > 0) k_gemv_t<<<(n + 15) / 16, 256, 0, s>>>(Mt, n, b, x);
+}
+
+// Right-hand side and direct solve in one launch: every block builds all of b
+// in LDS (the correction rows are short sparse sums of psi, the circulation
+// rows one masked rectangle sum of omega per body), then 16 entries of
+// x = Mt^T b, its matrix entries loaded before b is ready.  Block 0 also
+// stores b.
+constexpr int RHS_SOLVE_MAX_N = 6144;   // b in dynamic LDS (48 KiB)
+__global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __restrict__ psi,
+                                                   const double* __restrict__ omega,
+                                                   const double* __restrict__ Gamma,
+                                                   const double* __restrict__ Mt, int n, double* __restrict__ b,
+                                                   double* __restrict__ x) {
+  extern __shared__ double bs[];
+  __shared__ double red[16];
+  __shared__ double part[64][17];
+  const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;   // 16 outputs, 64 slices of each sum
+  const int p = blockIdx.x * 16 + lo;
+  double mv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = sl + 64 * u;
+    mv[u] = (p < n && q < n) ? Mt[(size_t)q * n + p] : 0.0;
+  }
+  for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
+    double acc = 0.0;
+#pragma unroll 4
+    for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
+    bs[a] = acc + g.bpsi[a];
+  }
+  for (int k = 0; k < g.nbc; ++k) {
+    const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
+    const int w = i1 - i0 + 1, cnt = w * (j1 - j0 + 1);
+    double acc = 0.0;
+    for (int q0 = threadIdx.x; q0 < cnt; q0 += 8 * blockDim.x) {
+      double v[8];
+      int8_t cl[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * blockDim.x;
+        cl[u] = 3;
+        v[u] = 0.0;
+        if (q < cnt) {
+          const int idx = (j0 + q / w) * g.nx + i0 + q % w;
+          cl[u] = g.cls[idx];
+          v[u] = omega[idx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (cl[u] < 2) acc += v[u];
+    }
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) bs[g.na + k] = sum - Gamma[k] * g.inv_h * g.inv_h;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < n; q += blockDim.x) b[q] = bs[q];
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = sl + 64 * u;
+    if (q < n) acc += mv[u] * bs[q];
+  }
+  if (p < n)
+    for (int q = sl + 512; q < n; q += 64) acc += Mt[(size_t)q * n + p] * bs[q];
+  part[sl][lo] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16 && p < n) {
+    double t = 0.0;
+    for (int k = 0; k < 64; ++k) t += part[k][lo];
+    x[p] = t;
+  }
+}
+
+bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
+                      const double* Mt, int n, double* b, double* x, hipStream_t s) {
+  if (n != g.na + g.nbc || n > RHS_SOLVE_MAX_N) return false;
+  if (n == 0) return true;
+  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)n * sizeof(double), s>>>(g, psi_ring, omega, Gamma, Mt, n, b, x);
+  return true;
 }
 
 __global__ void k_unit(double* v, int n, int q) {
