@@ -1001,25 +1001,32 @@ struct Vel {
     else
       return V[t];
   }
-  // any node (ii, jj); axis 0: u, 1: v
+  // any node (ii, jj); axis 0: u, 1: v.  The axis may differ between lanes:
+  // no pointer is selected by it (both arrays are read and the value
+  // selected), which keeps the pointers out of private (scratch) memory.
   __device__ __forceinline__ double node(const TGeom& g, int axis, int ii, int jj) const {
     const int nxr = g.nx + 2;
     if (ii < -1 || jj < -1 || ii > g.nx || jj > g.ny) return 0.0;
     const int t = (jj + 1) * nxr + ii + 1;
     if constexpr (FROM_PSI) {
-      if (ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny) {
-        // class, difference and extension value loaded together (all
-        // addresses lie in the ring), then selected
-        const int8_t cl = g.cls[jj * g.nx + ii];
-        const double d = axis == 0 ? u_at(g, t) : v_at(g, t);
-        const double e = axis == 0 ? U[t] : V[t];
-        return cl == 2 ? e : (cl > 2 ? 0.0 : d);
-      }
+      const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
       const bool side = (ii == -1 || ii == g.nx) && jj >= 0 && jj < g.ny;
       const bool topbot = (jj == -1 || jj == g.ny) && ii >= 0 && ii < g.nx;
-      if (axis == 0 ? !side : !topbot) return 0.0;
+      if (!in && (axis == 0 ? !side : !topbot)) return 0.0;
+      // psi at t +- o lies in the ring for every node that gets here
+      const int o = axis == 0 ? nxr : 1;
+      const double d = psi[t + o] - psi[t - o];
+      const double val = axis == 0 ? g.uinf_x + 0.5 * g.inv_h * d : g.uinf_y - 0.5 * g.inv_h * d;
+      if (!in) return val;
+      // class, difference and extension value loaded together, then selected
+      const int8_t cl = g.cls[jj * g.nx + ii];
+      const double ue = U[t], ve = V[t];
+      const double e = axis == 0 ? ue : ve;
+      return cl == 2 ? e : (cl > 2 ? 0.0 : val);
+    } else {
+      const double ue = U[t], ve = V[t];
+      return axis == 0 ? ue : ve;
     }
-    return axis == 0 ? u_at(g, t) : v_at(g, t);
   }
 };
 
