@@ -239,7 +239,7 @@ int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
  * the minimum of each shape) with every instantiated number of FFTs per
  * workgroup of the row passes and of the column pass (1, 2, 4; shapes over
  * 1024 threads or 128 KiB of LDS fall back to the default) and keeps the
- * fastest.
+ * fastest if it beats the default by at least 3 % (otherwise the default).
  * Outputs (nullable): the chosen counts (0 = default), the default's and the
  * best time per convolution in microseconds.  The shapes change only the
  * work per workgroup, not the arithmetic: results are bitwise the same.

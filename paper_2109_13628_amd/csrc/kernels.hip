@@ -1500,6 +1500,20 @@ template <> struct RP<512> { static constexpr int T = 64, E = 8; };
 template <> struct RP<1024> { static constexpr int T = IIM_FFT1024_THREADS, E = 1024 / IIM_FFT1024_THREADS; };
 template <> struct RP<2048> { static constexpr int T = 128, E = 16; };
 template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
+// Lanes per FFT of the row passes (ROWS) and of the column pass: the same
+// except at 1024 points, where the row passes run 256 lanes of 4 points
+// (faster there) and the column pass 128 lanes of 8 (faster there).
+#ifndef IIM_ROW_FFT1024_THREADS
+#define IIM_ROW_FFT1024_THREADS 256
+#endif
+template <int N, bool ROWS>
+struct RPX {
+  static constexpr int T = RP<N>::T, E = RP<N>::E;
+};
+template <>
+struct RPX<1024, true> {
+  static constexpr int T = IIM_ROW_FFT1024_THREADS, E = 1024 / IIM_ROW_FFT1024_THREADS;
+};
 
 #ifndef IIM_ROW_FFTS_PER_BLOCK
 #define IIM_ROW_FFTS_PER_BLOCK 4
@@ -1509,23 +1523,25 @@ template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
 #endif
 // FFTs per block: the default of the row passes (ROWS) and of the column
 // pass; a tuned value (DFft::row_per / col_per) selects another instantiation
+// (column pass: one FFT per block once an FFT has 128 lanes or more, which
+// measured faster inside the time step at 1024 points)
 template <int N, bool ROWS = false>
 struct RegDef {
-  static constexpr int T = RP<N>::T;
+  static constexpr int T = RPX<N, ROWS>::T;
   static constexpr int WANT = ROWS ? IIM_ROW_FFTS_PER_BLOCK : IIM_COL_FFTS_PER_BLOCK;
-  static constexpr int PER = (WANT * T > 256) ? (256 / T > 0 ? 256 / T : 1) : WANT;
+  static constexpr int PER = (!ROWS && T >= 128) ? 1 : (WANT * T > 256) ? (256 / T > 0 ? 256 / T : 1) : WANT;
 };
-template <int N, int PER_>
+template <int N, int PER_, bool ROWS = false>
 struct RegCfg {
-  static constexpr int T = RP<N>::T;
+  static constexpr int T = RPX<N, ROWS>::T;
   static constexpr int PER = PER_;
   static constexpr int THREADS = PER * T;
   static constexpr int LDSN = N + N / 16 + 1;      // padded length (one pad slot per 16 points)
 };
 // instantiated tile shapes: at most 1024 threads and 128 KiB of LDS per block
-template <int N, int PER, class CX>
+template <int N, int PER, class CX, bool ROWS = false>
 constexpr bool per_ok() {
-  return PER * RP<N>::T <= 1024 && (size_t)PER * (N + N / 16 + 1) * sizeof(CX) <= 131072;
+  return PER * RPX<N, ROWS>::T <= 1024 && (size_t)PER * (N + N / 16 + 1) * sizeof(CX) <= 131072;
 }
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
@@ -1693,9 +1709,9 @@ __device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const CX* _
   }
 }
 
-template <int N, bool INV, class CX>
-__device__ __forceinline__ void fft_reg(CX (&v)[RP<N>::E], CX* lds, int t, const CX* __restrict__ tw) {
-  constexpr int T = RP<N>::T, E = RP<N>::E;
+template <int N, bool INV, class CX, int E>
+__device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
+  constexpr int T = N / E;
   if constexpr (N == 256) {
     reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
     reg_pass<N, T, E, 4, 4, INV, false>(v, lds, t, tw);
@@ -1832,27 +1848,14 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 }
 
 // ---- forward rows: real FFT of length 2 HX (half-length complex FFT + split)
-template <int HX, class CX>
-__device__ __forceinline__ void add_at(CX (&v)[RP<HX>::E], int t, int i, double val) {
-  constexpr int T = RP<HX>::T, E = RP<HX>::E;
-  const int n = i >> 1;
-  if ((n % T) != t) return;
-  const int mm = n / T;
-#pragma unroll
-  for (int m = 0; m < E; ++m)
-    if (m == mm) {
-      if (i & 1) v[m].y += val; else v[m].x += val;
-    }
-}
-
 template <int HX, class CX, int PER>
-__global__ void __launch_bounds__((RegCfg<HX, PER>::THREADS))
+__global__ void __launch_bounds__((RegCfg<HX, PER, true>::THREADS))
 k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int count,
                const double* __restrict__ done) {
-  using C = RegCfg<HX, PER>;
+  using C = RegCfg<HX, PER, true>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
-  constexpr int T = RP<HX>::T, E = RP<HX>::E;
+  constexpr int T = RPX<HX, true>::T, E = RPX<HX, true>::E;
   __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int w = threadIdx.x / T, t = threadIdx.x % T;
@@ -1911,11 +1914,11 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int co
 
 // ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
 template <int HX, class CX, int PER>
-__global__ void __launch_bounds__((RegCfg<HX, PER>::THREADS))
+__global__ void __launch_bounds__((RegCfg<HX, PER, true>::THREADS))
 k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const double* __restrict__ done) {
-  using C = RegCfg<HX, PER>;
+  using C = RegCfg<HX, PER, true>;
   const FftT<CX> ft = fft_view<CX>(f);
-  constexpr int T = RP<HX>::T, E = RP<HX>::E;
+  constexpr int T = RPX<HX, true>::T, E = RPX<HX, true>::E;
   __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int lb = xcd_block();
@@ -1968,7 +1971,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
 template <int HX, class CX, int PER>
 void rows_fwd_go(const DGeom& g, const DFft& f, const double* omega, int j0, int count, const double* done,
                  hipStream_t s, Prof* prof, double bytes) {
-  using C = RegCfg<HX, PER>;
+  using C = RegCfg<HX, PER, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
   if (blocks > 0)
     IIM_LAUNCH(prof, KID_ROWS_FWD, bytes, k_rows_fwd_reg<HX IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f,
@@ -1985,7 +1988,7 @@ void cols_go(const DGeom& g, const DFft& f, bool dense, const double* gam, doubl
 template <int HX, class CX, int PER>
 void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done, hipStream_t s,
                  Prof* prof, double bytes) {
-  using C = RegCfg<HX, PER>;
+  using C = RegCfg<HX, PER, true>;
   const int blocks = (count + C::PER - 1) / C::PER;
   if (blocks > 0)
     IIM_LAUNCH(prof, KID_ROWS_INV, bytes, k_rows_inv_reg<HX IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f,
@@ -1998,10 +2001,10 @@ void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, 
   do {                                                                                 \
     constexpr int D_ = RegDef<N, ROWS>::PER;                                           \
     if constexpr (std::is_same<CX, double2>::value) {                                  \
-      if ((PER_RUNTIME) == 1 && per_ok<N, 1, CX>()) { GO<N, CX, 1>(__VA_ARGS__); break; } \
-      if constexpr (per_ok<N, 2, CX>())                                                \
+      if ((PER_RUNTIME) == 1 && per_ok<N, 1, CX, ROWS>()) { GO<N, CX, 1>(__VA_ARGS__); break; } \
+      if constexpr (per_ok<N, 2, CX, ROWS>())                                          \
         if ((PER_RUNTIME) == 2) { GO<N, CX, 2>(__VA_ARGS__); break; }                  \
-      if constexpr (per_ok<N, 4, CX>())                                                \
+      if constexpr (per_ok<N, 4, CX, ROWS>())                                          \
         if ((PER_RUNTIME) == 4) { GO<N, CX, 4>(__VA_ARGS__); break; }                  \
     }                                                                                  \
     GO<N, CX, D_>(__VA_ARGS__);                                                        \
