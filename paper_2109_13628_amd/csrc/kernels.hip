@@ -1667,21 +1667,48 @@ __device__ __forceinline__ void dftR(CX (&u)[R]) {
   }
 }
 
-template <int N, int T, int E, int R, int NS, bool INV, bool LAST, class CX>
-__device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
+// Twiddles of one radix pass for lane t: W^(r k step), k = (t + T b) mod NS,
+// r = 1 .. R-1 (none for the first pass, NS = 1).
+template <int N, int T, int E, int R, int NS, class CX>
+struct PassTw {
+  static constexpr int B = E / R;
+  static constexpr int K = NS > 1 ? R - 1 : 0;
+  CX w[B][K > 0 ? K : 1];
+  __device__ __forceinline__ void load(int t, const CX* __restrict__ tw) {
+    if constexpr (NS > 1) {
+      constexpr int step = N / (NS * R);
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int k = (t + T * b) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b][r - 1] = tw[r * k * step];
+      }
+    }
+  }
+};
+struct NoTw {
+  template <class CX>
+  __device__ __forceinline__ void load(int, const CX* __restrict__) {}
+};
+
+// One radix-R Stockham pass.  The next pass's twiddles are requested first,
+// so that their latency hides behind this pass's butterflies and LDS
+// exchange (only one pass ahead: preloading every pass's twiddles costs
+// registers and measured slower).
+template <int N, int T, int E, int R, int NS, bool INV, bool LAST, class CX, class NX>
+__device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const PassTw<N, T, E, R, NS, CX>& pw, NX& nx,
+                                         const CX* __restrict__ tw) {
+  nx.load(t, tw);
   constexpr int B = E / R;
   CX u[B][R];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = t + T * b;
-    const int k = j & (NS - 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) u[b][r] = v[b + r * B];
-    if (NS > 1) {
-      constexpr int step = N / (NS * R);
+    if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        CX w = tw[r * k * step];
+        CX w = pw.w[b][r - 1];
         if (INV) w.y = -w.y;
         u[b][r] = cmul(u[b][r], w);
       }
@@ -1709,43 +1736,62 @@ __device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const CX* _
   }
 }
 
+// Radix passes (R, NS) of each register FFT: N points, E per lane.
+template <int N, int E>
+struct Plan;
+template <> struct Plan<256, 4> {
+  static constexpr int P = 4;
+  static constexpr int R[P] = {4, 4, 4, 4}, NS[P] = {1, 4, 16, 64};
+};
+template <> struct Plan<512, 8> {
+  static constexpr int P = 3;
+  static constexpr int R[P] = {8, 8, 8}, NS[P] = {1, 8, 64};
+};
+template <> struct Plan<1024, 16> {
+  static constexpr int P = 3;
+  static constexpr int R[P] = {16, 16, 4}, NS[P] = {1, 16, 256};
+};
+template <> struct Plan<1024, 8> {
+  static constexpr int P = 4;
+  static constexpr int R[P] = {8, 8, 8, 2}, NS[P] = {1, 8, 64, 512};
+};
+template <> struct Plan<1024, 4> {
+  static constexpr int P = 5;
+  static constexpr int R[P] = {4, 4, 4, 4, 4}, NS[P] = {1, 4, 16, 64, 256};
+};
+template <> struct Plan<2048, 16> {
+  static constexpr int P = 3;
+  static constexpr int R[P] = {16, 16, 8}, NS[P] = {1, 16, 256};
+};
+template <> struct Plan<4096, 16> {
+  static constexpr int P = 3;
+  static constexpr int R[P] = {16, 16, 16}, NS[P] = {1, 16, 256};
+};
+
+template <int N, int E, int I, class CX>
+using PlanTw = PassTw<N, N / E, E, Plan<N, E>::R[I], Plan<N, E>::NS[I], CX>;
+
+template <int N, bool INV, class CX, int E, int I>
+__device__ __forceinline__ void fft_passes(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw,
+                                           const PlanTw<N, E, I, CX>& cur) {
+  using PL = Plan<N, E>;
+  constexpr int T = N / E;
+  if constexpr (I + 1 < PL::P) {
+    PlanTw<N, E, I + 1, CX> nxt;
+    reg_pass<N, T, E, PL::R[I], PL::NS[I], INV, false>(v, lds, t, cur, nxt, tw);
+    fft_passes<N, INV, CX, E, I + 1>(v, lds, t, tw, nxt);
+  } else {
+    NoTw none;
+    reg_pass<N, T, E, PL::R[I], PL::NS[I], INV, true>(v, lds, t, cur, none, tw);
+  }
+}
+
+// In-register FFT of N points, E per lane (T = N / E lanes), LDS exchanges
+// between passes.
 template <int N, bool INV, class CX, int E>
 __device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
-  constexpr int T = N / E;
-  if constexpr (N == 256) {
-    reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 4, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 16, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 64, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 512) {
-    reg_pass<N, T, E, 8, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 8, 8, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 8, 64, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 1024 && E == 16) {
-    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 256, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 1024 && E == 8) {
-    reg_pass<N, T, E, 8, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 8, 8, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 8, 64, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 2, 512, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 1024 && E == 4) {
-    reg_pass<N, T, E, 4, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 4, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 16, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 64, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 4, 256, INV, true>(v, lds, t, tw);
-  } else if constexpr (N == 2048) {
-    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 8, 256, INV, true>(v, lds, t, tw);
-  } else {
-    static_assert(N == 4096, "size");
-    reg_pass<N, T, E, 16, 1, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 16, 16, INV, false>(v, lds, t, tw);
-    reg_pass<N, T, E, 16, 256, INV, true>(v, lds, t, tw);
-  }
+  PlanTw<N, E, 0, CX> first;   // the first pass has no twiddles
+  fft_passes<N, INV, CX, E, 0>(v, lds, t, tw, first);
 }
 
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
