@@ -81,6 +81,7 @@ DStencil upload_stencil(iim_ctx* c, const Stencil& s, bool with_comp) {
     gidx[e] = s.jj[e] * nx + s.ii[e];
   }
   DStencil d;
+  d.nnz = (int)s.w.size();
   d.ptr = c->upload(s.ptr);
   d.ridx = c->upload(ridx);
   d.gidx = c->upload(gidx);
@@ -281,6 +282,17 @@ void setup_device(iim_ctx* c) {
   d.row_ptr = c->upload(rp);
   d.row_i = c->upload(ri);
   d.row_a = c->upload(ra);
+  {
+    std::vector<int2> ia(g.na);
+    for (int p = 0; p < g.na; ++p) ia[p] = make_int2(ri[p], ra[p]);
+    d.row_ia = c->upload(ia);
+    d.a_j0 = ny;
+    d.a_j1 = -1;
+    for (int a = 0; a < g.na; ++a) {
+      d.a_j0 = std::min(d.a_j0, g.a_j[a]);
+      d.a_j1 = std::max(d.a_j1, g.a_j[a]);
+    }
+  }
   d.special = c->upload(g.special);
   std::vector<int> ccol(g.nc);
   std::vector<double> psibt(g.nc), wbc(g.nc, 0.0);

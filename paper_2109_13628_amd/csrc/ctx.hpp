@@ -132,6 +132,9 @@ struct iim_ctx {
     if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return p;
   }
+  iim_ctx() = default;
+  iim_ctx(const iim_ctx&) = delete;        // owns device memory, streams, graphs
+  iim_ctx& operator=(const iim_ctx&) = delete;
   ~iim_ctx() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gstream) (void)hipStreamDestroy(gstream);

@@ -24,6 +24,7 @@ struct DStencil {
   const int* bc = nullptr;     // control point
   const double* bw = nullptr;
   int rows = 0;
+  int nnz = 0;                 // node entries (ptr[rows])
 };
 
 struct DGeom {
@@ -42,6 +43,8 @@ struct DGeom {
   const int* row_ptr;          // per grid row: affected points of that row
   const int* row_i;            //   column i
   const int* row_a;            //   affected index
+  const int2* row_ia;          //   (column i, affected index) packed, same order
+  int a_j0, a_j1;              // first and last grid row holding affected points (a_j0 > a_j1: none)
   const int* special;          // boundary-kernel fluid nodes (grid index)
   const int* c_col;            // control point -> circulation column (-1: none)
   const double* c_psibt;       // psi_b - psi_inf at control points
@@ -203,6 +206,9 @@ struct Prof {
     used = 0;
     for (int i = 0; i < KID_N; ++i) total_ms[i] = bytes[i] = 0.0, count[i] = 0;
   }
+  Prof() = default;
+  Prof(const Prof&) = delete;              // owns its events
+  Prof& operator=(const Prof&) = delete;
   ~Prof() {
     for (auto e : pool) (void)hipEventDestroy(e);
   }

@@ -1393,15 +1393,17 @@ void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStrea
 // Right-hand side and direct solve in one launch: every block builds all of b
 // in LDS (the correction rows are short sparse sums of psi, the circulation
 // rows one masked rectangle sum of omega per body), then 16 entries of
-// x = Mt^T b, its matrix entries loaded before b is ready.  Block 0 also
-// stores b.
-constexpr int RHS_SOLVE_MAX_N = 6144;   // b in dynamic LDS (48 KiB)
+// x = Mt^T b, its matrix entries loaded before b is ready.  The correction
+// rows are formed entry-parallel: each lane stores the products w psi of a
+// few entries in LDS (all their loads in flight together), then the lane
+// owning a row sums its entries in order.  Block 0 also stores b.
+constexpr int RHS_SOLVE_MAX_LDS = 6144;   // b and the entry products in dynamic LDS (48 KiB)
 __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __restrict__ psi,
                                                    const double* __restrict__ omega,
                                                    const double* __restrict__ Gamma,
                                                    const double* __restrict__ Mt, int n, double* __restrict__ b,
                                                    double* __restrict__ x) {
-  extern __shared__ double bs[];
+  extern __shared__ double bs[];   // b [n], then the entry products [nnz]
   __shared__ double red[16];
   __shared__ double part[64][17];
   const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;   // 16 outputs, 64 slices of each sum
@@ -1412,11 +1414,20 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
     const int q = sl + 64 * u;
     mv[u] = (p < n && q < n) ? Mt[(size_t)q * n + p] : 0.0;
   }
-  for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int e = g.aop.ptr[a]; e < g.aop.ptr[a + 1]; ++e) acc += g.aop.w[e] * psi[g.aop.ridx[e]];
-    bs[a] = acc + g.bpsi[a];
+  // this lane's first correction row: entry range and constant, loaded now
+  const int a_own = threadIdx.x;
+  const bool own = a_own < g.na;
+  const int pb = own ? g.aop.ptr[a_own] : 0, pe = own ? g.aop.ptr[a_own + 1] : 0;
+  const double bconst = own ? g.bpsi[a_own] : 0.0;
+  double* terms = bs + n;
+  const int nnz = g.aop.nnz;
+  for (int e0 = threadIdx.x; e0 < nnz; e0 += 2 * blockDim.x) {
+    const int e1 = e0 + blockDim.x;
+    const int r0 = g.aop.ridx[e0], r1 = e1 < nnz ? g.aop.ridx[e1] : 0;
+    const double w0 = g.aop.w[e0], w1 = e1 < nnz ? g.aop.w[e1] : 0.0;
+    const double p0 = psi[r0], p1 = e1 < nnz ? psi[r1] : 0.0;
+    terms[e0] = w0 * p0;
+    if (e1 < nnz) terms[e1] = w1 * p1;
   }
   for (int k = 0; k < g.nbc; ++k) {
     const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
@@ -1444,6 +1455,14 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
     if (threadIdx.x == 0) bs[g.na + k] = sum - Gamma[k] * g.inv_h * g.inv_h;
   }
   __syncthreads();
+  for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
+    const bool first = a == a_own;
+    const int e1 = first ? pe : g.aop.ptr[a + 1];
+    double acc = 0.0;
+    for (int e = first ? pb : g.aop.ptr[a]; e < e1; ++e) acc += terms[e];
+    bs[a] = acc + (first ? bconst : g.bpsi[a]);
+  }
+  __syncthreads();
   if (blockIdx.x == 0)
     for (int q = threadIdx.x; q < n; q += blockDim.x) b[q] = bs[q];
   double acc = 0.0;
@@ -1465,9 +1484,10 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
 
 bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
                       const double* Mt, int n, double* b, double* x, hipStream_t s) {
-  if (n != g.na + g.nbc || n > RHS_SOLVE_MAX_N) return false;
+  if (n != g.na + g.nbc || n + g.aop.nnz > RHS_SOLVE_MAX_LDS) return false;
   if (n == 0) return true;
-  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)n * sizeof(double), s>>>(g, psi_ring, omega, Gamma, Mt, n, b, x);
+  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)(n + g.aop.nnz) * sizeof(double), s>>>(g, psi_ring, omega, Gamma, Mt,
+                                                                                   n, b, x);
   return true;
 }
 
@@ -1824,8 +1844,11 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
     // Entries are grouped by row, so a row's terms are contiguous; more
     // entries than the buffer holds are taken in chunks.  Every lane of the
     // block runs the same chunks (the bounds depend on rj0, rj1 only).
+    // rows covering every affected row (all callers so far) take the whole
+    // entry range without reading the row offsets
     const int jb = max(rj0, 0), je = min(rj1, g.ny - 1);
-    const int eb = jb <= je ? g.row_ptr[jb] : 0, ee = jb <= je ? g.row_ptr[je + 1] : 0;
+    const int eb = jb <= je ? (jb <= g.a_j0 ? 0 : g.row_ptr[jb]) : 0;
+    const int ee = jb <= je ? (je >= g.a_j1 ? g.na : g.row_ptr[je + 1]) : 0;
     int rb[E], re[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -1840,11 +1863,13 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
       for (int e0 = c0 + t; e0 < c1; e0 += 4 * T) {
         int ii[4];
         double val[4];
+        int2 ia[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ia[u] = e0 + u * T < c1 ? g.row_ia[e0 + u * T] : make_int2(0, -1);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const bool ok = e0 + u * T < c1;
-          ii[u] = ok ? g.row_i[e0 + u * T] : 0;
-          val[u] = ok ? sgn * gam[g.row_a[e0 + u * T]] : 0.0;
+          ii[u] = ia[u].x;
+          val[u] = ia[u].y >= 0 ? sgn * gam[ia[u].y] : 0.0;
         }
         CX w1[4], w2[4];
 #pragma unroll
