@@ -249,8 +249,6 @@ void launch_conv(const DGeom& g, const DFft& f, const double* omega, const doubl
                  hipStream_t s, Prof* prof = nullptr, bool fp32 = false, bool rows_ready = false);
 void launch_dst(const DGeom& g, const DDst& d, const double* omega, const double* gam, double sgn,
                 double* psi_ring, const double* done_flag, hipStream_t s);
-void launch_poisson_plain(const DGeom& g, const DFft* f, const DDst* d, const double* src,
-                          double* psi_ring, hipStream_t s);
 
 void launch_rhs_vector(const DGeom& g, const double* psi_ring, const double* omega,
                        const double* Gamma, double* b, hipStream_t s);
