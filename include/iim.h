@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IIM_ABI_VERSION 1
+#define IIM_ABI_VERSION 2
 
 enum {
   IIM_OK = 0,
@@ -108,6 +108,11 @@ typedef struct {
   double u_rigid[2];      /* rigid translation velocity */
   double omega_rigid;     /* rigid angular velocity */
   int32_t rect[4];        /* bounding region R_k as node ranges i0,i1,j0,j1 (inclusive); rect[0] < 0 = automatic */
+  const double* bc_samples; /* optional host [n_points][3] = (u_x, u_y, psi_b) at the points, copied at
+                             create: boundary velocity and stream function (Sec. 3.1 boundary conditions)
+                             interpolated at the control points by periodic cubic splines in the curve's
+                             parameter; psi_b is defined up to the body's constant psibar.  NULL: the
+                             rigid motion above. */
 } iim_body_desc;
 
 typedef struct {
@@ -155,6 +160,8 @@ typedef struct {
   int32_t n_circ;
   const int32_t* rects;   /* [n_circ][4] i0, i1, j0, j1 */
   const int32_t* circ_body; /* [n_circ] body index of each circulation unknown */
+  const double* c_ub;     /* [n_control][2] boundary velocity at the control points */
+  const double* c_psib;   /* [n_control] boundary stream function psi_b at the control points */
 } iim_geometry_view;
 
 typedef struct iim_ctx iim_ctx;

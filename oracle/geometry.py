@@ -292,14 +292,14 @@ class Geometry:
     def _build_control_points(self):
         nx, ny, h = self.nx, self.ny, self.h
         solid = self.solid
-        recs = []  # (axis, i_f, j_f, sigma, theta, body, xc, yc, nx_, ny_)
+        recs = []  # (axis, i_f, j_f, sigma, theta, body, xc, yc, nx_, ny_, seg, s)
         # gather all crossings per (axis, line) over bodies
         for axis in (1, 0):
             allc = []
             for k, rec in enumerate(self.crossings):
                 seg, s, line, along, nrm, pos = rec[axis]
                 for q in range(line.size):
-                    allc.append((line[q], along[q], k, nrm[q, 0], nrm[q, 1], pos[q, 0], pos[q, 1]))
+                    allc.append((line[q], along[q], k, nrm[q, 0], nrm[q, 1], pos[q, 0], pos[q, 1], seg[q], s[q]))
             if not allc:
                 continue
             arr = np.array(allc, dtype=np.float64)
@@ -339,14 +339,14 @@ class Geometry:
                         i_f, j_f, ax = f_idx, L, 0
                     else:
                         i_f, j_f, ax = L, f_idx, 1
-                    recs.append((ax, i_f, j_f, sigma, theta, int(c[2]), c[5], c[6], c[3], c[4]))
+                    recs.append((ax, i_f, j_f, sigma, theta, int(c[2]), c[5], c[6], c[3], c[4], c[7], c[8]))
         # canonical order: by ghost node linear index, then axis, then sigma
         def ghost_lin(r):
             ax, i_f, j_f, sigma = r[0], r[1], r[2], r[3]
             gi, gj = (i_f + sigma, j_f) if ax == 0 else (i_f, j_f + sigma)
             return (gj * nx + gi, ax, sigma)
         recs.sort(key=ghost_lin)
-        R = np.array(recs, dtype=np.float64).reshape(-1, 10)
+        R = np.array(recs, dtype=np.float64).reshape(-1, 12)
         self.nc = R.shape[0]
         self.c_axis = R[:, 0].astype(int)        # 0: along x (horizontal line), 1: along y
         self.c_if = R[:, 1].astype(int)
@@ -358,15 +358,29 @@ class Geometry:
         self.c_y = R[:, 7]
         self.c_nx = R[:, 8]
         self.c_ny = R[:, 9]
+        self.c_seg = R[:, 10].astype(int)      # spline segment and parameter of the crossing
+        self.c_s = R[:, 11]
         self.c_ig = np.where(self.c_axis == 0, self.c_if + self.c_sigma, self.c_if)
         self.c_jg = np.where(self.c_axis == 1, self.c_jf + self.c_sigma, self.c_jf)
         if np.any(self.c_theta <= 0) or np.any(self.c_theta > 1):
             raise GeometryError("control point outside its grid edge")
-        # rigid-motion boundary data at the control points
+        # boundary data at the control points: rigid motion, or prescribed
+        # samples (u_x, u_y, psi_b) at the boundary points interpolated by
+        # periodic cubic splines in the curve's parameter (the same
+        # construction as the curve itself), evaluated at each crossing
         ub = np.zeros((self.nc, 2))
         psib = np.zeros(self.nc)
         for k, b in enumerate(self.bodies):
             m = self.c_body == k
+            smp = getattr(b, "bc_samples", None)
+            if smp is not None:
+                smp = np.asarray(smp, dtype=np.float64)
+                cu = periodic_spline(smp[:, 0:2])
+                cp = periodic_spline(np.stack([smp[:, 2], np.zeros(smp.shape[0])], axis=1))
+                seg, s = self.c_seg[m], self.c_s[m][:, None]
+                ub[m] = _cubic(tuple(cc[seg] for cc in cu), s)
+                psib[m] = _cubic(tuple(cc[seg] for cc in cp), s)[:, 0]
+                continue
             cx, cy = b.center
             U = np.asarray(b.u_rigid, dtype=np.float64)
             Om = float(b.omega_rigid)

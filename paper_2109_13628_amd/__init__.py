@@ -56,7 +56,7 @@ class GridDesc(C.Structure):
 class BodyDesc(C.Structure):
     _fields_ = [("n_points", C.c_int32), ("xy_host", C.POINTER(C.c_double)), ("is_enclosure", C.c_int32),
                 ("center", C.c_double * 2), ("u_rigid", C.c_double * 2), ("omega_rigid", C.c_double),
-                ("rect", C.c_int32 * 4)]
+                ("rect", C.c_int32 * 4), ("bc_samples", C.POINTER(C.c_double))]
 
 
 class SolverOpts(C.Structure):
@@ -105,7 +105,8 @@ class GeometryView(C.Structure):
     _fields_ = [("n_control", C.c_int32), ("c_xy", C.POINTER(C.c_double)), ("c_theta", C.POINTER(C.c_double)),
                 ("c_normal", C.POINTER(C.c_double)), ("c_int", C.POINTER(C.c_int32)),
                 ("n_affected", C.c_int32), ("a_int", C.POINTER(C.c_int32)), ("cls", C.POINTER(C.c_int8)),
-                ("n_circ", C.c_int32), ("rects", C.POINTER(C.c_int32)), ("circ_body", C.POINTER(C.c_int32))]
+                ("n_circ", C.c_int32), ("rects", C.POINTER(C.c_int32)), ("circ_body", C.POINTER(C.c_int32)),
+                ("c_ub", C.POINTER(C.c_double)), ("c_psib", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -242,19 +243,7 @@ class Context:
         g.u_inf[0], g.u_inf[1] = grid.u_inf
         self.grid = grid
         self._pts = []
-        arr = (BodyDesc * max(1, len(bodies)))()
-        for k, b in enumerate(bodies):
-            p = np.ascontiguousarray(b.points, dtype=np.float64)
-            self._pts.append(p)
-            arr[k].n_points = p.shape[0]
-            arr[k].xy_host = p.ctypes.data_as(C.POINTER(C.c_double))
-            arr[k].is_enclosure = int(b.is_enclosure)
-            arr[k].center[0], arr[k].center[1] = b.center
-            arr[k].u_rigid[0], arr[k].u_rigid[1] = b.u_rigid
-            arr[k].omega_rigid = b.omega_rigid
-            r = b.rect if b.rect is not None else (-1, -1, -1, -1)
-            for q in range(4):
-                arr[k].rect[q] = r[q]
+        arr = _body_array(bodies, self._pts)
         o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
                        max_refine=8, guess=guess, host_only=int(host_only), solver=solver)
         if stream is None and not host_only:
@@ -298,6 +287,7 @@ class Context:
             "c_normal": a(v.c_normal, 2 * nc).reshape(nc, 2), "c_int": a(v.c_int, 5 * nc).reshape(nc, 5),
             "a_int": a(v.a_int, 4 * na).reshape(na, 4), "cls": a(v.cls, nx * ny).reshape(ny, nx),
             "rects": a(v.rects, 4 * v.n_circ).reshape(v.n_circ, 4), "circ_body": a(v.circ_body, v.n_circ),
+            "c_ub": a(v.c_ub, 2 * nc).reshape(nc, 2), "c_psib": a(v.c_psib, nc),
         }
         return out
 
@@ -505,6 +495,13 @@ def _body_array(bodies, keep):
         r = b.rect if b.rect is not None else (-1, -1, -1, -1)
         for q in range(4):
             arr[k].rect[q] = r[q]
+        smp = getattr(b, "bc_samples", None)
+        if smp is not None:
+            smp = np.ascontiguousarray(smp, dtype=np.float64)
+            if smp.shape != (p.shape[0], 3):
+                raise ValueError("bc_samples must be shaped (n_points, 3)")
+            keep.append(smp)
+            arr[k].bc_samples = smp.ctypes.data_as(C.POINTER(C.c_double))
     return arr
 
 

@@ -784,6 +784,11 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       }
       bs[k].omega = b.omega_rigid;
       for (int q = 0; q < 4; ++q) bs[k].rect[q] = b.rect[q];
+      if (b.bc_samples) {
+        bs[k].samples.assign(b.bc_samples, b.bc_samples + 3 * (size_t)b.n_points);
+        for (double v : bs[k].samples)
+          if (!std::isfinite(v)) throw ArgError("body " + std::to_string(k) + ": non-finite boundary sample");
+      }
     }
     if (opts) {
       c->precision = opts->precision;
@@ -885,6 +890,8 @@ int iim_get_geometry(const iim_ctx* c, iim_geometry_view* o) {
   o->n_circ = g.nbc();
   o->rects = c->v_rects.data();
   o->circ_body = c->v_circ.data();
+  o->c_ub = g.c_ub.data();
+  o->c_psib = g.c_psib.data();
   return IIM_OK;
 }
 

@@ -101,6 +101,8 @@ inline double evd(const Spline& s, int ax, int k, double t) {
 
 struct Cross {
   int body;
+  int seg;        // spline segment and parameter t in (0, 1) of the crossing
+  double t;
   int line;       // line index
   double along;   // coordinate along the line
   double px, py;  // point
@@ -171,6 +173,8 @@ void spline_crossings(const Spline& s, int body, int ax, const std::vector<doubl
             throw GeomError("body " + std::to_string(body) + ": boundary tangent to a grid line");
         Cross c;
         c.body = body;
+        c.seg = k;
+        c.t = t;
         c.line = L;
         c.px = ev(s, 0, k, t);
         c.py = ev(s, 1, k, t);
@@ -301,8 +305,8 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
   // ---- control points
   struct CRec {
     long key0;
-    int axis, sigma, i_f, j_f, body;
-    double theta, x, y, nx, ny;
+    int axis, sigma, i_f, j_f, body, seg;
+    double theta, x, y, nx, ny, t;
   };
   std::vector<CRec> recs;
   auto scan_line = [&](int axis, int L, std::vector<Cross>& cl) {
@@ -343,6 +347,8 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
       r.i_f = axis == 0 ? f_idx : L;
       r.j_f = axis == 0 ? L : f_idx;
       r.body = best->body;
+      r.seg = best->seg;
+      r.t = best->t;
       r.theta = theta;
       r.x = best->px;
       r.y = best->py;
@@ -365,6 +371,22 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
   g.c_axis.resize(nc); g.c_sigma.resize(nc); g.c_if.resize(nc); g.c_jf.resize(nc);
   g.c_ig.resize(nc); g.c_jg.resize(nc); g.c_body.resize(nc);
   g.c_ub.resize(2 * (size_t)nc); g.c_psib.resize(nc);
+  // prescribed boundary data: periodic cubic splines of the samples in the
+  // same parameter as the boundary curve, evaluated at each control point
+  std::vector<Spline> s_vel(bodies.size()), s_psi(bodies.size());
+  for (size_t k = 0; k < bodies.size(); ++k) {
+    const auto& smp = bodies[k].samples;
+    if (smp.empty()) continue;
+    const size_t P = bodies[k].xy.size() / 2;
+    std::vector<double> uv(2 * P), pz(2 * P, 0.0);
+    for (size_t p = 0; p < P; ++p) {
+      uv[2 * p] = smp[3 * p];
+      uv[2 * p + 1] = smp[3 * p + 1];
+      pz[2 * p] = smp[3 * p + 2];
+    }
+    s_vel[k] = make_spline(uv);
+    s_psi[k] = make_spline(pz);
+  }
   for (int c = 0; c < nc; ++c) {
     const auto& r = recs[c];
     if (!(r.theta > 0.0 && r.theta <= 1.0)) throw GeomError("control point outside its grid edge");
@@ -374,6 +396,13 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
     g.c_jg[c] = r.axis == 0 ? r.j_f : r.j_f + r.sigma;
     g.c_body[c] = r.body;
     const auto& b = bodies[r.body];
+    if (!b.samples.empty()) {
+      g.c_ub[2 * c] = ev(s_vel[r.body], 0, r.seg, r.t);
+      g.c_ub[2 * c + 1] = ev(s_vel[r.body], 1, r.seg, r.t);
+      g.c_psib[c] = ev(s_psi[r.body], 0, r.seg, r.t);
+      continue;
+    }
+    // rigid motion: u = u_rigid + omega x (x - center), psi its stream function
     const double dx = r.x - b.center[0], dy = r.y - b.center[1];
     g.c_ub[2 * c] = b.u_rigid[0] - b.omega * dy;
     g.c_ub[2 * c + 1] = b.u_rigid[1] + b.omega * dx;

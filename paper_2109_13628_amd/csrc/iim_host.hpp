@@ -26,6 +26,7 @@ struct BodySpec {
   double u_rigid[2] = {0, 0};
   double omega = 0;
   int rect[4] = {-1, -1, -1, -1};
+  std::vector<double> samples;  // [n][3] u_x, u_y, psi_b at the points (empty: rigid motion)
 };
 
 struct GridSpec {

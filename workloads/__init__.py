@@ -19,6 +19,8 @@ import math
 from dataclasses import dataclass, field, asdict
 from typing import List, Optional, Tuple
 
+import dataclasses
+
 import numpy as np
 
 EXT_BOX = "box"          # Dirichlet box (stream function zero on the box faces)
@@ -46,6 +48,7 @@ class BodyDesc:
     u_rigid: Tuple[float, float] = (0.0, 0.0)
     omega_rigid: float = 0.0
     rect: Optional[Tuple[int, int, int, int]] = None   # (i0, i1, j0, j1) or None = automatic
+    bc_samples: Optional[np.ndarray] = None            # (P, 3): u_x, u_y, psi_b at the points; None = rigid
 
 
 @dataclass
@@ -218,6 +221,21 @@ def seeded_vortices(grid: GridDesc, seed: int, count=6, box=None, amp=2.0, width
 def seeded_gammas(n_bodies: int, seed: int, scale=0.5):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-scale, scale, size=n_bodies)
+
+
+def surface_driven_cylinder(nx=128, ny=96, h=1.0 / 32, points=128, center=(1.5, 0.0), speed=(0.5, 0.3, 3)):
+    """A fixed cylinder (D = 1) whose surface moves tangentially with speed
+    U(phi) = s0 + s1 sin(m phi) (phi: polar angle about the centre): boundary
+    data given as samples at the boundary points (zero normal velocity, so
+    psi_b is constant, here 0), in free stream u_inf = (1, 0)."""
+    w = cylinder(nx=nx, ny=ny, h=h, points=points, dt=0.005, steps=5, center=center)
+    pts = w.bodies[0].points
+    phi = np.arctan2(pts[:, 1] - center[1], pts[:, 0] - center[0])
+    s0, s1, m = speed
+    U = s0 + s1 * np.sin(m * phi)
+    samples = np.stack([-U * np.sin(phi), U * np.cos(phi), np.zeros_like(phi)], axis=1)
+    body = dataclasses.replace(w.bodies[0], bc_samples=samples)
+    return dataclasses.replace(w, name="surface_driven_cylinder_%dx%d" % (nx, ny), bodies=[body])
 
 
 def cylinder_outflow_small():
