@@ -185,6 +185,22 @@ int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
 
 /* Largest stable time step on the RK3 stability triangle of App. B for a
  * velocity bound a_max = max(|u_x| + |u_y|). */
+/* Surface loads of the bodies (Sec. 5.4): shear stress tau = nu omega_b and the
+ * surface pressure from the vorticity flux, d p / d s = nu d omega / d n on a
+ * stationary no-slip wall, integrated along each body's control points in the
+ * order of its curve's parameter from the first one (so p is relative to that
+ * point), with omega extended past the boundary by E3b (with omega_b) and
+ * differentiated with the stencil points of omega_b (Sec. 5.3); n is the unit
+ * normal into the fluid, s = k x n.  Inputs on the device: omega [ny][nx], u
+ * and v on the ring [ny+2][nx+2] with the ghost values of iim_reconstruct.
+ * Outputs on the host: point_host [n_control][4] = (omega_b, tau, d omega/dn,
+ * p), control points in the order of iim_get_geometry; body_host
+ * [n_bodies][3] = (F_x, F_y, torque about the body's centre) of the traction
+ * -p n + nu omega s, trapezoid rule over each closed polygon of control points
+ * (a constant in p integrates to zero around a body).  Synchronises the stream.
+ * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts. */
+int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
+                      double* point_host, double* body_host);
 int iim_dt_max(const iim_ctx* ctx, double a_max, double* dt_max_out);
 
 /* Lattice Green's function g(m, n) of the 5-point Laplacian (host, for

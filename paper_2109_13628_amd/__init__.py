@@ -26,7 +26,7 @@ NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
-EXPORTS = ["iim_abi_version", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
+EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_poisson_fp32", "iim_reconstruct", "iim_rhs",
            "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay", "iim_solver_counters",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
@@ -147,6 +147,8 @@ def lib():
     L.iim_reconstruct.argtypes = [vp, vp, dp, vp, vp, vp, C.POINTER(StepStats)]
     L.iim_rhs.restype = ip
     L.iim_rhs.argtypes = [vp, vp, vp, vp, vp, dp, vp]
+    L.iim_surface_loads.restype = ip
+    L.iim_surface_loads.argtypes = [vp, vp, vp, vp, dp, dp]
     L.iim_rk3_step.restype = ip
     L.iim_rk3_step.argtypes = [vp, vp, dp, C.c_double, C.POINTER(StepStats)]
     L.iim_rk3_steps.restype = ip
@@ -244,6 +246,7 @@ class Context:
         self.grid = grid
         self._pts = []
         arr = _body_array(bodies, self._pts)
+        self.n_bodies = len(bodies)
         o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
                        max_refine=8, guess=guess, host_only=int(host_only), solver=solver)
         if stream is None and not host_only:
@@ -309,6 +312,18 @@ class Context:
                                    _ptr(u), _ptr(v), C.byref(st))
         self._check(rc, "iim_reconstruct", allow=(IIM_ENOCONV,) if allow_noconv else ())
         return st.as_dict()
+
+    def surface_loads(self, omega, u, v):
+        """Per control point (omega_b, tau, d omega/dn, relative pressure)
+        and per body (F_x, F_y, torque); u, v: ring arrays from reconstruct."""
+        nc = self.info["n_control"]
+        pts = np.zeros((max(1, nc), 4))
+        bod = np.zeros((max(1, self.n_bodies), 3))
+        self._check(lib().iim_surface_loads(self._h, _ptr(omega), _ptr(u), _ptr(v),
+                                            pts.ctypes.data_as(C.POINTER(C.c_double)),
+                                            bod.ctypes.data_as(C.POINTER(C.c_double))), "iim_surface_loads")
+        return {"omega_b": pts[:nc, 0].copy(), "tau": pts[:nc, 1].copy(), "dwdn": pts[:nc, 2].copy(),
+                "p": pts[:nc, 3].copy(), "forces": bod[:self.n_bodies].copy()}
 
     def rhs(self, omega, u, v, domega, omega_b=None):
         dG = np.zeros(max(1, self.n_circ))

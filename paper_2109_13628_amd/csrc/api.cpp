@@ -307,6 +307,23 @@ void setup_device(iim_ctx* c) {
   d.c_psibt = c->upload(psibt);
   d.c_ub = c->upload(g.c_ub);
   d.wb_const = c->upload(wbc);
+  {
+    std::vector<double> lwx(g.nc, 0.0), lwy(g.nc, 0.0);
+    std::vector<double2> cn(g.nc);
+    for (int q = 0; q < g.nc; ++q) {
+      for (int e = g.wbc.bptr[q]; e < g.wbc.bptr[q + 1]; ++e) {
+        if (g.wbc.bc[e] != q) throw ArgError("boundary-vorticity stencil refers to another control point");
+        if (g.wbc.bcomp[e] == 1)
+          lwx[q] += g.wbc.bw[e];
+        else
+          lwy[q] -= g.wbc.bw[e];
+      }
+      cn[q] = make_double2(g.c_nx[q], g.c_ny[q]);
+    }
+    d.lw_x = c->upload(lwx);
+    d.lw_y = c->upload(lwy);
+    d.c_n = c->upload(cn);
+  }
   std::vector<double> bpsi(g.na, 0.0), b1((size_t)std::max(1, g.nbc()) * g.na, 0.0);
   for (int a = 0; a < g.na; ++a)
     for (int e = g.aop.bptr[a]; e < g.aop.bptr[a + 1]; ++e) {
@@ -419,6 +436,7 @@ void setup_device(iim_ctx* c) {
   c->U = c->dalloc<double>(NR);
   c->V = c->dalloc<double>(NR);
   c->wb = c->dalloc<double>(g.nc);
+  c->sdwdn = c->dalloc<double>(g.nc);
   c->w4 = c->dalloc<double>(N);
   c->w3b = c->dalloc<double>(N);
   c->w3n = c->dalloc<double>(N);
@@ -968,6 +986,69 @@ int iim_reconstruct(iim_ctx* c, const double* omega, const double* Gamma_host, d
       stats->converged = rc == IIM_OK;
     }
     if (rc != IIM_OK) return fail(c, rc, rc == IIM_ENOCONV ? "Krylov limit reached" : "non-finite residual");
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const double* v, double* point_host,
+                      double* body_host) {
+  if (!c || !omega || !u || !v || !point_host || !body_host) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    const Geometry& g = c->geo;
+    const int nc = g.nc;
+    const double nu = g.grid.nu;
+    launch_omega_bc(c->dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
+    launch_surface_dwdn(c->dg, omega, c->w3b, c->wb, c->sdwdn, c->stream);
+    std::vector<double> wb(nc), dwdn(nc), p(nc, 0.0);
+    if (nc) {
+      HIPCHK(hipMemcpyAsync(wb.data(), c->wb, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(dwdn.data(), c->sdwdn, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    // per body: the control points in the order of the curve's parameter;
+    // the tangential pressure gradient nu d omega/dn integrated from the
+    // first of them (trapezoid rule on the chords), then the force
+    // -p n + nu omega s (s = k x n) and its moment about the body's centre,
+    // summed with the trapezoid weights of the closed polygon
+    for (size_t k = 0; k < g.bodies.size(); ++k) {
+      std::vector<int> ord;
+      for (int q = 0; q < nc; ++q)
+        if (g.c_body[q] == (int)k) ord.push_back(q);
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int a, int b) { return g.c_seg[a] + g.c_t[a] < g.c_seg[b] + g.c_t[b]; });
+      double F[3] = {0.0, 0.0, 0.0};
+      const size_t m = ord.size();
+      if (m) {
+        std::vector<double> ds(m);
+        for (size_t q = 0; q < m; ++q) {
+          const int a = ord[q], b = ord[(q + 1) % m];
+          ds[q] = std::hypot(g.c_x[b] - g.c_x[a], g.c_y[b] - g.c_y[a]);
+        }
+        for (size_t q = 1; q < m; ++q)
+          p[ord[q]] = p[ord[q - 1]] + 0.5 * nu * (dwdn[ord[q - 1]] + dwdn[ord[q]]) * ds[q - 1];
+        const double cx = g.bodies[k].center[0], cy = g.bodies[k].center[1];
+        for (size_t q = 0; q < m; ++q) {
+          const int a = ord[q];
+          const double nx = g.c_nx[a], ny = g.c_ny[a];
+          const double fx = -p[a] * nx + nu * wb[a] * (-ny), fy = -p[a] * ny + nu * wb[a] * nx;
+          const double wgt = 0.5 * (ds[q] + ds[(q + m - 1) % m]);
+          F[0] += fx * wgt;
+          F[1] += fy * wgt;
+          F[2] += ((g.c_x[a] - cx) * fy - (g.c_y[a] - cy) * fx) * wgt;
+        }
+      }
+      for (int r = 0; r < 3; ++r) body_host[3 * k + r] = F[r];
+    }
+    for (int q = 0; q < nc; ++q) {
+      point_host[4 * q + 0] = wb[q];
+      point_host[4 * q + 1] = nu * wb[q];
+      point_host[4 * q + 2] = dwdn[q];
+      point_host[4 * q + 3] = p[q];
+    }
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
   }

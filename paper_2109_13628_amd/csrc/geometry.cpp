@@ -369,7 +369,7 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
   g.nc = nc;
   g.c_x.resize(nc); g.c_y.resize(nc); g.c_theta.resize(nc); g.c_nx.resize(nc); g.c_ny.resize(nc);
   g.c_axis.resize(nc); g.c_sigma.resize(nc); g.c_if.resize(nc); g.c_jf.resize(nc);
-  g.c_ig.resize(nc); g.c_jg.resize(nc); g.c_body.resize(nc);
+  g.c_ig.resize(nc); g.c_jg.resize(nc); g.c_body.resize(nc); g.c_seg.resize(nc); g.c_t.resize(nc);
   g.c_ub.resize(2 * (size_t)nc); g.c_psib.resize(nc);
   // prescribed boundary data: periodic cubic splines of the samples in the
   // same parameter as the boundary curve, evaluated at each control point
@@ -395,6 +395,8 @@ void build_geometry(Geometry& g, const GridSpec& grid, const std::vector<BodySpe
     g.c_ig[c] = r.axis == 0 ? r.i_f + r.sigma : r.i_f;
     g.c_jg[c] = r.axis == 0 ? r.j_f : r.j_f + r.sigma;
     g.c_body[c] = r.body;
+    g.c_seg[c] = r.seg;
+    g.c_t[c] = r.t;
     const auto& b = bodies[r.body];
     if (!b.samples.empty()) {
       g.c_ub[2 * c] = ev(s_vel[r.body], 0, r.seg, r.t);

@@ -54,6 +54,12 @@ struct DGeom {
   const double* b1;            // B 1_k, [nbc][na]
   const int* rects;            // [nbc][4]
   DStencil ext4b, ext3b, ext3n, aop, wbc;
+  // surface loads: the boundary-value weights of the boundary-vorticity
+  // stencil split into its d_x part (lw_x) and minus its d_y part (lw_y),
+  // and the unit normal into the fluid at each control point
+  const double* lw_x;
+  const double* lw_y;
+  const double2* c_n;
 };
 
 // The boundary quantities of a stage as affine forms of psi (ring), omega
@@ -291,5 +297,10 @@ void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStrea
 bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
                       const double* Mt, int n, double* b, double* x, hipStream_t s);
 void launch_unit(double* v, int n, int q, hipStream_t s);
+// d omega / dn at every control point: the boundary-vorticity stencil's d_x
+// and d_y parts applied to omega extended with E3b at the ghosts (w3b), with
+// omega_b (wb) as the boundary value, projected on the normal into the fluid.
+void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
+                         hipStream_t s);
 
 }  // namespace iim

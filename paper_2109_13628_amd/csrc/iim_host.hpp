@@ -55,6 +55,8 @@ struct Geometry {
   int nc = 0;
   std::vector<double> c_x, c_y, c_theta, c_nx, c_ny, c_ub, c_psib;  // c_ub: [nc][2]
   std::vector<int> c_axis, c_sigma, c_if, c_jf, c_ig, c_jg, c_body;
+  std::vector<int> c_seg;       // spline segment of the crossing; c_t its parameter in (0, 1)
+  std::vector<double> c_t;
   // node classes [ny][nx]
   std::vector<int8_t> cls;
   std::vector<int> ghost_id;  // [ny][nx], -1 if not a ghost
