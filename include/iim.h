@@ -197,7 +197,11 @@ int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
  * p), control points in the order of iim_get_geometry; body_host
  * [n_bodies][3] = (F_x, F_y, torque about the body's centre) of the traction
  * -p n + nu omega s, trapezoid rule over each closed polygon of control points
- * (a constant in p integrates to zero around a body).  Synchronises the stream.
+ * (a constant in p integrates to zero around a body).  A body in steady rigid
+ * motion (constant u_rigid, omega_rigid): viscous traction nu (omega - 2
+ * omega_rigid) s and the centripetal term omega_rigid^2 (x - c).s added to
+ * d p / d s; bodies with bc_samples are treated as stationary walls.
+ * Synchronises the stream.
  * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts. */
 int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                       double* point_host, double* body_host);

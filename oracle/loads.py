@@ -19,6 +19,12 @@ cpu_baseline leg use the oracle; the library shares none of this code.
   -p n + nu omega s (n: unit normal into the fluid, s = k x n), the
   trapezoid rule over the same closed polygon; a constant added to p
   integrates to zero around the body, so the relative pressure suffices.
+* A body in steady rigid motion (constant translation, rotation Omega about
+  its centre): the rigid motion carries vorticity 2 Omega and no strain, so
+  the viscous traction is nu (omega - 2 Omega) s; the wall's centripetal
+  acceleration -Omega^2 (x - c) adds Omega^2 (x - c).s to the tangential
+  pressure gradient (momentum balance at the no-slip wall).  Bodies with
+  sampled boundary data are treated as stationary walls.
 """
 import numpy as np
 
@@ -76,13 +82,19 @@ def integrate_surface(geom, wb, dwdn):
             continue
         xy = np.stack([geom.c_x[order], geom.c_y[order]], axis=1)
         ds = np.linalg.norm(np.roll(xy, -1, axis=0) - xy, axis=1)   # chord to the next point (closed)
+        Om = 0.0 if getattr(b, "bc_samples", None) is not None else float(b.omega_rigid)
+        rel = xy - np.asarray(b.center, dtype=np.float64)
+        nn = nrm[order]
+        # tangential pressure gradient: viscous part plus the rigid rotation's
+        # centripetal part Omega^2 (x - c).s
+        dpds = nu * dwdn[order] + Om * Om * (rel[:, 0] * (-nn[:, 1]) + rel[:, 1] * nn[:, 0])
         pk = np.zeros(order.size)
         for q in range(1, order.size):
-            pk[q] = pk[q - 1] + 0.5 * nu * (dwdn[order[q - 1]] + dwdn[order[q]]) * ds[q - 1]
+            pk[q] = pk[q - 1] + 0.5 * (dpds[q - 1] + dpds[q]) * ds[q - 1]
         p[order] = pk
         n = nrm[order]
         s = np.stack([-n[:, 1], n[:, 0]], axis=1)
-        f = -pk[:, None] * n + nu * wb[order][:, None] * s
+        f = -pk[:, None] * n + nu * (wb[order] - 2.0 * Om)[:, None] * s
         wgt = 0.5 * (ds + np.roll(ds, 1))                            # trapezoid weight of each point
         F = np.sum(f * wgt[:, None], axis=0)
         r = xy - np.asarray(b.center, dtype=np.float64)

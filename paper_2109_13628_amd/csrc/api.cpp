@@ -1013,7 +1013,11 @@ int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const do
     // the tangential pressure gradient nu d omega/dn integrated from the
     // first of them (trapezoid rule on the chords), then the force
     // -p n + nu omega s (s = k x n) and its moment about the body's centre,
-    // summed with the trapezoid weights of the closed polygon
+    // summed with the trapezoid weights of the closed polygon.  A body in
+    // steady rigid rotation Omega: its rigid motion carries vorticity
+    // 2 Omega and no strain, so the viscous traction is nu (omega - 2 Omega) s,
+    // and the wall's centripetal acceleration adds Omega^2 (x - c).s to the
+    // tangential pressure gradient.  Sampled boundary data: stationary wall.
     for (size_t k = 0; k < g.bodies.size(); ++k) {
       std::vector<int> ord;
       for (int q = 0; q < nc; ++q)
@@ -1028,13 +1032,17 @@ int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const do
           const int a = ord[q], b = ord[(q + 1) % m];
           ds[q] = std::hypot(g.c_x[b] - g.c_x[a], g.c_y[b] - g.c_y[a]);
         }
-        for (size_t q = 1; q < m; ++q)
-          p[ord[q]] = p[ord[q - 1]] + 0.5 * nu * (dwdn[ord[q - 1]] + dwdn[ord[q]]) * ds[q - 1];
         const double cx = g.bodies[k].center[0], cy = g.bodies[k].center[1];
+        const double om = g.bodies[k].samples.empty() ? g.bodies[k].omega : 0.0;
+        auto dpds = [&](int a) {
+          return nu * dwdn[a] + om * om * ((g.c_x[a] - cx) * (-g.c_ny[a]) + (g.c_y[a] - cy) * g.c_nx[a]);
+        };
+        for (size_t q = 1; q < m; ++q)
+          p[ord[q]] = p[ord[q - 1]] + 0.5 * (dpds(ord[q - 1]) + dpds(ord[q])) * ds[q - 1];
         for (size_t q = 0; q < m; ++q) {
           const int a = ord[q];
-          const double nx = g.c_nx[a], ny = g.c_ny[a];
-          const double fx = -p[a] * nx + nu * wb[a] * (-ny), fy = -p[a] * ny + nu * wb[a] * nx;
+          const double nx = g.c_nx[a], ny = g.c_ny[a], tv = nu * (wb[a] - 2.0 * om);
+          const double fx = -p[a] * nx + tv * (-ny), fy = -p[a] * ny + tv * nx;
           const double wgt = 0.5 * (ds[q] + ds[(q + m - 1) % m]);
           F[0] += fx * wgt;
           F[1] += fy * wgt;

@@ -42,7 +42,7 @@ def _run(n):
 
 
 def test_rotating_cylinder_converges_to_the_closed_form():
-    errs, werrs = [], []
+    errs, werrs, merrs = [], [], []
     for n in (128, 256):
         geo, om, loads, steps = _run(n)
         X, Y = np.meshgrid(geo.x, geo.y)
@@ -52,9 +52,15 @@ def test_rotating_cylinder_converges_to_the_closed_form():
         e = np.linalg.norm(om[m] - exact) / np.linalg.norm(exact)
         wb_exact = OMEGA * AR.omega_star(1.0, T_STAR)
         we = np.abs(np.mean(loads["omega_b"]) - wb_exact) / abs(wb_exact)
-        print("n", n, "steps", steps, "vorticity rel L2 error %.3e" % e, "wall vorticity rel error %.3e" % we)
+        # moment on the cylinder, nondimensional M* = M / (2 pi R^2 nu Omega) = omega*(1, t*) - 2
+        m_num = loads["forces"][0, 2] / (2 * np.pi * R * R * NU * OMEGA)
+        me = abs(m_num - (AR.omega_star(1.0, T_STAR) - 2.0)) / abs(AR.omega_star(1.0, T_STAR) - 2.0)
+        print("n", n, "steps", steps, "vorticity rel L2 error %.3e" % e, "wall vorticity rel error %.3e" % we,
+              "moment M* %.5f rel error %.3e" % (m_num, me))
         errs.append(e)
         werrs.append(we)
+        merrs.append(me)
     # measured: 1.48e-2 -> 2.64e-3 (field), 1.27e-2 -> 2.25e-3 (wall): above second order
     assert errs[1] < 0.3 * errs[0] and errs[1] < 0.01, errs
     assert werrs[1] < 0.3 * werrs[0] and werrs[1] < 0.01, werrs
+    assert merrs[1] < 0.5 * merrs[0] and merrs[1] < 0.01, merrs

@@ -52,6 +52,18 @@ def test_integration_converges_to_the_analytic_loads():
         assert e[1] < e[0] / 3.0 and e[2] < e[1] / 3.0, e
 
 
+def test_solid_body_rotation_carries_no_shear():
+    """A body rotating at Omega with the wall vorticity of solid-body rotation
+    (2 Omega) and no vorticity flux: no viscous traction, so the torque comes
+    only from the pressure, which on a circle the rotation leaves uniform."""
+    import dataclasses
+    w = wl.cylinder_small()
+    b = dataclasses.replace(w.bodies[0], omega_rigid=1.3)
+    g = OG.Geometry(w.grid, [b])
+    p, F = OL.integrate_surface(g, np.full(g.nc, 2.6), np.zeros(g.nc))
+    assert np.max(np.abs(F[0])) < 1e-12, F
+
+
 def test_loads_of_a_symmetric_flow():
     """A cylinder on a grid symmetric about its axis, started from rest: the
     flow stays mirror-symmetric, so the lift and the torque vanish to
