@@ -106,6 +106,10 @@ def test_argument_errors_of_the_additions():
     assert L.iim_set_warm_start(h, 7, None) == iim.IIM_EINVAL
     assert L.iim_set_warm_start(h, iim.GUESS_EXTRAPOLATE, None) == iim.IIM_OK
     assert L.iim_autotune(h, 1, None, None, None, None) == iim.IIM_EUNSUPPORTED
+    two = (C.c_double * 8)()
+    assert L.iim_surface_loads(h, one, one, one, None, two) == iim.IIM_EINVAL
+    assert L.iim_surface_loads(h, one, one, one, two, two) == iim.IIM_EUNSUPPORTED
+    assert L.iim_surface_loads(None, one, one, one, two, two) == iim.IIM_EINVAL
     assert L.iim_profile_replay(h, 0, 1, C.byref(C.c_double()), C.byref(C.c_double())) == iim.IIM_EUNSUPPORTED
     assert L.iim_warm_start_train(h, None, 1, 1, 1e-3, 0, None) == iim.IIM_EINVAL
     ctx.close()
