@@ -1,7 +1,7 @@
 """Alternative code paths that the library selects at context creation give
 the default path's result: the chained boundary kernels (ghost psi,
 velocity extension, omega_b, vorticity extensions in sequence; also the
-fallback for grids too large for the composed forms), the LDS-only FFT
+fallback where the composed forms cannot be built), the LDS-only FFT
 kernels, and eager steps instead of the captured step graph."""
 import os
 

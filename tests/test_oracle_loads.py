@@ -8,6 +8,8 @@
   converging at second order; a constant wall vorticity W on a circle of
   radius R gives zero force and the torque 2 pi nu W R^2, at second order;
 * the ordering follows the curve: consecutive control points are close."""
+import dataclasses
+
 import numpy as np
 
 import workloads as wl
@@ -81,3 +83,58 @@ def test_loads_of_a_symmetric_flow():
     Fx, Fy, T = L["forces"][0]
     assert Fx > 0.0
     assert abs(Fy) < 1e-10 * Fx and abs(T) < 1e-10 * Fx
+
+
+def test_pressure_loads_equal_the_vorticity_flux_identities():
+    """Sec. 5.4 writes the pressure force and moment directly in terms of the
+    tangential pressure gradient d p/ds = nu d omega/dn.  On a closed curve,
+    with n into the fluid and s = k x n, integration by parts gives
+    F_p = int (y, -x) dp/ds ds and M_p = -(1/2) int |x - c|^2 dp/ds ds.  (The
+    paper prints the moment with a plus sign; the traction -p n fixes the
+    minus, reading 25.)  An ellipse with a smooth surface pressure
+    P = sin(2x) cos(y) + x y^2: the oracle's route (p integrated along the
+    curve, then -p n summed) and both identities converge at second order to
+    the boundary integrals of -P n evaluated on the exact ellipse."""
+    from workloads import ellipse_points
+    ctr, a, b, ang = (2.0, 0.05), 0.8, 0.45, 0.35
+    P = lambda x, y: np.sin(2 * x) * np.cos(y) + x * y * y
+    dP = lambda x, y: (2 * np.cos(2 * x) * np.cos(y) + y * y, -np.sin(2 * x) * np.sin(y) + 2 * x * y)
+    # exact loads: the trapezoid rule in the ellipse's angle (spectrally accurate)
+    t = 2 * np.pi * np.arange(4096) / 4096
+    ca, sa = np.cos(ang), np.sin(ang)
+    x = ctr[0] + ca * a * np.cos(t) - sa * b * np.sin(t)
+    y = ctr[1] + sa * a * np.cos(t) + ca * b * np.sin(t)
+    xp = -ca * a * np.sin(t) - sa * b * np.cos(t)
+    yp = -sa * a * np.sin(t) + ca * b * np.cos(t)
+    dt = 2 * np.pi / t.size
+    Pv = P(x, y)
+    F_ex = np.array([-np.sum(Pv * yp), np.sum(Pv * xp)]) * dt              # -P n ds, n ds = (y', -x') dt
+    M_ex = np.sum(Pv * ((x - ctr[0]) * xp + (y - ctr[1]) * yp)) * dt        # (x - c) x (-P n ds)
+    errs = {"route": [], "F_id": [], "M_id": []}
+    M_printed = []
+    for h in (1 / 32, 1 / 64, 1 / 128):
+        n = int(round(4 / h))
+        w = wl.cylinder(nx=n, ny=n, h=h, points=256, center=ctr)
+        body = dataclasses.replace(w.bodies[0], points=ellipse_points(ctr, a, b, ang, 256))
+        g = OG.Geometry(w.grid, [body])
+        nu = g.grid.nu
+        gx, gy = dP(g.c_x, g.c_y)
+        dpds = gx * (-g.c_ny) + gy * g.c_nx
+        p, F = OL.integrate_surface(g, np.zeros(g.nc), dpds / nu)
+        errs["route"].append(max(np.hypot(*(F[0, :2] - F_ex)), abs(F[0, 2] - M_ex)))
+        o = OL.surface_order(g, 0)
+        xy = np.stack([g.c_x[o], g.c_y[o]], axis=1)
+        ds = np.linalg.norm(np.roll(xy, -1, axis=0) - xy, axis=1)
+        wgt = 0.5 * (ds + np.roll(ds, 1))
+        F_id = np.array([np.sum(xy[:, 1] * dpds[o] * wgt), np.sum(-xy[:, 0] * dpds[o] * wgt)])
+        r2 = np.sum((xy - np.asarray(ctr)) ** 2, axis=1)
+        M_id = -0.5 * np.sum(r2 * dpds[o] * wgt)
+        errs["F_id"].append(np.hypot(*(F_id - F_ex)))
+        errs["M_id"].append(abs(M_id - M_ex))
+        M_printed.append(-M_id)
+    # second order: about 16x over two halvings of h (each halving at least 2x:
+    # the control points' positions along the curve change with h)
+    for k, e in errs.items():
+        assert e[1] < e[0] / 2.0 and e[2] < e[1] / 2.0 and e[2] < e[0] / 10.0, (k, e)
+        assert e[2] < 2e-3 * (np.hypot(*F_ex) + abs(M_ex)), (k, e)
+    assert abs(M_ex) > 1e-2 and abs(M_printed[-1] - M_ex) > abs(M_ex)
