@@ -1,0 +1,128 @@
+"""Long validation run (not collected by pytest): the side-by-side cylinder
+pair of Sec. 6 at Re = 100, L/D = 3, started from rest, which sheds in
+antiphase.  The paper tabulates the long-time drag and lift statistics of
+each cylinder (mean C_D, mean C_L, RMS C_L, with C = 2F/(D U^2)), computed from
+the surface loads (Sec. 5.4): the library's surface pressure, shear, force
+and torque are sampled every few steps of the FP64 dense-solve time step.
+
+The run prints one progress line about every 20 s and writes the force
+history and the statistics as JSON:
+
+    python tests/long_side_by_side.py --t-end 200 --avg-from 120 --out sbs.json
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import workloads as wl  # noqa: E402
+import paper_2109_13628_amd as iim  # noqa: E402
+
+
+def stats(t, cd, cl, avg_from):
+    sel = t >= avg_from
+    out = {"C_D_mean": float(cd[sel].mean()), "C_L_mean": float(cl[sel].mean()),
+           "C_L_rms": float(np.sqrt(np.mean(cl[sel] ** 2))),
+           "C_L_rms_about_mean": float(cl[sel].std()), "samples": int(sel.sum())}
+    # shedding frequency from the upward zero crossings of C_L - mean
+    x = cl[sel] - cl[sel].mean()
+    tt = t[sel]
+    up = np.nonzero((x[:-1] < 0) & (x[1:] >= 0))[0]
+    if up.size >= 3:
+        tc = tt[up] - x[up] * (tt[up + 1] - tt[up]) / (x[up + 1] - x[up])
+        out["strouhal"] = float((up.size - 1) / (tc[-1] - tc[0]))
+    # stationarity: the two halves of the averaging window
+    half = tt[0] + 0.5 * (tt[-1] - tt[0])
+    a, b = tt < half, tt >= half
+    out["C_D_mean_halves"] = [float(cd[sel][a].mean()), float(cd[sel][b].mean())]
+    out["C_L_rms_halves"] = [float(np.sqrt(np.mean(cl[sel][a] ** 2))), float(np.sqrt(np.mean(cl[sel][b] ** 2)))]
+    return out
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--re", type=float, default=100.0)
+    p.add_argument("--gap", type=float, default=3.0)
+    p.add_argument("--d-over-h", type=int, default=64)
+    p.add_argument("--length", type=float, default=30.0)
+    p.add_argument("--height", type=float, default=12.0)
+    p.add_argument("--dt", type=float, default=0.0025)
+    p.add_argument("--t-end", type=float, default=200.0)
+    p.add_argument("--avg-from", type=float, default=120.0)
+    p.add_argument("--every", type=int, default=20, help="time steps between load samples")
+    p.add_argument("--out", default="side_by_side.json")
+    a = p.parse_args()
+
+    w = wl.side_by_side_cylinders(re=a.re, gap=a.gap, d_over_h=a.d_over_h, length=a.length, height=a.height,
+                                  dt=a.dt)
+    g = w.grid
+    t0 = time.time()
+    ctx = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
+    tune = ctx.autotune()
+    dt_max = ctx.dt_max(2.0 * math.sqrt(2.0))
+    if a.dt > dt_max:
+        raise SystemExit("dt %.3g above the stability limit %.3g" % (a.dt, dt_max))
+    print("setup %.1f s: %s, %d x %d, torus %d x %d, |A| = %d, dt = %g (limit %.3g), N_delta = %.2f, Q = %.3f"
+          % (time.time() - t0, w.name, g.nx, g.ny, ctx.info["fft_mx"], ctx.info["fft_my"],
+             ctx.info["n_affected"], a.dt, dt_max, a.d_over_h / math.sqrt(a.re), a.re ** 1.5 / a.d_over_h ** 2),
+          flush=True)
+
+    dev = torch.device("cuda:0")
+    om = torch.zeros((g.ny, g.nx), dtype=torch.float64, device=dev)
+    G = np.zeros(ctx.n_circ)
+    psi = torch.zeros((g.ny + 2, g.nx + 2), dtype=torch.float64, device=dev)
+    U, V = torch.zeros_like(psi), torch.zeros_like(psi)
+    n_total = int(round(a.t_end / a.dt))
+    hist = []
+    step_s = load_s = 0.0
+    last = time.time()
+    n = 0
+    while n < n_total:
+        k = min(a.every, n_total - n)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        G, _ = ctx.rk3_steps(om, G, a.dt, k)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
+        ctx.reconstruct(om, G, psi, U, V)
+        L = ctx.surface_loads(om, U, V)
+        s2 = time.perf_counter()
+        step_s += s1 - s0
+        load_s += s2 - s1
+        n += k
+        F = L["forces"]
+        hist.append([n * a.dt, 2 * F[0, 0], 2 * F[0, 1], 2 * F[1, 0], 2 * F[1, 1], F[0, 2], F[1, 2]])
+        if not np.all(np.isfinite(F)):
+            raise SystemExit("non-finite loads at t = %g" % (n * a.dt))
+        if time.time() - last > 20.0:
+            last = time.time()
+            print("t = %7.2f  lower C_D %.4f C_L %+.4f  upper C_D %.4f C_L %+.4f  (%.3f ms/step)"
+                  % (n * a.dt, hist[-1][1], hist[-1][2], hist[-1][3], hist[-1][4], 1e3 * step_s / n), flush=True)
+    H = np.array(hist)
+    t = H[:, 0]
+    res = {"workload": w.name, "Re": a.re, "L/D": a.gap, "D/h": a.d_over_h, "dt": a.dt, "t_end": a.t_end,
+           "avg_from": a.avg_from, "N_delta": a.d_over_h / math.sqrt(a.re), "Q": a.re ** 1.5 / a.d_over_h ** 2,
+           "fft_tiles": tune, "ms_per_step": 1e3 * step_s / n,
+           "ms_per_load_sample": 1e3 * load_s / len(hist),
+           "lower": stats(t, H[:, 1], H[:, 2], a.avg_from), "upper": stats(t, H[:, 3], H[:, 4], a.avg_from)}
+    sel = t >= a.avg_from
+    res["lift_correlation"] = float(np.corrcoef(H[sel, 2], H[sel, 4])[0, 1]) if sel.sum() > 2 else None
+    res["history"] = {"t": t.tolist(), "CD_lower": H[:, 1].tolist(), "CL_lower": H[:, 2].tolist(),
+                      "CD_upper": H[:, 3].tolist(), "CL_upper": H[:, 4].tolist()}
+    with open(a.out, "w") as f:
+        json.dump(res, f)
+    brief = {k: v for k, v in res.items() if k != "history"}
+    print(json.dumps(brief), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -246,6 +246,24 @@ def cylinder_outflow_small():
     return w
 
 
+def side_by_side_cylinders(re=100.0, gap=3.0, d_over_h=64, length=30.0, height=12.0, points=512, dt=0.0025,
+                           steps=80000):
+    """A side-by-side cylinder pair (Sec. 6): two cylinders of diameter 1 with
+    centres `gap` apart across a uniform stream U = 1, one diameter downstream
+    of the inflow edge, on a cell-centred grid of length x height diameters
+    with the outflow plane at the downstream face; nu = 1/Re.  The grid and
+    the pair are mirror-symmetric about y = 0 (started from rest, the pair
+    sheds in antiphase)."""
+    h = 1.0 / d_over_h
+    nx, ny = int(round(length / h)), int(round(height / h))
+    grid = GridDesc(nx=nx, ny=ny, x0=0.5 * h, y0=-0.5 * ny * h + 0.5 * h, h=h, exterior=EXT_OUTFLOW,
+                    u_inf=(1.0, 0.0), nu=1.0 / re)
+    bodies = [BodyDesc(points=circle_points((1.0, c), 0.5, points), center=(1.0, c))
+              for c in (-0.5 * gap, 0.5 * gap)]
+    return Workload("side_by_side_Re%d_LD%g_%dx%d_outflow" % (round(re), gap, nx, ny), grid, bodies, dt, steps,
+                    extra={"Re": re, "L/D": gap, "D/h": d_over_h})
+
+
 def multi_body(n=2048, seed=3, steps=500):
     """Four seeded nonconvex/elongated bodies in a uniform stream on [0,1]^2
     with an outflow plane at x = 1: two ellipses (aspect 1.5-3) and two
