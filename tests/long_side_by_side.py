@@ -6,7 +6,8 @@ the surface loads (Sec. 5.4): the library's surface pressure, shear, force
 and torque are sampled every few steps of the FP64 dense-solve time step.
 
 The run prints one progress line about every 20 s and writes the force
-history and the statistics as JSON:
+history and the statistics as JSON, with the paper's row for the same
+parameters and shedding mode (tests/golden/side_by_side_statistics.json):
 
     python tests/long_side_by_side.py --t-end 200 --avg-from 120 --out sbs.json
 """
@@ -115,6 +116,18 @@ def main():
            "lower": stats(t, H[:, 1], H[:, 2], a.avg_from), "upper": stats(t, H[:, 3], H[:, 4], a.avg_from)}
     sel = t >= a.avg_from
     res["lift_correlation"] = float(np.corrcoef(H[sel, 2], H[sel, 4])[0, 1]) if sel.sum() > 2 else None
+    # the paper's row for these parameters (antiphase: the lifts are mirror images)
+    with open(os.path.join(HERE, "golden", "side_by_side_statistics.json")) as f:
+        rows = json.load(f)["rows"]
+    mode = "antiphase" if (res["lift_correlation"] or 0.0) < -0.9 else "in-phase"
+    for r in rows:
+        if r["Re"] == a.re and r["L/D"] == a.gap and r["mode"] == mode:
+            lo = res["lower"]
+            res["paper"] = r
+            res["relative_difference"] = {
+                "C_D_mean": lo["C_D_mean"] / r["C_D_mean"] - 1.0,
+                "C_L_mean": abs(lo["C_L_mean"]) / r["C_L_mean"] - 1.0,
+                "C_L_rms_about_mean": lo["C_L_rms_about_mean"] / r["C_L_rms"] - 1.0}
     res["history"] = {"t": t.tolist(), "CD_lower": H[:, 1].tolist(), "CL_lower": H[:, 2].tolist(),
                       "CD_upper": H[:, 3].tolist(), "CL_upper": H[:, 4].tolist()}
     with open(a.out, "w") as f:
