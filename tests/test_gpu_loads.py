@@ -2,8 +2,12 @@
 vorticity, shear, vorticity flux, relative surface pressure and the force and
 torque on each body, from the same vorticity and circulations.  The tolerance
 allows for the reconstruction's 1e-11 velocity agreement carried through two
-differences at spacing h (omega_b, then d omega/dn).  The symmetric start
-from rest gives no lift and no torque."""
+differences at spacing h (omega_b, then d omega/dn).  Stationary bodies, a
+body in rigid translation and rotation (the rigid-motion terms of the
+traction and of the tangential pressure gradient), and a body with sampled
+boundary data.  The symmetric start from rest gives no lift and no torque."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -34,9 +38,19 @@ def _close(a, b, tol):
     return np.max(np.abs(np.asarray(a) - np.asarray(b))) <= tol * scale
 
 
-@pytest.mark.parametrize("make", [wl.cylinder_small, wl.two_c_shapes_lamb_oseen])
-def test_surface_loads_match_oracle(make):
-    w = make() if make is wl.cylinder_small else make(128)
+def _rigid_motion_cylinder():
+    w = wl.cylinder_small()
+    w.bodies[0] = dataclasses.replace(w.bodies[0], u_rigid=(0.2, -0.1), omega_rigid=1.3)
+    return w
+
+
+CASES = {"cylinder": wl.cylinder_small, "two_c_shapes": lambda: wl.two_c_shapes_lamb_oseen(128),
+         "rigid_motion": _rigid_motion_cylinder, "sampled_surface": wl.surface_driven_cylinder}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_surface_loads_match_oracle(name):
+    w = CASES[name]()
     geo = OG.Geometry(w.grid, w.bodies)
     om = np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, 51, count=6), 0.0)
     G = wl.seeded_gammas(geo.nbc, 52, scale=0.3)
