@@ -19,6 +19,18 @@ cpu_baseline leg use the oracle; the library shares none of this code.
   -p n + nu omega s (n: unit normal into the fluid, s = k x n), the
   trapezoid rule over the same closed polygon; a constant added to p
   integrates to zero around the body, so the relative pressure suffices.
+* Control-volume force (Noca's momentum formulation for a stationary
+  obstacle with no-slip walls and a stationary control volume, Sec. 5.4):
+  F = -d/dt int_V u dV - d/dt oint_S x x (n x u) dS + oint_S n . gamma dS,
+  gamma = |u|^2/2 I - u u - u (x x omega k) + x.(div T) I - x (div T) + T,
+  T = nu (grad u + grad u^T).  V is the box minus the body; with div u = 0
+  and u = 0 on the wall, int_V u dV = oint_S x (u.n) dS, so every term is an
+  integral over the box surface S.  The box is a rectangle of grid lines
+  through nodes, integrated by the trapezoid rule along its edges; the
+  derivatives are centred differences of the node values, and
+  div T = nu lap u = nu (-d_y omega, d_x omega).  control_volume_terms returns
+  the two instantaneous parts, S_t = oint_S [x (u.n) + x x (n x u)] dS and
+  S_gamma = oint_S n . gamma dS, so that F = S_gamma - d S_t / dt.
 * A body in steady rigid motion (constant translation, rotation Omega about
   its centre): the rigid motion carries vorticity 2 Omega and no strain, so
   the viscous traction is nu (omega - 2 Omega) s; the wall's centripetal
@@ -111,3 +123,45 @@ def surface_loads(geom, omega, U, V):
     dwdn = grad[:, 0] * geom.c_nx + grad[:, 1] * geom.c_ny
     p, forces = integrate_surface(geom, wb, dwdn)
     return {"omega_b": wb, "tau": geom.grid.nu * wb, "dwdn": dwdn, "p": p, "forces": forces}
+
+
+def control_volume_terms(grid, omega, U, V, box, origin=(0.0, 0.0)):
+    """(S_t, S_gamma) of the control-volume force on the box of nodes
+    i0..i1 x j0..j1 (box = (i0, i1, j0, j1)); U, V: velocity with the one-node
+    ring, [ny+2][nx+2]; omega: [ny][nx]; x measured from `origin`."""
+    i0, i1, j0, j1 = box
+    h, nu = grid.h, grid.nu
+    St = np.zeros(2)
+    Sg = np.zeros(2)
+
+    def node_terms(i, j, n, wgt):
+        x = grid.x0 + i * h - origin[0]
+        y = grid.y0 + j * h - origin[1]
+        u, v = U[j + 1, i + 1], V[j + 1, i + 1]
+        w = omega[j, i]
+        ux_x = (U[j + 1, i + 2] - U[j + 1, i]) / (2 * h)
+        ux_y = (U[j + 2, i + 1] - U[j, i + 1]) / (2 * h)
+        uy_x = (V[j + 1, i + 2] - V[j + 1, i]) / (2 * h)
+        uy_y = (V[j + 2, i + 1] - V[j, i + 1]) / (2 * h)
+        w_x = (omega[j, i + 1] - omega[j, i - 1]) / (2 * h)
+        w_y = (omega[j + 1, i] - omega[j - 1, i]) / (2 * h)
+        T = nu * np.array([[2 * ux_x, ux_y + uy_x], [ux_y + uy_x, 2 * uy_y]])
+        divT = nu * np.array([-w_y, w_x])
+        xv = np.array([x, y])
+        uv = np.array([u, v])
+        un = uv @ n
+        nxu = n[0] * v - n[1] * u                      # k-component of n x u
+        St[:] += wgt * (xv * un + nxu * np.array([y, -x]))
+        g = (0.5 * (u * u + v * v) * n - un * uv - un * w * np.array([y, -x])
+             + (xv @ divT) * n - (n @ xv) * divT + T @ n)
+        Sg[:] += wgt * g
+
+    edges = [((i0, j0), (1, 0), i1 - i0, np.array([0.0, -1.0])),   # bottom
+             ((i1, j0), (0, 1), j1 - j0, np.array([1.0, 0.0])),    # right
+             ((i0, j1), (1, 0), i1 - i0, np.array([0.0, 1.0])),    # top
+             ((i0, j0), (0, 1), j1 - j0, np.array([-1.0, 0.0]))]   # left
+    for (a, b), (di, dj), m, n in edges:
+        for k in range(m + 1):
+            wgt = h * (0.5 if k in (0, m) else 1.0)
+            node_terms(a + k * di, b + k * dj, n, wgt)
+    return St, Sg
