@@ -183,8 +183,6 @@ const char* iim_last_error(const iim_ctx* ctx);
 int iim_query(const iim_ctx* ctx, iim_info* out);
 int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
 
-/* Largest stable time step on the RK3 stability triangle of App. B for a
- * velocity bound a_max = max(|u_x| + |u_y|). */
 /* Surface loads of the bodies (Sec. 5.4): shear stress tau = nu omega_b and the
  * surface pressure from the vorticity flux, d p / d s = nu d omega / d n on a
  * stationary no-slip wall, integrated along each body's control points in the
@@ -205,6 +203,32 @@ int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
  * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts. */
 int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                       double* point_host, double* body_host);
+
+/* Control-volume force on the bodies inside a box (Sec. 5.4, Noca's momentum
+ * formulation for stationary obstacles with no-slip walls and a stationary
+ * control volume):
+ *   F = S_gamma - d S_t / dt,
+ *   S_t     = oint_S [x (u.n) + x x (n x u)] dS,
+ *   S_gamma = oint_S n . [|u|^2/2 I - u u - u (x x omega k) + x.(div T) I
+ *                         - x (div T) + T] dS,   T = nu (grad u + grad u^T),
+ * where the volume integral of u over the box minus the bodies is written as
+ * oint_S x (u.n) dS (div u = 0, u = 0 on the walls).  S is the rectangle of
+ * grid lines through the nodes i0..i1 x j0..j1 (box = {i0, i1, j0, j1}), n its
+ * outward normal, the trapezoid rule along its edges; derivatives are centred
+ * differences of the node values, div T = nu (-d_y omega, d_x omega); x is
+ * measured from origin_host[2].  The caller forms d S_t / dt from the values
+ * at successive times.  Inputs on the device: omega [ny][nx], u and v on the
+ * ring [ny+2][nx+2] as iim_reconstruct writes them.  Output on the host:
+ * out_host[4] = (S_t x, S_t y, S_gamma x, S_gamma y).  Synchronises the
+ * stream.  IIM_EINVAL on null arguments, a box outside 1 <= i0 < i1 <= nx-2,
+ * 1 <= j0 < j1 <= ny-2, or a box node or one of its four neighbours that is
+ * not a fluid node (named in iim_last_error); IIM_EUNSUPPORTED for host-only
+ * contexts. */
+int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
+                       const int32_t* box, const double* origin_host, double* out_host);
+
+/* Largest stable time step on the RK3 stability triangle of App. B for a
+ * velocity bound a_max = max(|u_x| + |u_y|). */
 int iim_dt_max(const iim_ctx* ctx, double a_max, double* dt_max_out);
 
 /* Lattice Green's function g(m, n) of the 5-point Laplacian (host, for

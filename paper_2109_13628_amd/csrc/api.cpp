@@ -437,6 +437,7 @@ void setup_device(iim_ctx* c) {
   c->V = c->dalloc<double>(NR);
   c->wb = c->dalloc<double>(g.nc);
   c->sdwdn = c->dalloc<double>(g.nc);
+  c->scv = c->dalloc<double>(4);
   c->w4 = c->dalloc<double>(N);
   c->w3b = c->dalloc<double>(N);
   c->w3n = c->dalloc<double>(N);
@@ -1057,6 +1058,42 @@ int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const do
       point_host[4 * q + 2] = dwdn[q];
       point_host[4 * q + 3] = p[q];
     }
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_cv_force_terms(iim_ctx* c, const double* omega, const double* u, const double* v, const int32_t* box,
+                       const double* origin, double* out_host) {
+  if (!c || !omega || !u || !v || !box || !origin || !out_host) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  const Geometry& g = c->geo;
+  const int nx = g.grid.nx, ny = g.grid.ny;
+  const int i0 = box[0], i1 = box[1], j0 = box[2], j1 = box[3];
+  if (!(1 <= i0 && i0 < i1 && i1 <= nx - 2 && 1 <= j0 && j0 < j1 && j1 <= ny - 2))
+    return fail(c, IIM_EINVAL, "control-volume box outside 1 <= i0 < i1 <= nx-2, 1 <= j0 < j1 <= ny-2");
+  // the centred differences read each box node's four neighbours: all fluid
+  auto fluid5 = [&](int i, int j) {
+    return g.cl(i, j) == CLS_FLUID && g.cl(i - 1, j) == CLS_FLUID && g.cl(i + 1, j) == CLS_FLUID &&
+           g.cl(i, j - 1) == CLS_FLUID && g.cl(i, j + 1) == CLS_FLUID;
+  };
+  for (int i = i0; i <= i1; ++i)
+    for (int j : {j0, j1})
+      if (!fluid5(i, j))
+        return fail(c, IIM_EINVAL, "control-volume box node (" + std::to_string(i) + ", " + std::to_string(j) +
+                                       ") or a neighbour is not a fluid node");
+  for (int j = j0; j <= j1; ++j)
+    for (int i : {i0, i1})
+      if (!fluid5(i, j))
+        return fail(c, IIM_EINVAL, "control-volume box node (" + std::to_string(i) + ", " + std::to_string(j) +
+                                       ") or a neighbour is not a fluid node");
+  try {
+    CvBox b{nx, i0, i1, j0, j1, g.grid.x0, g.grid.y0, g.grid.h, g.grid.nu, origin[0], origin[1]};
+    launch_cv_terms(b, omega, u, v, c->scv, c->stream);
+    HIPCHK(hipMemcpyAsync(out_host, c->scv, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
   }

@@ -81,6 +81,7 @@ struct iim_ctx {
   double *psi = nullptr, *U = nullptr, *V = nullptr;
   double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
   double* sdwdn = nullptr;        // d omega / dn at the control points (surface loads)
+  double* scv = nullptr;          // control-volume force terms (4 values)
   double *Qw = nullptr, *wtmp = nullptr, *wtmp2 = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
   bool have_prev = false;

@@ -300,6 +300,16 @@ void launch_unit(double* v, int n, int q, hipStream_t s);
 // d omega / dn at every control point: the boundary-vorticity stencil's d_x
 // and d_y parts applied to omega extended with E3b at the ghosts (w3b), with
 // omega_b (wb) as the boundary value, projected on the normal into the fluid.
+// Control-volume force box: nodes i0..i1 x j0..j1 of an nx-wide grid (node
+// (i, j) at (x0 + i h, y0 + j h)), x measured from (ox, oy).
+struct CvBox {
+  int nx, i0, i1, j0, j1;
+  double x0, y0, h, nu, ox, oy;
+};
+// out[4] = (S_t x, S_t y, S_gamma x, S_gamma y) of the box (device); the box
+// and its nodes' four neighbours must lie inside the grid.
+void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const double* V, double* out,
+                     hipStream_t s);
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s);
 

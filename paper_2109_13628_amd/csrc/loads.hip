@@ -1,5 +1,6 @@
-// HIP kernel of the surface-load diagnostics (Sec. 5.4): the vorticity
-// gradient at the control points.  Outside the time step's hot path.
+// HIP kernels of the load diagnostics (Sec. 5.4): the vorticity gradient at
+// the control points, and the box integrals of the control-volume force.
+// Outside the time step's hot path.
 #include <hip/hip_runtime.h>
 
 #include "iim_dev.hpp"
@@ -30,6 +31,66 @@ __global__ void k_surface_dwdn(DGeom g, const double* __restrict__ omega, const 
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s) {
   if (g.nc) k_surface_dwdn<<<(g.nc + 127) / 128, 128, 0, s>>>(g, omega, w3b, wb, dwdn);
+}
+
+// Control-volume force terms on the rectangle of grid lines through the
+// nodes i0..i1 x j0..j1: one workgroup walks the perimeter (bottom, right,
+// top, left edge; trapezoid weights, corners in both their edges), each lane
+// summing the terms of its nodes, then a fixed-order tree sum in LDS.
+// out = (S_t x, S_t y, S_gamma x, S_gamma y).
+constexpr int CV_THREADS = 256;
+
+__global__ void __launch_bounds__(CV_THREADS)
+    k_cv_terms(CvBox b, const double* __restrict__ omega, const double* __restrict__ U,
+               const double* __restrict__ V, double* __restrict__ out) {
+  const int mi = b.i1 - b.i0, mj = b.j1 - b.j0;
+  const int np = 2 * (mi + 1) + 2 * (mj + 1);
+  const int nxr = b.nx + 2;
+  const double h = b.h, nu = b.nu, i2h = 0.5 / b.h;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < np; p += CV_THREADS) {
+    int i, j, k, m;
+    double nx, ny;
+    if (p <= mi) {
+      k = p, m = mi, i = b.i0 + k, j = b.j0, nx = 0.0, ny = -1.0;
+    } else if (p <= mi + 1 + mj) {
+      k = p - (mi + 1), m = mj, i = b.i1, j = b.j0 + k, nx = 1.0, ny = 0.0;
+    } else if (p <= 2 * mi + 2 + mj) {
+      k = p - (mi + 2 + mj), m = mi, i = b.i0 + k, j = b.j1, nx = 0.0, ny = 1.0;
+    } else {
+      k = p - (2 * mi + 3 + mj), m = mj, i = b.i0, j = b.j0 + k, nx = -1.0, ny = 0.0;
+    }
+    const double wgt = (k == 0 || k == m) ? 0.5 * h : h;
+    const double x = b.x0 + i * h - b.ox, y = b.y0 + j * h - b.oy;
+    const size_t r = (size_t)(j + 1) * nxr + (i + 1), q = (size_t)j * b.nx + i;
+    const double u = U[r], v = V[r], w = omega[q];
+    const double ux_x = (U[r + 1] - U[r - 1]) * i2h, ux_y = (U[r + nxr] - U[r - nxr]) * i2h;
+    const double uy_x = (V[r + 1] - V[r - 1]) * i2h, uy_y = (V[r + nxr] - V[r - nxr]) * i2h;
+    const double w_x = (omega[q + 1] - omega[q - 1]) * i2h, w_y = (omega[q + b.nx] - omega[q - b.nx]) * i2h;
+    const double dtx = -nu * w_y, dty = nu * w_x;                  // div T = nu lap u
+    const double sh = ux_y + uy_x;
+    const double un = u * nx + v * ny;
+    const double nxu = nx * v - ny * u;                            // n x u (k component)
+    acc[0] += wgt * (x * un + nxu * y);
+    acc[1] += wgt * (y * un - nxu * x);
+    const double ke = 0.5 * (u * u + v * v), xd = x * dtx + y * dty, nxx = nx * x + ny * y;
+    acc[2] += wgt * (ke * nx - un * u - un * w * y + xd * nx - nxx * dtx + nu * (2.0 * ux_x * nx + sh * ny));
+    acc[3] += wgt * (ke * ny - un * v + un * w * x + xd * ny - nxx * dty + nu * (sh * nx + 2.0 * uy_y * ny));
+  }
+  __shared__ double red[4][CV_THREADS];
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int s = CV_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const double* V, double* out,
+                     hipStream_t s) {
+  k_cv_terms<<<1, CV_THREADS, 0, s>>>(b, omega, U, V, out);
 }
 
 }  // namespace iim

@@ -1,9 +1,12 @@
 """Long validation run (not collected by pytest): the side-by-side cylinder
 pair of Sec. 6 at Re = 100, L/D = 3, started from rest, which sheds in
 antiphase.  The paper tabulates the long-time drag and lift statistics of
-each cylinder (mean C_D, mean C_L, RMS C_L, with C = 2F/(D U^2)), computed from
-the surface loads (Sec. 5.4): the library's surface pressure, shear, force
-and torque are sampled every few steps of the FP64 dense-solve time step.
+each cylinder (mean C_D, mean C_L, RMS C_L, with C = 2F/(D U^2)).  The forces
+come from the surface loads (Sec. 5.4: surface pressure from the vorticity
+flux, shear), sampled every few steps of the FP64 dense-solve time step, and
+for comparison from the control-volume formulation of the same section on a
+box around each cylinder (its time derivative by central differences of the
+samples).
 
 The run prints one progress line about every 20 s and writes the force
 history and the statistics as JSON, with the paper's row for the same
@@ -83,6 +86,14 @@ def main():
     U, V = torch.zeros_like(psi), torch.zeros_like(psi)
     n_total = int(round(a.t_end / a.dt))
     hist = []
+    # control-volume boxes: 0.3 D upstream, 1 D downstream, 0.3 D beyond the
+    # outer side, 0.3 D from the centre line between the cylinders
+    def box(x0, x1, y0, y1):
+        return (int(round((x0 - g.x0) / g.h)), int(round((x1 - g.x0) / g.h)),
+                int(round((y0 - g.y0) / g.h)), int(round((y1 - g.y0) / g.h)))
+    half = 0.5 * a.gap
+    boxes = [box(0.2, 2.5, -half - 0.8, -0.3), box(0.2, 2.5, 0.3, half + 0.8)]
+    cv = []
     step_s = load_s = 0.0
     last = time.time()
     n = 0
@@ -95,6 +106,8 @@ def main():
         s1 = time.perf_counter()
         ctx.reconstruct(om, G, psi, U, V)
         L = ctx.surface_loads(om, U, V)
+        cv.append([np.concatenate([q["S_t"], q["S_gamma"]]) for q in
+                   (ctx.cv_force_terms(om, U, V, b, w.bodies[k].center) for k, b in enumerate(boxes))])
         s2 = time.perf_counter()
         step_s += s1 - s0
         load_s += s2 - s1
@@ -109,11 +122,19 @@ def main():
                   % (n * a.dt, hist[-1][1], hist[-1][2], hist[-1][3], hist[-1][4], 1e3 * step_s / n), flush=True)
     H = np.array(hist)
     t = H[:, 0]
+    # control-volume forces at the interior samples: F = S_gamma - d S_t / dt
+    Cv = np.array(cv)                                   # [sample][body][S_t x, y, S_gamma x, y]
+    dts = a.every * a.dt
+    Fcv = 2.0 * (Cv[1:-1, :, 2:] - (Cv[2:, :, :2] - Cv[:-2, :, :2]) / (2 * dts))
+    tc = t[1:-1]
     res = {"workload": w.name, "Re": a.re, "L/D": a.gap, "D/h": a.d_over_h, "dt": a.dt, "t_end": a.t_end,
            "avg_from": a.avg_from, "N_delta": a.d_over_h / math.sqrt(a.re), "Q": a.re ** 1.5 / a.d_over_h ** 2,
            "fft_tiles": tune, "ms_per_step": 1e3 * step_s / n,
            "ms_per_load_sample": 1e3 * load_s / len(hist),
-           "lower": stats(t, H[:, 1], H[:, 2], a.avg_from), "upper": stats(t, H[:, 3], H[:, 4], a.avg_from)}
+           "lower": stats(t, H[:, 1], H[:, 2], a.avg_from), "upper": stats(t, H[:, 3], H[:, 4], a.avg_from),
+           "control_volume": {"boxes": boxes,
+                              "lower": stats(tc, Fcv[:, 0, 0], Fcv[:, 0, 1], a.avg_from),
+                              "upper": stats(tc, Fcv[:, 1, 0], Fcv[:, 1, 1], a.avg_from)}}
     sel = t >= a.avg_from
     res["lift_correlation"] = float(np.corrcoef(H[sel, 2], H[sel, 4])[0, 1]) if sel.sum() > 2 else None
     # the paper's row for these parameters (antiphase: the lifts are mirror images)
@@ -129,7 +150,8 @@ def main():
                 "C_L_mean": abs(lo["C_L_mean"]) / r["C_L_mean"] - 1.0,
                 "C_L_rms_about_mean": lo["C_L_rms_about_mean"] / r["C_L_rms"] - 1.0}
     res["history"] = {"t": t.tolist(), "CD_lower": H[:, 1].tolist(), "CL_lower": H[:, 2].tolist(),
-                      "CD_upper": H[:, 3].tolist(), "CL_upper": H[:, 4].tolist()}
+                      "CD_upper": H[:, 3].tolist(), "CL_upper": H[:, 4].tolist(),
+                      "t_cv": tc.tolist(), "CD_lower_cv": Fcv[:, 0, 0].tolist(), "CL_lower_cv": Fcv[:, 0, 1].tolist()}
     with open(a.out, "w") as f:
         json.dump(res, f)
     brief = {k: v for k, v in res.items() if k != "history"}
