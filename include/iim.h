@@ -223,7 +223,8 @@ int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev
  * stream.  IIM_EINVAL on null arguments, a box outside 1 <= i0 < i1 <= nx-2,
  * 1 <= j0 < j1 <= ny-2, or a box node or one of its four neighbours that is
  * not a fluid node (named in iim_last_error); IIM_EUNSUPPORTED for host-only
- * contexts. */
+ * contexts and when a body with a control point inside the box moves (rigid
+ * motion or boundary samples: the formulation is for stationary walls). */
 int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                        const int32_t* box, const double* origin_host, double* out_host);
 

@@ -1088,6 +1088,16 @@ int iim_cv_force_terms(iim_ctx* c, const double* omega, const double* u, const d
       if (!fluid5(i, j))
         return fail(c, IIM_EINVAL, "control-volume box node (" + std::to_string(i) + ", " + std::to_string(j) +
                                        ") or a neighbour is not a fluid node");
+  // the formulation assumes stationary no-slip walls inside the box
+  const double bx0 = g.grid.x0 + i0 * g.grid.h, bx1 = g.grid.x0 + i1 * g.grid.h;
+  const double by0 = g.grid.y0 + j0 * g.grid.h, by1 = g.grid.y0 + j1 * g.grid.h;
+  for (int q = 0; q < g.nc; ++q) {
+    if (g.c_x[q] < bx0 || g.c_x[q] > bx1 || g.c_y[q] < by0 || g.c_y[q] > by1) continue;
+    const BodySpec& bs = g.bodies[g.c_body[q]];
+    if (!bs.samples.empty() || bs.u_rigid[0] != 0.0 || bs.u_rigid[1] != 0.0 || bs.omega != 0.0)
+      return fail(c, IIM_EUNSUPPORTED, "control-volume force: body " + std::to_string(g.c_body[q]) +
+                                           " inside the box is not a stationary wall");
+  }
   try {
     CvBox b{nx, i0, i1, j0, j1, g.grid.x0, g.grid.y0, g.grid.h, g.grid.nu, origin[0], origin[1]};
     launch_cv_terms(b, omega, u, v, c->scv, c->stream);

@@ -2,7 +2,10 @@
 GPU against the FP64 oracle: from the same velocity and vorticity (1e-12 of
 the largest term), and end to end from the oracle's own reconstruction (the
 1e-11 velocity agreement carried through one difference at spacing h: 1e-9).
-Boxes that leave the grid or touch the body are rejected."""
+Boxes that leave the grid or touch the body, and moving bodies inside the
+box, are rejected."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -69,4 +72,11 @@ def test_cv_box_checks():
     with pytest.raises(iim.IIMError) as e:
         ctx.cv_force_terms(om, U, V, (ic, ic + 30, 10, 80))
     assert e.value.code == iim.IIM_EINVAL and "fluid" in str(e.value)
+    ctx.close()
+    # a rotating body inside the box: not a stationary wall
+    b = dataclasses.replace(w.bodies[0], omega_rigid=0.5)
+    ctx = iim.Context(w.grid, [b], solver=iim.SOLVER_DIRECT)
+    with pytest.raises(iim.IIMError) as e:
+        ctx.cv_force_terms(om, U, V, _box(w.grid, 0.7, 2.4, -0.8, 0.8))
+    assert e.value.code == iim.IIM_EUNSUPPORTED
     ctx.close()
