@@ -15,6 +15,7 @@ parameters and shedding mode (tests/golden/side_by_side_statistics.json):
     python tests/long_side_by_side.py --t-end 200 --avg-from 120 --out sbs.json
 """
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -62,6 +63,9 @@ def main():
     p.add_argument("--t-end", type=float, default=200.0)
     p.add_argument("--avg-from", type=float, default=120.0)
     p.add_argument("--every", type=int, default=20, help="time steps between load samples")
+    p.add_argument("--perturb-v", type=float, default=0.0,
+                   help="cross-stream free-stream component until --perturb-until (breaks the mirror symmetry)")
+    p.add_argument("--perturb-until", type=float, default=0.0)
     p.add_argument("--out", default="side_by_side.json")
     a = p.parse_args()
 
@@ -71,6 +75,12 @@ def main():
     t0 = time.time()
     ctx = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
     tune = ctx.autotune()
+    pert = None
+    if a.perturb_v != 0.0 and a.perturb_until > 0.0:
+        # the same run with the free stream (1, perturb_v) until perturb_until
+        gp = dataclasses.replace(g, u_inf=(g.u_inf[0], a.perturb_v))
+        pert = iim.Context(gp, w.bodies, solver=iim.SOLVER_DIRECT)
+        pert.set_fft_shape(tune["row_per"], tune["col_per"])
     dt_max = ctx.dt_max(2.0 * math.sqrt(2.0))
     if a.dt > dt_max:
         raise SystemExit("dt %.3g above the stability limit %.3g" % (a.dt, dt_max))
@@ -99,15 +109,23 @@ def main():
     n = 0
     while n < n_total:
         k = min(a.every, n_total - n)
+        cur = ctx
+        if pert is not None:
+            if n * a.dt < a.perturb_until:
+                cur = pert
+                k = min(k, max(1, int(round(a.perturb_until / a.dt)) - n))
+            else:
+                pert.close()
+                pert = None
         torch.cuda.synchronize()
         s0 = time.perf_counter()
-        G, _ = ctx.rk3_steps(om, G, a.dt, k)
+        G, _ = cur.rk3_steps(om, G, a.dt, k)
         torch.cuda.synchronize()
         s1 = time.perf_counter()
-        ctx.reconstruct(om, G, psi, U, V)
-        L = ctx.surface_loads(om, U, V)
+        cur.reconstruct(om, G, psi, U, V)
+        L = cur.surface_loads(om, U, V)
         cv.append([np.concatenate([q["S_t"], q["S_gamma"]]) for q in
-                   (ctx.cv_force_terms(om, U, V, b, w.bodies[k].center) for k, b in enumerate(boxes))])
+                   (cur.cv_force_terms(om, U, V, b, w.bodies[q].center) for q, b in enumerate(boxes))])
         s2 = time.perf_counter()
         step_s += s1 - s0
         load_s += s2 - s1
@@ -124,10 +142,11 @@ def main():
     t = H[:, 0]
     # control-volume forces at the interior samples: F = S_gamma - d S_t / dt
     Cv = np.array(cv)                                   # [sample][body][S_t x, y, S_gamma x, y]
-    dts = a.every * a.dt
-    Fcv = 2.0 * (Cv[1:-1, :, 2:] - (Cv[2:, :, :2] - Cv[:-2, :, :2]) / (2 * dts))
+    span = (t[2:] - t[:-2])[:, None, None]
+    Fcv = 2.0 * (Cv[1:-1, :, 2:] - (Cv[2:, :, :2] - Cv[:-2, :, :2]) / span)
     tc = t[1:-1]
     res = {"workload": w.name, "Re": a.re, "L/D": a.gap, "D/h": a.d_over_h, "dt": a.dt, "t_end": a.t_end,
+           "perturbation": {"v": a.perturb_v, "until": a.perturb_until},
            "avg_from": a.avg_from, "N_delta": a.d_over_h / math.sqrt(a.re), "Q": a.re ** 1.5 / a.d_over_h ** 2,
            "fft_tiles": tune, "ms_per_step": 1e3 * step_s / n,
            "ms_per_load_sample": 1e3 * load_s / len(hist),
