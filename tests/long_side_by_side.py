@@ -1,6 +1,6 @@
 """Long validation run (not collected by pytest): the side-by-side cylinder
-pair of Sec. 6 at Re = 100, L/D = 3, started from rest, which sheds in
-antiphase.  The paper tabulates the long-time drag and lift statistics of
+pair of Sec. 6 (by default Re = 100, L/D = 3), started from rest, which sheds
+in antiphase.  The paper tabulates the long-time drag and lift statistics of
 each cylinder (mean C_D, mean C_L, RMS C_L, with C = 2F/(D U^2)).  The forces
 come from the surface loads (Sec. 5.4: surface pressure from the vorticity
 flux, shear), sampled every few steps of the FP64 dense-solve time step, and
@@ -12,7 +12,10 @@ The run prints one progress line about every 20 s and writes the force
 history and the statistics as JSON, with the paper's row for the same
 parameters and shedding mode (tests/golden/side_by_side_statistics.json):
 
-    python tests/long_side_by_side.py --t-end 200 --avg-from 120 --out sbs.json
+    python tests/long_side_by_side.py --t-end 300 --avg-from 150 --out sbs.json
+
+Other rows of the table: --re 160 and/or --gap 4; in-phase shedding from a
+free stream perturbed across until t = 10: --perturb-v 0.2 --perturb-until 10.
 """
 import argparse
 import dataclasses
