@@ -381,20 +381,35 @@ class Geometry:
                 ub[m] = _cubic(tuple(cc[seg] for cc in cu), s)
                 psib[m] = _cubic(tuple(cc[seg] for cc in cp), s)[:, 0]
                 continue
-            cx, cy = b.center
-            U = np.asarray(b.u_rigid, dtype=np.float64)
-            Om = float(b.omega_rigid)
-            dx, dy = self.c_x[m] - cx, self.c_y[m] - cy
-            ub[m, 0] = U[0] - Om * dy
-            ub[m, 1] = U[1] + Om * dx
-            # stream function of the rigid motion (u = d_y psi, v = -d_x psi)
-            psib[m] = U[0] * self.c_y[m] - U[1] * self.c_x[m] - 0.5 * Om * (dx * dx + dy * dy)
+            ub[m], psib[m] = self._rigid_data(m, b.center, b.u_rigid, b.omega_rigid)
         if self._bc_override is not None:
             psi_fn, u_fn = self._bc_override
             psib = np.asarray(psi_fn(self.c_x, self.c_y), dtype=np.float64)
             ub = np.stack(u_fn(self.c_x, self.c_y), axis=1).astype(np.float64)
         self.c_ub = ub
         self.c_psib = psib
+
+    def _rigid_data(self, m, center, u_rigid, omega):
+        """u_b and psi_b of the rigid motion u_rigid + omega k x (x - center)
+        at the control points selected by m."""
+        U = np.asarray(u_rigid, dtype=np.float64)
+        Om = float(omega)
+        dx, dy = self.c_x[m] - center[0], self.c_y[m] - center[1]
+        ub = np.stack([U[0] - Om * dy, U[1] + Om * dx], axis=1)
+        # stream function of the rigid motion (u = d_y psi, v = -d_x psi)
+        psib = U[0] * self.c_y[m] - U[1] * self.c_x[m] - 0.5 * Om * (dx * dx + dy * dy)
+        return ub, psib
+
+    def set_rigid_motion(self, motions):
+        """Boundary data of a time-dependent rigid motion: motions[k] =
+        (u_x, u_y, omega) of body k at the current time (bodies with boundary
+        samples are not allowed)."""
+        for k, b in enumerate(self.bodies):
+            if getattr(b, "bc_samples", None) is not None:
+                raise ValueError("body %d has prescribed boundary samples" % k)
+            m = self.c_body == k
+            ux, uy, om = motions[k]
+            self.c_ub[m], self.c_psib[m] = self._rigid_data(m, b.center, (ux, uy), om)
 
     # ------------------------------------------------------------------
     def _build_sets(self):

@@ -35,6 +35,17 @@ def rk3_williamson(state, rhs, dt):
     return state
 
 
+def rk3_stage_times():
+    """Times of the three stages within a step, in units of dt: the same
+    recurrences applied to the time itself (d t / d t = 1)."""
+    t, q, c = 0.0, 0.0, []
+    for s in range(3):
+        c.append(t)
+        q = RK_A[s] * q + 1.0
+        t = t + RK_B[s] * q
+    return c
+
+
 def dt_max(h, nu, a_max):
     return 1.0 / (a_max / (1.620 * h) + nu / (0.314 * h * h))
 
@@ -65,11 +76,21 @@ class Stepper:
         dw, dG, wb, _ = transport.rhs(self.geom, omega, rec.U, rec.V, self.nu)
         return dw, dG, rec, x, info
 
-    def step(self, omega, Gamma, dt, record=None):
+    def set_motion(self, motions):
+        """Rigid motion (u_x, u_y, omega) of every body from now on."""
+        self.geom.set_rigid_motion(motions)
+        self.rec.psib_t = self.geom.psi_tilde_b()
+
+    def step(self, omega, Gamma, dt, record=None, motion=None, t=0.0):
+        """One RK3 step from time t; motion: optional function of time giving
+        the rigid motion of every body, applied at each stage's time."""
         omega = np.where(self.geom.fluid, omega, 0.0)
         last = {"x": None}
+        c = rk3_stage_times()
 
         def rhs(state, s):
+            if motion is not None:
+                self.set_motion(motion(t + c[s] * dt))
             w, G = state
             dw, dG, rec, x, info = self.stage(w, G, x0=last["x"])
             last["x"] = x
