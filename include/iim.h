@@ -228,6 +228,28 @@ int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev
 int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                        const int32_t* box, const double* origin_host, double* out_host);
 
+/* Time-dependent rigid motion of the bodies (Sec. 2: the boundary data u_b and
+ * psi_b of each body's motion u + omega k x (x - centre) about its centre).
+ * iim_set_body_motion sets motion_host[n_bodies][3] = (u_x, u_y, omega), in
+ * the order of the bodies given to iim_create, for the calls that follow
+ * (iim_reconstruct, iim_rhs, iim_rk3_steps).  iim_rk3_steps_moving runs
+ * n_steps RK3 steps with the motion given at every stage's time:
+ * motion_host[n_steps][3][n_bodies][3], stage s of step n at
+ * t_n + c_s dt with c = (0, 1/3, 3/4), the stage times of the low-storage
+ * RK3; afterwards the last stage's motion stays set.  The first call switches
+ * the context for good from the composed boundary forms to the chained
+ * boundary kernels (which read the boundary-data tables) and to steps without
+ * the captured graph; results equal those of a fixed rigid motion when the
+ * motion is constant.  Synchronises the stream after every step.
+ * IIM_EINVAL on null or non-finite arguments, dt <= 0 or n_steps < 0;
+ * IIM_EUNSUPPORTED for host-only contexts and for bodies with bc_samples.
+ * After either call iim_surface_loads returns IIM_EUNSUPPORTED (its
+ * traction assumes steady motion) and iim_cv_force_terms takes the current
+ * motion to decide which bodies move. */
+int iim_set_body_motion(iim_ctx* ctx, const double* motion_host);
+int iim_rk3_steps_moving(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt, int32_t n_steps,
+                         const double* motion_host, iim_step_stats* stats);
+
 /* Largest stable time step on the RK3 stability triangle of App. B for a
  * velocity bound a_max = max(|u_x| + |u_y|). */
 int iim_dt_max(const iim_ctx* ctx, double a_max, double* dt_max_out);

@@ -26,7 +26,7 @@ NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
-EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_force_terms", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
+EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_force_terms", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_poisson_fp32", "iim_reconstruct", "iim_rhs",
            "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay", "iim_solver_counters",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
@@ -150,6 +150,10 @@ def lib():
     L.iim_surface_loads.restype = ip
     L.iim_surface_loads.argtypes = [vp, vp, vp, vp, dp, dp]
     L.iim_cv_force_terms.restype = ip
+    L.iim_set_body_motion.restype = ip
+    L.iim_set_body_motion.argtypes = [vp, dp]
+    L.iim_rk3_steps_moving.restype = ip
+    L.iim_rk3_steps_moving.argtypes = [vp, vp, dp, C.c_double, C.c_int32, dp, vp]
     L.iim_cv_force_terms.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int32), dp, dp]
     L.iim_rk3_step.restype = ip
     L.iim_rk3_step.argtypes = [vp, vp, dp, C.c_double, C.POINTER(StepStats)]
@@ -394,6 +398,29 @@ class Context:
         st = StepStats()
         self._check(lib().iim_rk3_steps(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                         n_steps, C.byref(st)), "iim_rk3_steps")
+        return G[:self.n_circ], st.as_dict()
+
+    def set_body_motion(self, motion):
+        """Rigid motion (u_x, u_y, omega) of every body from now on."""
+        m = np.ascontiguousarray(motion, dtype=np.float64).reshape(-1)
+        if m.size != 3 * self.n_bodies:
+            raise ValueError("expected (u_x, u_y, omega) for each of %d bodies" % self.n_bodies)
+        self._check(lib().iim_set_body_motion(self._h, m.ctypes.data_as(C.POINTER(C.c_double))),
+                    "iim_set_body_motion")
+
+    def rk3_steps_moving(self, omega, Gamma, dt, motion):
+        """RK3 steps with the bodies' rigid motion at every stage's time:
+        motion[n_steps][3][n_bodies][3] = (u_x, u_y, omega)."""
+        m = np.ascontiguousarray(motion, dtype=np.float64)
+        if m.ndim != 4 or m.shape[1:] != (3, self.n_bodies, 3):
+            raise ValueError("expected motion of shape (n_steps, 3, %d, 3)" % self.n_bodies)
+        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).copy()
+        if G.size == 0:
+            G = np.zeros(1)
+        st = StepStats()
+        self._check(lib().iim_rk3_steps_moving(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
+                                               m.shape[0], m.ctypes.data_as(C.POINTER(C.c_double)),
+                                               C.byref(st)), "iim_rk3_steps_moving")
         return G[:self.n_circ], st.as_dict()
 
     # ---- learned initial guess

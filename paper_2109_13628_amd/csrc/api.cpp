@@ -649,6 +649,72 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   return IIM_OK;
 }
 
+// Boundary-data tables of a rigid motion m[n_bodies][3] = (u_x, u_y, omega)
+// about each body's centre, laid out [psi_b - psi_inf (nc) | u_b (2 nc) |
+// boundary-velocity part of omega_b (nc) | B (psi_b - psi_inf) (na)], the same
+// construction as at set-up.
+void motion_tables(iim_ctx* c, const double* m, std::vector<double>& out) {
+  const Geometry& g = c->geo;
+  const int nc = g.nc, na = g.na;
+  out.assign((size_t)4 * nc + na, 0.0);
+  double* psibt = out.data();
+  double* ub = psibt + nc;
+  double* wbc = ub + 2 * nc;
+  double* bpsi = wbc + nc;
+  for (int q = 0; q < nc; ++q) {
+    const int k = g.c_body[q];
+    const double ux = m[3 * k], uy = m[3 * k + 1], om = m[3 * k + 2];
+    const double dx = g.c_x[q] - g.bodies[k].center[0], dy = g.c_y[q] - g.bodies[k].center[1];
+    ub[2 * q] = ux - om * dy;
+    ub[2 * q + 1] = uy + om * dx;
+    const double psib = ux * g.c_y[q] - uy * g.c_x[q] - 0.5 * om * (dx * dx + dy * dy);
+    psibt[q] = psib - (c->dg.uinf_x * g.c_y[q] - c->dg.uinf_y * g.c_x[q]);
+  }
+  for (int q = 0; q < nc; ++q)
+    for (int e = g.wbc.bptr[q]; e < g.wbc.bptr[q + 1]; ++e)
+      wbc[q] += g.wbc.bw[e] * ub[2 * g.wbc.bc[e] + g.wbc.bcomp[e]];
+  for (int a = 0; a < na; ++a)
+    for (int e = g.aop.bptr[a]; e < g.aop.bptr[a + 1]; ++e) bpsi[a] += g.aop.bw[e] * psibt[g.aop.bc[e]];
+}
+
+// Stream-ordered copy of motion tables into the device tables; the host
+// vector must stay untouched until the stream has passed the copies.
+void upload_motion(iim_ctx* c, const std::vector<double>& v) {
+  const int nc = c->geo.nc, na = c->geo.na;
+  DGeom& d = c->dg;
+  const double* p = v.data();
+  if (nc) {
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(d.c_psibt), p, nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(d.c_ub), p + nc, 2 * nc * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(d.wb_const), p + 3 * nc, nc * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+  }
+  if (na)
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(d.bpsi), p + 4 * nc, na * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+}
+
+// Switch a context to time-dependent rigid motion: the composed boundary
+// forms carry the set-up boundary data in their constants, so the chained
+// boundary kernels (which read the tables) take over, and steps run eagerly.
+int enter_motion_mode(iim_ctx* c) {
+  for (size_t k = 0; k < c->geo.bodies.size(); ++k)
+    if (!c->geo.bodies[k].samples.empty())
+      return fail(c, IIM_EUNSUPPORTED, "time-dependent motion: body " + std::to_string(k) +
+                                           " has prescribed boundary samples");
+  if (!c->motion_mode) {
+    c->motion_mode = true;
+    c->bnd_ok = false;
+    c->use_graph = false;
+    if (c->gexec) {
+      HIPCHK(hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+  }
+  return IIM_OK;
+}
+
 }  // namespace
 
 int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
@@ -669,6 +735,13 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
     double* out = bufs[s + 1];
     int it;
     double r0, r1;
+    if (c->motion_stage) {
+      // boundary data of the rigid motion at this stage's time
+      const size_t nb = c->geo.bodies.size();
+      motion_tables(c, c->motion_stage + 3 * nb * s, c->motion_buf[s]);
+      upload_motion(c, c->motion_buf[s]);
+      c->motion_now.assign(c->motion_stage + 3 * nb * s, c->motion_stage + 3 * nb * (s + 1));
+    }
     c->cur_stage = s;
     const int rc = reconstruct_stage(c, in, c->Gd, it, r0, r1, !c->bnd_ok);
     c->cur_stage = -1;
@@ -997,6 +1070,8 @@ int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const do
                       double* body_host) {
   if (!c || !omega || !u || !v || !point_host || !body_host) return IIM_EINVAL;
   if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  if (c->motion_mode)
+    return fail(c, IIM_EUNSUPPORTED, "surface loads assume steady rigid motion (time-dependent motion was set)");
   try {
     const Geometry& g = c->geo;
     const int nc = g.nc;
@@ -1093,8 +1168,12 @@ int iim_cv_force_terms(iim_ctx* c, const double* omega, const double* u, const d
   const double by0 = g.grid.y0 + j0 * g.grid.h, by1 = g.grid.y0 + j1 * g.grid.h;
   for (int q = 0; q < g.nc; ++q) {
     if (g.c_x[q] < bx0 || g.c_x[q] > bx1 || g.c_y[q] < by0 || g.c_y[q] > by1) continue;
-    const BodySpec& bs = g.bodies[g.c_body[q]];
-    if (!bs.samples.empty() || bs.u_rigid[0] != 0.0 || bs.u_rigid[1] != 0.0 || bs.omega != 0.0)
+    const int k = g.c_body[q];
+    const BodySpec& bs = g.bodies[k];
+    const double* m = c->motion_mode ? &c->motion_now[3 * k] : nullptr;
+    const bool moving = m ? (m[0] != 0.0 || m[1] != 0.0 || m[2] != 0.0)
+                          : (!bs.samples.empty() || bs.u_rigid[0] != 0.0 || bs.u_rigid[1] != 0.0 || bs.omega != 0.0);
+    if (moving)
       return fail(c, IIM_EUNSUPPORTED, "control-volume force: body " + std::to_string(g.c_body[q]) +
                                            " inside the box is not a stationary wall");
   }
@@ -1152,6 +1231,51 @@ int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int3
     return fail(c, e.code, e.what());
   }
   return IIM_OK;
+}
+
+int iim_set_body_motion(iim_ctx* c, const double* motion) {
+  if (!c || !motion) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  const size_t nb = c->geo.bodies.size();
+  for (size_t q = 0; q < 3 * nb; ++q)
+    if (!std::isfinite(motion[q])) return fail(c, IIM_EINVAL, "non-finite body motion");
+  try {
+    const int rc = enter_motion_mode(c);
+    if (rc != IIM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    motion_tables(c, motion, c->motion_buf[0]);
+    upload_motion(c, c->motion_buf[0]);
+    c->motion_now.assign(motion, motion + 3 * nb);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
+int iim_rk3_steps_moving(iim_ctx* c, double* omega, double* Gamma_host, double dt, int32_t n_steps,
+                         const double* motion, iim_step_stats* stats) {
+  if (!c || !omega || !motion || (c->geo.nbc() > 0 && !Gamma_host) || !(dt > 0) || n_steps < 0) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  const size_t nb = c->geo.bodies.size();
+  for (size_t q = 0; q < (size_t)n_steps * 9 * nb; ++q)
+    if (!std::isfinite(motion[q])) return fail(c, IIM_EINVAL, "non-finite body motion");
+  int rc = IIM_OK;
+  try {
+    rc = enter_motion_mode(c);
+    if (rc != IIM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  // one step at a time: each synchronises the stream (host circulations),
+  // so the per-stage staging vectors are free again before the next step
+  for (int s = 0; s < n_steps && rc == IIM_OK; ++s) {
+    c->motion_stage = motion + (size_t)s * 9 * nb;
+    rc = iim_rk3_steps(c, omega, Gamma_host, dt, 1, stats);
+    c->motion_stage = nullptr;
+  }
+  return rc;
 }
 
 int iim_profile(iim_ctx* c, int32_t kernel_mask) {

@@ -82,6 +82,14 @@ struct iim_ctx {
   double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
   double* sdwdn = nullptr;        // d omega / dn at the control points (surface loads)
   double* scv = nullptr;          // control-volume force terms (4 values)
+  // time-dependent rigid motion (set by iim_set_body_motion or
+  // iim_rk3_steps_moving): the boundary-data tables follow motion_now
+  // ([n_bodies][3] = u_x, u_y, omega); motion_stage, while a moving step
+  // runs, points at that step's [3 stages][n_bodies][3] schedule
+  bool motion_mode = false;
+  std::vector<double> motion_now;
+  const double* motion_stage = nullptr;
+  std::vector<double> motion_buf[3];
   double *Qw = nullptr, *wtmp = nullptr, *wtmp2 = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
   bool have_prev = false;
