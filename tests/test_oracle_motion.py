@@ -6,7 +6,9 @@ the step's own recurrences applied to the time).
 * the Lamb-Oseen vortex on its co-rotating cylinder (an exact Navier-Stokes
   solution, the paper's convergence case of Sec. 6) from t = 1 to 1.05 at
   N = 32, 64, 128: the velocity error converges at second order and the
-  vorticity error decreases."""
+  vorticity error decreases;
+* the wall-vorticity stencils on the exact velocity of that vortex: second
+  order."""
 import dataclasses
 
 import numpy as np
@@ -53,3 +55,21 @@ def test_lamb_oseen_on_rotating_cylinder_converges():
         assert np.log2(a[2] / b[2]) > 1.9, e        # velocity L2
         assert np.log2(a[3] / b[3]) > 1.5, e        # velocity Linf
         assert b[0] < a[0] and b[1] < a[1], e       # vorticity
+
+
+def test_wall_vorticity_stencil_second_order_on_the_exact_vortex():
+    """The boundary-vorticity stencils applied to the exact velocity of the
+    vortex (wall vorticity 0.90, a small difference of velocity derivatives of
+    size 22): second order."""
+    from oracle.transport import boundary_vorticity
+    t = 1.0
+    wex = E3.G0 / (4 * np.pi * E3.NU * t) * np.exp(-E3.R ** 2 / (4 * E3.NU * t))
+    err = []
+    for n in (64, 128, 256):
+        grid, body = E3.case(n, t)
+        geo = OG.Geometry(grid, [body])
+        xs = grid.h * np.arange(-1, n + 1)
+        X, Y = np.meshgrid(xs, xs)
+        _, U, V = E3.exact(X, Y, t)
+        err.append(np.abs(boundary_vorticity(geo, U, V) - wex).mean())
+    assert np.log2(err[1] / err[2]) > 1.8, err
