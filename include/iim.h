@@ -240,7 +240,8 @@ int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_de
  * the context for good from the composed boundary forms to the chained
  * boundary kernels (which read the boundary-data tables) and to steps without
  * the captured graph; results equal those of a fixed rigid motion when the
- * motion is constant.  Synchronises the stream after every step.
+ * motion is constant.  Synchronises the stream after every step; stats (may
+ * be NULL) receives the last step's.
  * IIM_EINVAL on null or non-finite arguments, dt <= 0 or n_steps < 0;
  * IIM_EUNSUPPORTED for host-only contexts and for bodies with bc_samples.
  * After either call iim_surface_loads returns IIM_EUNSUPPORTED (its

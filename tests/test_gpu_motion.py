@@ -6,6 +6,9 @@ iim_rk3_steps_moving):
   stage, N = 64, four steps: the FP64 gate (velocity of both results 1e-11),
   vorticity within its rounding bound, and the result far closer to the
   oracle's than to a run that holds each step's starting motion;
+* an oscillating cylinder (translation and rotation) in a free stream, and an
+  accelerating inner cylinder inside a stationary enclosure, against the
+  oracle (the same gate);
 * a constant schedule equals the fixed rigid rotation given at creation: to
   rounding on the same (chained) boundary kernels, and within the FP64 gate
   against the composed boundary forms;
@@ -21,6 +24,7 @@ import pytest
 import torch
 
 import paper_2109_13628_amd as iim
+import workloads as wl
 from oracle import geometry as OG
 from oracle import ns as ONS
 from gpu_util import to_dev, ring_zeros, rel
@@ -79,6 +83,43 @@ def test_moving_steps_match_oracle():
     # the stage times matter: far closer to the right ones than to the motion
     # held at each step's start
     assert e_ok < 1e-3 * rel(om_w, om_r, mask=geo.fluid), (e_ok, rel(om_w, om_r, mask=geo.fluid))
+
+
+def _oscillating_cylinder():
+    w = wl.cylinder_small()
+    return w, lambda t: [(0.3 * np.sin(5 * t), 0.2 * np.cos(3 * t), 0.5 + 0.4 * np.sin(4 * t))]
+
+
+def _accelerating_couette():
+    w = wl.taylor_couette(64)
+    return w, lambda t: [(0.0, 0.0, 1.0 + 0.5 * np.sin(6 * t))] + [(0.0, 0.0, 0.0)] * (len(w.bodies) - 1)
+
+
+@pytest.mark.parametrize("make", [_oscillating_cylinder, _accelerating_couette])
+def test_translation_rotation_and_enclosure_match_oracle(make):
+    w, mot = make()
+    geo = OG.Geometry(w.grid, w.bodies)
+    om = np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, 91, count=5), 0.0)
+    G = wl.seeded_gammas(geo.nbc, 92, scale=0.2)
+    t0, n, dt = 0.3, 3, 0.5 * w.dt if w.dt > 0 else 2e-3
+    st = ONS.Stepper(geo)
+    om_r, G_r = om, G
+    for k in range(n):
+        om_r, G_r = st.step(om_r, G_r, dt, motion=mot, t=t0 + k * dt)
+    sched = np.array([[mot(t0 + (k + c) * dt) for c in C_STAGE] for k in range(n)])
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    d = to_dev(om)
+    G1, _ = ctx.rk3_steps_moving(d, G, dt, sched)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    st.set_motion(mot(t0 + n * dt))
+    a = st.rec.reconstruct(got, G1)
+    b = st.rec.reconstruct(om_r, G_r)
+    fl = np.pad(geo.fluid, 1)
+    assert rel(np.stack([a.U[fl], a.V[fl]]), np.stack([b.U[fl], b.V[fl]])) < 1e-11
+    assert rel(got, om_r, mask=geo.fluid) < 2e-9
+    assert np.max(np.abs(G1 - G_r)) < 1e-10 * (1 + np.abs(G_r).max())
+    ctx.close()
 
 
 def _chained_context(grid, bodies):
