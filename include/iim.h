@@ -230,6 +230,9 @@ int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_de
 
 /* Time-dependent rigid motion of the bodies (Sec. 2: the boundary data u_b and
  * psi_b of each body's motion u + omega k x (x - centre) about its centre).
+ * The boundary itself stays in place: the motion enters as boundary data,
+ * the physical case for a motion that keeps the boundary where it is (a
+ * circle rotating about its centre).
  * iim_set_body_motion sets motion_host[n_bodies][3] = (u_x, u_y, omega), in
  * the order of the bodies given to iim_create, for the calls that follow
  * (iim_reconstruct, iim_rhs, iim_rk3_steps).  iim_rk3_steps_moving runs
