@@ -209,3 +209,30 @@ def test_lamb_oseen_rotating_cylinder_convergence():
     # 512 to 1024 its largest errors, within h of the wall, fall by 2.3
     # (order 1.2), unchanged when dt is halved
     assert order[0][1] > 1.8 and order[1][1] > 1.8 and order[2][1] > 1.0, (order, e)
+
+
+def test_motion_argument_checks():
+    w = wl.surface_driven_cylinder()
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    om = torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(iim.IIMError) as e:                  # sampled boundary data
+        ctx.set_body_motion([0.0, 0.0, 1.0])
+    assert e.value.code == iim.IIM_EUNSUPPORTED
+    ctx.close()
+    grid, body = E3.case(64, 1.0)
+    ctx = iim.Context(grid, [body], solver=iim.SOLVER_DIRECT)
+    om = torch.zeros((grid.ny, grid.nx), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(iim.IIMError) as e:
+        ctx.set_body_motion([0.0, np.nan, 1.0])
+    assert e.value.code == iim.IIM_EINVAL
+    bad = np.zeros((2, 3, 1, 3))
+    bad[1, 2, 0, 2] = np.inf
+    with pytest.raises(iim.IIMError) as e:
+        ctx.rk3_steps_moving(om, np.zeros(1), 1e-3, bad)
+    assert e.value.code == iim.IIM_EINVAL
+    with pytest.raises(iim.IIMError) as e:
+        ctx.rk3_steps_moving(om, np.zeros(1), -1e-3, np.zeros((1, 3, 1, 3)))
+    assert e.value.code == iim.IIM_EINVAL
+    G, _ = ctx.rk3_steps_moving(om, np.zeros(1), 1e-3, np.zeros((0, 3, 1, 3)))   # zero steps
+    assert G[0] == 0.0
+    ctx.close()
