@@ -31,6 +31,20 @@ cpu_baseline leg use the oracle; the library shares none of this code.
   div T = nu lap u = nu (-d_y omega, d_x omega).  control_volume_terms returns
   the two instantaneous parts, S_t = oint_S [x (u.n) + x x (n x u)] dS and
   S_gamma = oint_S n . gamma dS, so that F = S_gamma - d S_t / dt.
+* Control-volume moment (the paper's analogue of Noca's formulation for the
+  moment, Sec. 5.4 and its appendix): M = -d/dt int_V x x u dV
+  + d/dt oint_S |x|^2/2 n x u dS + oint_S lambda(n) dS, with
+  lambda(n) = |u|^2/2 (x x n) - (x x u)(u.n) - |x|^2/2 n x (u x omega k)
+  + |x|^2/2 (div T) x n + x x (T.n).  Since div(|x|^2/2 (u_y, -u_x)) =
+  x x u + |x|^2/2 omega and u = 0 on the walls, the two time-derivative terms
+  together are d/dt int_V |x|^2/2 omega dV over the box minus the body, so
+  M = d I / dt + S_lambda with I = int_V |x|^2/2 omega dV.  I is a sum over
+  the box's nodes of omega times the fluid area of each node's dual cell
+  (h x h about the node; half or a quarter of it on the box's edges and
+  corners), omega extended to the ghost nodes by E3b; the fluid area of a
+  cell cut by a body is the cell minus its intersection with the polygon of
+  the body's boundary points (the boundary points of an enclosure bound the
+  fluid instead).
 * A body in steady rigid motion (constant translation, rotation Omega about
   its centre): the rigid motion carries vorticity 2 Omega and no strain, so
   the viscous traction is nu (omega - 2 Omega) s; the wall's centripetal
@@ -165,3 +179,107 @@ def control_volume_terms(grid, omega, U, V, box, origin=(0.0, 0.0)):
             wgt = h * (0.5 if k in (0, m) else 1.0)
             node_terms(a + k * di, b + k * dj, n, wgt)
     return St, Sg
+
+
+def cv_moment_surface(grid, omega, U, V, box, origin=(0.0, 0.0)):
+    """S_lambda = oint_S lambda(n) dS on the box (the same box, nodes, weights
+    and differences as control_volume_terms)."""
+    i0, i1, j0, j1 = box
+    h, nu = grid.h, grid.nu
+    total = 0.0
+    edges = [((i0, j0), (1, 0), i1 - i0, (0.0, -1.0)), ((i1, j0), (0, 1), j1 - j0, (1.0, 0.0)),
+             ((i0, j1), (1, 0), i1 - i0, (0.0, 1.0)), ((i0, j0), (0, 1), j1 - j0, (-1.0, 0.0))]
+    for (a, b), (di, dj), m, (nx, ny) in edges:
+        for k in range(m + 1):
+            i, j = a + k * di, b + k * dj
+            wgt = h * (0.5 if k in (0, m) else 1.0)
+            x = grid.x0 + i * h - origin[0]
+            y = grid.y0 + j * h - origin[1]
+            u, v = U[j + 1, i + 1], V[j + 1, i + 1]
+            w = omega[j, i]
+            ux_x = (U[j + 1, i + 2] - U[j + 1, i]) / (2 * h)
+            ux_y = (U[j + 2, i + 1] - U[j, i + 1]) / (2 * h)
+            uy_x = (V[j + 1, i + 2] - V[j + 1, i]) / (2 * h)
+            uy_y = (V[j + 2, i + 1] - V[j, i + 1]) / (2 * h)
+            w_x = (omega[j, i + 1] - omega[j, i - 1]) / (2 * h)
+            w_y = (omega[j + 1, i] - omega[j - 1, i]) / (2 * h)
+            Tn = (nu * (2 * ux_x * nx + (ux_y + uy_x) * ny), nu * ((ux_y + uy_x) * nx + 2 * uy_y * ny))
+            divT = (-nu * w_y, nu * w_x)
+            r2 = 0.5 * (x * x + y * y)
+            un = u * nx + v * ny
+            lam = (0.5 * (u * u + v * v) * (x * ny - y * nx)      # |u|^2/2 (x x n)
+                   - (x * v - y * u) * un                         # -(x x u)(u.n)
+                   + r2 * w * un                                  # -|x|^2/2 n x (u x omega k)
+                   + r2 * (divT[0] * ny - divT[1] * nx)           # |x|^2/2 (div T) x n
+                   + (x * Tn[1] - y * Tn[0]))                     # x x (T.n)
+            total += wgt * lam
+    return total
+
+
+def _clip_area(poly, x0, x1, y0, y1):
+    """Area of the polygon (closed, either orientation) inside the rectangle
+    [x0, x1] x [y0, y1]: clipped against the four half-planes in turn."""
+    pts = [tuple(p) for p in poly]
+    for axis, bound, keep_below in ((0, x0, False), (0, x1, True), (1, y0, False), (1, y1, True)):
+        out = []
+        n = len(pts)
+        for q in range(n):
+            a, b = pts[q - 1], pts[q]
+            ina = (a[axis] <= bound) if keep_below else (a[axis] >= bound)
+            inb = (b[axis] <= bound) if keep_below else (b[axis] >= bound)
+            if inb:
+                if not ina:
+                    out.append(_cut(a, b, axis, bound))
+                out.append(b)
+            elif ina:
+                out.append(_cut(a, b, axis, bound))
+        pts = out
+        if not pts:
+            return 0.0
+    xs = np.array([p[0] for p in pts])
+    ys = np.array([p[1] for p in pts])
+    return abs(0.5 * np.sum(xs * np.roll(ys, -1) - np.roll(xs, -1) * ys))
+
+
+def _cut(a, b, axis, bound):
+    t = (bound - a[axis]) / (b[axis] - a[axis])
+    return (a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1]))
+
+
+def fluid_weights(geom):
+    """[ny][nx] fluid area of each node's dual cell (h x h about the node)."""
+    g = geom.grid
+    h = g.h
+    W = np.where(geom.fluid, h * h, 0.0)
+    for b in geom.bodies:
+        P = np.asarray(b.points, dtype=np.float64)
+        # the dual cells the boundary passes through: those holding points
+        # sampled along every edge of the polygon (edges are shorter than h)
+        cells = set()
+        for q in range(len(P)):
+            a, c = P[q - 1], P[q]
+            for s in np.linspace(0.0, 1.0, 5):
+                x, y = a + s * (c - a)
+                cells.add((int(np.floor((x - g.x0) / h + 0.5)), int(np.floor((y - g.y0) / h + 0.5))))
+        for (i, j) in cells:
+            if not (0 <= i < g.nx and 0 <= j < g.ny):
+                continue
+            xc, yc = g.x0 + i * h, g.y0 + j * h
+            inside = _clip_area(P, xc - 0.5 * h, xc + 0.5 * h, yc - 0.5 * h, yc + 0.5 * h)
+            W[j, i] = inside if b.is_enclosure else h * h - inside
+    return W
+
+
+def cv_moment_volume(geom, omega_ext, W, box, origin=(0.0, 0.0)):
+    """I = int |x|^2/2 omega over the box minus the bodies: node values times
+    the fluid area of their dual cells, halved on the box's edges."""
+    i0, i1, j0, j1 = box
+    g = geom.grid
+    total = 0.0
+    for j in range(j0, j1 + 1):
+        for i in range(i0, i1 + 1):
+            f = (0.5 if i in (i0, i1) else 1.0) * (0.5 if j in (j0, j1) else 1.0)
+            x = g.x0 + i * g.h - origin[0]
+            y = g.y0 + j * g.h - origin[1]
+            total += f * W[j, i] * 0.5 * (x * x + y * y) * omega_ext[j, i]
+    return total
