@@ -204,29 +204,40 @@ int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
 int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                       double* point_host, double* body_host);
 
-/* Control-volume force on the bodies inside a box (Sec. 5.4, Noca's momentum
- * formulation for stationary obstacles with no-slip walls and a stationary
+/* Control-volume force and moment on the bodies inside a box (Sec. 5.4 and
+ * its appendix: Noca's momentum formulation and the paper's analogue for the
+ * moment, for stationary obstacles with no-slip walls and a stationary
  * control volume):
- *   F = S_gamma - d S_t / dt,
- *   S_t     = oint_S [x (u.n) + x x (n x u)] dS,
- *   S_gamma = oint_S n . [|u|^2/2 I - u u - u (x x omega k) + x.(div T) I
- *                         - x (div T) + T] dS,   T = nu (grad u + grad u^T),
- * where the volume integral of u over the box minus the bodies is written as
- * oint_S x (u.n) dS (div u = 0, u = 0 on the walls).  S is the rectangle of
- * grid lines through the nodes i0..i1 x j0..j1 (box = {i0, i1, j0, j1}), n its
- * outward normal, the trapezoid rule along its edges; derivatives are centred
- * differences of the node values, div T = nu (-d_y omega, d_x omega); x is
- * measured from origin_host[2].  The caller forms d S_t / dt from the values
- * at successive times.  Inputs on the device: omega [ny][nx], u and v on the
- * ring [ny+2][nx+2] as iim_reconstruct writes them.  Output on the host:
- * out_host[4] = (S_t x, S_t y, S_gamma x, S_gamma y).  Synchronises the
- * stream.  IIM_EINVAL on null arguments, a box outside 1 <= i0 < i1 <= nx-2,
+ *   F = S_gamma - d S_t / dt,    M = d I / dt + S_lambda,
+ *   S_t      = oint_S [x (u.n) + x x (n x u)] dS,
+ *   S_gamma  = oint_S n . [|u|^2/2 I - u u - u (x x omega k) + x.(div T) I
+ *                          - x (div T) + T] dS,   T = nu (grad u + grad u^T),
+ *   S_lambda = oint_S [|u|^2/2 (x x n) - (x x u)(u.n)
+ *                      - |x|^2/2 n x (u x omega k) + |x|^2/2 (div T) x n
+ *                      + x x (T.n)] dS,
+ *   I        = int_V |x|^2/2 omega dV over the box minus the bodies.
+ * With div u = 0 and u = 0 on the walls, the force's volume integral of u is
+ * oint_S x (u.n) dS and the moment's two time-derivative terms are d I / dt,
+ * so the caller forms F and M from values at successive times.  S is the
+ * rectangle of grid lines through the nodes i0..i1 x j0..j1 (box = {i0, i1,
+ * j0, j1}), n its outward normal, the trapezoid rule along its edges;
+ * derivatives are centred differences of the node values, div T = nu (-d_y
+ * omega, d_x omega).  I sums |x|^2/2 omega times the fluid area of each box
+ * node's dual cell (h x h about the node, halved on the box's edges), omega
+ * extended by E3b at the ghost nodes and zero at the other solid nodes; a cell
+ * cut by a body loses its part inside the polygon of the body's boundary
+ * points (an enclosure keeps that part).  x is measured from origin_host[2]
+ * (M is the moment about it).  Inputs on the device: omega [ny][nx], u and v
+ * on the ring [ny+2][nx+2] as iim_reconstruct writes them.  Output on the
+ * host: out_host[6] = (S_t x, S_t y, S_gamma x, S_gamma y, I, S_lambda).
+ * The first call computes the cut-cell areas once.  Synchronises the stream.
+ * IIM_EINVAL on null arguments, a box outside 1 <= i0 < i1 <= nx-2,
  * 1 <= j0 < j1 <= ny-2, or a box node or one of its four neighbours that is
  * not a fluid node (named in iim_last_error); IIM_EUNSUPPORTED for host-only
  * contexts and when a body with a control point inside the box moves (rigid
  * motion or boundary samples: the formulation is for stationary walls). */
-int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
-                       const int32_t* box, const double* origin_host, double* out_host);
+int iim_cv_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
+                 const int32_t* box, const double* origin_host, double* out_host);
 
 /* Time-dependent rigid motion of the bodies (Sec. 2: the boundary data u_b and
  * psi_b of each body's motion u + omega k x (x - centre) about its centre).
@@ -248,7 +259,7 @@ int iim_cv_force_terms(iim_ctx* ctx, const double* omega_dev, const double* u_de
  * IIM_EINVAL on null or non-finite arguments, dt <= 0 or n_steps < 0;
  * IIM_EUNSUPPORTED for host-only contexts and for bodies with bc_samples.
  * After either call iim_surface_loads returns IIM_EUNSUPPORTED (its
- * traction assumes steady motion) and iim_cv_force_terms takes the current
+ * traction assumes steady motion) and iim_cv_terms takes the current
  * motion to decide which bodies move. */
 int iim_set_body_motion(iim_ctx* ctx, const double* motion_host);
 int iim_rk3_steps_moving(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt, int32_t n_steps,

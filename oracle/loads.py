@@ -283,3 +283,16 @@ def cv_moment_volume(geom, omega_ext, W, box, origin=(0.0, 0.0)):
             y = g.y0 + j * g.h - origin[1]
             total += f * W[j, i] * 0.5 * (x * x + y * y) * omega_ext[j, i]
     return total
+
+
+def cv_moment_terms(geom, omega, U, V, box, origin=(0.0, 0.0), W=None):
+    """(I, S_lambda) of the control-volume moment, with omega extended by E3b
+    (with omega_b) at the ghost nodes and zero at the other solid nodes."""
+    wb = boundary_vorticity(geom, U, V)
+    ext = np.where(geom.fluid, np.asarray(omega, dtype=np.float64), 0.0)
+    _, e3b, _ = vorticity_extensions(geom, omega, wb)
+    ext[geom.g_j, geom.g_i] = e3b
+    if W is None:
+        W = fluid_weights(geom)
+    return (cv_moment_volume(geom, ext, W, box, origin),
+            cv_moment_surface(geom.grid, omega, U, V, box, origin))

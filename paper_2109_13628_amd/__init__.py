@@ -26,7 +26,7 @@ NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
-EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_force_terms", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
+EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_poisson_fp32", "iim_reconstruct", "iim_rhs",
            "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay", "iim_solver_counters",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
@@ -149,12 +149,12 @@ def lib():
     L.iim_rhs.argtypes = [vp, vp, vp, vp, vp, dp, vp]
     L.iim_surface_loads.restype = ip
     L.iim_surface_loads.argtypes = [vp, vp, vp, vp, dp, dp]
-    L.iim_cv_force_terms.restype = ip
+    L.iim_cv_terms.restype = ip
     L.iim_set_body_motion.restype = ip
     L.iim_set_body_motion.argtypes = [vp, dp]
     L.iim_rk3_steps_moving.restype = ip
     L.iim_rk3_steps_moving.argtypes = [vp, vp, dp, C.c_double, C.c_int32, dp, vp]
-    L.iim_cv_force_terms.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int32), dp, dp]
+    L.iim_cv_terms.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int32), dp, dp]
     L.iim_rk3_step.restype = ip
     L.iim_rk3_step.argtypes = [vp, vp, dp, C.c_double, C.POINTER(StepStats)]
     L.iim_rk3_steps.restype = ip
@@ -331,17 +331,18 @@ class Context:
         return {"omega_b": pts[:nc, 0].copy(), "tau": pts[:nc, 1].copy(), "dwdn": pts[:nc, 2].copy(),
                 "p": pts[:nc, 3].copy(), "forces": bod[:self.n_bodies].copy()}
 
-    def cv_force_terms(self, omega, u, v, box, origin=(0.0, 0.0)):
-        """Control-volume force parts on the box of nodes (i0, i1, j0, j1):
-        S_t and S_gamma, with F = S_gamma - d S_t / dt (the caller
-        differences S_t in time); u, v: ring arrays from reconstruct."""
+    def cv_terms(self, omega, u, v, box, origin=(0.0, 0.0)):
+        """Control-volume parts on the box of nodes (i0, i1, j0, j1), x from
+        origin: S_t, S_gamma (F = S_gamma - d S_t / dt) and I, S_lambda
+        (M = d I / dt + S_lambda); the caller differences S_t and I in time.
+        u, v: ring arrays from reconstruct."""
         b = (C.c_int32 * 4)(*[int(q) for q in box])
         o = np.ascontiguousarray(origin, dtype=np.float64)
-        out = np.zeros(4)
-        self._check(lib().iim_cv_force_terms(self._h, _ptr(omega), _ptr(u), _ptr(v), b,
-                                             o.ctypes.data_as(C.POINTER(C.c_double)),
-                                             out.ctypes.data_as(C.POINTER(C.c_double))), "iim_cv_force_terms")
-        return {"S_t": out[:2].copy(), "S_gamma": out[2:].copy()}
+        out = np.zeros(6)
+        self._check(lib().iim_cv_terms(self._h, _ptr(omega), _ptr(u), _ptr(v), b,
+                                       o.ctypes.data_as(C.POINTER(C.c_double)),
+                                       out.ctypes.data_as(C.POINTER(C.c_double))), "iim_cv_terms")
+        return {"S_t": out[:2].copy(), "S_gamma": out[2:4].copy(), "I": float(out[4]), "S_lambda": float(out[5])}
 
     def rhs(self, omega, u, v, domega, omega_b=None):
         dG = np.zeros(max(1, self.n_circ))

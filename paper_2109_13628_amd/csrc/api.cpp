@@ -437,7 +437,7 @@ void setup_device(iim_ctx* c) {
   c->V = c->dalloc<double>(NR);
   c->wb = c->dalloc<double>(g.nc);
   c->sdwdn = c->dalloc<double>(g.nc);
-  c->scv = c->dalloc<double>(4);
+  c->scv = c->dalloc<double>(6);
   c->w4 = c->dalloc<double>(N);
   c->w3b = c->dalloc<double>(N);
   c->w3n = c->dalloc<double>(N);
@@ -713,6 +713,84 @@ int enter_motion_mode(iim_ctx* c) {
     }
   }
   return IIM_OK;
+}
+
+// Area of the closed polygon xy[2n] (either orientation) inside the
+// rectangle [x0, x1] x [y0, y1]: the polygon clipped by the rectangle's four
+// half-planes in turn (exact for any simple polygon), then the shoelace sum.
+double clipped_area(const std::vector<double>& xy, double x0, double x1, double y0, double y1) {
+  struct P { double x, y; };
+  std::vector<P> a, b;
+  const size_t n = xy.size() / 2;
+  a.reserve(n + 8);
+  for (size_t q = 0; q < n; ++q) a.push_back({xy[2 * q], xy[2 * q + 1]});
+  for (int side = 0; side < 4 && !a.empty(); ++side) {
+    const bool use_x = side < 2;
+    const double bound = side == 0 ? x0 : side == 1 ? x1 : side == 2 ? y0 : y1;
+    const bool below = side == 1 || side == 3;   // keep coordinate <= bound
+    auto coord = [&](const P& p) { return use_x ? p.x : p.y; };
+    auto keep = [&](const P& p) { return below ? coord(p) <= bound : coord(p) >= bound; };
+    auto cross = [&](const P& p, const P& r) {
+      const double t = (bound - coord(p)) / (coord(r) - coord(p));
+      return P{p.x + t * (r.x - p.x), p.y + t * (r.y - p.y)};
+    };
+    b.clear();
+    for (size_t q = 0; q < a.size(); ++q) {
+      const P& p = a[(q + a.size() - 1) % a.size()];
+      const P& r = a[q];
+      if (keep(r)) {
+        if (!keep(p)) b.push_back(cross(p, r));
+        b.push_back(r);
+      } else if (keep(p)) {
+        b.push_back(cross(p, r));
+      }
+    }
+    std::swap(a, b);
+  }
+  double s2 = 0.0;
+  for (size_t q = 0; q < a.size(); ++q) {
+    const P& p = a[q];
+    const P& r = a[(q + 1) % a.size()];
+    s2 += p.x * r.y - r.x * p.y;
+  }
+  return 0.5 * std::fabs(s2);
+}
+
+// Fluid area of every node's dual cell (h x h about the node): h^2 at fluid
+// nodes and 0 at solid ones, except in the cells that a body's boundary
+// polygon (its boundary points) passes through -- found from points at
+// quarters of every polygon edge, edges being shorter than h -- where it is
+// the cell minus its part inside the polygon (for an enclosure, that part).
+std::vector<double> fluid_area_weights(const iim_ctx* c) {
+  const Geometry& g = c->geo;
+  const int nx = g.grid.nx, ny = g.grid.ny;
+  const double h = g.grid.h, x0 = g.grid.x0, y0 = g.grid.y0;
+  std::vector<double> W((size_t)nx * ny);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) W[(size_t)j * nx + i] = g.cl(i, j) == CLS_FLUID ? h * h : 0.0;
+  for (const BodySpec& b : g.bodies) {
+    const size_t n = b.xy.size() / 2;
+    std::vector<std::pair<int, int>> cells;
+    for (size_t q = 0; q < n; ++q) {
+      const size_t p = (q + n - 1) % n;
+      for (int s = 0; s <= 4; ++s) {
+        const double t = 0.25 * s;
+        const double x = b.xy[2 * p] + t * (b.xy[2 * q] - b.xy[2 * p]);
+        const double y = b.xy[2 * p + 1] + t * (b.xy[2 * q + 1] - b.xy[2 * p + 1]);
+        cells.emplace_back((int)std::floor((x - x0) / h + 0.5), (int)std::floor((y - y0) / h + 0.5));
+      }
+    }
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    for (const auto& ij : cells) {
+      const int i = ij.first, j = ij.second;
+      if (i < 0 || j < 0 || i >= nx || j >= ny) continue;
+      const double xc = x0 + i * h, yc = y0 + j * h;
+      const double in = clipped_area(b.xy, xc - 0.5 * h, xc + 0.5 * h, yc - 0.5 * h, yc + 0.5 * h);
+      W[(size_t)j * nx + i] = b.enclosure ? in : h * h - in;
+    }
+  }
+  return W;
 }
 
 }  // namespace
@@ -1139,8 +1217,8 @@ int iim_surface_loads(iim_ctx* c, const double* omega, const double* u, const do
   return IIM_OK;
 }
 
-int iim_cv_force_terms(iim_ctx* c, const double* omega, const double* u, const double* v, const int32_t* box,
-                       const double* origin, double* out_host) {
+int iim_cv_terms(iim_ctx* c, const double* omega, const double* u, const double* v, const int32_t* box,
+                 const double* origin, double* out_host) {
   if (!c || !omega || !u || !v || !box || !origin || !out_host) return IIM_EINVAL;
   if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
   const Geometry& g = c->geo;
@@ -1174,13 +1252,20 @@ int iim_cv_force_terms(iim_ctx* c, const double* omega, const double* u, const d
     const bool moving = m ? (m[0] != 0.0 || m[1] != 0.0 || m[2] != 0.0)
                           : (!bs.samples.empty() || bs.u_rigid[0] != 0.0 || bs.u_rigid[1] != 0.0 || bs.omega != 0.0);
     if (moving)
-      return fail(c, IIM_EUNSUPPORTED, "control-volume force: body " + std::to_string(g.c_body[q]) +
+      return fail(c, IIM_EUNSUPPORTED, "control volume: body " + std::to_string(g.c_body[q]) +
                                            " inside the box is not a stationary wall");
   }
   try {
+    if (!c->cvw) {
+      const std::vector<double> W = fluid_area_weights(c);
+      c->cvw = c->upload(W);
+    }
     CvBox b{nx, i0, i1, j0, j1, g.grid.x0, g.grid.y0, g.grid.h, g.grid.nu, origin[0], origin[1]};
+    // omega extended by E3b at the ghost nodes (with omega_b from u, v)
+    launch_omega_bc(c->dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
     launch_cv_terms(b, omega, u, v, c->scv, c->stream);
-    HIPCHK(hipMemcpyAsync(out_host, c->scv, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    launch_cv_volume(b, c->dg.cls, omega, c->w3b, c->cvw, c->scv, c->stream);
+    HIPCHK(hipMemcpyAsync(out_host, c->scv, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {

@@ -306,10 +306,14 @@ struct CvBox {
   int nx, i0, i1, j0, j1;
   double x0, y0, h, nu, ox, oy;
 };
-// out[4] = (S_t x, S_t y, S_gamma x, S_gamma y) of the box (device); the box
-// and its nodes' four neighbours must lie inside the grid.
+// out[0..3] = (S_t x, S_t y, S_gamma x, S_gamma y), out[5] = S_lambda of the
+// box (device); the box and its nodes' four neighbours must lie inside the grid.
 void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const double* V, double* out,
                      hipStream_t s);
+// out[4] = I, the box's sum of |x|^2/2 omega_ext W (W: fluid area of each
+// node's dual cell, [ny][nx]; omega_ext: w3b at ghost nodes, 0 at solid ones).
+void launch_cv_volume(const CvBox& b, const int8_t* cls, const double* omega, const double* w3b, const double* W,
+                      double* out, hipStream_t s);
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s);
 

@@ -33,11 +33,12 @@ void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b,
   if (g.nc) k_surface_dwdn<<<(g.nc + 127) / 128, 128, 0, s>>>(g, omega, w3b, wb, dwdn);
 }
 
-// Control-volume force terms on the rectangle of grid lines through the
+// Control-volume surface terms on the rectangle of grid lines through the
 // nodes i0..i1 x j0..j1: one workgroup walks the perimeter (bottom, right,
 // top, left edge; trapezoid weights, corners in both their edges), each lane
 // summing the terms of its nodes, then a fixed-order tree sum in LDS.
-// out = (S_t x, S_t y, S_gamma x, S_gamma y).
+// out[0..3] = (S_t x, S_t y, S_gamma x, S_gamma y) of the force, out[5] =
+// S_lambda of the moment.
 constexpr int CV_THREADS = 256;
 
 __global__ void __launch_bounds__(CV_THREADS)
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(CV_THREADS)
   const int np = 2 * (mi + 1) + 2 * (mj + 1);
   const int nxr = b.nx + 2;
   const double h = b.h, nu = b.nu, i2h = 0.5 / b.h;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int p = threadIdx.x; p < np; p += CV_THREADS) {
     int i, j, k, m;
     double nx, ny;
@@ -76,21 +77,61 @@ __global__ void __launch_bounds__(CV_THREADS)
     const double ke = 0.5 * (u * u + v * v), xd = x * dtx + y * dty, nxx = nx * x + ny * y;
     acc[2] += wgt * (ke * nx - un * u - un * w * y + xd * nx - nxx * dtx + nu * (2.0 * ux_x * nx + sh * ny));
     acc[3] += wgt * (ke * ny - un * v + un * w * x + xd * ny - nxx * dty + nu * (sh * nx + 2.0 * uy_y * ny));
+    // lambda(n) = |u|^2/2 (x x n) - (x x u)(u.n) - |x|^2/2 n x (u x omega k)
+    //           + |x|^2/2 (div T) x n + x x (T.n)   (k components)
+    const double r2 = 0.5 * (x * x + y * y);
+    const double tnx = nu * (2.0 * ux_x * nx + sh * ny), tny = nu * (sh * nx + 2.0 * uy_y * ny);
+    acc[4] += wgt * (ke * (x * ny - y * nx) - (x * v - y * u) * un + r2 * w * un + r2 * (dtx * ny - dty * nx) +
+                     (x * tny - y * tnx));
   }
-  __shared__ double red[4][CV_THREADS];
-  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = acc[c];
+  __shared__ double red[5][CV_THREADS];
+  for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int s = CV_THREADS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+      for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 4) out[5] = red[4][0];
+}
+
+// Volume term of the control-volume moment: I = sum over the box's nodes of
+// |x|^2/2 omega times the fluid area of the node's dual cell (W), halved on
+// the box's edges; omega extended by E3b at the ghost nodes, zero at the
+// other solid nodes.  One workgroup, fixed-order tree sum; out[4] = I.
+__global__ void __launch_bounds__(CV_THREADS)
+    k_cv_volume(CvBox b, const int8_t* __restrict__ cls, const double* __restrict__ omega,
+                const double* __restrict__ w3b, const double* __restrict__ W, double* __restrict__ out) {
+  const int wi = b.i1 - b.i0 + 1, wj = b.j1 - b.j0 + 1;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < wi * wj; p += CV_THREADS) {
+    const int i = b.i0 + p % wi, j = b.j0 + p / wi;
+    const size_t q = (size_t)j * b.nx + i;
+    const int c = cls[q];
+    const double val = c == 2 ? w3b[q] : (c == 3 ? 0.0 : omega[q]);
+    const double f = (i == b.i0 || i == b.i1 ? 0.5 : 1.0) * (j == b.j0 || j == b.j1 ? 0.5 : 1.0);
+    const double x = b.x0 + i * b.h - b.ox, y = b.y0 + j * b.h - b.oy;
+    acc += f * W[q] * 0.5 * (x * x + y * y) * val;
+  }
+  __shared__ double red[CV_THREADS];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = CV_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[4] = red[0];
 }
 
 void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const double* V, double* out,
                      hipStream_t s) {
   k_cv_terms<<<1, CV_THREADS, 0, s>>>(b, omega, U, V, out);
+}
+
+void launch_cv_volume(const CvBox& b, const int8_t* cls, const double* omega, const double* w3b, const double* W,
+                      double* out, hipStream_t s) {
+  k_cv_volume<<<1, CV_THREADS, 0, s>>>(b, cls, omega, w3b, W, out);
 }
 
 }  // namespace iim

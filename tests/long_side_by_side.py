@@ -5,8 +5,8 @@ each cylinder (mean C_D, mean C_L, RMS C_L, with C = 2F/(D U^2)).  The forces
 come from the surface loads (Sec. 5.4: surface pressure from the vorticity
 flux, shear), sampled every few steps of the FP64 dense-solve time step, and
 for comparison from the control-volume formulation of the same section on a
-box around each cylinder (its time derivative by central differences of the
-samples).
+box around each cylinder (its time derivatives by central differences of the
+samples), which also gives the moment about each centre.
 
 The run prints one progress line about every 20 s and writes the force
 history and the statistics as JSON, with the paper's row for the same
@@ -127,8 +127,8 @@ def main():
         s1 = time.perf_counter()
         cur.reconstruct(om, G, psi, U, V)
         L = cur.surface_loads(om, U, V)
-        cv.append([np.concatenate([q["S_t"], q["S_gamma"]]) for q in
-                   (cur.cv_force_terms(om, U, V, b, w.bodies[q].center) for q, b in enumerate(boxes))])
+        cv.append([np.concatenate([q["S_t"], q["S_gamma"], [q["I"], q["S_lambda"]]]) for q in
+                   (cur.cv_terms(om, U, V, b, w.bodies[q].center) for q, b in enumerate(boxes))])
         s2 = time.perf_counter()
         step_s += s1 - s0
         load_s += s2 - s1
@@ -144,9 +144,10 @@ def main():
     H = np.array(hist)
     t = H[:, 0]
     # control-volume forces at the interior samples: F = S_gamma - d S_t / dt
-    Cv = np.array(cv)                                   # [sample][body][S_t x, y, S_gamma x, y]
+    Cv = np.array(cv)                                   # [sample][body][S_t x, y, S_gamma x, y, I, S_lambda]
     span = (t[2:] - t[:-2])[:, None, None]
-    Fcv = 2.0 * (Cv[1:-1, :, 2:] - (Cv[2:, :, :2] - Cv[:-2, :, :2]) / span)
+    Fcv = 2.0 * (Cv[1:-1, :, 2:4] - (Cv[2:, :, :2] - Cv[:-2, :, :2]) / span)
+    Mcv = (Cv[2:, :, 4] - Cv[:-2, :, 4]) / span[:, :, 0] + Cv[1:-1, :, 5]       # moment about each centre
     tc = t[1:-1]
     res = {"workload": w.name, "Re": a.re, "L/D": a.gap, "D/h": a.d_over_h, "dt": a.dt, "t_end": a.t_end,
            "perturbation": {"v": a.perturb_v, "until": a.perturb_until},
@@ -157,6 +158,13 @@ def main():
            "control_volume": {"boxes": boxes,
                               "lower": stats(tc, Fcv[:, 0, 0], Fcv[:, 0, 1], a.avg_from),
                               "upper": stats(tc, Fcv[:, 1, 0], Fcv[:, 1, 1], a.avg_from)}}
+    # moment coefficient 2 M / (D^2 U^2) about each centre: surface loads and control volume
+    sel_m = tc >= a.avg_from
+    res["moment"] = {
+        "lower_surface_rms": float(np.sqrt(np.mean((2 * H[1:-1, 5][sel_m]) ** 2))),
+        "lower_cv_rms": float(np.sqrt(np.mean((2 * Mcv[sel_m, 0]) ** 2))),
+        "lower_surface_mean": float(np.mean(2 * H[1:-1, 5][sel_m])),
+        "lower_cv_mean": float(np.mean(2 * Mcv[sel_m, 0]))}
     sel = t >= a.avg_from
     res["lift_correlation"] = float(np.corrcoef(H[sel, 2], H[sel, 4])[0, 1]) if sel.sum() > 2 else None
     # the paper's row for these parameters (antiphase: the lifts are mirror images)
@@ -173,7 +181,8 @@ def main():
                 "C_L_rms_about_mean": lo["C_L_rms_about_mean"] / r["C_L_rms"] - 1.0}
     res["history"] = {"t": t.tolist(), "CD_lower": H[:, 1].tolist(), "CL_lower": H[:, 2].tolist(),
                       "CD_upper": H[:, 3].tolist(), "CL_upper": H[:, 4].tolist(),
-                      "t_cv": tc.tolist(), "CD_lower_cv": Fcv[:, 0, 0].tolist(), "CL_lower_cv": Fcv[:, 0, 1].tolist()}
+                      "t_cv": tc.tolist(), "CD_lower_cv": Fcv[:, 0, 0].tolist(), "CL_lower_cv": Fcv[:, 0, 1].tolist(),
+                      "CM_lower": (2 * H[:, 5]).tolist(), "CM_lower_cv": (2 * Mcv[:, 0]).tolist()}
     with open(a.out, "w") as f:
         json.dump(res, f)
     brief = {k: v for k, v in res.items() if k != "history"}

@@ -116,9 +116,9 @@ def test_argument_errors_of_the_additions():
     assert L.iim_rk3_steps_moving(h, one, two, C.c_double(-0.1), 1, two, None) == iim.IIM_EINVAL
     assert L.iim_rk3_steps_moving(h, one, two, C.c_double(0.1), 0, two, None) == iim.IIM_EUNSUPPORTED
     box = (C.c_int32 * 4)(4, 20, 4, 20)
-    assert L.iim_cv_force_terms(h, one, one, one, None, two, two) == iim.IIM_EINVAL
-    assert L.iim_cv_force_terms(h, one, one, one, box, two, None) == iim.IIM_EINVAL
-    assert L.iim_cv_force_terms(h, one, one, one, box, two, two) == iim.IIM_EUNSUPPORTED
+    assert L.iim_cv_terms(h, one, one, one, None, two, two) == iim.IIM_EINVAL
+    assert L.iim_cv_terms(h, one, one, one, box, two, None) == iim.IIM_EINVAL
+    assert L.iim_cv_terms(h, one, one, one, box, two, two) == iim.IIM_EUNSUPPORTED
     assert L.iim_profile_replay(h, 0, 1, C.byref(C.c_double()), C.byref(C.c_double())) == iim.IIM_EUNSUPPORTED
     assert L.iim_warm_start_train(h, None, 1, 1, 1e-3, 0, None) == iim.IIM_EINVAL
     ctx.close()

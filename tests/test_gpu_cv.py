@@ -1,7 +1,9 @@
-"""Control-volume force terms (Sec. 5.4, Noca's momentum formulation) on the
-GPU against the FP64 oracle: from the same velocity and vorticity (1e-12 of
-the largest term), and end to end from the oracle's own reconstruction (the
-1e-11 velocity agreement carried through one difference at spacing h: 1e-9).
+"""Control-volume terms (Sec. 5.4: Noca's momentum formulation for the force,
+the paper's analogue for the moment) on the GPU against the FP64 oracle:
+S_t, S_gamma, the cut-cell volume term I and S_lambda, from the same velocity
+and vorticity (1e-12), and end to end from the oracle's own reconstruction
+(the 1e-11 velocity agreement carried through one difference at spacing h:
+1e-9).
 Boxes that leave the grid or touch the body, and moving bodies inside the
 box, are rejected."""
 import dataclasses
@@ -42,18 +44,26 @@ def test_cv_terms_match_oracle(name):
     psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
     d = to_dev(om)
     ctx.reconstruct(d, G, psi, U, V)
-    got = ctx.cv_force_terms(d, U, V, box, origin)
+    got = ctx.cv_terms(d, U, V, box, origin)
     torch.cuda.synchronize()
-    # the kernel alone: the oracle's box integrals of the library's fields
-    St, Sg = OL.control_volume_terms(w.grid, om, U.cpu().numpy(), V.cpu().numpy(), box, origin)
+    W = OL.fluid_weights(geo)
+    # the kernels alone: the oracle's box integrals of the library's fields
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    St, Sg = OL.control_volume_terms(w.grid, om, Uh, Vh, box, origin)
+    I, Sl = OL.cv_moment_terms(geo, om, Uh, Vh, box, origin, W)
     scale = max(np.abs(St).max(), np.abs(Sg).max())
     assert np.abs(got["S_t"] - St).max() < 1e-12 * scale, (got, St)
     assert np.abs(got["S_gamma"] - Sg).max() < 1e-12 * scale, (got, Sg)
+    assert abs(got["I"] - I) < 1e-12 * abs(I), (got["I"], I)
+    assert abs(got["S_lambda"] - Sl) < 1e-12 * abs(Sl), (got["S_lambda"], Sl)
     # end to end: from the oracle's reconstruction of the same state
     ref = Reconstructor(geo).reconstruct(om, G)
     St, Sg = OL.control_volume_terms(w.grid, om, ref.U, ref.V, box, origin)
+    I, Sl = OL.cv_moment_terms(geo, om, ref.U, ref.V, box, origin, W)
     assert np.abs(got["S_t"] - St).max() < 1e-9 * scale
     assert np.abs(got["S_gamma"] - Sg).max() < 1e-9 * scale
+    assert abs(got["I"] - I) < 1e-9 * abs(I)
+    assert abs(got["S_lambda"] - Sl) < 1e-9 * abs(Sl)
     ctx.close()
 
 
@@ -65,18 +75,18 @@ def test_cv_box_checks():
     nx, ny = w.grid.nx, w.grid.ny
     for box in [(0, 20, 5, 20), (5, nx - 1, 5, 20), (20, 10, 5, 20), (5, 20, 5, ny - 1)]:
         with pytest.raises(iim.IIMError) as e:
-            ctx.cv_force_terms(om, U, V, box)
+            ctx.cv_terms(om, U, V, box)
         assert e.value.code == iim.IIM_EINVAL
     # an edge through the cylinder (centre column of the body)
     ic = int(round((1.5 - w.grid.x0) / w.grid.h))
     with pytest.raises(iim.IIMError) as e:
-        ctx.cv_force_terms(om, U, V, (ic, ic + 30, 10, 80))
+        ctx.cv_terms(om, U, V, (ic, ic + 30, 10, 80))
     assert e.value.code == iim.IIM_EINVAL and "fluid" in str(e.value)
     ctx.close()
     # a rotating body inside the box: not a stationary wall
     b = dataclasses.replace(w.bodies[0], omega_rigid=0.5)
     ctx = iim.Context(w.grid, [b], solver=iim.SOLVER_DIRECT)
     with pytest.raises(iim.IIMError) as e:
-        ctx.cv_force_terms(om, U, V, _box(w.grid, 0.7, 2.4, -0.8, 0.8))
+        ctx.cv_terms(om, U, V, _box(w.grid, 0.7, 2.4, -0.8, 0.8))
     assert e.value.code == iim.IIM_EUNSUPPORTED
     ctx.close()
