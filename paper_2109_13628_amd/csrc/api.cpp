@@ -437,7 +437,7 @@ void setup_device(iim_ctx* c) {
   c->V = c->dalloc<double>(NR);
   c->wb = c->dalloc<double>(g.nc);
   c->sdwdn = c->dalloc<double>(g.nc);
-  c->scv = c->dalloc<double>(6);
+  c->scv = c->dalloc<double>(8 + (size_t)ny);   // 6 results, then one partial sum per grid row
   c->w4 = c->dalloc<double>(N);
   c->w3b = c->dalloc<double>(N);
   c->w3n = c->dalloc<double>(N);
@@ -1264,7 +1264,7 @@ int iim_cv_terms(iim_ctx* c, const double* omega, const double* u, const double*
     // omega extended by E3b at the ghost nodes (with omega_b from u, v)
     launch_omega_bc(c->dg, omega, u, v, c->wb, c->w4, c->w3b, c->w3n, c->stream);
     launch_cv_terms(b, omega, u, v, c->scv, c->stream);
-    launch_cv_volume(b, c->dg.cls, omega, c->w3b, c->cvw, c->scv, c->stream);
+    launch_cv_volume(b, c->dg.cls, omega, c->w3b, c->cvw, c->scv + 8, c->scv, c->stream);
     HIPCHK(hipMemcpyAsync(out_host, c->scv, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());

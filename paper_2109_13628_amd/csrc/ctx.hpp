@@ -81,7 +81,7 @@ struct iim_ctx {
   double *psi = nullptr, *U = nullptr, *V = nullptr;
   double *wb = nullptr, *w4 = nullptr, *w3b = nullptr, *w3n = nullptr;
   double* sdwdn = nullptr;        // d omega / dn at the control points (surface loads)
-  double* scv = nullptr;          // control-volume terms (6 values)
+  double* scv = nullptr;          // control-volume terms (6 values), then per-row partial sums
   double* cvw = nullptr;          // fluid area of every node's dual cell (made at first use)
   // time-dependent rigid motion (set by iim_set_body_motion or
   // iim_rk3_steps_moving): the boundary-data tables follow motion_now

@@ -311,9 +311,10 @@ struct CvBox {
 void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const double* V, double* out,
                      hipStream_t s);
 // out[4] = I, the box's sum of |x|^2/2 omega_ext W (W: fluid area of each
-// node's dual cell, [ny][nx]; omega_ext: w3b at ghost nodes, 0 at solid ones).
+// node's dual cell, [ny][nx]; omega_ext: w3b at ghost nodes, 0 at solid ones);
+// part: one partial sum per box row (j1 - j0 + 1 values).
 void launch_cv_volume(const CvBox& b, const int8_t* cls, const double* omega, const double* w3b, const double* W,
-                      double* out, hipStream_t s);
+                      double* part, double* out, hipStream_t s);
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s);
 

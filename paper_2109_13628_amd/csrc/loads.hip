@@ -99,21 +99,35 @@ __global__ void __launch_bounds__(CV_THREADS)
 // Volume term of the control-volume moment: I = sum over the box's nodes of
 // |x|^2/2 omega times the fluid area of the node's dual cell (W), halved on
 // the box's edges; omega extended by E3b at the ghost nodes, zero at the
-// other solid nodes.  One workgroup, fixed-order tree sum; out[4] = I.
+// other solid nodes.  One workgroup per box row writes the row's sum to
+// part[row]; k_cv_sum then adds the rows in a fixed order into out[4].
 __global__ void __launch_bounds__(CV_THREADS)
     k_cv_volume(CvBox b, const int8_t* __restrict__ cls, const double* __restrict__ omega,
-                const double* __restrict__ w3b, const double* __restrict__ W, double* __restrict__ out) {
-  const int wi = b.i1 - b.i0 + 1, wj = b.j1 - b.j0 + 1;
+                const double* __restrict__ w3b, const double* __restrict__ W, double* __restrict__ part) {
+  const int j = b.j0 + blockIdx.x;
+  const double fj = (j == b.j0 || j == b.j1) ? 0.5 : 1.0;
+  const double y = b.y0 + j * b.h - b.oy;
   double acc = 0.0;
-  for (int p = threadIdx.x; p < wi * wj; p += CV_THREADS) {
-    const int i = b.i0 + p % wi, j = b.j0 + p / wi;
+  for (int i = b.i0 + threadIdx.x; i <= b.i1; i += CV_THREADS) {
     const size_t q = (size_t)j * b.nx + i;
     const int c = cls[q];
     const double val = c == 2 ? w3b[q] : (c == 3 ? 0.0 : omega[q]);
-    const double f = (i == b.i0 || i == b.i1 ? 0.5 : 1.0) * (j == b.j0 || j == b.j1 ? 0.5 : 1.0);
-    const double x = b.x0 + i * b.h - b.ox, y = b.y0 + j * b.h - b.oy;
-    acc += f * W[q] * 0.5 * (x * x + y * y) * val;
+    const double x = b.x0 + i * b.h - b.ox;
+    acc += (i == b.i0 || i == b.i1 ? 0.5 : 1.0) * W[q] * 0.5 * (x * x + y * y) * val;
   }
+  __shared__ double red[CV_THREADS];
+  red[threadIdx.x] = fj * acc;
+  __syncthreads();
+  for (int s = CV_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(CV_THREADS) k_cv_sum(const double* __restrict__ part, int n, double* out) {
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < n; r += CV_THREADS) acc += part[r];
   __shared__ double red[CV_THREADS];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -130,8 +144,10 @@ void launch_cv_terms(const CvBox& b, const double* omega, const double* U, const
 }
 
 void launch_cv_volume(const CvBox& b, const int8_t* cls, const double* omega, const double* w3b, const double* W,
-                      double* out, hipStream_t s) {
-  k_cv_volume<<<1, CV_THREADS, 0, s>>>(b, cls, omega, w3b, W, out);
+                      double* part, double* out, hipStream_t s) {
+  const int rows = b.j1 - b.j0 + 1;
+  k_cv_volume<<<rows, CV_THREADS, 0, s>>>(b, cls, omega, w3b, W, part);
+  k_cv_sum<<<1, CV_THREADS, 0, s>>>(part, rows, out);
 }
 
 }  // namespace iim
