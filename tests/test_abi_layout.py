@@ -42,3 +42,56 @@ def test_struct_layouts_match_header(tmp_path):
         assert got == int(value), (name, int(value), got)
         checked += 1
     assert checked == len(STRUCTS) + sum(len(p._fields_) for p in STRUCTS.values())
+
+
+def _prototypes():
+    """name -> list of parameter type strings, from every prototype in the header."""
+    import re
+    text = open(os.path.join(ROOT, "include", "iim.h")).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(?:int|int64_t|const char\s*\*)\s+(iim_\w+)\s*\(([^)]*)\)\s*;", text):
+        params = [p.strip() for p in m.group(2).split(",")]
+        if params == ["void"]:
+            params = []
+        # drop the parameter name: the type is everything before the last identifier
+        types = []
+        for p in params:
+            t = re.sub(r"\b\w+\s*$", "", p).strip() if re.search(r"[\w\*]\s+\w+$", p) else p
+            types.append(" ".join(t.replace("*", " * ").split()))
+        out[m.group(1)] = types
+    return out
+
+
+_SCALARS = {"int32_t": C.c_int32, "int64_t": C.c_int64, "uint64_t": C.c_uint64, "double": C.c_double,
+            "float": C.c_float, "int": C.c_int}
+_POINTEES = {"double": C.c_double, "float": C.c_float, "int32_t": C.c_int32, "int64_t": C.c_int64}
+
+
+def test_argument_types_match_header():
+    protos = _prototypes()
+    L = iim.lib()
+    checked = 0
+    for name in iim.EXPORTS:
+        fn = getattr(L, name)
+        if fn.argtypes is None:
+            continue
+        types = protos[name]
+        assert len(types) == len(fn.argtypes), (name, types, fn.argtypes)
+        for ct, at in zip(types, fn.argtypes):
+            if "*" in ct:
+                # a pointer: the binding passes a pointer of the same pointee
+                # size (or an untyped / string / structure pointer)
+                assert at in (C.c_void_p, C.c_char_p) or hasattr(at, "_type_") and not isinstance(at._type_, str) \
+                    or issubclass(at, C._Pointer), (name, ct, at)
+                base = ct.replace("const", "").replace("*", "").split()
+                if issubclass(at, C._Pointer) and len(base) == 1 and base[0] in _POINTEES \
+                        and ct.count("*") == 1:
+                    assert C.sizeof(at._type_) == C.sizeof(_POINTEES[base[0]]), (name, ct, at)
+            else:
+                base = ct.replace("const", "").split()[-1]
+                if base in _SCALARS:
+                    assert C.sizeof(at) == C.sizeof(_SCALARS[base]), (name, ct, at)
+                    assert (at in (C.c_double, C.c_float)) == (base in ("double", "float")), (name, ct, at)
+            checked += 1
+    assert checked > 100
