@@ -86,3 +86,24 @@ def test_device_error_paths():
     with pytest.raises(iim.IIMError) as e:
         ctx.rk3_steps(om, np.zeros(1), w.dt, 1)
     assert e.value.code == iim.IIM_ENONFINITE
+
+
+def test_krylov_limit_reports_no_convergence():
+    """An iteration limit below what the tolerance needs: IIM_ENOCONV, with the
+    statistics filled and the (unconverged) result written."""
+    w = wl.cylinder_small()
+    geo = OG.Geometry(w.grid, w.bodies)
+    om = np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, 5, count=5), 0.0)
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_KRYLOV, tol=1e-13, max_iter=3,
+                      guess=iim.GUESS_ZERO)
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    st = ctx.reconstruct(to_dev(om), np.array([0.1]), psi, U, V, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert st["converged"] == 0 and 1 <= st["iters"][0] <= 3, st
+    assert 1e-13 < st["res"][0] < st["res0"][0], st
+    assert np.all(np.isfinite(U.cpu().numpy())) and np.abs(U.cpu().numpy()).max() > 0
+    d = to_dev(om)
+    with pytest.raises(iim.IIMError) as e:
+        ctx.rk3_steps(d, np.array([0.1]), w.dt, 1)
+    assert e.value.code == iim.IIM_ENOCONV
+    ctx.close()
