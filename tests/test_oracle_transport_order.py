@@ -1,0 +1,48 @@
+"""Convergence order of the transport scheme (Sec. 3), pinned to an exact
+solution: with a uniform velocity (1, 2) and no body, a Gaussian vortex is
+carried and spreads exactly (variance s0^2 + 2 nu t, amplitude s0^2 / that).
+The paper states third order where advection dominates (cell Reynolds number
+above one) and second order where diffusion does; the oracle's RK3 steps of
+its transport right-hand side show both."""
+import numpy as np
+
+import workloads as wl
+from oracle import geometry as OG
+from oracle import ns as ONS
+from oracle import transport as OT
+
+U0, S0, C0 = (1.0, 2.0), 0.12, (-0.3, -0.45)
+
+
+def _error(n, nu, T, cfl=0.5):
+    h = 2.0 / n
+    g = wl.GridDesc(nx=n, ny=n, x0=-1 + 0.5 * h, y0=-1 + 0.5 * h, h=h, nu=nu)
+    geo = OG.Geometry(g, [])
+    X, Y = wl.node_coords(g)
+
+    def exact(t):
+        s2 = S0 * S0 + 2 * nu * t
+        return (S0 * S0 / s2) * np.exp(-((X - C0[0] - U0[0] * t) ** 2 + (Y - C0[1] - U0[1] * t) ** 2) / (2 * s2))
+
+    U = np.full((n + 2, n + 2), U0[0])
+    V = np.full((n + 2, n + 2), U0[1])
+    steps = int(np.ceil(T / (cfl * ONS.dt_max(h, nu, abs(U0[0]) + abs(U0[1])))))
+    dt = T / steps
+    om = exact(0.0)
+    rhs = lambda st, s: [OT.rhs(geo, st[0], U, V, nu)[0]]
+    for _ in range(steps):
+        om = ONS.rk3_williamson([om], rhs, dt)[0]
+    e = om - exact(T)
+    return np.sqrt(np.mean(e ** 2)), np.abs(e).max()
+
+
+def test_third_order_where_advection_dominates():
+    e = [_error(n, 1e-5, 0.2) for n in (64, 128, 256)]
+    for a, b in zip(e[:-1], e[1:]):
+        assert np.log2(a[0] / b[0]) > 2.8 and np.log2(a[1] / b[1]) > 2.7, e
+
+
+def test_second_order_where_diffusion_dominates():
+    e = [_error(n, 0.5, 0.01) for n in (32, 64, 128)]
+    for a, b in zip(e[:-1], e[1:]):
+        assert np.log2(a[0] / b[0]) > 1.75 and np.log2(a[1] / b[1]) > 1.75, e
