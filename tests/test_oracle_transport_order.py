@@ -14,7 +14,7 @@ from oracle import transport as OT
 U0, S0, C0 = (1.0, 2.0), 0.12, (-0.3, -0.45)
 
 
-def _error(n, nu, T, cfl=0.5):
+def _error(n, nu, T, c0=C0, cfl=0.5):
     h = 2.0 / n
     g = wl.GridDesc(nx=n, ny=n, x0=-1 + 0.5 * h, y0=-1 + 0.5 * h, h=h, nu=nu)
     geo = OG.Geometry(g, [])
@@ -22,7 +22,7 @@ def _error(n, nu, T, cfl=0.5):
 
     def exact(t):
         s2 = S0 * S0 + 2 * nu * t
-        return (S0 * S0 / s2) * np.exp(-((X - C0[0] - U0[0] * t) ** 2 + (Y - C0[1] - U0[1] * t) ** 2) / (2 * s2))
+        return (S0 * S0 / s2) * np.exp(-((X - c0[0] - U0[0] * t) ** 2 + (Y - c0[1] - U0[1] * t) ** 2) / (2 * s2))
 
     U = np.full((n + 2, n + 2), U0[0])
     V = np.full((n + 2, n + 2), U0[1])
@@ -43,6 +43,8 @@ def test_third_order_where_advection_dominates():
 
 
 def test_second_order_where_diffusion_dominates():
-    e = [_error(n, 0.5, 0.01) for n in (32, 64, 128)]
+    # centred, so that the spread vortex stays below 1e-8 at the domain's
+    # edge (beyond which the free-space transport takes no vorticity)
+    e = [_error(n, 0.5, 0.01, c0=(0.0, 0.0)) for n in (32, 64, 128)]
     for a, b in zip(e[:-1], e[1:]):
         assert np.log2(a[0] / b[0]) > 1.75 and np.log2(a[1] / b[1]) > 1.75, e
