@@ -45,7 +45,9 @@ def test_lgf_matches_closed_forms_and_oracle():
     assert np.max(np.abs(lap)) < 1e-14
 
 
-CASES = [lambda: wl.taylor_couette(128), wl.cylinder_small, lambda: wl.two_c_shapes_lamb_oseen(128)]
+CASES = [lambda: wl.taylor_couette(128), wl.cylinder_small, lambda: wl.two_c_shapes_lamb_oseen(128),
+         lambda: wl.multi_body(512), lambda: wl.batch_serving(2, seed=5)[0], lambda: wl.batch_serving(2, seed=5)[1],
+         lambda: wl.side_by_side_cylinders(d_over_h=32)]
 
 
 @pytest.mark.parametrize("make", CASES)
@@ -139,3 +141,16 @@ def test_argument_errors_of_the_additions():
     keep = []
     arr = iim._body_array(w.bodies, keep)
     assert L.iim_create(C.byref(g), 1, arr, C.byref(o), None, C.byref(out)) == iim.IIM_EINVAL
+
+
+def test_tangent_curve_rejected_by_both():
+    """A circle that touches grid lines (its top, bottom and sides on node
+    lines) is rejected by the library and by the oracle alike."""
+    h = 1.0 / 32
+    g = wl.GridDesc(nx=96, ny=96, x0=0.0, y0=0.0, h=h, exterior="free", u_inf=(1.0, 0.0), nu=0.01)
+    b = wl.BodyDesc(points=wl.circle_points((1.5, 1.5), 8 * h, 128), center=(1.5, 1.5))
+    with pytest.raises(iim.IIMError) as e:
+        iim.Context(g, [b], host_only=True)
+    assert e.value.code == iim.IIM_EGEOM
+    with pytest.raises(OG.GeometryError):
+        OG.Geometry(g, [b])
