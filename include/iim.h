@@ -200,7 +200,9 @@ int iim_get_geometry(const iim_ctx* ctx, iim_geometry_view* out);
  * omega_rigid) s and the centripetal term omega_rigid^2 (x - c).s added to
  * d p / d s; bodies with bc_samples are treated as stationary walls.
  * Synchronises the stream.
- * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts. */
+ * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts and
+ * for contexts given a time-dependent motion (iim_set_body_motion,
+ * iim_rk3_steps_moving), whose wall accelerations the traction leaves out. */
 int iim_surface_loads(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
                       double* point_host, double* body_host);
 
