@@ -254,9 +254,11 @@ int iim_cv_terms(iim_ctx* ctx, const double* omega_dev, const double* u_dev, con
  * t_n + c_s dt with c = (0, 1/3, 3/4), the stage times of the low-storage
  * RK3; afterwards the last stage's motion stays set.  The first call switches
  * the context for good from the composed boundary forms to the chained
- * boundary kernels (which read the boundary-data tables) and to steps without
- * the captured graph; results equal those of a fixed rigid motion when the
- * motion is constant.  Synchronises the stream after every step; stats (may
+ * boundary kernels (which read the boundary-data tables); with the dense
+ * solver the moving steps run from a captured step graph whose stages copy
+ * their tables from device memory staged before each step, and plain steps
+ * run without the graph.  Results equal those of a fixed rigid motion when
+ * the motion is constant.  Synchronises the stream after every step; stats (may
  * be NULL) receives the last step's.
  * IIM_EINVAL on null or non-finite arguments, dt <= 0 or n_steps < 0;
  * IIM_EUNSUPPORTED for host-only contexts and for bodies with bc_samples.

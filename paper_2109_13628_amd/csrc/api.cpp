@@ -813,7 +813,24 @@ int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
     double* out = bufs[s + 1];
     int it;
     double r0, r1;
-    if (c->motion_stage) {
+    if (c->motion_from_dev) {
+      // boundary data of the rigid motion at this stage's time, staged on the
+      // device before the step (device copies: the step may be captured)
+      const int nc = c->geo.nc, na = c->geo.na;
+      const double* src = c->motion_dev + (size_t)s * (4 * nc + na);
+      DGeom& d = c->dg;
+      if (nc) {
+        HIPCHK(hipMemcpyAsync(const_cast<double*>(d.c_psibt), src, nc * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(const_cast<double*>(d.c_ub), src + nc, 2 * nc * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(const_cast<double*>(d.wb_const), src + 3 * nc, nc * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+      }
+      if (na)
+        HIPCHK(hipMemcpyAsync(const_cast<double*>(d.bpsi), src + 4 * nc, na * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    } else if (c->motion_stage) {
       // boundary data of the rigid motion at this stage's time
       const size_t nb = c->geo.bodies.size();
       motion_tables(c, c->motion_stage + 3 * nb * s, c->motion_buf[s]);
@@ -1354,11 +1371,43 @@ int iim_rk3_steps_moving(iim_ctx* c, double* omega, double* Gamma_host, double d
     return fail(c, e.code, e.what());
   }
   // one step at a time: each synchronises the stream (host circulations),
-  // so the per-stage staging vectors are free again before the next step
+  // so the host staging vector is free again before the next step.  With the
+  // dense solver the step runs from the captured graph: the three stages'
+  // tables are staged on the device first and each stage copies its part.
+  const bool graph = c->solver == IIM_SOLVER_DIRECT && c->prof.mask == 0 && c->rec_cap == 0 &&
+                     std::getenv("IIM_NO_GRAPH") == nullptr;
+  const int nc = c->geo.nc, na = c->geo.na;
+  const size_t stride = (size_t)4 * nc + na;
+  try {
+    if (graph && !c->motion_dev && stride) c->motion_dev = c->dalloc<double>(3 * stride);
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
   for (int s = 0; s < n_steps && rc == IIM_OK; ++s) {
-    c->motion_stage = motion + (size_t)s * 9 * nb;
-    rc = iim_rk3_steps(c, omega, Gamma_host, dt, 1, stats);
-    c->motion_stage = nullptr;
+    const double* m = motion + (size_t)s * 9 * nb;
+    if (graph && stride) {
+      try {
+        c->motion_host.resize(3 * stride);
+        for (int q = 0; q < 3; ++q) {
+          motion_tables(c, m + 3 * nb * q, c->motion_buf[q]);
+          std::copy(c->motion_buf[q].begin(), c->motion_buf[q].end(), c->motion_host.begin() + q * stride);
+        }
+        HIPCHK(hipMemcpyAsync(c->motion_dev, c->motion_host.data(), 3 * stride * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
+      } catch (const HipError& e) {
+        return fail(c, e.code, e.what());
+      }
+      c->motion_from_dev = true;
+      c->use_graph = true;
+      rc = iim_rk3_steps(c, omega, Gamma_host, dt, 1, stats);
+      c->use_graph = false;
+      c->motion_from_dev = false;
+    } else {
+      c->motion_stage = m;
+      rc = iim_rk3_steps(c, omega, Gamma_host, dt, 1, stats);
+      c->motion_stage = nullptr;
+    }
+    c->motion_now.assign(m + 6 * nb, m + 9 * nb);
   }
   return rc;
 }

@@ -91,6 +91,12 @@ struct iim_ctx {
   std::vector<double> motion_now;
   const double* motion_stage = nullptr;
   std::vector<double> motion_buf[3];
+  // captured moving steps: the three stages' tables staged on the device
+  // before each step ([3][4 nc + na]); each stage of the step graph copies
+  // its part into the live tables
+  double* motion_dev = nullptr;
+  bool motion_from_dev = false;
+  std::vector<double> motion_host;
   double *Qw = nullptr, *wtmp = nullptr, *wtmp2 = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
   bool have_prev = false;
