@@ -3,7 +3,9 @@ solution: with a uniform velocity (1, 2) and no body, a Gaussian vortex is
 carried and spreads exactly (variance s0^2 + 2 nu t, amplitude s0^2 / that).
 The paper states third order where advection dominates (cell Reynolds number
 above one) and second order where diffusion does; the oracle's RK3 steps of
-its transport right-hand side show both."""
+its transport right-hand side show both, without a body and with the paper's
+C-shaped body in the vortex's path (its boundary vorticity from the exact
+solution, as the paper prescribes its body's boundary data)."""
 import numpy as np
 
 import workloads as wl
@@ -48,3 +50,46 @@ def test_second_order_where_diffusion_dominates():
     e = [_error(n, 0.5, 0.01, c0=(0.0, 0.0)) for n in (32, 64, 128)]
     for a, b in zip(e[:-1], e[1:]):
         assert np.log2(a[0] / b[0]) > 1.75 and np.log2(a[1] / b[1]) > 1.75, e
+
+
+def _error_with_body(n, nu, T, s0=0.06, cfl=0.5):
+    """The same vortex started near the C-shaped body of the paper's
+    transport study (Sec. 3 table: centre (0.507, 0.531), r_a 0.201, r_b
+    0.054, theta_a 0.5, theta_b 2.4) and carried past it, the body's
+    boundary vorticity set to the exact solution at each stage's time (as
+    the paper sets omega_b and u_b of its body to match the solution)."""
+    c0 = (0.35, 0.4)
+    h = 2.0 / n
+    g = wl.GridDesc(nx=n, ny=n, x0=-0.5, y0=-0.5, h=h, nu=nu)
+    body = wl.BodyDesc(points=wl.c_shape_points((0.507, 0.531), 0.201, 0.054, 0.5, 2.4, max(256, int(8.0 / h))),
+                       center=(0.507, 0.531))
+    geo = OG.Geometry(g, [body])
+    X, Y = wl.node_coords(g)
+
+    def exact(x, y, t):
+        s2 = s0 * s0 + 2 * nu * t
+        return (s0 * s0 / s2) * np.exp(-((x - c0[0] - U0[0] * t) ** 2 + (y - c0[1] - U0[1] * t) ** 2) / (2 * s2))
+
+    U = np.full((n + 2, n + 2), U0[0])
+    V = np.full((n + 2, n + 2), U0[1])
+    steps = int(np.ceil(T / (cfl * ONS.dt_max(h, nu, abs(U0[0]) + abs(U0[1])))))
+    dt = T / steps
+    cs = ONS.rk3_stage_times()
+    om = np.where(geo.fluid, exact(X, Y, 0.0), 0.0)
+    for k in range(steps):
+        t = k * dt
+        rhs = lambda st, s: [OT.rhs(geo, st[0], U, V, nu, wb=exact(geo.c_x, geo.c_y, t + cs[s] * dt))[0]]
+        om = ONS.rk3_williamson([om], rhs, dt)[0]
+    e = (om - exact(X, Y, T))[geo.fluid]
+    return np.sqrt(np.mean(e ** 2)), np.abs(e).max()
+
+
+def test_orders_with_a_body():
+    """Advection-dominated (nu 1e-5): third order; diffusion-dominated
+    (nu 0.5): second order, up to the body."""
+    e = [_error_with_body(n, 1e-5, 0.2) for n in (64, 128, 256)]
+    for a, b in zip(e[:-1], e[1:]):
+        assert np.log2(a[0] / b[0]) > 2.8 and np.log2(a[1] / b[1]) > 2.8, e
+    e = [_error_with_body(n, 0.5, 0.01) for n in (32, 64, 128)]
+    for a, b in zip(e[:-1], e[1:]):
+        assert np.log2(a[0] / b[0]) > 1.8 and np.log2(a[1] / b[1]) > 1.7, e
