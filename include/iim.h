@@ -305,6 +305,16 @@ int iim_reconstruct(iim_ctx* ctx, const double* omega_dev, const double* Gamma_h
 int iim_rhs(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
             double* domega_dev, double* dGamma_host, double* omega_b_dev);
 
+/* The same right-hand side with the wall vorticity given instead of computed
+ * from the velocity: omega_b_dev [n_control] (device, the order of
+ * iim_get_geometry) enters the vorticity extensions E4b and E3b, as in the
+ * transport study of Sec. 3, whose body carries the exact solution's
+ * boundary data.  Callers that prescribe the velocity too (a uniform stream)
+ * pass it on the ring, ghost nodes included.  Synchronises the stream.
+ * IIM_EINVAL on null arguments; IIM_EUNSUPPORTED for host-only contexts. */
+int iim_rhs_given_wb(iim_ctx* ctx, const double* omega_dev, const double* u_dev, const double* v_dev,
+                     const double* omega_b_dev, double* domega_dev, double* dGamma_host);
+
 /* One low-storage RK3 step (Sec. 5.5) of (omega, Gamma) in place.
  * omega_dev: grid field; Gamma_host: [n_circ]; dt > 0. */
 int iim_rk3_step(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt,

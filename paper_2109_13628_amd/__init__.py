@@ -26,7 +26,7 @@ NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
 
 # every symbol declared in include/iim.h
-EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
+EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_given_wb", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
            "iim_get_geometry", "iim_dt_max", "iim_lgf_table", "iim_poisson", "iim_poisson_fp32", "iim_reconstruct", "iim_rhs",
            "iim_rk3_step", "iim_rk3_steps", "iim_profile", "iim_profile_read", "iim_krylov_totals", "iim_profile_replay", "iim_solver_counters",
            "iim_net_create", "iim_net_destroy", "iim_net_num_params", "iim_net_get_params", "iim_net_set_params",
@@ -150,6 +150,8 @@ def lib():
     L.iim_surface_loads.restype = ip
     L.iim_surface_loads.argtypes = [vp, vp, vp, vp, dp, dp]
     L.iim_cv_terms.restype = ip
+    L.iim_rhs_given_wb.restype = ip
+    L.iim_rhs_given_wb.argtypes = [vp, vp, vp, vp, vp, vp, dp]
     L.iim_set_body_motion.restype = ip
     L.iim_set_body_motion.argtypes = [vp, dp]
     L.iim_rk3_steps_moving.restype = ip
@@ -348,6 +350,14 @@ class Context:
         dG = np.zeros(max(1, self.n_circ))
         self._check(lib().iim_rhs(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(domega),
                                   dG.ctypes.data_as(C.POINTER(C.c_double)), _ptr(omega_b)), "iim_rhs")
+        return dG[:self.n_circ]
+
+    def rhs_given_wb(self, omega, u, v, omega_b, domega):
+        """Transport right-hand side with the wall vorticity omega_b (device,
+        per control point) given instead of computed from the velocity."""
+        dG = np.zeros(max(1, self.n_circ))
+        self._check(lib().iim_rhs_given_wb(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(omega_b), _ptr(domega),
+                                           dG.ctypes.data_as(C.POINTER(C.c_double))), "iim_rhs_given_wb")
         return dG[:self.n_circ]
 
     def profile(self, mask):

@@ -1312,6 +1312,25 @@ int iim_rhs(iim_ctx* c, const double* omega, const double* u, const double* v, d
   return IIM_OK;
 }
 
+int iim_rhs_given_wb(iim_ctx* c, const double* omega, const double* u, const double* v, const double* omega_b,
+                     double* domega, double* dGamma_host) {
+  if (!c || !omega || !u || !v || !omega_b || !domega || (c->geo.nbc() > 0 && !dGamma_host)) return IIM_EINVAL;
+  if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
+  try {
+    const DGeom& dg = c->dg;
+    launch_extensions_given_wb(dg, omega, omega_b, c->w4, c->w3b, c->w3n, c->stream);
+    launch_transport_all(dg, omega, nullptr, u, v, c->w4, c->w3b, c->w3n, domega, c->Qw, c->dGd, nullptr, nullptr, 0.0,
+                         0.0, 0.0, 0, c->stream);
+    const int nb = c->geo.nbc();
+    if (nb) HIPCHK(hipMemcpyAsync(dGamma_host, c->dGd, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    return fail(c, e.code, e.what());
+  }
+  return IIM_OK;
+}
+
 int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int32_t n_steps, iim_step_stats* stats) {
   if (!c || !omega || (c->geo.nbc() > 0 && !Gamma_host) || !(dt > 0) || n_steps < 0) return IIM_EINVAL;
   if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");

@@ -317,5 +317,8 @@ void launch_cv_volume(const CvBox& b, const int8_t* cls, const double* omega, co
                       double* part, double* out, hipStream_t s);
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s);
+// E4b, E3b, E3n at the ghost nodes from omega and a given wall vorticity wb.
+void launch_extensions_given_wb(const DGeom& g, const double* omega, const double* wb, double* w4, double* w3b,
+                                double* w3n, hipStream_t s);
 
 }  // namespace iim

@@ -28,6 +28,30 @@ __global__ void k_surface_dwdn(DGeom g, const double* __restrict__ omega, const 
   dwdn[c] = g.c_n[c].x * dx + g.c_n[c].y * dy;
 }
 
+// Vorticity extensions E4b, E3b (with the given wall vorticity wb) and E3n at
+// the ghost nodes, for a transport right-hand side whose wall vorticity is
+// prescribed instead of computed from the velocity.
+__global__ void k_extensions_given_wb(DGeom g, const double* __restrict__ omega, const double* __restrict__ wb,
+                                      double* __restrict__ w4, double* __restrict__ w3b, double* __restrict__ w3n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.ng) return;
+  double a4 = 0.0, a3 = 0.0, an = 0.0;
+  for (int e = g.ext4b.ptr[q]; e < g.ext4b.ptr[q + 1]; ++e) a4 += g.ext4b.w[e] * omega[g.ext4b.gidx[e]];
+  for (int e = g.ext4b.bptr[q]; e < g.ext4b.bptr[q + 1]; ++e) a4 += g.ext4b.bw[e] * wb[g.ext4b.bc[e]];
+  for (int e = g.ext3b.ptr[q]; e < g.ext3b.ptr[q + 1]; ++e) a3 += g.ext3b.w[e] * omega[g.ext3b.gidx[e]];
+  for (int e = g.ext3b.bptr[q]; e < g.ext3b.bptr[q + 1]; ++e) a3 += g.ext3b.bw[e] * wb[g.ext3b.bc[e]];
+  for (int e = g.ext3n.ptr[q]; e < g.ext3n.ptr[q + 1]; ++e) an += g.ext3n.w[e] * omega[g.ext3n.gidx[e]];
+  const int gi = g.g_gidx[q];
+  w4[gi] = a4;
+  w3b[gi] = a3;
+  w3n[gi] = an;
+}
+
+void launch_extensions_given_wb(const DGeom& g, const double* omega, const double* wb, double* w4, double* w3b,
+                                double* w3n, hipStream_t s) {
+  if (g.ng) k_extensions_given_wb<<<(g.ng + 127) / 128, 128, 0, s>>>(g, omega, wb, w4, w3b, w3n);
+}
+
 void launch_surface_dwdn(const DGeom& g, const double* omega, const double* w3b, const double* wb, double* dwdn,
                          hipStream_t s) {
   if (g.nc) k_surface_dwdn<<<(g.nc + 127) / 128, 128, 0, s>>>(g, omega, w3b, wb, dwdn);

@@ -113,6 +113,8 @@ def test_argument_errors_of_the_additions():
     assert L.iim_surface_loads(h, one, one, one, two, two) == iim.IIM_EUNSUPPORTED
     assert L.iim_surface_loads(None, one, one, one, two, two) == iim.IIM_EINVAL
     assert L.iim_set_body_motion(h, None) == iim.IIM_EINVAL
+    assert L.iim_rhs_given_wb(h, one, one, one, None, one, two) == iim.IIM_EINVAL
+    assert L.iim_rhs_given_wb(h, one, one, one, one, one, two) == iim.IIM_EUNSUPPORTED
     assert L.iim_set_body_motion(h, two) == iim.IIM_EUNSUPPORTED
     assert L.iim_rk3_steps_moving(h, one, two, C.c_double(0.1), 1, None, None) == iim.IIM_EINVAL
     assert L.iim_rk3_steps_moving(h, one, two, C.c_double(-0.1), 1, two, None) == iim.IIM_EINVAL
