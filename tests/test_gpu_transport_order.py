@@ -130,8 +130,9 @@ def test_orders_with_a_body():
     from the exact solution at each stage's time, at N = 128 ... 512.
     Advection-dominated: L2 third order (measured 3.09, 2.78); L-infinity
     third order to N = 256 (3.04) and second order from 256 to 512 (2.02,
-    at nodes next to the body, unchanged when dt is quartered).  Diffusion-
-    dominated: second order."""
+    at nodes next to the body, unchanged when dt is quartered: the downwind
+    stencils that the method forces at inflow boundary faces are second order,
+    as Sec. 3 states).  Diffusion-dominated: second order."""
     e = [_body_error(n, 1e-5, 0.2) for n in (128, 256, 512)]
     print(e)
     orders = [(np.log2(a[0] / b[0]), np.log2(a[1] / b[1])) for a, b in zip(e[:-1], e[1:])]
