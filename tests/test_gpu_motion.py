@@ -239,3 +239,23 @@ def test_motion_argument_checks():
     G, _ = ctx.rk3_steps_moving(om, np.zeros(1), 1e-3, np.zeros((0, 3, 1, 3)))   # zero steps
     assert G[0] == 0.0
     ctx.close()
+
+
+def test_control_volume_follows_the_current_motion():
+    """iim_cv_terms decides from the current motion whether a body inside the
+    box moves: refused while it rotates, accepted once its motion is zero."""
+    w = wl.cylinder_small()
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    om = torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device="cuda:0")
+    U, V = ring_zeros(w.grid), ring_zeros(w.grid)
+    h = w.grid.h
+    box = (int(round((0.7 - w.grid.x0) / h)), int(round((2.4 - w.grid.x0) / h)),
+           int(round((-0.8 - w.grid.y0) / h)), int(round((0.8 - w.grid.y0) / h)))
+    ctx.cv_terms(om, U, V, box)                       # stationary body: accepted
+    ctx.set_body_motion([0.0, 0.0, 0.7])
+    with pytest.raises(iim.IIMError) as e:
+        ctx.cv_terms(om, U, V, box)
+    assert e.value.code == iim.IIM_EUNSUPPORTED
+    ctx.set_body_motion([0.0, 0.0, 0.0])
+    ctx.cv_terms(om, U, V, box)
+    ctx.close()
