@@ -49,6 +49,12 @@ def _parse():
     return p.parse_args()
 
 
+def _say(msg):
+    """One progress line on stderr, flushed at once: it names the leg that is
+    about to run, so a run that dies shows where."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profile_kernels=None, tol=1e-13,
               net=None, per_step=False, tiles=None):
     g = w.grid
@@ -269,11 +275,13 @@ def main():
     # a scratch context, outside every measurement)
     tiles = None
     if not args.no_autotune:
+        _say("autotune of the FFT tile shapes")
         tctx = iim.Context(g, w.bodies, precision=prec, solver=iim.SOLVER_KRYLOV)
         tiles = tctx.autotune(reps=10)
         tctx.close()
     # headline path: warm-up (kernels timed with events only to find the dominant
     # one), then exactly `steps` timed steps without instrumentation
+    _say("headline path: %d warm-up and %d timed steps on %s" % (args.warmup, args.steps, w.name))
     ctx, omega, Gamma, head, pre = _run_path(iim, w, torch, np, prec, solver, iim.GUESS_PREVIOUS,
                                              args.warmup, args.steps, profile_kernels=all_kernels, tiles=tiles)
     dominant = max(pre, key=lambda k: pre[k]["total_ms"]) if pre else "fft_cols_conv"
@@ -285,6 +293,7 @@ def main():
     # then its largest launch repeated back to back between one event pair
     # (per-launch events also time the dispatch latency that back-to-back
     # launches hide, which a kernel profiler does not count)
+    _say("roofline timing of %s" % dominant)
     ctx.profile(1 << iim.KERNEL_NAMES.index(dominant))
     Gamma, _ = ctx.rk3_steps(omega, Gamma, w.dt, args.steps)
     torch.cuda.synchronize()
@@ -315,12 +324,15 @@ def main():
         kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles)
         for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
             for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
+                _say("GMRES path %s, guess %s" % (p_name, g_name))
                 c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
                 paths["%s_krylov_%s" % (p_name, g_name)] = r_
                 c_.close()
         if args.train_runs:
+            _say("warm-start network: %d recorded runs, %d training iterations" % (args.train_runs, args.train_iters))
             net, warm = _train_network(iim, w, torch, np, args.train_runs, args.train_steps, args.train_iters)
             for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+                _say("GMRES path %s, guess network" % p_name)
                 c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, iim.GUESS_NETWORK,
                                             net=net, **kw)
                 paths["%s_krylov_network" % p_name] = r_
@@ -354,13 +366,16 @@ def main():
         "kernel_time_share_warmup": shares,
     }
     if args.batch_sims:
+        _say("batch of %d simulations" % args.batch_sims)
         out["batch"] = _batch(iim, wl, torch, np, args.batch_sims, args.batch_steps)
     if not args.no_cpu_baseline:
+        _say("CPU baseline: the oracle over %d steps" % args.cpu_steps)
         cpu, ref_state = _cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"] = cpu
         # the state after the same steps from rest on the mixed-precision
         # network path (GMRES to the same tolerance as 'paths') against the
         # FP64 oracle: vorticity and velocity relative errors
+        _say("accuracy of the library's state against the oracle's")
         out["accuracy_vs_oracle"] = _accuracy(iim, w, torch, np, ref_state, net, args.krylov_tol)
     if args.copy_probe:
         # one copy kernel that reads and writes exactly 256 MiB: the reference
@@ -371,7 +386,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = src.numel() * 4
-    print(json.dumps(out))
+    # flushed at once: the line is on its way before the contexts are torn down
+    print(json.dumps(out), flush=True)
+    _say("result written")
 
 
 def _batch(iim, wl, torch, np, n_sims, steps):
