@@ -242,6 +242,16 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _gamma_array(Gamma, n_circ):
+    """Host copy of the body circulations with room for the n_circ values the
+    library reads and writes back (at least one element, so that the pointer
+    is valid when there are none)."""
+    G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).reshape(-1).copy()
+    if G.size < n_circ:
+        raise ValueError("expected %d body circulations, got %d" % (n_circ, G.size))
+    return G if G.size else np.zeros(1)
+
+
 class Context:
     """One IIM problem (grid + bodies) on the current device."""
 
@@ -314,7 +324,7 @@ class Context:
         self._check(lib().iim_poisson_fp32(self._h, _ptr(src), _ptr(psi)), "iim_poisson_fp32")
 
     def reconstruct(self, omega, Gamma, psi, u, v, allow_noconv=False):
-        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64)))
+        G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
         rc = lib().iim_reconstruct(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), _ptr(psi),
                                    _ptr(u), _ptr(v), C.byref(st))
@@ -403,9 +413,7 @@ class Context:
         return s.value, m.value
 
     def rk3_steps(self, omega, Gamma, dt, n_steps=1):
-        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).copy()
-        if G.size == 0:
-            G = np.zeros(1)
+        G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
         self._check(lib().iim_rk3_steps(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                         n_steps, C.byref(st)), "iim_rk3_steps")
@@ -425,9 +433,7 @@ class Context:
         m = np.ascontiguousarray(motion, dtype=np.float64)
         if m.ndim != 4 or m.shape[1:] != (3, self.n_bodies, 3):
             raise ValueError("expected motion of shape (n_steps, 3, %d, 3)" % self.n_bodies)
-        G = np.ascontiguousarray(np.atleast_1d(np.asarray(Gamma, dtype=np.float64))).copy()
-        if G.size == 0:
-            G = np.zeros(1)
+        G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
         self._check(lib().iim_rk3_steps_moving(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                                m.shape[0], m.ctypes.data_as(C.POINTER(C.c_double)),
@@ -624,7 +630,10 @@ class Batch:
         gammas: list of float64 numpy arrays (in place); dts: per simulation."""
         n = self.n
         om = (C.c_void_p * n)(*[_ptr(t) for t in omegas])
-        gs = [np.ascontiguousarray(g, dtype=np.float64) if np.size(g) else np.zeros(1) for g in gammas]
+        if not (len(omegas) == len(gammas) == len(dts) == n):
+            raise ValueError("expected %d vorticity fields, circulation arrays and time steps" % n)
+        gs = [_gamma_array(g, len([b for b in w.bodies if not b.is_enclosure]))
+              for g, w in zip(gammas, self.workloads)]
         gp = (C.POINTER(C.c_double) * n)(*[g.ctypes.data_as(C.POINTER(C.c_double)) for g in gs])
         dt = (C.c_double * n)(*dts)
         st = BatchStats()

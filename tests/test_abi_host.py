@@ -156,3 +156,22 @@ def test_tangent_curve_rejected_by_both():
     assert e.value.code == iim.IIM_EGEOM
     with pytest.raises(OG.GeometryError):
         OG.Geometry(g, [b])
+
+
+def test_binding_refuses_short_circulation_arrays():
+    """The library reads n_circ circulations and writes them back into the
+    caller's array: the binding refuses an array too short for them before
+    any call reaches the library (two bodies, two circulations)."""
+    w = wl.two_c_shapes_lamb_oseen(128)
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    assert ctx.n_circ == 2
+    for call in (lambda G: ctx.rk3_steps(None, G, 0.01, 1),
+                 lambda G: ctx.reconstruct(None, G, None, None, None),
+                 lambda G: ctx.rk3_steps_moving(None, G, 0.01, np.zeros((1, 3, ctx.n_bodies, 3)))):
+        for G in ([], [0.0], np.zeros(ctx.n_circ - 1)):
+            with pytest.raises(ValueError, match="circulations"):
+                call(G)
+    ctx.close()
+    # the copy handed to the library keeps n_circ entries and at least one
+    assert iim._gamma_array([], 0).shape == (1,)
+    assert iim._gamma_array([1.0, 2.0, 3.0], 2).tolist() == [1.0, 2.0, 3.0]
