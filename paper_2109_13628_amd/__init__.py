@@ -527,12 +527,25 @@ class Network:
         self._check(lib().iim_net_set_params(self._h, flat.ctypes.data_as(C.c_void_p), flat.size),
                     "iim_net_set_params")
 
-    def forward(self, x, seq, y):
+    def _shapes(self, x, seq, out):
+        """Batch and length from x [batch][P][in_channels]; seq must be
+        [3][P] and the output or target [batch][P], so that no kernel reads
+        or writes past a buffer."""
+        if x.dim() != 3 or x.shape[2] != self.shape[0]:
+            raise ValueError("x must be [batch][P][%d]" % self.shape[0])
         B, P = x.shape[0], x.shape[1]
+        if tuple(seq.shape) != (3, P):
+            raise ValueError("seq must be [3][%d]" % P)
+        if out.numel() != B * P:
+            raise ValueError("output and target must hold batch * P = %d values" % (B * P))
+        return B, P
+
+    def forward(self, x, seq, y):
+        B, P = self._shapes(x, seq, y)
         self._check(lib().iim_net_forward(self._h, _fptr(x), B, P, _fptr(seq, "int32"), _fptr(y)), "iim_net_forward")
 
     def grad_mse(self, x, seq, target):
-        B, P = x.shape[0], x.shape[1]
+        B, P = self._shapes(x, seq, target)
         loss = C.c_float()
         self._check(lib().iim_net_grad_mse(self._h, _fptr(x), B, P, _fptr(seq, "int32"), _fptr(target),
                                            C.byref(loss)), "iim_net_grad_mse")

@@ -206,3 +206,23 @@ def test_learned_guess_in_the_krylov_solve():
     for k, v in out.items():
         e = rel(v[0], om, mask=geo.fluid)
         assert e < 1e-8, (k, e)
+
+
+def test_binding_refuses_mismatched_shapes():
+    """x, seq and the output or target must agree in batch and length: the
+    binding raises before any kernel can read or write past a buffer."""
+    sizes = SIZES["small"]
+    X, T, params, flat = _case(sizes, [40, 24], B=2, seed=3)
+    net = iim.Network(in_channels=sizes[0], width=sizes[1], layers=len(sizes) - 1, bf16=False)
+    seq = torch.as_tensor(_segments([40, 24]), device=DEV)
+    x, t = _dev32(X), _dev32(T)
+    y = torch.zeros((X.shape[0], X.shape[1]), dtype=torch.float32, device=DEV)
+    for args in ((x, seq[:, :-1], y), (x, seq, y[:, :-1]), (x, seq, y[:1]), (x[:, :, :-1], seq, y), (x[0], seq, y)):
+        with pytest.raises(ValueError):
+            net.forward(*args)
+    with pytest.raises(ValueError):
+        net.grad_mse(x, seq, t[:, :-1])
+    net.forward(x, seq, y)              # the consistent call still runs
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(y).all())
+    net.close()
