@@ -242,6 +242,14 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _sized(t, n, what):
+    """_ptr of a tensor that must hold at least n values (None -> NULL)."""
+    p = _ptr(t)
+    if t is not None and t.numel() < n:
+        raise ValueError("%s needs at least %d values, got %d" % (what, n, t.numel()))
+    return p
+
+
 def _gamma_array(Gamma, n_circ):
     """Host copy of the body circulations with room for the n_circ values the
     library reads and writes back (at least one element, so that the pointer
@@ -297,6 +305,16 @@ class Context:
             raise IIMError(rc, "%s: %s" % (what, (lib().iim_last_error(self._h) or b"").decode()))
         return rc
 
+    # device arguments, checked against the sizes the kernels index
+    def _grid(self, t):
+        return _sized(t, self.grid.nx * self.grid.ny, "a grid field [ny][nx]")
+
+    def _ring(self, t):
+        return _sized(t, (self.grid.nx + 2) * (self.grid.ny + 2), "a ring field [ny+2][nx+2]")
+
+    def _ctrl(self, t):
+        return _sized(t, self.info["n_control"], "a control-point array")
+
     def geometry(self):
         v = GeometryView()
         self._check(lib().iim_get_geometry(self._h, C.byref(v)), "iim_get_geometry")
@@ -318,16 +336,16 @@ class Context:
         return d.value
 
     def poisson(self, src, psi):
-        self._check(lib().iim_poisson(self._h, _ptr(src), _ptr(psi)), "iim_poisson")
+        self._check(lib().iim_poisson(self._h, self._grid(src), self._ring(psi)), "iim_poisson")
 
     def poisson_fp32(self, src, psi):
-        self._check(lib().iim_poisson_fp32(self._h, _ptr(src), _ptr(psi)), "iim_poisson_fp32")
+        self._check(lib().iim_poisson_fp32(self._h, self._grid(src), self._ring(psi)), "iim_poisson_fp32")
 
     def reconstruct(self, omega, Gamma, psi, u, v, allow_noconv=False):
         G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
-        rc = lib().iim_reconstruct(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), _ptr(psi),
-                                   _ptr(u), _ptr(v), C.byref(st))
+        rc = lib().iim_reconstruct(self._h, self._grid(omega), G.ctypes.data_as(C.POINTER(C.c_double)),
+                                   self._ring(psi), self._ring(u), self._ring(v), C.byref(st))
         self._check(rc, "iim_reconstruct", allow=(IIM_ENOCONV,) if allow_noconv else ())
         return st.as_dict()
 
@@ -337,7 +355,7 @@ class Context:
         nc = self.info["n_control"]
         pts = np.zeros((max(1, nc), 4))
         bod = np.zeros((max(1, self.n_bodies), 3))
-        self._check(lib().iim_surface_loads(self._h, _ptr(omega), _ptr(u), _ptr(v),
+        self._check(lib().iim_surface_loads(self._h, self._grid(omega), self._ring(u), self._ring(v),
                                             pts.ctypes.data_as(C.POINTER(C.c_double)),
                                             bod.ctypes.data_as(C.POINTER(C.c_double))), "iim_surface_loads")
         return {"omega_b": pts[:nc, 0].copy(), "tau": pts[:nc, 1].copy(), "dwdn": pts[:nc, 2].copy(),
@@ -351,22 +369,23 @@ class Context:
         b = (C.c_int32 * 4)(*[int(q) for q in box])
         o = np.ascontiguousarray(origin, dtype=np.float64)
         out = np.zeros(6)
-        self._check(lib().iim_cv_terms(self._h, _ptr(omega), _ptr(u), _ptr(v), b,
+        self._check(lib().iim_cv_terms(self._h, self._grid(omega), self._ring(u), self._ring(v), b,
                                        o.ctypes.data_as(C.POINTER(C.c_double)),
                                        out.ctypes.data_as(C.POINTER(C.c_double))), "iim_cv_terms")
         return {"S_t": out[:2].copy(), "S_gamma": out[2:4].copy(), "I": float(out[4]), "S_lambda": float(out[5])}
 
     def rhs(self, omega, u, v, domega, omega_b=None):
         dG = np.zeros(max(1, self.n_circ))
-        self._check(lib().iim_rhs(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(domega),
-                                  dG.ctypes.data_as(C.POINTER(C.c_double)), _ptr(omega_b)), "iim_rhs")
+        self._check(lib().iim_rhs(self._h, self._grid(omega), self._ring(u), self._ring(v), self._grid(domega),
+                                  dG.ctypes.data_as(C.POINTER(C.c_double)), self._ctrl(omega_b)), "iim_rhs")
         return dG[:self.n_circ]
 
     def rhs_given_wb(self, omega, u, v, omega_b, domega):
         """Transport right-hand side with the wall vorticity omega_b (device,
         per control point) given instead of computed from the velocity."""
         dG = np.zeros(max(1, self.n_circ))
-        self._check(lib().iim_rhs_given_wb(self._h, _ptr(omega), _ptr(u), _ptr(v), _ptr(omega_b), _ptr(domega),
+        self._check(lib().iim_rhs_given_wb(self._h, self._grid(omega), self._ring(u), self._ring(v), self._ctrl(omega_b),
+                                           self._grid(domega),
                                            dG.ctypes.data_as(C.POINTER(C.c_double))), "iim_rhs_given_wb")
         return dG[:self.n_circ]
 
@@ -415,7 +434,7 @@ class Context:
     def rk3_steps(self, omega, Gamma, dt, n_steps=1):
         G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
-        self._check(lib().iim_rk3_steps(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
+        self._check(lib().iim_rk3_steps(self._h, self._grid(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                         n_steps, C.byref(st)), "iim_rk3_steps")
         return G[:self.n_circ], st.as_dict()
 
@@ -435,7 +454,7 @@ class Context:
             raise ValueError("expected motion of shape (n_steps, 3, %d, 3)" % self.n_bodies)
         G = _gamma_array(Gamma, self.n_circ)
         st = StepStats()
-        self._check(lib().iim_rk3_steps_moving(self._h, _ptr(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
+        self._check(lib().iim_rk3_steps_moving(self._h, self._grid(omega), G.ctypes.data_as(C.POINTER(C.c_double)), dt,
                                                m.shape[0], m.ctypes.data_as(C.POINTER(C.c_double)),
                                                C.byref(st)), "iim_rk3_steps_moving")
         return G[:self.n_circ], st.as_dict()
@@ -642,7 +661,8 @@ class Batch:
         """omegas: contiguous float64 CUDA tensors [ny][nx] (in place);
         gammas: list of float64 numpy arrays (in place); dts: per simulation."""
         n = self.n
-        om = (C.c_void_p * n)(*[_ptr(t) for t in omegas])
+        om = (C.c_void_p * n)(*[_sized(t, w.grid.nx * w.grid.ny, "a grid field [ny][nx]")
+                                for t, w in zip(omegas, self.workloads)])
         if not (len(omegas) == len(gammas) == len(dts) == n):
             raise ValueError("expected %d vorticity fields, circulation arrays and time steps" % n)
         gs = [_gamma_array(g, len([b for b in w.bodies if not b.is_enclosure]))
