@@ -107,3 +107,27 @@ def test_krylov_limit_reports_no_convergence():
         ctx.rk3_steps(d, np.array([0.1]), w.dt, 1)
     assert e.value.code == iim.IIM_ENOCONV
     ctx.close()
+
+
+def test_binding_refuses_undersized_device_tensors():
+    """Grid fields [ny][nx], ring fields [ny+2][nx+2] and per-control-point
+    arrays smaller than the kernels index are refused before any launch."""
+    import numpy as _np
+    import torch as _torch
+    import workloads as _wl
+    import paper_2109_13628_amd as _iim
+    w = _wl.cylinder_small()
+    g = w.grid
+    ctx = _iim.Context(g, w.bodies, solver=_iim.SOLVER_DIRECT)
+    z = lambda *s: _torch.zeros(s, dtype=_torch.float64, device="cuda:0")
+    om, ring, small = z(g.ny, g.nx), z(g.ny + 2, g.nx + 2), z(g.ny, g.nx - 1)
+    G = _np.zeros(ctx.n_circ)
+    with pytest.raises(ValueError, match="ring"):
+        ctx.reconstruct(om, G, None, om, ring)        # a grid-sized tensor where a ring is needed
+    with pytest.raises(ValueError, match="grid"):
+        ctx.rk3_steps(small, G, w.dt, 1)
+    with pytest.raises(ValueError, match="control"):
+        ctx.rhs_given_wb(om, ring, ring, z(max(0, ctx.info["n_control"] - 1)), om)
+    ctx.reconstruct(om, G, None, ring, z(g.ny + 2, g.nx + 2))   # the right sizes still run
+    _torch.cuda.synchronize()
+    ctx.close()
