@@ -38,7 +38,7 @@ def _parse():
     p.add_argument("--batch-steps", type=int, default=20)
     p.add_argument("--no-autotune", action="store_true", help="keep the default FFT tile shapes on the headline path")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=10)
+    p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
                    help="write the text summary of a rocprofv3 --kernel-trace --stats run and exit")
     p.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
@@ -46,6 +46,12 @@ def _parse():
     p.add_argument("--command", default="", help="command line recorded in a summary")
     p.add_argument("--copy-probe", action="store_true",
                    help="end with one plain device copy of 256 MiB (scale reference for HBM byte counters)")
+    p.add_argument("--batch-only", action="store_true",
+                   help="run only the batched-serving leg and print its JSON object (the benchmark runs this "
+                        "in a child process)")
+    p.add_argument("--batch-timeout", type=float, default=420.0, help="seconds allowed for the batch child process")
+    p.add_argument("--cpu-single-steps", type=int, default=3,
+                   help="oracle steps timed on one core beside the multi-core CPU baseline (0: none)")
     return p.parse_args()
 
 
@@ -256,13 +262,22 @@ def main():
         _summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2], args.command)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
     import workloads as wl
     import paper_2109_13628_amd as iim
+
+    if args.batch_only:
+        try:
+            res = _batch(iim, wl, torch, np, args.batch_sims, args.batch_steps)
+        except Exception as e:   # reported to the parent as the leg's result
+            res = {"error": repr(e)}
+        print(json.dumps(res), flush=True)
+        sys.exit(3 if "error" in res else 0)
+    failed = []
 
     w = wl.cylinder()
     g = w.grid
@@ -320,27 +335,17 @@ def main():
     paths = {tag + "_" + args.solver: head}
     warm = None
     net = None
+    try:
+        paths.update(_extra_workloads(iim, wl, torch, np))
+    except Exception as e:       # recorded; the other legs still run
+        failed.append("workloads")
+        paths["workloads_error"] = repr(e)
     if args.krylov_steps:
-        kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles)
-        for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
-            for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
-                _say("GMRES path %s, guess %s" % (p_name, g_name))
-                c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
-                paths["%s_krylov_%s" % (p_name, g_name)] = r_
-                c_.close()
-        if args.train_runs:
-            _say("warm-start network: %d recorded runs, %d training iterations" % (args.train_runs, args.train_iters))
-            net, warm = _train_network(iim, w, torch, np, args.train_runs, args.train_steps, args.train_iters)
-            for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
-                _say("GMRES path %s, guess network" % p_name)
-                c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, iim.GUESS_NETWORK,
-                                            net=net, **kw)
-                paths["%s_krylov_network" % p_name] = r_
-                c_.close()
-        base = paths["fp64_krylov_previous"]["ms_per_step"]
-        warm = warm or {}
-        warm["speedup_vs_fp64_krylov_previous"] = {k: base / v["ms_per_step"] for k, v in paths.items()
-                                                  if "krylov" in k}
+        try:
+            net, warm = _krylov_paths(iim, w, torch, np, args, tiles, paths)
+        except Exception as e:   # recorded; the other legs still run
+            failed.append("krylov_paths")
+            paths["krylov_error"] = repr(e)
 
     out = {
         "metric": "RK3 step cell-updates/s at 1e-8 rel. error; FP64 plain vs mixed+learned warm-start",
@@ -365,18 +370,42 @@ def main():
         "roofline": roof,
         "kernel_time_share_warmup": shares,
     }
-    if args.batch_sims:
-        _say("batch of %d simulations" % args.batch_sims)
-        out["batch"] = _batch(iim, wl, torch, np, args.batch_sims, args.batch_steps)
+    if "fp64_krylov_previous" in paths and "mixed_krylov_network" in paths:
+        # the metric's named comparison on the paper's iterative solve:
+        # plain FP64 GMRES against mixed precision with the learned guess
+        a, b = paths["fp64_krylov_previous"], paths["mixed_krylov_network"]
+        out["comparison"] = {"fp64_krylov_previous_cell_updates_per_s": a["value"],
+                             "mixed_krylov_network_cell_updates_per_s": b["value"],
+                             "speedup": b["value"] / a["value"],
+                             "direct_fp64_cell_updates_per_s": head["value"]}
     if not args.no_cpu_baseline:
-        _say("CPU baseline: the oracle over %d steps" % args.cpu_steps)
-        cpu, ref_state = _cpu_baseline(w, args.cpu_steps)
-        out["cpu_baseline"] = cpu
-        # the state after the same steps from rest on the mixed-precision
-        # network path (GMRES to the same tolerance as 'paths') against the
-        # FP64 oracle: vorticity and velocity relative errors
-        _say("accuracy of the library's state against the oracle's")
-        out["accuracy_vs_oracle"] = _accuracy(iim, w, torch, np, ref_state, net, args.krylov_tol)
+        ref_state = None
+        try:
+            _say("CPU baseline: the oracle over %d steps (and %d on one core)" % (args.cpu_steps,
+                                                                               args.cpu_single_steps))
+            cpu, ref_state = _cpu_baseline(w, args.cpu_steps, args.cpu_single_steps)
+            out["cpu_baseline"] = cpu
+        except Exception as e:
+            failed.append("cpu_baseline")
+            out["cpu_baseline"] = {"error": repr(e)}
+        if ref_state is not None:
+            # the state after the same steps from rest on the FP64 direct path
+            # and on the mixed-precision network path (GMRES to the same
+            # tolerance as 'paths') against the FP64 oracle
+            try:
+                _say("accuracy of the library's state against the oracle's")
+                out["accuracy_vs_oracle"] = _accuracy(iim, w, torch, np, ref_state, net, args.krylov_tol)
+            except Exception as e:
+                failed.append("accuracy")
+                out["accuracy_vs_oracle"] = {"error": repr(e)}
+    if args.batch_sims:
+        # in a child process: a failure there cannot take this line with it
+        _say("batch of %d simulations (child process)" % args.batch_sims)
+        out["batch"] = _batch_child(args)
+        if "error" in out["batch"]:
+            failed.append("batch")
+    if failed:
+        out["legs_failed"] = failed
     if args.copy_probe:
         # one copy kernel that reads and writes exactly 256 MiB: the reference
         # for converting FETCH_SIZE / WRITE_SIZE counters into bytes
@@ -389,21 +418,102 @@ def main():
     # flushed at once: the line is on its way before the contexts are torn down
     print(json.dumps(out), flush=True)
     _say("result written")
+    if failed:
+        _say("legs failed: %s" % ", ".join(failed))
+        sys.exit(3)
+
+
+def _krylov_paths(iim, w, torch, np, args, tiles, paths):
+    """The paper's iterative solve (GMRES with the FFT product) in FP64 and in
+    mixed precision, with the previous-stage, extrapolated and network
+    guesses; fills `paths` and returns the trained network and its record."""
+    kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles)
+    for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+        for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
+            _say("GMRES path %s, guess %s" % (p_name, g_name))
+            c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
+            paths["%s_krylov_%s" % (p_name, g_name)] = r_
+            c_.close()
+    net, warm = None, {}
+    if args.train_runs:
+        _say("warm-start network: %d recorded runs, %d training iterations" % (args.train_runs, args.train_iters))
+        net, warm = _train_network(iim, w, torch, np, args.train_runs, args.train_steps, args.train_iters)
+        for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+            _say("GMRES path %s, guess network" % p_name)
+            c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, iim.GUESS_NETWORK,
+                                        net=net, **kw)
+            paths["%s_krylov_network" % p_name] = r_
+            c_.close()
+    base = paths["fp64_krylov_previous"]["ms_per_step"]
+    warm["speedup_vs_fp64_krylov_previous"] = {k: base / v["ms_per_step"] for k, v in paths.items()
+                                              if "krylov" in k and "ms_per_step" in v}
+    return net, warm
+
+
+def _batch_child(args):
+    """The batched-serving leg in a child process (its own HIP runtime and
+    device memory); its JSON object, or the failure."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--batch-only", "--batch-sims", str(args.batch_sims),
+           "--batch-steps", str(args.batch_steps)]
+    # the child's progress lines go straight to this process's stderr
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=args.batch_timeout)
+    except subprocess.TimeoutExpired:
+        return {"error": "timed out after %.0f s" % args.batch_timeout}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    res = json.loads(lines[-1]) if lines else {}
+    if r.returncode != 0 and "error" not in res:
+        res["error"] = "exit status %d" % r.returncode
+    return res
+
+
+def _extra_workloads(iim, wl, torch, np):
+    """The other single-GPU configurations, FP64 dense solver, graph replay:
+    Taylor-Couette in the DST box (128 x 128, 20 steps) and four nonconvex
+    bodies with an outflow plane (2048 x 2048)."""
+    res = {}
+    for name, w, warm, steps in (("taylor_couette_128_box", wl.taylor_couette(128), 5, 20),
+                                 ("multi_body_2048_outflow", wl.multi_body(2048), 3, 10)):
+        _say("workload %s: %d warm-up and %d timed steps" % (w.name, warm, steps))
+        t0 = time.perf_counter()
+        ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        om = torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device="cuda:0")
+        G = np.zeros(ctx.n_circ)
+        G, _ = ctx.rk3_steps(om, G, w.dt, warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G, _ = ctx.rk3_steps(om, G, w.dt, steps)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        inf = ctx.info
+        res[name] = {"value": w.grid.nx * w.grid.ny * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "steps": steps, "unit": "cell-updates/s", "nx": w.grid.nx, "ny": w.grid.ny,
+                     "bodies": len(w.bodies), "schur_unknowns": inf["n_affected"] + inf["n_circ"],
+                     "fft": [inf["fft_mx"], inf["fft_my"]], "dt": w.dt, "setup_s": setup,
+                     "finite": bool(torch.isfinite(om).all())}
+        ctx.close()
+    return res
 
 
 def _batch(iim, wl, torch, np, n_sims, steps):
     """Batched serving: n_sims independent simulations advanced by one HIP
     graph per batch step; aggregate throughput and batch-step latency."""
     ws = wl.batch_serving(n_sims, seed=5)
+    _say("batch: creating %d simulations (dense Schur inverses, tile autotune, branch timing)" % n_sims)
     t0 = time.perf_counter()
     b = iim.Batch(ws)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     info = b.info()
+    _say("batch: created in %.1f s, %d branches; warm-up steps" % (setup, info["branches"]))
     oms = [torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device="cuda:0") for w in ws]
     Gs = [np.zeros(len(w.bodies)) for w in ws]
     dts = [w.dt for w in ws]
     b.step(oms, Gs, dts, 3)                  # graph capture + warm-up
+    _say("batch: %d timed steps" % steps)
     st = b.step(oms, Gs, dts, steps)
     torch.cuda.synchronize()
     finite = all(bool(torch.isfinite(o).all()) for o in oms)
@@ -413,6 +523,7 @@ def _batch(iim, wl, torch, np, n_sims, steps):
             "step_ms_p50": st["ms_p50"], "step_ms_p99": st["ms_p99"], "step_ms_max": st["ms_max"],
             "setup_s": setup, "branches": info["branches"], "branch_ms_tried": info["branch_ms"],
             "fft_tiles": info["tuning"], "finite": finite, "dtype": "f64",
+            "branch_notes": info.get("notes"),
             "workload": "%d free-space simulations from rest, N x N nodes with N uniform in [256, 1024] on a 4 x 4 "
                         "domain, 1-6 seeded circles/ellipses each, u_inf = 1, Re uniform in [50, 500]" % n_sims,
             "timing": "HIP events around every batch-step graph launch"}
@@ -448,13 +559,19 @@ def _accuracy(iim, w, torch, np, ref, net, tol):
     return res
 
 
-def _cpu_baseline(w, steps):
+def _cpu_baseline(w, steps, single_steps):
     """The FP64 oracle, timed on this host's cores over a bounded sample of the
-    same workload (a few RK3 steps from rest; set-up excluded).  Also returns
-    its final state for the accuracy check."""
+    same workload (RK3 steps from rest; set-up excluded), and on one core over
+    a few more steps.  Also returns its state after the multi-core steps for
+    the accuracy check.  The host share of one GPU is 16 cores, so at most 16
+    threads are used."""
     import numpy as np
     import scipy.fft as sfft
     from oracle import geometry as OG, ns as ONS
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:          # BLAS threads then stay as configured
+        threadpool_limits = None
     cores = len(os.sched_getaffinity(0))
     cores = max(1, min(cores, 16))
     geo = OG.Geometry(w.grid, w.bodies)
@@ -470,8 +587,34 @@ def _cpu_baseline(w, steps):
     cpu = {"value": w.grid.nx * w.grid.ny * steps / secs, "unit": "cell-updates/s", "cores": cores,
            "kind": "oracle",
            "sample": "%d RK3 steps of the same 1024x512 cylinder workload after one set-up step from rest "
-                     "(FP64 NumPy/SciPy, dense Schur LU, scipy.fft workers=%d)" % (steps, cores)}
+                     "(FP64 NumPy/SciPy, dense Schur LU, scipy.fft workers=%d)" % (steps, cores),
+           "cpu_model": _cpu_model()}
+    if single_steps:
+        om1, G1 = om.copy(), G.copy()
+        limit = threadpool_limits(limits=1) if threadpool_limits else None
+        try:
+            with sfft.set_workers(1):
+                t0 = time.perf_counter()
+                for _ in range(single_steps):
+                    om1, G1 = st.step(om1, G1, w.dt)
+                secs1 = time.perf_counter() - t0
+        finally:
+            if limit is not None:
+                limit.unregister() if hasattr(limit, "unregister") else limit.__exit__(None, None, None)
+        cpu["single_core"] = {"value": w.grid.nx * w.grid.ny * single_steps / secs1, "cores": 1,
+                              "steps": single_steps, "blas_threads_limited": threadpool_limits is not None}
     return cpu, (om, G, steps + 1, st.rec, geo)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -270,8 +270,22 @@ int iim_rk3_steps_moving(iim_ctx* ctx, double* omega_dev, double* Gamma_host, do
                          const double* motion_host, iim_step_stats* stats);
 
 /* Largest stable time step on the RK3 stability triangle of App. B for a
- * velocity bound a_max = max(|u_x| + |u_y|). */
+ * velocity bound a_max = max(|u_x| + |u_y|):
+ * dt = 1 / (a_max / (1.620 h) + nu / (0.314 h^2)). */
 int iim_dt_max(const iim_ctx* ctx, double a_max, double* dt_max_out);
+/* The step-size limit that the RK3 steps enforce: iim_dt_max at the
+ * context's velocity bound.  That bound is sqrt(2) times the larger of twice
+ * the free-stream speed (none for the box) and the largest boundary speed at
+ * the control points (Sec. 5.5 leaves the bound open; the free-stream
+ * doubling covers the speed-up past a body): set at create from the rigid
+ * motion or the boundary samples, raised to the motion's speed by
+ * iim_set_body_motion and, per call, by iim_rk3_steps_moving.
+ * iim_set_speed_bound replaces it (a_max >= 0, finite) for good, e.g. with
+ * the measured maximum of |u| + |v| of a developed flow.  iim_rk3_step(s),
+ * iim_rk3_steps_moving and iim_batch_step return IIM_EINVAL, computing
+ * nothing, when dt exceeds the limit. */
+int iim_dt_limit(const iim_ctx* ctx, double* dt_limit_out);
+int iim_set_speed_bound(iim_ctx* ctx, double a_max);
 
 /* Lattice Green's function g(m, n) of the 5-point Laplacian (host, for
  * tests): out_host[n*(mx+1) + m] for 0 <= m <= mx, 0 <= n <= my. */
@@ -316,7 +330,12 @@ int iim_rhs_given_wb(iim_ctx* ctx, const double* omega_dev, const double* u_dev,
                      const double* omega_b_dev, double* domega_dev, double* dGamma_host);
 
 /* One low-storage RK3 step (Sec. 5.5) of (omega, Gamma) in place.
- * omega_dev: grid field; Gamma_host: [n_circ]; dt > 0. */
+ * omega_dev: grid field; Gamma_host: [n_circ]; 0 < dt <= the context's
+ * limit (iim_dt_limit), else IIM_EINVAL.  The RK update raises a device flag
+ * when a new vorticity or circulation value is NaN or Inf; the call reads it
+ * at its final synchronisation and returns IIM_ENONFINITE (the state holds
+ * the non-finite values), on every solver path, the captured step graph of
+ * the dense solver included. */
 int iim_rk3_step(iim_ctx* ctx, double* omega_dev, double* Gamma_host, double dt,
                  iim_step_stats* stats);
 
@@ -341,7 +360,9 @@ int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
  * source plus the correction sources; reps repeats, three interleaved rounds,
  * the minimum of each shape) with every instantiated number of FFTs per
  * workgroup of the row passes and of the column pass (1, 2, 4; shapes over
- * 1024 threads or 128 KiB of LDS fall back to the default) and keeps the
+ * 1024 threads or 128 KiB of LDS fall back to the default; shapes whose
+ * kernels the device cannot launch, or whose launches report an error, are
+ * never chosen) and keeps the
  * fastest if it beats the default by at least 3 % (otherwise the default).
  * Outputs (nullable): the chosen counts (0 = default), the default's and the
  * best time per convolution in microseconds.  The shapes change only the
@@ -350,7 +371,9 @@ int iim_krylov_totals(const iim_ctx* ctx, int64_t* solves, int64_t* matvecs);
 int iim_autotune(iim_ctx* ctx, int32_t reps, int32_t* row_per, int32_t* col_per, double* us_default,
                  double* us_best);
 /* Set the FFTs per workgroup directly (0 = default), e.g. from another
- * context's autotune of the same FFT size. */
+ * context's autotune of the same FFT size.  IIM_EINVAL when the device
+ * cannot launch the shape's kernels (register-limited block size, LDS per
+ * block, scratch memory), with the kernel named in iim_last_error. */
 int iim_set_fft_shape(iim_ctx* ctx, int32_t row_per, int32_t col_per);
 /* All solver counters since create. */
 typedef struct {
@@ -412,6 +435,12 @@ int iim_net_grad_mse(iim_net* net, const float* x_dev, int32_t batch, int32_t P,
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
  * current gradients. */
 int iim_net_adam_step(iim_net* net, float lr);
+/* One training step on a batch: iim_net_grad_mse followed by
+ * iim_net_adam_step with learning rate lr (> 0), on the network's stream;
+ * loss_host (nullable) receives the batch loss before the update.
+ * IIM_EINVAL as either call. */
+int iim_net_train_step(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                       const float* target_dev, float lr, float* loss_host);
 int iim_net_save(const iim_net* net, const char* path);
 int iim_net_load(iim_net* net, const char* path);
 
@@ -470,7 +499,11 @@ typedef struct {
 
 /* grids[n_sims]; n_bodies[n_sims]; bodies[s] = the n_bodies[s] bodies of
  * simulation s.  Errors as iim_create (the message, from
- * iim_batch_last_error(NULL), names the simulation). */
+ * iim_batch_last_error(NULL), names the simulation and ends with the free and
+ * total device memory, the memory the simulations hold and the node count of
+ * the last captured batch graph).  A branch count whose graph fails is
+ * skipped (its time reads -1 in iim_batch_info, its error stays readable with
+ * iim_batch_last_error(batch)); one branch must work. */
 int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* n_bodies,
                      const iim_body_desc* const* bodies, const iim_solver_opts* opts, void* hip_stream,
                      iim_batch** out);
@@ -479,7 +512,9 @@ const char* iim_batch_last_error(const iim_batch* batch);
 /* n_steps RK3 steps of every simulation: omega_dev[s] grid field of
  * simulation s (in place), Gamma_host[s] its circulations (in place), dt[s]
  * its step.  The graph is captured on the first call and again whenever a
- * pointer or a dt changes.  stats (nullable). */
+ * pointer or a dt changes.  stats (nullable).  IIM_EINVAL (nothing run) when
+ * a dt exceeds its simulation's limit (iim_dt_limit); IIM_ENONFINITE when a
+ * simulation's new state holds a NaN or Inf (named in iim_batch_last_error). */
 int iim_batch_step(iim_batch* batch, double* const* omega_dev, double* const* Gamma_host, const double* dt,
                    int32_t n_steps, iim_batch_stats* stats);
 /* Chosen branch count; the autotuner's choices (tunings: room for n_sims

@@ -33,7 +33,8 @@ EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_give
            "iim_net_forward", "iim_net_grad_mse", "iim_net_adam_step", "iim_net_save", "iim_net_load",
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
            "iim_warm_start_sequences", "iim_reset_history", "iim_autotune", "iim_set_fft_shape",
-           "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info"]
+           "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info",
+           "iim_dt_limit", "iim_set_speed_bound", "iim_net_train_step"]
 KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport", "arnoldi"]
 
 
@@ -137,6 +138,10 @@ def lib():
     L.iim_get_geometry.argtypes = [vp, C.POINTER(GeometryView)]
     L.iim_dt_max.restype = ip
     L.iim_dt_max.argtypes = [vp, C.c_double, dp]
+    L.iim_dt_limit.restype = ip
+    L.iim_dt_limit.argtypes = [vp, dp]
+    L.iim_set_speed_bound.restype = ip
+    L.iim_set_speed_bound.argtypes = [vp, C.c_double]
     L.iim_lgf_table.restype = ip
     L.iim_lgf_table.argtypes = [C.c_int32, C.c_int32, dp]
     L.iim_poisson.restype = ip
@@ -188,6 +193,8 @@ def lib():
     L.iim_net_grad_mse.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_float)]
     L.iim_net_adam_step.restype = ip
     L.iim_net_adam_step.argtypes = [vp, C.c_float]
+    L.iim_net_train_step.restype = ip
+    L.iim_net_train_step.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.c_float, C.POINTER(C.c_float)]
     L.iim_net_save.restype = ip
     L.iim_net_save.argtypes = [vp, C.c_char_p]
     L.iim_net_load.restype = ip
@@ -334,6 +341,15 @@ class Context:
         d = C.c_double()
         self._check(lib().iim_dt_max(self._h, a_max, C.byref(d)), "iim_dt_max")
         return d.value
+
+    def dt_limit(self):
+        """The step-size limit the RK3 steps enforce (iim_dt_limit)."""
+        d = C.c_double()
+        self._check(lib().iim_dt_limit(self._h, C.byref(d)), "iim_dt_limit")
+        return d.value
+
+    def set_speed_bound(self, a_max):
+        self._check(lib().iim_set_speed_bound(self._h, a_max), "iim_set_speed_bound")
 
     def poisson(self, src, psi):
         self._check(lib().iim_poisson(self._h, self._grid(src), self._ring(psi)), "iim_poisson")
@@ -573,6 +589,15 @@ class Network:
     def adam_step(self, lr):
         self._check(lib().iim_net_adam_step(self._h, lr), "iim_net_adam_step")
 
+    def train_step(self, x, seq, target, lr):
+        """Gradients of the batch loss and one Adam step (iim_net_train_step);
+        returns the loss before the update."""
+        B, P = self._shapes(x, seq, target)
+        loss = C.c_float()
+        self._check(lib().iim_net_train_step(self._h, _fptr(x), B, P, _fptr(seq, "int32"), _fptr(target), lr,
+                                             C.byref(loss)), "iim_net_train_step")
+        return loss.value
+
     def save(self, path):
         self._check(lib().iim_net_save(self._h, path.encode()), "iim_net_save")
 
@@ -654,8 +679,10 @@ class Batch:
         if rc:
             raise IIMError(rc, "iim_batch_info")
         tuning = [{f[0]: getattr(tun[i], f[0]) for f in BatchTuning._fields_} for i in range(nt.value)]
-        tried = [1, 2, 4, 8][:sum(1 for v in bms if v > 0)]
-        return {"branches": nbr.value, "tuning": tuning, "branch_ms": dict(zip(tried, list(bms)[:len(tried)]))}
+        tried = [c for c in (1, 2, 4, 8) if c <= min(8, self.n)]
+        notes = (lib().iim_batch_last_error(self._h) or b"").decode()
+        return {"branches": nbr.value, "tuning": tuning, "branch_ms": dict(zip(tried, list(bms)[:len(tried)])),
+                "notes": notes or None}
 
     def step(self, omegas, gammas, dts, n_steps=1):
         """omegas: contiguous float64 CUDA tensors [ny][nx] (in place);

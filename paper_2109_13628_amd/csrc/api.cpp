@@ -415,6 +415,10 @@ void setup_device(iim_ctx* c) {
       f.spec32 = c->dalloc<float2>((size_t)(f.hx + 1) * f.ld);
       f.spec32_out = c->dalloc<float2>((size_t)(f.hx + 1) * f.ld);
     }
+    std::string why;
+    if (!reg_shapes_fit(f, false, &why) ||
+        (c->precision == IIM_PREC_MIXED && f.spec32 && !reg_shapes_fit(f, true, &why)))
+      throw HipError("FFT kernels cannot be launched on this device: " + why, IIM_EUNSUPPORTED);
   }
   // Krylov state
   DKrylov& k = c->dk;
@@ -431,6 +435,11 @@ void setup_device(iim_ctx* c) {
   k.st = c->dalloc<double>(KS_SIZE);
   HIPCHK(hipMemset(k.x, 0, k.n * sizeof(double)));
   HIPCHK(hipHostMalloc(&c->st_host, KS_SIZE * sizeof(double)));
+  c->nf_dev = c->dalloc<int>(1);
+  HIPCHK(hipMemset(c->nf_dev, 0, sizeof(int)));
+  HIPCHK(hipHostMalloc(&c->nf_host, sizeof(int)));
+  *c->nf_host = 0;
+  d.nonfinite = c->nf_dev;
   // fields
   c->psi = c->dalloc<double>(NR);
   c->U = c->dalloc<double>(NR);
@@ -795,6 +804,62 @@ std::vector<double> fluid_area_weights(const iim_ctx* c) {
 
 }  // namespace
 
+bool iim::take_nonfinite(iim_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->nf_host, c->nf_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (*c->nf_host == 0) return false;
+  // cleared by a kernel (the flag's clear must not be a memset node when
+  // callers capture the stream)
+  launch_fill_int(c->nf_dev, 0, 1, c->stream);
+  *c->nf_host = 0;
+  return true;
+}
+
+double iim::dt_limit(const iim_ctx* c, double a) {
+  const double h = c->geo.grid.h, nu = c->geo.grid.nu;
+  return 1.0 / (a / (1.620 * h) + nu / (0.314 * h * h));
+}
+
+namespace {
+
+// The velocity bound of the step-size check: sqrt(2) times the larger of
+// twice the free-stream speed and the largest boundary speed (|u| + |v| <=
+// sqrt(2) |u|; twice the free stream covers the speed-up past a body).
+double speed_bound(const iim_ctx* c, double boundary_speed) {
+  const Geometry& g = c->geo;
+  const bool box = g.grid.exterior == IIM_EXT_BOX;
+  const double uinf = box ? 0.0 : std::hypot(g.grid.u_inf[0], g.grid.u_inf[1]);
+  return std::sqrt(2.0) * std::max(2.0 * uinf, boundary_speed);
+}
+
+// largest boundary speed at the control points for the rigid motion
+// m[n_bodies][3] = (u_x, u_y, omega) about each body's centre
+double motion_speed(const iim_ctx* c, const double* m) {
+  const Geometry& g = c->geo;
+  double v = 0.0;
+  for (int q = 0; q < g.nc; ++q) {
+    const int k = g.c_body[q];
+    const double dx = g.c_x[q] - g.bodies[k].center[0], dy = g.c_y[q] - g.bodies[k].center[1];
+    v = std::max(v, std::hypot(m[3 * k] - m[3 * k + 2] * dy, m[3 * k + 1] + m[3 * k + 2] * dx));
+  }
+  return v;
+}
+
+// IIM_EINVAL (with the limit in the message) when dt lies above the
+// stability triangle's step for the velocity bound a
+int check_dt(iim_ctx* c, double dt, double a) {
+  const double lim = dt_limit(c, a);
+  if (dt > lim * (1.0 + 1e-12)) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "dt = %.6g exceeds the RK3 stability limit %.6g (velocity bound %.6g)", dt, lim,
+                  a);
+    return fail(c, IIM_EINVAL, buf);
+  }
+  return IIM_OK;
+}
+
+}  // namespace
+
 int iim::run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats) {
   const DGeom& dg = c->dg;
   // stage inputs/outputs omega -> wtmp -> wtmp2 -> omega: no copy at the end;
@@ -993,6 +1058,11 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
     if (c->guess < IIM_GUESS_ZERO || c->guess > IIM_GUESS_NETWORK) throw ArgError("unknown initial guess");
     build_geometry(c->geo, gs, bs);
     c->stream = (hipStream_t)hip_stream;
+    {
+      double vb = 0.0;
+      for (int q = 0; q < c->geo.nc; ++q) vb = std::max(vb, std::hypot(c->geo.c_ub[2 * q], c->geo.c_ub[2 * q + 1]));
+      c->a_max = speed_bound(c, vb);
+    }
     // geometry views
     const Geometry& g = c->geo;
     for (int q = 0; q < g.nc; ++q) {
@@ -1088,6 +1158,19 @@ int iim_dt_max(const iim_ctx* c, double a_max, double* dt) {
   const double denom = a_max / (1.620 * h) + nu / (0.314 * h * h);
   if (!(denom > 0)) return IIM_EINVAL;
   *dt = 1.0 / denom;
+  return IIM_OK;
+}
+
+int iim_dt_limit(const iim_ctx* c, double* dt) {
+  if (!c || !dt) return IIM_EINVAL;
+  *dt = dt_limit(c, c->a_max);
+  return IIM_OK;
+}
+
+int iim_set_speed_bound(iim_ctx* c, double a_max) {
+  if (!c || !(a_max >= 0) || !std::isfinite(a_max)) return IIM_EINVAL;
+  c->a_max = a_max;
+  c->a_max_user = true;
   return IIM_OK;
 }
 
@@ -1333,6 +1416,11 @@ int iim_rhs_given_wb(iim_ctx* c, const double* omega, const double* u, const dou
 
 int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int32_t n_steps, iim_step_stats* stats) {
   if (!c || !omega || (c->geo.nbc() > 0 && !Gamma_host) || !(dt > 0) || n_steps < 0) return IIM_EINVAL;
+  // moving steps check dt against their own motion before they get here
+  if (!c->motion_stage && !c->motion_from_dev) {
+    const int rc = check_dt(c, dt, c->a_max);
+    if (rc != IIM_OK) return rc;
+  }
   if (c->host_only) return fail(c, IIM_EUNSUPPORTED, "host-only context");
   try {
     const int nb = c->geo.nbc();
@@ -1347,6 +1435,8 @@ int iim_rk3_steps(iim_ctx* c, double* omega, double* Gamma_host, double dt, int3
     if (nb) HIPCHK(hipMemcpyAsync(Gamma_host, c->Gd, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
+    if (n_steps > 0 && take_nonfinite(c))
+      return fail(c, IIM_ENONFINITE, "non-finite vorticity or circulation after the RK3 steps");
     if (status != IIM_OK) return fail(c, status, "Krylov limit reached");
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
@@ -1367,6 +1457,7 @@ int iim_set_body_motion(iim_ctx* c, const double* motion) {
     motion_tables(c, motion, c->motion_buf[0]);
     upload_motion(c, c->motion_buf[0]);
     c->motion_now.assign(motion, motion + 3 * nb);
+    if (!c->a_max_user) c->a_max = speed_bound(c, motion_speed(c, motion));
     HIPCHK(hipStreamSynchronize(c->stream));
   } catch (const HipError& e) {
     return fail(c, e.code, e.what());
@@ -1381,6 +1472,13 @@ int iim_rk3_steps_moving(iim_ctx* c, double* omega, double* Gamma_host, double d
   const size_t nb = c->geo.bodies.size();
   for (size_t q = 0; q < (size_t)n_steps * 9 * nb; ++q)
     if (!std::isfinite(motion[q])) return fail(c, IIM_EINVAL, "non-finite body motion");
+  {
+    // step size against the fastest boundary motion of the schedule
+    double vb = 0.0;
+    for (size_t q = 0; q < (size_t)n_steps * 3; ++q) vb = std::max(vb, motion_speed(c, motion + q * 3 * nb));
+    const int rc = check_dt(c, dt, c->a_max_user ? c->a_max : speed_bound(c, vb));
+    if (rc != IIM_OK) return rc;
+  }
   int rc = IIM_OK;
   try {
     rc = enter_motion_mode(c);
@@ -1518,12 +1616,20 @@ int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, d
       const int opts[3] = {1, 2, 4};
       // (0, 0): the defaults; then every pair of tuned shapes.  Three
       // interleaved rounds, the minimum of each shape kept.
+      // only shapes whose kernels the device can launch (a refused launch
+      // would time as the fastest); the default must be one of them
       std::vector<std::pair<int, int>> shapes{{0, 0}};
       for (int r = 0; r < 3; ++r)
-        for (int q = 0; q < 3; ++q) shapes.emplace_back(opts[r], opts[q]);
+        for (int q = 0; q < 3; ++q) {
+          c->df.row_per = opts[r];
+          c->df.col_per = opts[q];
+          if (reg_shapes_fit(c->df, false, nullptr)) shapes.emplace_back(opts[r], opts[q]);
+        }
       std::vector<double> us_min(shapes.size(), 1e300);
+      (void)hipGetLastError();
       for (int round = 0; round < 3; ++round)
         for (size_t k = 0; k < shapes.size(); ++k) {
+          if (us_min[k] < 0) continue;   // failed before
           c->df.row_per = shapes[k].first;
           c->df.col_per = shapes[k].second;
           for (int w = 0; w < 2; ++w) apply_G(c, c->dg, c->wtmp, gam, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
@@ -1531,6 +1637,12 @@ int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, d
           for (int w = 0; w < reps; ++w) apply_G(c, c->dg, c->wtmp, gam, -1.0, 0, ny - 1, -1, ny, c->psi, nullptr);
           HIPCHK(hipEventRecord(b, c->stream));
           HIPCHK(hipEventSynchronize(b));
+          // a launch error of this shape's kernels: never chosen
+          if (hipGetLastError() != hipSuccess) {
+            if (k == 0) throw HipError("the default FFT tile shape failed to launch", IIM_EDEVICE);
+            us_min[k] = -1.0;
+            continue;
+          }
           float ms = 0.f;
           HIPCHK(hipEventElapsedTime(&ms, a, b));
           us_min[k] = std::min(us_min[k], 1e3 * ms / reps);
@@ -1540,7 +1652,8 @@ int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, d
       def = us_min[0];
       best = def;
       for (size_t k = 1; k < shapes.size(); ++k)
-        if (us_min[k] < best && us_min[k] < 0.97 * def) best = us_min[k], br = shapes[k].first, bc = shapes[k].second;
+        if (us_min[k] > 0 && us_min[k] < best && us_min[k] < 0.97 * def)
+          best = us_min[k], br = shapes[k].first, bc = shapes[k].second;
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       c->df.row_per = br;
@@ -1559,6 +1672,13 @@ int iim_autotune(iim_ctx* c, int32_t reps, int32_t* row_per, int32_t* col_per, d
 
 int iim_set_fft_shape(iim_ctx* c, int32_t row_per, int32_t col_per) {
   if (!c || row_per < 0 || col_per < 0) return IIM_EINVAL;
+  if (!c->host_only && !c->box) {
+    DFft f = c->df;
+    f.row_per = row_per;
+    f.col_per = col_per;
+    std::string why;
+    if (!reg_shapes_fit(f, false, &why)) return fail(c, IIM_EINVAL, "tile shape cannot be launched: " + why);
+  }
   c->df.row_per = row_per;
   c->df.col_per = col_per;
   if (c->gexec) {

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <map>
 #include <numeric>
 #include <string>
@@ -41,7 +42,9 @@ struct iim_batch {
   std::vector<double*> g_omega;
   std::vector<double> g_dt;
   std::vector<iim_batch_tuning> tunes;
-  std::vector<double> branch_ms;           // batch-step time of each branch count tried
+  std::vector<double> branch_ms;           // batch-step time of each branch count tried (-1: failed)
+  std::vector<std::string> branch_err;     // why a branch count failed
+  size_t graph_nodes = 0;                  // nodes of the last captured batch-step graph
   double setup_s = 0.0;
   ~iim_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -99,11 +102,53 @@ hipGraphExec_t capture(iim_batch* b, const std::vector<double*>& omega, const st
     (void)hipGraphDestroy(graph);
     throw HipError("step capture failed", rc);
   }
+  size_t nodes = 0;
+  if (hipGraphGetNodes(graph, nullptr, &nodes) == hipSuccess) b->graph_nodes = nodes;
   hipGraphExec_t exec = nullptr;
   const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   HIPCHK(ei);
   return exec;
+}
+
+// State of the device and of the batch for error messages: free and total
+// device memory, the memory the simulations hold, the last graph's size.
+std::string diagnostics(const iim_batch* b) {
+  size_t fr = 0, tot = 0;
+  const bool mem = hipMemGetInfo(&fr, &tot) == hipSuccess;
+  size_t held = 0;
+  for (const iim_ctx* c : b->sims) held += c->dev_bytes;
+  char buf[256];
+  std::snprintf(buf, sizeof buf,
+                " [device memory free %.3f of %.3f GiB; %zu simulations hold %.3f GiB; last batch graph %zu nodes]",
+                mem ? fr / 1073741824.0 : -1.0, mem ? tot / 1073741824.0 : -1.0, b->sims.size(),
+                held / 1073741824.0, b->graph_nodes);
+  return buf;
+}
+
+// One batch step with nbr branches, captured, launched once to warm up and
+// twice between events: its time in ms.
+double time_branches(iim_batch* b, const std::vector<double*>& omega, const std::vector<double>& dt, int nbr,
+                     hipEvent_t t0, hipEvent_t t1) {
+  hipGraphExec_t ex = capture(b, omega, dt, nbr);
+  try {
+    HIPCHK(hipGraphLaunch(ex, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipEventRecord(t0, b->stream));
+    HIPCHK(hipGraphLaunch(ex, b->stream));
+    HIPCHK(hipGraphLaunch(ex, b->stream));
+    HIPCHK(hipEventRecord(t1, b->stream));
+    HIPCHK(hipEventSynchronize(t1));
+  } catch (...) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(ex);
+    throw;
+  }
+  float ms = 0.f;
+  const hipError_t e = hipEventElapsedTime(&ms, t0, t1);
+  (void)hipGraphExecDestroy(ex);
+  HIPCHK(e);
+  return ms / 2;
 }
 
 double percentile(std::vector<double> v, double p) {
@@ -126,8 +171,17 @@ int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* 
   if (n_sims < 1 || !grids || !n_bodies || !bodies) return IIM_EINVAL;
   iim_batch* b = new (std::nothrow) iim_batch();
   if (!b) return IIM_ENOMEM;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<double*> scratch;
+  auto release = [&]() {
+    for (double* p : scratch)
+      if (p) (void)hipFree(p);
+    scratch.clear();
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    t0 = t1 = nullptr;
+  };
   try {
-    hipEvent_t t0, t1;
     b->stream = (hipStream_t)hip_stream;
     iim_solver_opts o{};
     if (opts) o = *opts;
@@ -138,7 +192,7 @@ int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* 
       iim_ctx* c = nullptr;
       const int rc = iim_create(&grids[s], n_bodies[s], bodies[s], &o, hip_stream, &c);
       if (rc != IIM_OK) {
-        g_batch_error = "simulation " + std::to_string(s) + ": " + iim_last_error(nullptr);
+        g_batch_error = "simulation " + std::to_string(s) + ": " + iim_last_error(nullptr) + diagnostics(b);
         delete b;
         return rc;
       }
@@ -161,14 +215,16 @@ int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* 
         t.fft_my = c->df.my;
         t.tuned_on = s;
         const int rc = iim_autotune(c, 5, &t.row_per, &t.col_per, &t.us_default, &t.us_best);
-        if (rc != IIM_OK) throw HipError("autotune: " + std::string(iim_last_error(c)), rc);
+        if (rc != IIM_OK) throw HipError("autotune of simulation " + std::to_string(s) + ": " + iim_last_error(c), rc);
         it = by_size.emplace(key, t).first;
         b->tunes.push_back(t);
       }
-      iim_set_fft_shape(c, it->second.row_per, it->second.col_per);
+      const int rc = iim_set_fft_shape(c, it->second.row_per, it->second.col_per);
+      if (rc != IIM_OK) throw HipError("tile shape of simulation " + std::to_string(s) + ": " + iim_last_error(c), rc);
     }
     // branches: time one batch step (after a warm-up step) of scratch states
-    // for 1, 2, 4 and 8 branches and keep the fastest
+    // for 1, 2, 4 and 8 branches and keep the fastest; a branch count whose
+    // graph fails is recorded and skipped (one branch must work)
     HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     const int max_br = std::min(8, n_sims);
@@ -180,35 +236,39 @@ int iim_batch_create(int32_t n_sims, const iim_grid_desc* grids, const int32_t* 
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       b->join.push_back(e);
     }
-    std::vector<double*> scratch(n_sims);
+    scratch.assign(n_sims, nullptr);
     std::vector<double> dts(n_sims);
     for (int s = 0; s < n_sims; ++s) {
       HIPCHK(hipMalloc(&scratch[s], b->cells[s] * sizeof(double)));
       launch_fill(scratch[s], 0.0, b->cells[s], b->stream);
       dts[s] = 1e-3 * grids[s].h;
     }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipGetLastError());
     double best = 1e300;
     for (int nbr = 1; nbr <= max_br; nbr *= 2) {
-      hipGraphExec_t ex = capture(b, scratch, dts, nbr);
-      HIPCHK(hipGraphLaunch(ex, b->stream));
-      HIPCHK(hipEventRecord(t0, b->stream));
-      HIPCHK(hipGraphLaunch(ex, b->stream));
-      HIPCHK(hipGraphLaunch(ex, b->stream));
-      HIPCHK(hipEventRecord(t1, b->stream));
-      HIPCHK(hipEventSynchronize(t1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-      (void)hipGraphExecDestroy(ex);
-      b->branch_ms.push_back(ms / 2);
-      if (ms / 2 < best) best = ms / 2, b->n_branches = nbr;
+      double ms = -1.0;
+      try {
+        ms = time_branches(b, scratch, dts, nbr, t0, t1);
+      } catch (const HipError& e) {
+        if (nbr == 1) throw;
+        b->branch_err.push_back(std::to_string(nbr) + " branches: " + e.what());
+        (void)hipGetLastError();
+      }
+      b->branch_ms.push_back(ms);
+      if (ms >= 0 && ms < best) best = ms, b->n_branches = nbr;
     }
-    for (double* p : scratch) (void)hipFree(p);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
+    for (iim_ctx* c : b->sims)
+      if (take_nonfinite(c)) throw HipError("non-finite state in the branch timing of the scratch states", IIM_ENONFINITE);
+    // failed branch counts stay readable through iim_batch_last_error(batch)
+    for (const std::string& e : b->branch_err) b->err += e + "; ";
+    release();
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
-    g_batch_error = e.what();
+    g_batch_error = e.what() + diagnostics(b);
     const int code = e.code;
+    (void)hipStreamSynchronize(b->stream);
+    release();
     delete b;
     return code;
   }
@@ -241,6 +301,14 @@ int iim_batch_step(iim_batch* b, double* const* omega_dev, double* const* Gamma_
   const size_t n = b->sims.size();
   for (size_t s = 0; s < n; ++s)
     if (!omega_dev[s] || !(dt[s] > 0) || (b->sims[s]->geo.nbc() > 0 && !Gamma_host[s])) return IIM_EINVAL;
+  for (size_t s = 0; s < n; ++s) {
+    const double lim = dt_limit(b->sims[s], b->sims[s]->a_max);
+    if (dt[s] > lim * (1.0 + 1e-12)) {
+      b->err = "simulation " + std::to_string(s) + ": dt = " + std::to_string(dt[s]) +
+               " exceeds the RK3 stability limit " + std::to_string(lim);
+      return IIM_EINVAL;
+    }
+  }
   std::vector<hipEvent_t> ev;
   try {
     for (size_t s = 0; s < n; ++s) {
@@ -273,6 +341,13 @@ int iim_batch_step(iim_batch* b, double* const* omega_dev, double* const* Gamma_
     }
     HIPCHK(hipStreamSynchronize(b->stream));
     HIPCHK(hipGetLastError());
+    for (size_t s = 0; s < n && n_steps > 0; ++s)
+      if (take_nonfinite(b->sims[s])) {
+        for (auto e2 : ev)
+          if (e2) (void)hipEventDestroy(e2);
+        b->err = "simulation " + std::to_string(s) + ": non-finite vorticity or circulation";
+        return IIM_ENONFINITE;
+      }
     std::vector<double> ms(n_steps);
     for (int k = 0; k < n_steps; ++k) {
       float t = 0.f;

@@ -99,6 +99,15 @@ struct iim_ctx {
   std::vector<double> motion_host;
   double *Qw = nullptr, *wtmp = nullptr, *wtmp2 = nullptr, *Gd = nullptr, *QGd = nullptr, *dGd = nullptr;
   double* st_host = nullptr;
+  // non-finite flag: set on the device by the transport when a new vorticity
+  // or circulation value is NaN or Inf; read (and cleared) after the steps
+  int* nf_dev = nullptr;
+  int* nf_host = nullptr;          // pinned
+  // velocity bound of the step-size check (RK3 stability triangle): set at
+  // create from the free stream and the boundary speed; iim_set_speed_bound
+  // replaces it, moving steps raise it to the speed of their motion
+  double a_max = 0.0;
+  bool a_max_user = false;
   bool have_prev = false;
   int solver = IIM_SOLVER_KRYLOV;
   double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
@@ -157,6 +166,7 @@ struct iim_ctx {
     if (gstream) (void)hipStreamDestroy(gstream);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
+    if (nf_host) (void)hipHostFree(nf_host);
   }
 };
 
@@ -170,6 +180,11 @@ void read_status(iim_ctx* c);
 void set_status(iim_ctx* c);
 // one RK3 step of the context's state (kernels enqueued on c->stream)
 int run_step(iim_ctx* c, double* omega, double dt, iim_step_stats* stats);
+// the non-finite flag of the steps enqueued so far (synchronises the
+// context's stream); a set flag is cleared
+bool take_nonfinite(iim_ctx* c);
+// largest stable step for the velocity bound a (stability triangle)
+double dt_limit(const iim_ctx* c, double a);
 
 // warm_start.cpp
 // Prepare the initial guess of the Krylov solve whose right-hand side is in

@@ -9,6 +9,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <string>
 #include <vector>
 
 namespace iim {
@@ -60,6 +61,9 @@ struct DGeom {
   const double* lw_x;
   const double* lw_y;
   const double2* c_n;
+  // set to 1 by the RK update of the transport when a new vorticity or
+  // circulation value is not finite (never cleared by a kernel of the step)
+  int* nonfinite;
 };
 
 // The boundary quantities of a stage as affine forms of psi (ring), omega
@@ -250,6 +254,10 @@ inline long grid_size(dim3 g) { return (long)g.x * g.y * g.z; }
 // call left in spec are used: they must be those of the same omega over the
 // same rows [rj0, rj1] and precision.
 bool conv_reg_supported(int hx, int my);
+// whether the register FFT kernels selected by f's tile shapes (row_per,
+// col_per; FP64 or the FP32 copies) can be launched on the current device;
+// why (nullable) names the failing kernel and its limits
+bool reg_shapes_fit(const DFft& f, bool fp32, std::string* why);
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
                  hipStream_t s, Prof* prof = nullptr, bool fp32 = false, bool rows_ready = false);
@@ -288,6 +296,7 @@ void launch_transport_all(const DGeom& g, const double* omega, const double* psi
                           double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
                           Prof* prof = nullptr);
 void launch_fill(double* p, double v, size_t n, hipStream_t s);
+void launch_fill_int(int* p, int v, size_t n, hipStream_t s);
 // dense Schur complement: in-place Gauss-Jordan inverse, transposed GEMV, unit vector
 void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s);
 void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s);

@@ -25,6 +25,7 @@
 // GMRES (Sec. 4.2): Arnoldi with classical Gram-Schmidt applied twice, Givens
 // rotations, all in one workgroup per step, state in device memory.
 #include <hip/hip_runtime.h>
+#include <string>
 
 #include <type_traits>
 
@@ -501,6 +502,13 @@ __global__ void k_fill(double* p, double v, size_t n) {
 void launch_fill(double* p, double v, size_t n, hipStream_t s) {
   if (n) k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
 }
+__global__ void k_fill_int(int* p, int v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+void launch_fill_int(int* p, int v, size_t n, hipStream_t s) {
+  if (n) k_fill_int<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+}
 
 // Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in all threads.
 __device__ double block_sum(double v, double* red) {
@@ -973,7 +981,13 @@ struct TGeom {
   const int8_t* __restrict__ cls;
   const int* __restrict__ special;
   const int* __restrict__ rects;
+  int* nonfinite;              // flag raised by the RK update on a NaN / Inf result
 };
+
+// Raise the non-finite flag (every writer stores the same value).
+__device__ __forceinline__ void mark_nonfinite(const TGeom& g, double v) {
+  if (!isfinite(v)) *g.nonfinite = 1;
+}
 
 // Node velocities of the transport.  FROM_PSI = false: read from U / V on the
 // ring (zero beyond it).  FROM_PSI = true: formed from the stream function as
@@ -1154,7 +1168,9 @@ __device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __r
     const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
     const double qn = a * qp + dt * rhs;
     Q[q] = qn;
-    out[q] = wc + b * qn;
+    const double wn = wc + b * qn;
+    out[q] = wn;
+    mark_nonfinite(g, wn);
   }
 }
 
@@ -1188,7 +1204,9 @@ __device__ __forceinline__ void transport_special(const TGeom& g, const double* 
     const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
     const double qn = a * qp + dt * rhs;
     Q[q] = qn;
-    out[q] = omega[q] + b * qn;
+    const double wn = omega[q] + b * qn;
+    out[q] = wn;
+    mark_nonfinite(g, wn);
   }
 }
 
@@ -1220,7 +1238,9 @@ __device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict_
       const double qp = a == 0.0 ? 0.0 : QG[k];
       const double qn = a * qp + dt * rate;
       QG[k] = qn;
-      Gamma[k] += b * qn;
+      const double gn = Gamma[k] + b * qn;
+      Gamma[k] = gn;
+      mark_nonfinite(g, gn);
     }
   }
 }
@@ -1262,7 +1282,7 @@ void launch_transport_all(const DGeom& g, const double* omega, const double* psi
                           Prof* prof) {
   const int blocks = ((g.nx + 255) / 256) * g.ny + (4 * g.nsp + 255) / 256 + g.nbc;
   const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls, g.special,
-                 g.rects};
+                 g.rects, g.nonfinite};
   if (psi) {
     // algorithmic bytes per cell: omega, psi, Q read; out, Q written
     IIM_LAUNCH(prof, KID_TRANSPORT, 40.0 * g.nx * g.ny, k_transport_all<true>, blocks, 256, s, tg, omega, psi, U, V,
@@ -2109,6 +2129,72 @@ void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, doubl
   }
 
 bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
+
+// ---- launch-resource check of the register FFT instantiations that a tile
+// shape selects: the block must fit the kernel's register-limited thread
+// count, its LDS the device's per-block limit, and it must use no scratch
+// memory.  A launch that fails these is refused by the runtime, so the
+// autotuner and the set-up check them before any shape is used.
+struct FitCheck {
+  int max_lds = 0;
+  bool ok = true;
+  std::string why;
+  void add(const void* fn, int threads, const char* what) {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) {
+      ok = false;
+      why += std::string(what) + ": attributes unavailable; ";
+      return;
+    }
+    if (a.maxThreadsPerBlock < threads || (int)a.sharedSizeBytes > max_lds || a.localSizeBytes > 0) {
+      ok = false;
+      why += std::string(what) + ": " + std::to_string(threads) + " threads (max " +
+             std::to_string(a.maxThreadsPerBlock) + "), " + std::to_string(a.sharedSizeBytes) + " B LDS (max " +
+             std::to_string(max_lds) + "), " + std::to_string(a.localSizeBytes) + " B scratch; ";
+    }
+  }
+};
+template <int HX, class CX, int PER>
+void rows_fwd_fit(FitCheck& fc) {
+  fc.add((const void*)k_rows_fwd_reg<HX, CX, PER>, RegCfg<HX, PER, true>::THREADS, "row pass");
+}
+template <int MY, class CX, int PER>
+void cols_fit(FitCheck& fc) {
+  fc.add((const void*)k_cols_reg<MY, CX, PER>, RegCfg<MY, PER>::THREADS, "column pass");
+}
+template <int HX, class CX, int PER>
+void rows_inv_fit(FitCheck& fc) {
+  fc.add((const void*)k_rows_inv_reg<HX, CX, PER>, RegCfg<HX, PER, true>::THREADS, "inverse row pass");
+}
+template <int HX, class CX>
+void rows_fit_sw(const DFft& f, FitCheck& fc) {
+  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_fwd_fit, fc);
+  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_inv_fit, fc);
+}
+template <int MY, class CX>
+void cols_fit_sw(const DFft& f, FitCheck& fc) {
+  IIM_PER_DISPATCH(MY, CX, f.col_per, false, cols_fit, fc);
+}
+
+bool reg_shapes_fit(const DFft& f, bool fp32, std::string* why) {
+  if (!conv_reg_supported(f.hx, f.my)) return true;
+  FitCheck fc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&fc.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    if (why) *why = "device attributes unavailable";
+    return false;
+  }
+  if (fp32) {
+    IIM_REG_SWITCH(f.hx, rows_fit_sw, float2, f, fc);
+    IIM_REG_SWITCH(f.my, cols_fit_sw, float2, f, fc);
+  } else {
+    IIM_REG_SWITCH(f.hx, rows_fit_sw, double2, f, fc);
+    IIM_REG_SWITCH(f.my, cols_fit_sw, double2, f, fc);
+  }
+  if (why) *why = fc.why;
+  return fc.ok;
+}
 
 void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn, int rj0,
                      int rj1, int oj0, int oj1, double* psi_ring, const double* done, hipStream_t s, Prof* prof,

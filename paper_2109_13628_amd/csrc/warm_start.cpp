@@ -398,6 +398,14 @@ int iim_net_adam_step(iim_net* net, float lr) {
   return hipGetLastError() == hipSuccess ? IIM_OK : IIM_EDEVICE;
 }
 
+int iim_net_train_step(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                       const float* target_dev, float lr, float* loss_host) {
+  if (!(lr > 0.f)) return IIM_EINVAL;
+  const int rc = iim_net_grad_mse(net, x_dev, batch, P, seq_dev, target_dev, loss_host);
+  if (rc != IIM_OK) return rc;
+  return iim_net_adam_step(net, lr);
+}
+
 int iim_net_save(const iim_net* net, const char* path) {
   if (!net || !path) return IIM_EINVAL;
   std::vector<float> p(net->nparam);

@@ -175,3 +175,55 @@ def test_binding_refuses_short_circulation_arrays():
     # the copy handed to the library keeps n_circ entries and at least one
     assert iim._gamma_array([], 0).shape == (1,)
     assert iim._gamma_array([1.0, 2.0, 3.0], 2).tolist() == [1.0, 2.0, 3.0]
+
+
+def test_step_size_limit():
+    """The RK3 steps refuse dt above the stability triangle's step (App. B)
+    for the context's velocity bound: sqrt(2) max(2 |u_inf|, boundary speed),
+    or the bound the caller sets; nothing is computed (checked on host-only
+    contexts, where a valid step is refused as unsupported instead)."""
+    L = iim.lib()
+    one = C.c_void_p(1)
+    G = (C.c_double * 2)()
+    # cylinder in a uniform stream: the free stream decides
+    w = wl.cylinder_small()
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    a = np.sqrt(2.0) * 2.0 * 1.0
+    lim = 1.0 / (a / (1.620 * w.grid.h) + w.grid.nu / (0.314 * w.grid.h ** 2))
+    assert abs(ctx.dt_limit() - lim) < 1e-15 * lim
+    assert abs(ctx.dt_limit() - ctx.dt_max(a)) < 1e-18
+    assert L.iim_rk3_steps(ctx._h, one, G, C.c_double(0.999 * lim), 1, None) == iim.IIM_EUNSUPPORTED
+    assert L.iim_rk3_steps(ctx._h, one, G, C.c_double(1.001 * lim), 1, None) == iim.IIM_EINVAL
+    assert "stability limit" in L.iim_last_error(ctx._h).decode()
+    # a caller's bound replaces it
+    ctx.set_speed_bound(10.0)
+    assert abs(ctx.dt_limit() - ctx.dt_max(10.0)) < 1e-18
+    assert L.iim_rk3_steps(ctx._h, one, G, C.c_double(0.999 * lim), 1, None) == iim.IIM_EINVAL
+    assert L.iim_set_speed_bound(ctx._h, C.c_double(-1.0)) == iim.IIM_EINVAL
+    assert L.iim_set_speed_bound(ctx._h, C.c_double(float("nan"))) == iim.IIM_EINVAL
+    ctx.close()
+    # box with a rotating inner wall: the boundary speed decides (r = 0.25,
+    # omega = 1), and the Taylor-Couette step (C_stab = 0.5) is within it
+    w = wl.taylor_couette(64)
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    assert abs(ctx.dt_limit() - ctx.dt_max(np.sqrt(2.0) * 0.25)) < 1e-6 * ctx.dt_limit()
+    assert w.dt <= ctx.dt_limit()
+    ctx.close()
+    # no bodies, no free stream: the diffusive limit
+    g = wl.GridDesc(nx=32, ny=32, x0=0.0, y0=0.0, h=0.05, exterior="free", u_inf=(0.0, 0.0), nu=0.02)
+    ctx = iim.Context(g, [], host_only=True)
+    assert abs(ctx.dt_limit() - 0.314 * 0.05 ** 2 / 0.02) < 1e-15
+    ctx.close()
+
+
+def test_workload_steps_within_limit():
+    """The named workloads' time steps lie within the step-size limit the
+    library enforces (the GPU tests and the benchmark run them)."""
+    cases = [wl.cylinder_small(), wl.cylinder_mid(), wl.cylinder_outflow_small(), wl.taylor_couette(64),
+             wl.taylor_couette(128), wl.surface_driven_cylinder(), wl.multi_body(256),
+             wl.cylinder(nx=300, ny=170, h=1.0 / 32, points=128, dt=0.005, steps=2, center=(2.5, 0.0))]
+    cases += wl.batch_serving(5, seed=11, nmin=120, nmax=300)
+    for w in cases:
+        ctx = iim.Context(w.grid, w.bodies, host_only=True)
+        assert w.dt <= ctx.dt_limit(), (w.name, w.dt, ctx.dt_limit())
+        ctx.close()
