@@ -50,6 +50,8 @@ def _parse():
                    help="run only the batched-serving leg and print its JSON object (the benchmark runs this "
                         "in a child process)")
     p.add_argument("--batch-timeout", type=float, default=420.0, help="seconds allowed for the batch child process")
+    p.add_argument("--no-extra-workloads", action="store_true",
+                   help="skip the Taylor-Couette box and four-body outflow legs (profiling runs of the headline)")
     p.add_argument("--cpu-single-steps", type=int, default=3,
                    help="oracle steps timed on one core beside the multi-core CPU baseline (0: none)")
     return p.parse_args()
@@ -172,8 +174,8 @@ def _summarize_trace(trace_dir, out, command):
     kernels the average duration per launch shape (the full-size launches of
     the RK3 steps are the largest grid)."""
     import glob
-    stats = _read_csv(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0])
-    trace = _read_csv(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])
+    stats = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0])
+    trace = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0])
     lines = ["# rocprofv3 kernel trace: RK3 steps of the 1024x512 free-space cylinder workload", "",
              "command: " + command, "", "kernel | calls | avg us | total ms | share %", "---|---|---|---|---"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
@@ -204,7 +206,7 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
     import glob
     res = {}
     for tag, d in (("fetch", fetch_dir), ("write", write_dir)):
-        rows = _read_csv(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])
+        rows = _read_csv(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0])
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
         probe = max(copies, key=lambda r: int(r["Dispatch_Id"]))
         res[tag + "_scale"] = (256 * 1024) / float(probe["Counter_Value"])
@@ -335,11 +337,12 @@ def main():
     paths = {tag + "_" + args.solver: head}
     warm = None
     net = None
-    try:
-        paths.update(_extra_workloads(iim, wl, torch, np))
-    except Exception as e:       # recorded; the other legs still run
-        failed.append("workloads")
-        paths["workloads_error"] = repr(e)
+    if not args.no_extra_workloads:
+        try:
+            paths.update(_extra_workloads(iim, wl, torch, np))
+        except Exception as e:   # recorded; the other legs still run
+            failed.append("workloads")
+            paths["workloads_error"] = repr(e)
     if args.krylov_steps:
         try:
             net, warm = _krylov_paths(iim, w, torch, np, args, tiles, paths)
