@@ -428,6 +428,20 @@ int iim_net_get_params(const iim_net* net, int32_t which, float* host, int64_t n
 int iim_net_set_params(iim_net* net, const float* host, int64_t n);
 int iim_net_forward(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
                     float* y_dev);
+/* iim_net_forward without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  iim_net_forward grows the network's activation
+ * buffers with hipMalloc when batch * P exceeds what it holds; this call
+ * keeps the hidden activations in a 16 MiB device array of the library
+ * instead (one per GPU, held until the process ends) and writes the last
+ * layer straight into y_dev, with the same kernels: its outputs are
+ * identical.  Limit: batch * P <= 2^21 / max hidden width (16384 positions
+ * at width 128), else IIM_EINVAL naming the limit.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (two streams, or
+ * two threads) race and must be serialised by the caller.  IIM_EINVAL as
+ * iim_net_forward; IIM_EDEVICE if the array's address cannot be had. */
+int iim_net_forward_noalloc(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                            float* y_dev);
 /* Gradients of mean((y - target)^2) over batch*P outputs; loss_host
  * (nullable) receives the loss. */
 int iim_net_grad_mse(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,

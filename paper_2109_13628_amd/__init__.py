@@ -34,7 +34,7 @@ EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_give
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
            "iim_warm_start_sequences", "iim_reset_history", "iim_autotune", "iim_set_fft_shape",
            "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info",
-           "iim_dt_limit", "iim_set_speed_bound", "iim_net_train_step"]
+           "iim_dt_limit", "iim_set_speed_bound", "iim_net_train_step", "iim_net_forward_noalloc"]
 KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport", "arnoldi"]
 
 
@@ -189,6 +189,8 @@ def lib():
     L.iim_net_set_params.argtypes = [vp, vp, C.c_int64]
     L.iim_net_forward.restype = ip
     L.iim_net_forward.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp]
+    L.iim_net_forward_noalloc.restype = ip
+    L.iim_net_forward_noalloc.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp]
     L.iim_net_grad_mse.restype = ip
     L.iim_net_grad_mse.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_float)]
     L.iim_net_adam_step.restype = ip

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -27,6 +28,37 @@
 #include "ctx.hpp"
 
 using namespace iim;
+
+// Activation scratch of the allocation-free forward pass
+// (iim_net_forward_noalloc): the hidden layers' outputs alternate between the
+// two halves of this file-scope array, which every GPU the library runs on
+// holds for the life of the process.
+constexpr size_t NET_SCRATCH_FLOATS = (size_t)4 << 20;   // 16 MiB
+static __device__ __align__(256) float scratch[NET_SCRATCH_FLOATS];
+
+namespace {
+
+// Device address of the current GPU's scratch array, resolved once per device
+// with that device current (the array's name is not a device address in host
+// code); a fixed table, so that no call allocates.
+constexpr int MAX_DEVICES = 256;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return IIM_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IIM_EDEVICE;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return IIM_OK;
+}
+
+}  // namespace
 
 iim_net::~iim_net() {
   for (void* p : act_allocs) (void)hipFree(p);
@@ -314,6 +346,10 @@ int iim_net_create(const iim_net_desc* d, void* hip_stream, iim_net** out) {
     HIPCHK(hipMemset(net->grads, 0, off * sizeof(float)));
     HIPCHK(hipMemset(net->m, 0, off * sizeof(float)));
     HIPCHK(hipMemset(net->v, 0, off * sizeof(float)));
+    // the allocation-free forward pass's scratch on this device, resolved at
+    // set-up (a later first call on another device resolves that one)
+    float* sp = nullptr;
+    if (scratch_address(&sp) != IIM_OK) throw HipError("scratch array address unavailable", IIM_EDEVICE);
   } catch (const HipError& e) {
     const int code = e.code;
     delete net;
@@ -360,6 +396,42 @@ int iim_net_forward(iim_net* net, const float* x_dev, int32_t batch, int32_t P, 
     net_forward(net, s, batch, x_dev, false, net->stream);
     HIPCHK(hipMemcpyAsync(y_dev, net->H.back(), (size_t)batch * P * sizeof(float), hipMemcpyDeviceToDevice,
                           net->stream));
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    net->err = e.what();
+    return e.code;
+  }
+  return IIM_OK;
+}
+
+int iim_net_forward_noalloc(iim_net* net, const float* x_dev, int32_t batch, int32_t P, const int32_t* seq_dev,
+                            float* y_dev) {
+  if (!net || !x_dev || !seq_dev || !y_dev || batch < 1 || P < 1) return IIM_EINVAL;
+  if (net->lout.back() != 1) return IIM_EINVAL;
+  size_t wmax = 1;
+  for (int l = 0; l + 1 < net->layers; ++l) wmax = std::max(wmax, (size_t)net->lout[l]);
+  const size_t rows = (size_t)batch * P;
+  if (rows > NET_SCRATCH_FLOATS / (2 * wmax)) {
+    net->err = "iim_net_forward_noalloc: batch * P = " + std::to_string(rows) + " exceeds the scratch limit of " +
+               std::to_string(NET_SCRATCH_FLOATS / (2 * wmax)) + " positions for hidden width " + std::to_string(wmax);
+    return IIM_EINVAL;
+  }
+  float* buf = nullptr;
+  if (scratch_address(&buf) != IIM_OK) {
+    net->err = "iim_net_forward_noalloc: scratch array address unavailable";
+    return IIM_EDEVICE;
+  }
+  try {
+    const Seq s{seq_dev, seq_dev + P, seq_dev + 2 * P, P};
+    const float* in = x_dev;
+    for (int l = 0; l < net->layers; ++l) {
+      const bool last = l == net->layers - 1;
+      // hidden layers alternate between the scratch halves; the last writes y
+      float* out = last ? y_dev : buf + (size_t)(l & 1) * rows * wmax;
+      launch_conv_fwd(net->bf16, s, batch, in, net->lin[l], net->params + net->offW[l], net->params + net->offb[l],
+                      net->lout[l], nullptr, out, last ? 0 : 1, net->stream);
+      in = out;
+    }
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     net->err = e.what();
