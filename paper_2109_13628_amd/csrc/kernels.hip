@@ -1826,12 +1826,98 @@ __device__ __forceinline__ void fft_passes(CX (&v)[E], CX* lds, int t, const CX*
   }
 }
 
+// FP64 twiddles: a radix-R pass multiplies input r of a butterfly group by
+// W^(r k step); the lane loads only W^(k step) for each of its groups, once
+// per kernel for all passes (the same for the forward and the conjugated
+// inverse FFT), and forms the powers by products where they are applied.
+// The table loads were the longest dependent-latency chain of the passes;
+// the products add r - 1 roundings (about 1e-16 each) to a twiddle.
+template <int N, int E, class CX>
+struct Tw1 {
+  using PL = Plan<N, E>;
+  static constexpr int T = N / E;
+  CX w[PL::P][E];
+  __device__ __forceinline__ void load(int t, const CX* __restrict__ tw) {
+#pragma unroll
+    for (int i = 1; i < PL::P; ++i) {           // the first pass has NS = 1, no twiddles
+      const int R = PL::R[i], NS = PL::NS[i], step = N / (NS * R);
+#pragma unroll
+      for (int b = 0; b < E; ++b)
+        if (b < E / R) w[i][b] = tw[((t + T * b) & (NS - 1)) * step];
+    }
+  }
+};
+
+template <int N, int T, int E, int R, int NS, bool INV, bool LAST, class CX>
+__device__ __forceinline__ void reg_pass_w(CX (&v)[E], CX* lds, int t, const CX* w1) {
+  constexpr int B = E / R;
+  CX u[B][R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[b][r] = v[b + r * B];
+    if constexpr (NS > 1) {
+      CX wb = w1[b];
+      if (INV) wb.y = -wb.y;
+      CX w = wb;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        if (r > 1) w = cmul(w, wb);
+        u[b][r] = cmul(u[b][r], w);
+      }
+    }
+    dftR<R, INV>(u[b]);
+  }
+  if (LAST) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * B] = u[b][r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + T * b;
+      const int k = j & (NS - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[padi(base + r * NS)] = u[b][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = lds[padi(t + T * m)];
+    __syncthreads();
+  }
+}
+
+template <int N, bool INV, class CX, int E, int I>
+__device__ __forceinline__ void fft_passes_w(CX (&v)[E], CX* lds, int t, const Tw1<N, E, CX>& tw1) {
+  using PL = Plan<N, E>;
+  constexpr int T = N / E;
+  reg_pass_w<N, T, E, PL::R[I], PL::NS[I], INV, (I + 1 == PL::P)>(v, lds, t, tw1.w[I]);
+  if constexpr (I + 1 < PL::P) fft_passes_w<N, INV, CX, E, I + 1>(v, lds, t, tw1);
+}
+
 // In-register FFT of N points, E per lane (T = N / E lanes), LDS exchanges
-// between passes.
+// between passes; FP64 with the twiddles of Tw1 (preloaded by the caller).
+template <int N, bool INV, class CX, int E>
+__device__ __forceinline__ void fft_reg_w(CX (&v)[E], CX* lds, int t, const Tw1<N, E, CX>& tw1) {
+  fft_passes_w<N, INV, CX, E, 0>(v, lds, t, tw1);
+}
+
+// In-register FFT of N points, E per lane (T = N / E lanes), LDS exchanges
+// between passes.  FP64: base twiddles loaded up front (Tw1); FP32 (the
+// mixed-precision products, whose error budget assumes table twiddles): every
+// power from the table, one pass ahead.
 template <int N, bool INV, class CX, int E>
 __device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
-  PlanTw<N, E, 0, CX> first;   // the first pass has no twiddles
-  fft_passes<N, INV, CX, E, 0>(v, lds, t, tw, first);
+  if constexpr (std::is_same<CX, double2>::value) {
+    Tw1<N, E, CX> tw1;
+    tw1.load(t, tw);
+    fft_reg_w<N, INV, CX, E>(v, lds, t, tw1);
+  } else {
+    PlanTw<N, E, 0, CX> first;   // the first pass has no twiddles
+    fft_passes<N, INV, CX, E, 0>(v, lds, t, tw, first);
+  }
 }
 
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
@@ -1921,13 +2007,25 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
     const int n = t + T * m;
     gk[m] = gh[n <= MY / 2 ? n : MY - n];
   }
-  fft_reg<MY, false>(v, lds[w], t, ft.tw_y);
+  if constexpr (std::is_same<CX, double2>::value) {
+    Tw1<MY, E, CX> tw1;   // both FFTs' base twiddles
+    tw1.load(t, ft.tw_y);
+    fft_reg_w<MY, false>(v, lds[w], t, tw1);
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    v[m].x *= gk[m];
-    v[m].y *= gk[m];
+    for (int m = 0; m < E; ++m) {
+      v[m].x *= gk[m];
+      v[m].y *= gk[m];
+    }
+    fft_reg_w<MY, true>(v, lds[w], t, tw1);
+  } else {
+    fft_reg<MY, false>(v, lds[w], t, ft.tw_y);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      v[m].x *= gk[m];
+      v[m].y *= gk[m];
+    }
+    fft_reg<MY, true>(v, lds[w], t, ft.tw_y);
   }
-  fft_reg<MY, true>(v, lds[w], t, ft.tw_y);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
