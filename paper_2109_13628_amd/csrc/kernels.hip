@@ -1068,17 +1068,14 @@ __device__ double flux_general(const TGeom& g, const double* __restrict__ omega,
     } else {
       const int q = jj * g.nx + ii;
       const int c = g.cls[q];
+      const double oq = omega[q];
+      const double e4 = w4 ? w4[q] : 0.0, eb = w3b ? w3b[q] : 0.0, en = w3n ? w3n[q] : 0.0;
       kind[t] = c < 2 ? NK_FLUID : (c == 2 ? NK_GHOST : NK_SOLID);
-      if (kind[t] == NK_FLUID) {
-        w[t] = w4v[t] = wb[t] = wn[t] = omega[q];
-      } else if (kind[t] == NK_GHOST) {
-        w[t] = 0.0;
-        w4v[t] = w4[q];
-        wb[t] = w3b[q];
-        wn[t] = w3n[q];
-      } else {
-        w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
-      }
+      const bool fl = kind[t] == NK_FLUID, gh = kind[t] == NK_GHOST;
+      w[t] = fl ? oq : 0.0;
+      w4v[t] = fl ? oq : (gh ? e4 : 0.0);
+      wb[t] = fl ? oq : (gh ? eb : 0.0);
+      wn[t] = fl ? oq : (gh ? en : 0.0);
     }
   }
   const bool fl0 = kind[1] == NK_FLUID || kind[1] == NK_OUT;
@@ -1099,6 +1096,25 @@ __device__ double flux_general(const TGeom& g, const double* __restrict__ omega,
     f[t] = u[t] * om;
   }
   return flux_core(use_left, f[0], f[1], f[2], f[3], w4v[1], w4v[2], g.nu * g.inv_h);
+}
+
+// Face between node (i, j) and (i, j) + e_axis whose four stencil nodes are
+// all regular fluid nodes inside the grid (the faces of a bounding region
+// R_k): the values come straight from omega and psi (or U / V), no class loads.
+template <bool P>
+__device__ __forceinline__ double flux_interior(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                                int i, int j, int axis) {
+  const int nxr = g.nx + 2;
+  const int dq = axis == 0 ? 1 : g.nx, dr = axis == 0 ? 1 : nxr;
+  const int q = j * g.nx + i, r = (j + 1) * nxr + i + 1;
+  double u[4], w[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    w[t] = omega[q + (t - 1) * dq];
+    const int rt = r + (t - 1) * dr;
+    u[t] = axis == 0 ? vel.u_at(g, rt) : vel.v_at(g, rt);
+  }
+  return flux_std(u[0], u[1], u[2], u[3], w[0], w[1], w[2], w[3], g.nu * g.inv_h);
 }
 
 // Bulk nodes (cls 0): all stencil nodes are fluid and inside the grid.
@@ -1187,8 +1203,13 @@ __device__ __forceinline__ void transport_special(const TGeom& g, const double* 
   const bool act = sp < g.nsp;
   int q = 0;
   double fl = 0.0;
+  double qp = 0.0, wq = 0.0;
   if (act) {
     q = g.special[sp];
+    if (face == 0 && mode == 1) {
+      qp = a == 0.0 ? 0.0 : Q[q];
+      wq = omega[q];
+    }
     const int i = q % g.nx, j = q / g.nx;
     const int fi = face == 1 ? i - 1 : i, fj = face == 3 ? j - 1 : j;
     fl = flux_general(g, omega, vel, w4, w3b, w3n, fi, fj, face >> 1);
@@ -1201,10 +1222,9 @@ __device__ __forceinline__ void transport_special(const TGeom& g, const double* 
   if (mode == 0) {
     out[q] = rhs;
   } else {
-    const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
     const double qn = a * qp + dt * rhs;
     Q[q] = qn;
-    const double wn = omega[q] + b * qn;
+    const double wn = wq + b * qn;
     out[q] = wn;
     mark_nonfinite(g, wn);
   }
@@ -1219,16 +1239,18 @@ __device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict_
   const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
   const int nv = j1 - j0 + 1, nh = i1 - i0 + 1;
   double acc = 0.0;
-  for (int t = threadIdx.x; t < 2 * (nv + nh); t += blockDim.x) {
-    if (t < nv) {
-      acc += flux_general(g, omega, vel, nullptr, nullptr, nullptr, i1, j0 + t, 0);           // right (+)
-    } else if (t < 2 * nv) {
-      acc -= flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 - 1, j0 + t - nv, 0);  // left (-)
-    } else if (t < 2 * nv + nh) {
-      acc += flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 + t - 2 * nv, j1, 1);  // top (+)
-    } else {
-      acc -= flux_general(g, omega, vel, nullptr, nullptr, nullptr, i0 + t - 2 * nv - nh, j0 - 1, 1);  // bottom
-    }
+  const int nf = 2 * (nv + nh);
+  auto face = [&](int t) {
+    if (t < nv) return flux_interior(g, omega, vel, i1, j0 + t, 0);                 // right (+)
+    if (t < 2 * nv) return -flux_interior(g, omega, vel, i0 - 1, j0 + t - nv, 0);   // left (-)
+    if (t < 2 * nv + nh) return flux_interior(g, omega, vel, i0 + t - 2 * nv, j1, 1);  // top (+)
+    return -flux_interior(g, omega, vel, i0 + t - 2 * nv - nh, j0 - 1, 1);            // bottom (-)
+  };
+  for (int t = threadIdx.x; t < nf; t += 2 * blockDim.x) {
+    const int t2 = t + blockDim.x;
+    const double a0 = face(t), a1 = t2 < nf ? face(t2) : 0.0;
+    acc += a0;
+    acc += a1;
   }
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) {
@@ -1940,7 +1962,8 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    v[m] = (valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
+    // rows at and past MY / 2 are the zero padding of every source
+    v[m] = (m < E / 2 && valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
   }
   if (gam) {
     // Correction sources: the column's T lanes compute the terms
@@ -1959,7 +1982,7 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int n = t + T * m;
-      const bool in = n >= jb && n <= je;
+      const bool in = m < E / 2 && n >= jb && n <= je;   // sources lie below MY / 2
       rb[m] = in ? g.row_ptr[n] : 0;
       re[m] = in ? g.row_ptr[n + 1] : 0;
     }
@@ -1992,7 +2015,7 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
       }
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
+      for (int m = 0; m < E / 2; ++m) {
         const int q1 = min(re[m], c1);
         for (int q = max(rb[m], c0); q < q1; ++q) v[m] = cadd(v[m], lds[w][q - c0]);
       }
