@@ -18,6 +18,14 @@ function g of oracle.lgf, evaluated by a zero-padded FFT convolution on a
 
 Outflow: free space in y and at x_min, with an even mirror of the source
 across the face x_{nx-1/2}:  psi(i) = sum_i' [g(i - i') + g(i + i' - 2 nx + 1)] s(i').
+
+Periodic (Sec. 4.1, the periodic exterior): node i + nx is node i (same in
+y).  The 5-point operator on the periodic lattice is diagonalised by the
+discrete Fourier transform with eigenvalues
+(4/h^2) [sin^2(pi kx / nx) + sin^2(pi ky / ny)]; its null space is the
+constant, so the source's mean is removed and psi is the solution of zero
+mean (the paper's gauge for the periodic part of the stream function).  The
+ring holds the periodic images.
 """
 from __future__ import annotations
 
@@ -47,6 +55,21 @@ def box_dirichlet(s, h):
     out[-1, 0] = psi[-1, 0]
     out[-1, -1] = psi[-1, -1]
     return out
+
+
+def periodic(s, h):
+    s = np.asarray(s, dtype=np.float64)
+    ny, nx = s.shape
+    lam = (4.0 / h ** 2) * (np.sin(np.pi * np.arange(ny) / ny)[:, None] ** 2
+                            + np.sin(np.pi * np.arange(nx) / nx)[None, :] ** 2)
+    sh = sfft.fft2(s)
+    lam[0, 0] = 1.0
+    sh = sh / lam
+    sh[0, 0] = 0.0                     # zero mean: the gauge of the periodic part
+    psi = sfft.ifft2(sh).real
+    jj = np.arange(-1, ny + 1) % ny
+    ii = np.arange(-1, nx + 1) % nx
+    return psi[np.ix_(jj, ii)]
 
 
 class FreeSpace:

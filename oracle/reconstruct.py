@@ -19,7 +19,13 @@ The circulation row follows from summing the 5-point equation over R_k
 
 psi is the perturbation stream function; in free space the total stream
 function is psi + psi_inf, psi_inf = u_inf,x y - u_inf,y x, and
-psi_b_tilde = psi_b - psi_inf at the control points.
+psi_b_tilde = psi_b - psi_inf at the control points.  With the periodic
+exterior (Sec. 4.1) u_inf is the prescribed mean velocity, psi is periodic
+with zero mean, and the system is solvable when the circulations satisfy
+the discrete form of the paper's solvability condition,
+h^2 sum_{outside every R_k} omega = -sum_k Gamma_k (summing the 5-point
+equation over the periodic lattice gives sum omega = sum_A gamma, and the
+circulation rows give sum_A gamma); G drops the mean of its source.
 
 Velocity (Sec. 4.2, last paragraph): psi is extrapolated to A- at fourth
 order with the boundary value psi_b_tilde + psibar_k, then
@@ -52,6 +58,9 @@ class Reconstructor:
         self.ext = grid.exterior
         if self.ext == "box":
             self._G = lambda s: poisson.box_dirichlet(s, self.h)
+            self._tab = None
+        elif self.ext == "periodic":
+            self._G = lambda s: poisson.periodic(s, self.h)
             self._tab = None
         else:
             out = self.ext == "outflow"

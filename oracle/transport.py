@@ -26,7 +26,9 @@ Domain edges in free space (our reading): nodes outside the grid carry
 omega = 0 and count as fluid for the choice of stencil; the face velocity
 at the outermost face uses the exact ring velocity.  With an outflow plane
 at the face x_{nx-1/2} (Sec. 5.2) the two nodes past it carry the mirrored
-vorticity and x-velocity instead.
+vorticity and x-velocity instead.  With the periodic exterior (Sec. 4.1)
+node i + nx is node i: the two nodes past every edge carry the values,
+classes and extensions of the nodes they repeat.
 
 Boundary vorticity omega_b at each control point: the stencil of
 Geometry.vorticity_bc_stencil applied to the extended velocity.
@@ -68,6 +70,15 @@ def vorticity_extensions(geom, omega, wb):
 
 def _padded(geom, omega, U, V, e4b, e3b, e3n):
     nx, ny = geom.nx, geom.ny
+    if geom.grid.exterior == "periodic":
+        wrap = lambda a: np.pad(a, 2, mode="wrap")
+        w = np.where(geom.fluid, omega, 0.0)
+        w4, w3b, w3n = np.zeros((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx))
+        w4[geom.g_j, geom.g_i] = e4b
+        w3b[geom.g_j, geom.g_i] = e3b
+        w3n[geom.g_j, geom.g_i] = e3n
+        return (wrap(geom.cls), wrap(w), wrap(w4), wrap(w3b), wrap(w3n), wrap(U[1:-1, 1:-1]),
+                wrap(V[1:-1, 1:-1]))
     P = lambda fill: np.full((ny + 4, nx + 4), fill, dtype=np.float64)
     cls = np.full((ny + 4, nx + 4), OUTSIDE, dtype=int)
     cls[2:-2, 2:-2] = geom.cls

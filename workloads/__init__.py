@@ -26,6 +26,7 @@ import numpy as np
 EXT_BOX = "box"          # Dirichlet box (stream function zero on the box faces)
 EXT_FREE = "free"        # unbounded domain
 EXT_OUTFLOW = "outflow"  # unbounded, with an even mirror plane at the x_max face
+EXT_PERIODIC = "periodic"  # periodic in both directions, u_inf = the mean velocity
 
 
 @dataclass
@@ -236,6 +237,37 @@ def surface_driven_cylinder(nx=128, ny=96, h=1.0 / 32, points=128, center=(1.5, 
     samples = np.stack([-U * np.sin(phi), U * np.cos(phi), np.zeros_like(phi)], axis=1)
     body = dataclasses.replace(w.bodies[0], bc_samples=samples)
     return dataclasses.replace(w, name="surface_driven_cylinder_%dx%d" % (nx, ny), bodies=[body])
+
+
+def periodic_cylinder(nx=128, ny=64, h=1.0 / 16, points=128, dt=0.01, center=(2.0, 0.0), mean=(1.0, 0.0)):
+    """A D = 1 cylinder in a box periodic in both directions (a row-and-column
+    array of cylinders) with the mean velocity `mean`; cell-centred grid on
+    [0, nx*h) x [-ny*h/2, ny*h/2); nx, ny powers of two."""
+    w = cylinder(nx=nx, ny=ny, h=h, points=points, dt=dt, steps=5, center=center)
+    w.grid.exterior = EXT_PERIODIC
+    w.grid.u_inf = tuple(mean)
+    w.name = "periodic_cylinder_%dx%d" % (nx, ny)
+    return w
+
+
+def cosine_wave_transport(n, nu, u=(1.0, 2.0), k=(4 * math.pi, 2 * math.pi)):
+    """The transport study of Sec. 3 (its periodic case): the unit square,
+    x_ij = (i/n, j/n), periodic in both directions, a C-shaped body (centre
+    (0.507, 0.531), r_a 0.201, r_b 0.054, theta_a 0.5, theta_b 2.4), the
+    uniform velocity u and the exact field omega = cos(k.(x - u t))
+    exp(-nu |k|^2 t) (returned by extra['exact'](x, y, t)); dt = 0.9 dt_max
+    for a_max = |u_x| + |u_y|."""
+    h = 1.0 / n
+    grid = GridDesc(nx=n, ny=n, x0=0.0, y0=0.0, h=h, exterior=EXT_PERIODIC, u_inf=tuple(u), nu=nu)
+    body = BodyDesc(points=c_shape_points((0.507, 0.531), 0.201, 0.054, 0.5, 2.4, max(256, int(8.0 / h))),
+                    center=(0.507, 0.531), u_rigid=tuple(u))
+    kk = k[0] * k[0] + k[1] * k[1]
+
+    def exact(x, y, t):
+        return np.cos(k[0] * (x - u[0] * t) + k[1] * (y - u[1] * t)) * math.exp(-nu * kk * t)
+
+    dt = dt_from_polygon(h, nu, abs(u[0]) + abs(u[1]), 0.9)
+    return Workload("cosine_wave_transport_%d" % n, grid, [body], dt, 0, extra={"exact": exact, "u": u})
 
 
 def cylinder_outflow_small():
