@@ -473,11 +473,14 @@ def _batch_child(args):
 
 def _extra_workloads(iim, wl, torch, np):
     """The other single-GPU configurations, FP64 dense solver, graph replay:
-    Taylor-Couette in the DST box (128 x 128, 20 steps) and four nonconvex
-    bodies with an outflow plane (2048 x 2048)."""
+    Taylor-Couette in the DST box (128 x 128, 20 steps), four nonconvex
+    bodies with an outflow plane (2048 x 2048) and the cylinder of the
+    headline in a periodic box (1024 x 512, mean velocity (1, 0))."""
     res = {}
     for name, w, warm, steps in (("taylor_couette_128_box", wl.taylor_couette(128), 5, 20),
-                                 ("multi_body_2048_outflow", wl.multi_body(2048), 3, 10)):
+                                 ("multi_body_2048_outflow", wl.multi_body(2048), 3, 10),
+                                 ("periodic_cylinder_1024x512", wl.periodic_cylinder(
+                                     nx=1024, ny=512, h=1.0 / 64, points=256, dt=0.0025, center=(4.0, 0.0)), 5, 20)):
         _say("workload %s: %d warm-up and %d timed steps" % (w.name, warm, steps))
         t0 = time.perf_counter()
         ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)

@@ -60,7 +60,14 @@ enum {
 enum {
   IIM_EXT_BOX = 0,        /* stream function zero on the box faces half a cell outside the edge nodes */
   IIM_EXT_FREE = 1,       /* unbounded domain: lattice Green's function convolution */
-  IIM_EXT_OUTFLOW = 2     /* unbounded, with the vorticity mirrored (even) across the face x_{nx-1/2} */
+  IIM_EXT_OUTFLOW = 2,    /* unbounded, with the vorticity mirrored (even) across the face x_{nx-1/2} */
+  IIM_EXT_PERIODIC = 3    /* periodic in x and y (Sec. 4.1): node i + nx is node i, j + ny is j; u_inf is
+                             the mean velocity, the periodic part of the stream function has zero mean
+                             (its source's mean is dropped), nx and ny are powers of two >= 32, and the
+                             bodies' bounding regions lie inside the grid; steps keep the discrete
+                             solvability sum h^2 sum_{outside every R_k} omega + sum_k Gamma_k, which the
+                             caller's state must start at zero for the reconstruction to solve the
+                             paper's problem */
 };
 
 /* Precision of the Krylov solve.  MIXED: once the GMRES residual estimate

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("IIM_LIBRARY") or os.path.join(HERE, "libiim.so")
 
 IIM_OK, IIM_EINVAL, IIM_ENOMEM, IIM_EGEOM, IIM_ENOCONV, IIM_ENONFINITE, IIM_EDEVICE, IIM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
-EXT = {"box": 0, "free": 1, "outflow": 2}
+EXT = {"box": 0, "free": 1, "outflow": 2, "periodic": 3}
 PREC_FP64, PREC_MIXED = 0, 1
 GUESS_ZERO, GUESS_PREVIOUS, GUESS_EXTRAPOLATE, GUESS_NETWORK = 0, 1, 2, 3
 NET_FEATURES = 10

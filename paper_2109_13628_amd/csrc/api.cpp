@@ -62,6 +62,25 @@ std::vector<double> kernel_spectrum(int mx, int my, double h) {
   return out;
 }
 
+// Spectrum of the zero-mean periodic inverse of the 5-point Laplacian on
+// the mx x my torus of the grid: 1 / lambda(kx, ky) with lambda =
+// (4 / h^2) (sin^2(pi kx / mx) + sin^2(pi ky / my)), the constant mode
+// dropped, scaled by 1/(mx my) like the free-space spectrum:
+// out[kx*(my/2+1) + ky], kx <= mx/2, ky <= my/2 (even in both directions).
+std::vector<double> periodic_spectrum(int mx, int my, double h) {
+  std::vector<double> out((size_t)(mx / 2 + 1) * (my / 2 + 1));
+  const double c = 4.0 / (h * h), scale = 1.0 / ((double)mx * my);
+  for (int kx = 0; kx <= mx / 2; ++kx) {
+    const double sx = std::sin(M_PI * kx / mx);
+    for (int ky = 0; ky <= my / 2; ++ky) {
+      const double sy = std::sin(M_PI * ky / my);
+      const double lam = c * (sx * sx + sy * sy);
+      out[(size_t)kx * (my / 2 + 1) + ky] = (kx == 0 && ky == 0) ? 0.0 : scale / lam;
+    }
+  }
+  return out;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- helpers
@@ -242,6 +261,7 @@ void setup_device(iim_ctx* c) {
   d.nsp = (int)g.special.size();
   d.n = g.na + g.nbc();
   d.outflow = g.grid.exterior == IIM_EXT_OUTFLOW ? 1 : 0;
+  d.periodic = g.grid.exterior == IIM_EXT_PERIODIC ? 1 : 0;
   // classes: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
   std::vector<int8_t> cls(N);
   for (size_t q = 0; q < N; ++q) cls[q] = g.cls[q] == CLS_FLUID ? 0 : (g.cls[q] == CLS_GHOST ? 2 : 3);
@@ -376,7 +396,12 @@ void setup_device(iim_ctx* c) {
     c->dd.src = c->dalloc<double>(N);
   } else {
     const bool outflow = g.grid.exterior == IIM_EXT_OUTFLOW;
-    const int mx = next_pow2((outflow ? 4 : 2) * nx), my = next_pow2(2 * ny);
+    const bool periodic = g.grid.exterior == IIM_EXT_PERIODIC;
+    if (periodic && (nx < 32 || ny < 32 || next_pow2(nx) != nx || next_pow2(ny) != ny))
+      throw ArgError("the periodic exterior needs power-of-two nx, ny >= 32");
+    // free space: a zero-padded torus (>= 2 nx, >= 2 ny; 4 nx with the
+    // outflow mirror); periodic: the grid itself
+    const int mx = periodic ? nx : next_pow2((outflow ? 4 : 2) * nx), my = periodic ? ny : next_pow2(2 * ny);
     if (mx / 2 > 4096 || my > 4096) throw ArgError("grid too large for the FFT plan (mx/2, my <= 4096)");
     DFft& f = c->df;
     f.mx = mx;
@@ -384,8 +409,9 @@ void setup_device(iim_ctx* c) {
     f.hx = mx / 2;
     f.ld = ny + 2;
     f.outflow = outflow;
+    f.periodic = periodic;
     f.use_reg = std::getenv("IIM_FFT_LDS_ONLY") == nullptr;
-    const std::vector<double> ghat = kernel_spectrum(mx, my, h);
+    const std::vector<double> ghat = periodic ? periodic_spectrum(mx, my, h) : kernel_spectrum(mx, my, h);
     f.ghat = c->upload(ghat);
     auto twid = [](int n, int count) {
       std::vector<double2> t(count);
@@ -1020,7 +1046,10 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
     gs.u_inf[0] = grid->u_inf[0];
     gs.u_inf[1] = grid->u_inf[1];
     gs.nu = grid->nu;
-    if (gs.exterior < IIM_EXT_BOX || gs.exterior > IIM_EXT_OUTFLOW) throw ArgError("unknown exterior condition");
+    if (gs.exterior < IIM_EXT_BOX || gs.exterior > IIM_EXT_PERIODIC) throw ArgError("unknown exterior condition");
+    if (gs.exterior == IIM_EXT_PERIODIC &&
+        (gs.nx < 32 || gs.ny < 32 || next_pow2(gs.nx) != gs.nx || next_pow2(gs.ny) != gs.ny))
+      throw ArgError("the periodic exterior needs power-of-two nx, ny >= 32");
     if (!(gs.nu >= 0.0)) throw ArgError("nu must be >= 0");
     std::vector<BodySpec> bs(n_bodies);
     for (int k = 0; k < n_bodies; ++k) {

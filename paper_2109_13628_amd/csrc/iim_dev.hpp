@@ -35,6 +35,7 @@ struct DGeom {
   int nc, ng, na, nbc, nsp;
   int n;                       // Krylov unknowns: na + nbc
   int outflow;                 // 1: even mirror plane at the face x_{nx-1/2}
+  int periodic;                // 1: periodic in x and y (node i + nx is node i)
   const int8_t* cls;           // [ny][nx]: 0 bulk fluid, 1 boundary-kernel fluid, 2 ghost, 3 solid
   const int* g_ridx;           // ghost -> ring index
   const int* g_gidx;           // ghost -> grid index
@@ -101,6 +102,7 @@ struct DFft {
   float2* spec32 = nullptr;
   float2* spec32_out = nullptr;
   bool outflow;
+  bool periodic = false;       // unpadded torus of the grid itself: every row and column carries data
   bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
   int row_per = 0, col_per = 0; // FFTs per workgroup of the row / column passes (0: default; tuned)
 };

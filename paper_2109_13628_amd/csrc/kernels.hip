@@ -328,7 +328,9 @@ k_rows_inv(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, const d
     const int rr = t / (g.nx + 2), ii = t % (g.nx + 2) - 1;   // ii in [-1, nx]
     const int jo = j0 + blockIdx.x * C::PER + rr;
     if (jo >= j0 + count) continue;
-    const int i = ii < 0 ? 2 * HX - 1 : ii;
+    // ring columns -1 and nx: torus positions mx - 1 and nx (nx wraps to 0
+    // on the unpadded periodic torus)
+    const int i = ii < 0 ? 2 * HX - 1 : (ii >= 2 * HX ? ii - 2 * HX : ii);
     const double2 zz = lds[rr][i >> 1];
     psi[(size_t)(jo + 1) * nxr + (ii + 1)] = (i & 1) ? zz.y : zz.x;
   }
@@ -976,7 +978,7 @@ enum { NK_FLUID = 0, NK_GHOST = 1, NK_SOLID = 2, NK_OUT = 3 };
 // geometry's many other table pointers do not occupy scalar registers of
 // this large kernel (they spilled to scratch memory).
 struct TGeom {
-  int nx, ny, nsp, nbc, outflow;
+  int nx, ny, nsp, nbc, outflow, periodic;
   double h, inv_h, nu, uinf_x, uinf_y;
   const int8_t* __restrict__ cls;
   const int* __restrict__ special;
@@ -1054,7 +1056,11 @@ __device__ double flux_general(const TGeom& g, const double* __restrict__ omega,
   double u[4], w[4], w4v[4], wb[4], wn[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int ii = i + (t - 1) * di, jj = j + (t - 1) * dj;
+    int ii = i + (t - 1) * di, jj = j + (t - 1) * dj;
+    if (g.periodic) {   // the node a periodic edge repeats
+      ii = (ii + g.nx) % g.nx;
+      jj = (jj + g.ny) % g.ny;
+    }
     const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
     u[t] = vel.node(g, axis, ii, jj);
     if (!in) {
@@ -1161,17 +1167,24 @@ __device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __r
     }
     wc = omega[q];
     // near the grid edge: nodes outside carry omega = 0; velocities come from the ring
-    // with an outflow plane at x_{nx-1/2}, nodes nx, nx+1 mirror nx-1, nx-2 (omega and u_x even)
-    const bool mir = g.outflow != 0;
+    // with an outflow plane at x_{nx-1/2}, nodes nx, nx+1 mirror nx-1, nx-2 (omega and u_x even);
+    // periodic: the nodes past an edge are the nodes they repeat
+    const bool mir = g.outflow != 0, per = g.periodic != 0;
+    auto wx = [&](int ii) { return per ? (ii + nx) % nx : ii; };
+    auto wy = [&](int jj) { return per ? (jj + ny) % ny : jj; };
     auto W = [&](int ii, int jj) {
+      ii = wx(ii);
+      jj = wy(jj);
       if (mir && ii >= nx && ii <= nx + 1 && jj >= 0 && jj < ny) ii = 2 * nx - 1 - ii;
       return (ii >= 0 && jj >= 0 && ii < nx && jj < ny) ? omega[jj * nx + ii] : 0.0;
     };
     auto UU = [&](int ii, int jj) {
+      ii = wx(ii);
+      jj = wy(jj);
       if (mir && ii == nx + 1) ii = nx - 2;
       return vel.node(g, 0, ii, jj);
     };
-    auto VV = [&](int ii, int jj) { return vel.node(g, 1, ii, jj); };
+    auto VV = [&](int ii, int jj) { return vel.node(g, 1, wx(ii), wy(jj)); };
     fxr = flux_std(UU(i - 1, j), UU(i, j), UU(i + 1, j), UU(i + 2, j), W(i - 1, j), wc, W(i + 1, j), W(i + 2, j), nih);
     fxl = flux_std(UU(i - 2, j), UU(i - 1, j), UU(i, j), UU(i + 1, j), W(i - 2, j), W(i - 1, j), wc, W(i + 1, j), nih);
     fyt = flux_std(VV(i, j - 1), VV(i, j), VV(i, j + 1), VV(i, j + 2), W(i, j - 1), wc, W(i, j + 1), W(i, j + 2), nih);
@@ -1303,8 +1316,8 @@ void launch_transport_all(const DGeom& g, const double* omega, const double* psi
                           double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
                           Prof* prof) {
   const int blocks = ((g.nx + 255) / 256) * g.ny + (4 * g.nsp + 255) / 256 + g.nbc;
-  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls, g.special,
-                 g.rects, g.nonfinite};
+  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
+                 g.special, g.rects, g.nonfinite};
   if (psi) {
     // algorithmic bytes per cell: omega, psi, Q read; out, Q written
     IIM_LAUNCH(prof, KID_TRANSPORT, 40.0 * g.nx * g.ny, k_transport_all<true>, blocks, 256, s, tg, omega, psi, U, V,
@@ -1943,7 +1956,9 @@ __device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __
 }
 
 // ---- column pass: FFT, multiply by the kernel spectrum, inverse FFT; in/out rows pruned
-template <int MY, class CX, int PER>
+// PADY: the torus is the zero-padded free-space one (rows at and past MY / 2
+// carry no source); false: the unpadded periodic torus of the grid itself.
+template <int MY, class CX, int PER, bool PADY>
 __global__ void __launch_bounds__((RegCfg<MY, PER>::THREADS))
 k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double sgn, int rj0, int rj1, int oj0,
            int oj1, const double* __restrict__ done) {
@@ -1959,11 +1974,15 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
   const CX* col = ft.spec + (size_t)(valid ? kx : 0) * f.ld;
   CX* out = ft.out + (size_t)(valid ? kx : 0) * f.ld;
   CX v[E];
+  // rows at and past MY / 2 are the zero padding of every source on the
+  // padded free-space torus (folded at compile time); the periodic torus is
+  // the grid itself
+  constexpr bool pad_y = PADY;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int n = t + T * m;
-    // rows at and past MY / 2 are the zero padding of every source
-    v[m] = (m < E / 2 && valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
+    const bool row_ok = pad_y ? (m < E / 2) : true;
+    v[m] = (row_ok && valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
   }
   if (gam) {
     // Correction sources: the column's T lanes compute the terms
@@ -1982,7 +2001,7 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int n = t + T * m;
-      const bool in = m < E / 2 && n >= jb && n <= je;   // sources lie below MY / 2
+      const bool in = (pad_y ? m < E / 2 : true) && n >= jb && n <= je;   // padded: sources lie below MY / 2
       rb[m] = in ? g.row_ptr[n] : 0;
       re[m] = in ? g.row_ptr[n + 1] : 0;
     }
@@ -2015,9 +2034,11 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
       }
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < E / 2; ++m) {
-        const int q1 = min(re[m], c1);
-        for (int q = max(rb[m], c0); q < q1; ++q) v[m] = cadd(v[m], lds[w][q - c0]);
+      for (int m = 0; m < E; ++m) {
+        if (!pad_y || m < E / 2) {   // padded: rows past MY / 2 carry no source
+          const int q1 = min(re[m], c1);
+          for (int q = max(rb[m], c0); q < q1; ++q) v[m] = cadd(v[m], lds[w][q - c0]);
+        }
       }
       __syncthreads();
     }
@@ -2053,8 +2074,16 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int n = t + T * m;
-      const int jo = (n == MY - 1) ? -1 : n;
-      if (jo >= oj0 && jo <= oj1) out[jo + 1] = v[m];
+      if (pad_y) {
+        // ring row -1 is torus row MY - 1, ring row ny torus row ny
+        const int jo = (n == MY - 1) ? -1 : n;
+        if (jo >= oj0 && jo <= oj1) out[jo + 1] = v[m];
+      } else {
+        // the grid's own rows; the ring rows -1 and ny repeat rows ny - 1 and 0
+        if (n >= oj0 && n <= oj1) out[n + 1] = v[m];
+        if (n == MY - 1 && oj0 <= -1) out[0] = v[m];
+        if (n == 0 && oj1 >= g.ny) out[g.ny + 1] = v[m];
+      }
     }
   }
 }
@@ -2177,6 +2206,7 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
     if (i0 <= g.nx) row[i0 + 1] = v[m].x;
     if (i1 <= g.nx) row[i1 + 1] = v[m].y;
     if (i1 == 2 * HX - 1) row[0] = v[m].y;
+    if (f.periodic && i0 == 0) row[g.nx + 1] = v[m].x;   // ring column nx repeats column 0
   }
 }
 
@@ -2194,8 +2224,12 @@ void cols_go(const DGeom& g, const DFft& f, bool dense, const double* gam, doubl
              int oj1, const double* done, hipStream_t s, Prof* prof, double bytes) {
   using C = RegCfg<MY, PER>;
   const int blocks = (f.hx + 1 + C::PER - 1) / C::PER;
-  IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER>, blocks, C::THREADS, s, g, f, dense, gam,
-             sgn, rj0, rj1, oj0, oj1, done);
+  if (f.periodic)
+    IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER IIM_COMMA false>, blocks, C::THREADS, s,
+               g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done);
+  else
+    IIM_LAUNCH(prof, KID_COLS, bytes, k_cols_reg<MY IIM_COMMA CX IIM_COMMA PER IIM_COMMA true>, blocks, C::THREADS, s,
+               g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done);
 }
 template <int HX, class CX, int PER>
 void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done, hipStream_t s,
@@ -2281,7 +2315,8 @@ void rows_fwd_fit(FitCheck& fc) {
 }
 template <int MY, class CX, int PER>
 void cols_fit(FitCheck& fc) {
-  fc.add((const void*)k_cols_reg<MY, CX, PER>, RegCfg<MY, PER>::THREADS, "column pass");
+  fc.add((const void*)k_cols_reg<MY, CX, PER, true>, RegCfg<MY, PER>::THREADS, "column pass");
+  fc.add((const void*)k_cols_reg<MY, CX, PER, false>, RegCfg<MY, PER>::THREADS, "column pass (periodic)");
 }
 template <int HX, class CX, int PER>
 void rows_inv_fit(FitCheck& fc) {

@@ -227,3 +227,22 @@ def test_workload_steps_within_limit():
         ctx = iim.Context(w.grid, w.bodies, host_only=True)
         assert w.dt <= ctx.dt_limit(), (w.name, w.dt, ctx.dt_limit())
         ctx.close()
+
+
+def test_periodic_exterior_host_side():
+    """The periodic exterior: power-of-two grids of at least 32 nodes per
+    side; the bodies' geometry and step limit as in free space (the mean
+    velocity in place of the free stream)."""
+    w = wl.periodic_cylinder()
+    ctx = iim.Context(w.grid, w.bodies, host_only=True)
+    ref = iim.Context(wl.cylinder(nx=128, ny=64, h=1.0 / 16, points=128, dt=0.01, center=(2.0, 0.0)).grid,
+                      w.bodies, host_only=True)
+    assert ctx.info["n_affected"] == ref.info["n_affected"] and ctx.n_circ == 1
+    assert abs(ctx.dt_limit() - ctx.dt_max(np.sqrt(2.0) * 2.0 * np.hypot(*w.grid.u_inf))) < 1e-15
+    ctx.close()
+    ref.close()
+    for nx, ny in ((96, 64), (64, 16), (64, 48)):
+        g = wl.GridDesc(nx=nx, ny=ny, x0=0.0, y0=0.0, h=0.1, exterior=wl.EXT_PERIODIC)
+        with pytest.raises(iim.IIMError) as e:
+            iim.Context(g, [], host_only=True)
+        assert e.value.code == iim.IIM_EINVAL and "power-of-two" in str(e.value)

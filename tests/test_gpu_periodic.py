@@ -1,0 +1,126 @@
+"""The periodic exterior (Sec. 4.1) on the GPU against the oracle: the
+zero-mean periodic Poisson operator, the reconstruction, the RK3 step (dense
+and Krylov solvers) and the transport right-hand side of the paper's
+periodic cosine-wave study (Sec. 3), on grids that take the LDS FFT kernels
+(64 x 32, 128 x 64) and the register FFT kernels (512 x 256); the discrete
+solvability sum over several steps."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+import paper_2109_13628_amd as iim
+from oracle import geometry as OG
+from oracle import poisson as OP
+from oracle import ns as ONS
+from oracle import transport as OT
+from gpu_util import to_dev, ring_zeros, rel
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-11
+
+
+@functools.lru_cache(maxsize=None)
+def _case(name):
+    if name == "small":
+        w = wl.periodic_cylinder(nx=128, ny=64, h=1.0 / 16, points=128, center=(2.0, 0.0), mean=(0.8, 0.15))
+    else:
+        w = wl.periodic_cylinder(nx=512, ny=256, h=1.0 / 32, points=256, dt=0.005, center=(3.0, 0.0),
+                                 mean=(1.0, 0.0))
+    geo = OG.Geometry(w.grid, w.bodies)
+    return w, geo, ONS.Stepper(geo)
+
+
+def _state(w, geo, seed):
+    """Seeded vorticity with the circulation that meets the solvability sum."""
+    cx = w.bodies[0].center
+    om = wl.seeded_vortices(w.grid, seed, count=6, amp=2.0, box=(cx[0] - 1.0, cx[0] + 4.0, cx[1] - 1.5, cx[1] + 1.5),
+                            width=(0.1, 0.4))
+    om = np.where(geo.fluid, om, 0.0)
+    i0, i1, j0, j1 = geo.rects[0]
+    inside = np.zeros_like(geo.fluid)
+    inside[j0:j1 + 1, i0:i1 + 1] = True
+    return om, np.array([-w.grid.h ** 2 * om[~inside].sum()]), inside
+
+
+@pytest.mark.parametrize("n", [(64, 32), (512, 256)])
+def test_periodic_poisson(n):
+    nx, ny = n
+    g = wl.GridDesc(nx=nx, ny=ny, x0=0.0, y0=0.0, h=0.05, exterior=wl.EXT_PERIODIC, u_inf=(0.3, 0.1), nu=0.01)
+    rng = np.random.default_rng(5)
+    src = rng.standard_normal((ny, nx))
+    ctx = iim.Context(g, [])
+    psi = ring_zeros(g)
+    ctx.poisson(to_dev(src), psi)
+    torch.cuda.synchronize()
+    ref = OP.periodic(src, g.h)
+    assert rel(psi.cpu().numpy(), ref) < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("solver", [iim.SOLVER_DIRECT, iim.SOLVER_KRYLOV])
+@pytest.mark.parametrize("name", ["small", "mid"])
+def test_periodic_reconstruct_and_step(name, solver):
+    w, geo, st = _case(name)
+    om, G, _ = _state(w, geo, 31)
+    ctx = iim.Context(w.grid, w.bodies, solver=solver, tol=1e-13)
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    ctx.reconstruct(to_dev(om), G, psi, U, V)
+    torch.cuda.synchronize()
+    ref = st.rec.reconstruct(om, G)
+    fl = np.pad(geo.fluid, 1)
+    ev = rel(np.stack([U.cpu().numpy()[fl], V.cpu().numpy()[fl]]), np.stack([ref.U[fl], ref.V[fl]]))
+    assert ev < TOL64, ev
+    assert rel(psi.cpu().numpy()[fl], ref.psi[fl]) < TOL64
+    # one RK3 step from the same state
+    om_ref, G_ref = st.step(om, G, w.dt)
+    d = to_dev(om)
+    G1, _ = ctx.rk3_steps(d, G.copy(), w.dt, 1)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    a = st.rec.reconstruct(got, G1)
+    b = st.rec.reconstruct(om_ref, G_ref)
+    assert rel(np.stack([a.U[fl], a.V[fl]]), np.stack([b.U[fl], b.V[fl]])) < TOL64
+    assert rel(got, om_ref, mask=geo.fluid) < 1e-10
+    assert abs(G1[0] - G_ref[0]) < 1e-10 * (1 + abs(G_ref[0]))
+    ctx.close()
+
+
+def test_periodic_steps_keep_the_solvability_sum():
+    w, geo, _ = _case("small")
+    om, G, inside = _state(w, geo, 44)
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    d = to_dev(om)
+    h = w.grid.h
+    scale = h ** 2 * np.abs(om).sum()
+    for _ in range(5):
+        G, _ = ctx.rk3_steps(d, G, w.dt, 4)
+        got = d.cpu().numpy()
+        assert abs(h ** 2 * got[~inside].sum() + G[0]) < 1e-12 * scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [64, 512])
+def test_periodic_transport_cosine_wave(n):
+    """The transport right-hand side with the prescribed uniform velocity and
+    the exact wall vorticity of Sec. 3's periodic cosine-wave case."""
+    w = wl.cosine_wave_transport(n, 0.002)
+    g, ex = w.grid, w.extra["exact"]
+    geo = OG.Geometry(g, w.bodies)
+    X, Y = wl.node_coords(g)
+    om = np.where(geo.fluid, ex(X, Y, 0.13), 0.0)
+    wb = ex(geo.c_x, geo.c_y, 0.13)
+    U = np.full((n + 2, n + 2), w.extra["u"][0])
+    V = np.full((n + 2, n + 2), w.extra["u"][1])
+    dw_ref, dG_ref, _, _ = OT.rhs(geo, om, U, V, g.nu, wb=wb)
+    ctx = iim.Context(g, w.bodies)
+    # the library orders control points as the oracle does
+    assert np.allclose(ctx.geometry()["c_xy"], np.stack([geo.c_x, geo.c_y], 1), atol=1e-12)
+    dw = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
+    dG = ctx.rhs_given_wb(to_dev(om), to_dev(U), to_dev(V), to_dev(wb), dw)
+    torch.cuda.synchronize()
+    assert rel(dw.cpu().numpy(), dw_ref, mask=geo.fluid) < 1e-12
+    assert abs(dG[0] - dG_ref[0]) < 1e-11 * (1 + abs(dG_ref[0]))
+    ctx.close()
