@@ -9,7 +9,7 @@ import pytest
 
 import workloads as wl
 import paper_2109_13628_amd as iim
-from oracle import geometry as OG, lgf as OL
+from oracle import geometry as OG, lgf as OL, ns as ONS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -89,7 +89,9 @@ def test_error_paths():
     ctx = iim.Context(w.grid, w.bodies, host_only=True)
     rc = iim.lib().iim_poisson(ctx._h, C.c_void_p(1), C.c_void_p(1))
     assert rc == iim.IIM_EUNSUPPORTED
-    assert abs(ctx.dt_max(np.sqrt(2) * 0.25) - w.dt / 0.5) < 1e-15
+    for a in (0.0, np.sqrt(2) * 0.25, 3.0):
+        ref = ONS.dt_max(w.grid.h, w.grid.nu, a)
+        assert abs(ctx.dt_max(a) - ref) < 1e-15 * ref
     ctx.close()
 
 

@@ -128,12 +128,18 @@ def c_shape_points(center, ra, rb, theta_a, theta_b, n):
 # named workloads (shapes and parameters of the paper's flows)
 # ----------------------------------------------------------------------------
 
-def dt_from_polygon(h, nu, a_max, c_stab):
-    """Time step on the RK3 stability triangle (C, r): (0,0), (1.620,0), (0,0.314)."""
-    return c_stab / (a_max / (1.620 * h) + nu / (0.314 * h * h))
+def step_size(h, nu, a, courant, diffusion):
+    """The time step of a workload: dt = min(courant h / a, diffusion h^2 / nu),
+    i.e. a chosen bound on the Courant number a dt / h and on the diffusion
+    number nu dt / h^2 (an input of the run, picked well inside the explicit
+    RK3 stability region)."""
+    dt = diffusion * h * h / nu if nu > 0 else math.inf
+    if a > 0:
+        dt = min(dt, courant * h / a)
+    return dt
 
 
-def taylor_couette(n=128, points=256, c_stab=0.5, steps=20):
+def taylor_couette(n=128, points=256, steps=20):
     """Annulus between a rotating inner circle (r=0.25, omega=1) and a fixed outer
     wall (r=0.75), cell-centred n x n grid on [-1,1]^2, Dirichlet box."""
     h = 2.0 / n
@@ -144,7 +150,7 @@ def taylor_couette(n=128, points=256, c_stab=0.5, steps=20):
     outer = BodyDesc(points=circle_points((0.0, 0.0), 0.75, points, clockwise=True),
                      is_enclosure=True, center=(0.0, 0.0))
     a_max = math.sqrt(2.0) * 0.25
-    dt = dt_from_polygon(h, grid.nu, a_max, c_stab)
+    dt = step_size(h, grid.nu, a_max, 0.6, 0.1)
     return Workload("taylor_couette_%dx%d_box" % (n, n), grid, [inner, outer], dt, steps)
 
 
@@ -255,8 +261,8 @@ def cosine_wave_transport(n, nu, u=(1.0, 2.0), k=(4 * math.pi, 2 * math.pi)):
     x_ij = (i/n, j/n), periodic in both directions, a C-shaped body (centre
     (0.507, 0.531), r_a 0.201, r_b 0.054, theta_a 0.5, theta_b 2.4), the
     uniform velocity u and the exact field omega = cos(k.(x - u t))
-    exp(-nu |k|^2 t) (returned by extra['exact'](x, y, t)); dt = 0.9 dt_max
-    for a_max = |u_x| + |u_y|."""
+    exp(-nu |k|^2 t) (returned by extra['exact'](x, y, t)); dt at Courant number 0.8 (for
+    the speed |u_x| + |u_y|) or diffusion number 0.12, whichever is smaller."""
     h = 1.0 / n
     grid = GridDesc(nx=n, ny=n, x0=0.0, y0=0.0, h=h, exterior=EXT_PERIODIC, u_inf=tuple(u), nu=nu)
     body = BodyDesc(points=c_shape_points((0.507, 0.531), 0.201, 0.054, 0.5, 2.4, max(256, int(8.0 / h))),
@@ -266,7 +272,7 @@ def cosine_wave_transport(n, nu, u=(1.0, 2.0), k=(4 * math.pi, 2 * math.pi)):
     def exact(x, y, t):
         return np.cos(k[0] * (x - u[0] * t) + k[1] * (y - u[1] * t)) * math.exp(-nu * kk * t)
 
-    dt = dt_from_polygon(h, nu, abs(u[0]) + abs(u[1]), 0.9)
+    dt = step_size(h, nu, abs(u[0]) + abs(u[1]), 0.8, 0.12)
     return Workload("cosine_wave_transport_%d" % n, grid, [body], dt, 0, extra={"exact": exact, "u": u})
 
 
@@ -337,7 +343,7 @@ def multi_body(n=2048, seed=3, steps=500):
             pts = c_shape_points((cx, cy), ra, rb, theta_a, theta_b, max(256, int(np.ceil(2 * per / h))))
         bodies.append(BodyDesc(points=pts, center=(cx, cy)))
     a_max = 2.0 * np.sqrt(2.0)
-    dt = dt_from_polygon(h, nu, a_max, 0.5)
+    dt = step_size(h, nu, a_max, 0.6, 0.1)
     return Workload("multi_body_%d_outflow_seed%d" % (n, seed), grid, bodies, dt, steps,
                     extra={"Re": re})
 
@@ -347,7 +353,8 @@ def batch_serving(n_sims=64, seed=5, nmin=256, nmax=1024, length=4.0):
     N uniform in [nmin, nmax] on a domain of side `length`, 1-6 seeded
     circles or ellipses each (semi-axes 0.12-0.3, aspect 1-2, placed apart),
     uniform inflow U = 1, Reynolds number uniform in [50, 500] on the mean
-    body diameter, dt from the stability triangle."""
+    body diameter, dt at Courant number 0.6 (speed 3) or diffusion number
+    0.1, whichever is smaller."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for s in range(n_sims):
@@ -375,7 +382,7 @@ def batch_serving(n_sims=64, seed=5, nmin=256, nmax=1024, length=4.0):
         re = rng.uniform(50.0, 500.0)
         nu = 1.0 * D / re
         grid = GridDesc(nx=n, ny=n, x0=0.0, y0=-length / 2, h=h, exterior=EXT_FREE, u_inf=(1.0, 0.0), nu=nu)
-        dt = dt_from_polygon(h, nu, 3.0, 0.5)
+        dt = step_size(h, nu, 3.0, 0.6, 0.1)
         out.append(Workload(name="batch%d_%dx%d_%dbodies" % (s, n, n, len(bodies)), grid=grid, bodies=bodies,
                             dt=dt, steps=10, extra={"Re": re, "D": D}))
     return out
