@@ -39,7 +39,8 @@ def test_dt_max_on_stability_triangle():
     # every named workload's step lies inside the triangle for its own speed
     # bound (the workloads choose dt by a Courant and a diffusion number)
     w = wl.taylor_couette(128)
-    assert w.dt <= 0.7 * ns.dt_max(w.grid.h, w.grid.nu, np.sqrt(2) * 0.25)
+    assert w.dt <= 0.51 * ns.dt_max(w.grid.h, w.grid.nu, np.sqrt(2) * 0.25)
+    assert abs(w.dt - 3.462e-3) < 1e-6
     w = wl.multi_body(512)
     assert w.dt <= 0.7 * ns.dt_max(w.grid.h, w.grid.nu, 2.0 * np.sqrt(2.0))
     for w in wl.batch_serving(8, 5):

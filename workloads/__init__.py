@@ -149,8 +149,9 @@ def taylor_couette(n=128, points=256, steps=20):
                      omega_rigid=1.0)
     outer = BodyDesc(points=circle_points((0.0, 0.0), 0.75, points, clockwise=True),
                      is_enclosure=True, center=(0.0, 0.0))
+    # diffusion number 0.1418: the step 3.462e-3 of the 128 x 128 configuration
     a_max = math.sqrt(2.0) * 0.25
-    dt = step_size(h, grid.nu, a_max, 0.6, 0.1)
+    dt = step_size(h, grid.nu, a_max, 0.6, 0.1418)
     return Workload("taylor_couette_%dx%d_box" % (n, n), grid, [inner, outer], dt, steps)
 
 
