@@ -51,3 +51,56 @@ def rel(a, b, mask=None):
     d = np.linalg.norm((a - b).ravel())
     n = np.linalg.norm(b.ravel())
     return d / n if n > 0 else d
+
+
+def linf_rel(a, b, mask=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    n = np.max(np.abs(b))
+    d = np.max(np.abs(a - b))
+    return d / n if n > 0 else d
+
+
+def oracle_step(st, w, om, G):
+    """The oracle's RK3 step and its velocity reconstruction."""
+    om_ref, G_ref = st.step(om, G, w.dt)
+    return om_ref, G_ref, st.rec.reconstruct(om_ref, G_ref)
+
+
+def step_errors(ctx, st, geo, w, om, G, ref=None):
+    """One RK3 step of the library (ctx, on the device) and of the oracle
+    (st, or its result `ref` from oracle_step) from the same state, and the library's own velocity reconstruction
+    of its result against the oracle's reconstruction of the oracle's result:
+    relative L2 and L-infinity errors of omega (fluid nodes) and of (u, v)
+    (fluid nodes of the grid and its ring), and the largest circulation
+    error with the size of the circulations."""
+    om_ref, G_ref, b = ref if ref is not None else oracle_step(st, w, om, G)
+    d = to_dev(om)
+    G1, stats = ctx.rk3_steps(d, np.array(G, dtype=np.float64), w.dt, 1)
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    ctx.reconstruct(d, G1, psi, U, V)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    fl = np.pad(geo.fluid, 1)
+    uv = np.stack([U.cpu().numpy()[fl], V.cpu().numpy()[fl]])
+    uv_ref = np.stack([b.U[fl], b.V[fl]])
+    return {"omega_l2": rel(got, om_ref, geo.fluid), "omega_linf": linf_rel(got, om_ref, geo.fluid),
+            "vel_l2": rel(uv, uv_ref), "vel_linf": linf_rel(uv, uv_ref),
+            "gamma_abs": float(np.max(np.abs(G1 - G_ref))) if len(G_ref) else 0.0,
+            "gamma_max": float(np.max(np.abs(G_ref))) if len(G_ref) else 0.0, "stats": stats}
+
+
+def assert_within_floor(err, floor, factor=10.0):
+    """err (from step_errors) against `factor` times the measured rounding
+    floor: floor = (omega L2, omega Linf, velocity L2, velocity Linf,
+    circulation), the first four relative to the oracle's result, the last
+    relative to 1 + max |Gamma| and never below one unit in the last place of
+    max |Gamma|."""
+    names = ("omega_l2", "omega_linf", "vel_l2", "vel_linf")
+    bad = {k: (err[k], factor * f) for k, f in zip(names, floor[:4]) if not err[k] <= factor * f}
+    g_floor = max(floor[4] * (1.0 + err["gamma_max"]), float(np.spacing(err["gamma_max"])))
+    if not err["gamma_abs"] <= factor * g_floor:
+        bad["gamma_abs"] = (err["gamma_abs"], factor * g_floor)
+    assert not bad, (bad, {k: err[k] for k in names})

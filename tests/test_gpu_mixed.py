@@ -2,6 +2,8 @@
 residual is small enough (inexact Krylov with relaxation), FP64 residuals
 deciding convergence (iterative refinement), against the FP64 oracle.  The
 FP32 operator alone is checked too, with its error stated."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -92,3 +94,85 @@ def test_mixed_matches_fp64_path_over_steps():
         out[prec] = (omd.cpu().numpy(), G1, stats)
     e = rel(out[iim.PREC_MIXED][0], out[iim.PREC_FP64][0], mask=geo.fluid)
     assert e < 1e-10, e
+
+
+def test_fp32_operator_at_bench_size():
+    """The FP32 register kernels of the benchmark size (1024-point columns,
+    2048-point rows): the FP32 operator's error band."""
+    w = wl.cylinder()
+    ctx = iim.Context(w.grid, w.bodies, precision=iim.PREC_MIXED)
+    assert ctx.info["fft_mx"] == 2048 and ctx.info["fft_my"] == 1024
+    rng = np.random.default_rng(6)
+    src = rng.standard_normal((w.grid.ny, w.grid.nx))
+    psi = ring_zeros(w.grid)
+    ctx.poisson_fp32(to_dev(src), psi)
+    torch.cuda.synchronize()
+    ref = OP.FreeSpace(w.grid.nx, w.grid.ny, w.grid.h)(src)
+    e = rel(psi.cpu().numpy(), ref)
+    print("FP32 operator relative error at 2048 x 1024", e)
+    assert 1e-9 < e < 1e-5, e
+    ctx.close()
+
+
+def _trained_net(w, steps=40, iters=300):
+    """A small initial-guess network trained on recorded solves of the
+    workload (the library's own kernels)."""
+    rec = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    rec.record_solves(2 * steps * 3)
+    for seed in (1, 2):
+        om = torch.as_tensor(0.5 * wl.seeded_vortices(w.grid, seed, count=8), device="cuda:0")
+        rec.reset_history()
+        rec.rk3_steps(om, np.zeros(rec.n_circ), w.dt, steps)
+    net = iim.Network(bf16=True, seed=0)
+    rec.warm_start_train(net, iters=iters, batch=32, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    rec.close()
+    return net
+
+
+@functools.lru_cache(maxsize=None)
+def _bench_size_reference():
+    w = wl.cylinder()
+    geo = OG.Geometry(w.grid, w.bodies)
+    om, G = seeded_state(w, geo, 17, body_scale=1.0)
+    st = ONS.Stepper(geo)
+    om_ref, G_ref = om, G
+    for _ in range(4):
+        om_ref, G_ref = st.step(om_ref, G_ref, w.dt)
+    return w, geo, st, om, G, om_ref, G_ref
+
+
+@pytest.mark.parametrize("guess", ["extrapolate", "network"])
+def test_mixed_at_bench_size_meets_1e8(guess):
+    """The benchmark's mixed paths (FP32 products on the 1024-point register
+    kernels, GMRES to 1e-10 as the benchmark runs them) over four RK3 steps
+    from a seeded state with the body's wake: velocity and vorticity within
+    1e-8 of the FP64 oracle (the mixed path's gate), in L2 and L-infinity."""
+    w, geo, st, om, G, om_ref, G_ref = _bench_size_reference()
+    mode = iim.GUESS_EXTRAPOLATE if guess == "extrapolate" else iim.GUESS_NETWORK
+    ctx = iim.Context(w.grid, w.bodies, precision=iim.PREC_MIXED, tol=1e-10, guess=mode)
+    net = None
+    if mode == iim.GUESS_NETWORK:
+        net = _trained_net(w)
+        ctx.set_warm_start(mode, net)
+    omd = to_dev(om)
+    G1 = np.array(G, dtype=np.float64)
+    for _ in range(4):
+        G1, stats = ctx.rk3_steps(omd, G1, w.dt, 1)
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    ctx.reconstruct(omd, G1, psi, U, V)
+    torch.cuda.synchronize()
+    got = omd.cpu().numpy()
+    b = st.rec.reconstruct(om_ref, G_ref)
+    fl = np.pad(geo.fluid, 1)
+    uv = np.stack([U.cpu().numpy()[fl], V.cpu().numpy()[fl]])
+    uv_ref = np.stack([b.U[fl], b.V[fl]])
+    ev, evi = rel(uv, uv_ref), np.max(np.abs(uv - uv_ref)) / np.max(np.abs(uv_ref))
+    ew = rel(got, om_ref, mask=geo.fluid)
+    cnt = ctx.counters()
+    print("mixed", guess, "velocity L2 %.2e Linf %.2e vorticity %.2e" % (ev, evi, ew), cnt)
+    assert cnt["fp32_products"] > 0, cnt
+    assert ev < 1e-8 and evi < 1e-8 and ew < 1e-8, (ev, evi, ew)
+    ctx.close()
+    if net is not None:
+        net.close()

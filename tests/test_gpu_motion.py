@@ -3,9 +3,10 @@ iim_rk3_steps_moving):
 
 * parity with the FP64 oracle on the Lamb-Oseen vortex around its co-rotating
   cylinder (the convergence case of Sec. 6), rotation rate changing at every
-  stage, N = 64, four steps: the FP64 gate (velocity of both results 1e-11),
-  vorticity within its rounding bound, and the result far closer to the
-  oracle's than to a run that holds each step's starting motion;
+  stage, N = 64, four steps: omega, Gamma and the library's own velocity, in
+  L2 and L-infinity, within ten times the oracle's measured rounding floor on
+  the same run, and the result far closer to the oracle's than to a run that
+  holds each step's starting motion;
 * an oscillating cylinder (translation and rotation) in a free stream, and an
   accelerating inner cylinder inside a stationary enclosure, against the
   oracle (the same gate);
@@ -27,7 +28,7 @@ import paper_2109_13628_amd as iim
 import workloads as wl
 from oracle import geometry as OG
 from oracle import ns as ONS
-from gpu_util import to_dev, ring_zeros, rel
+from gpu_util import to_dev, ring_zeros, rel, linf_rel, assert_within_floor
 import e3_lamb_oseen as E3
 
 pytestmark = pytest.mark.gpu
@@ -51,6 +52,28 @@ def _lib_run(grid, body, om, G, t0, dt, n):
     return out
 
 
+# The oracle's rounding floor on each run (the larger of the spread between
+# the free-space convolution on a 2n and on a 3n torus, or for the box
+# between the fast sine transform and the transform as explicit matrix
+# products, and the spread under a one-unit-roundoff change of the input
+# omega).  Columns: omega L2, omega L-infinity, velocity L2, velocity
+# L-infinity (relative), circulation (max |dGamma| / (1 + max |Gamma|)).
+FLOOR = {
+    "lamb_oseen64": (6.1e-11, 9.2e-11, 2.0e-13, 4.1e-13, 0.0),
+    "oscillating_cylinder": (3.7e-14, 4.2e-14, 3.1e-14, 2.0e-13, 6.7e-18),
+    "accelerating_couette": (1.7e-15, 2.4e-15, 8.6e-15, 1.3e-14, 0.0),
+}
+
+
+def _errors(geo, got, G1, U, V, om_r, G_r, b):
+    fl = np.pad(geo.fluid, 1)
+    uv = np.stack([U[fl], V[fl]])
+    uv_ref = np.stack([b.U[fl], b.V[fl]])
+    return {"omega_l2": rel(got, om_r, geo.fluid), "omega_linf": linf_rel(got, om_r, geo.fluid),
+            "vel_l2": rel(uv, uv_ref), "vel_linf": linf_rel(uv, uv_ref),
+            "gamma_abs": float(np.max(np.abs(G1 - G_r))), "gamma_max": float(np.max(np.abs(G_r)))}
+
+
 def test_moving_steps_match_oracle():
     t0, n = 1.0, 4
     grid, body = E3.case(64, t0)
@@ -69,20 +92,14 @@ def test_moving_steps_match_oracle():
     # the same with the motion of each step's start at all three stages
     om_w, _ = oracle_run(lambda t: [(0.0, 0.0, E3.rotation(t0 + np.floor((t - t0) / dt + 1e-9) * dt))])
     got, G1, U, V = _lib_run(grid, body, om, G, t0, dt, n)
-    # the FP64 gate: velocities of both results, reconstructed by the oracle
-    st.set_motion([(0.0, 0.0, E3.rotation(t0 + n * dt))])
-    a = st.rec.reconstruct(got, G1)
-    b = st.rec.reconstruct(om_r, G_r)
-    fl = np.pad(geo.fluid, 1)
-    assert rel(np.stack([a.U[fl], a.V[fl]]), np.stack([b.U[fl], b.V[fl]])) < 1e-11
     # the library's own reconstruction with the motion set afterwards, against
-    # the oracle's of the same vorticity
-    assert rel(np.stack([U[fl], V[fl]]), np.stack([a.U[fl], a.V[fl]])) < 1e-11
-    # vorticity: the wall flux carries the rounding of psi differentiated
-    # twice (the bound of the full-size step test)
-    e_ok = rel(got, om_r, mask=geo.fluid)
-    assert e_ok < 2e-9
-    assert abs(G1[0] - G_r[0]) < 1e-10 * abs(G_r[0])
+    # the oracle's of its own result
+    st.set_motion([(0.0, 0.0, E3.rotation(t0 + n * dt))])
+    b = st.rec.reconstruct(om_r, G_r)
+    err = _errors(geo, got, G1, U, V, om_r, G_r, b)
+    print("lamb_oseen64", err)
+    assert_within_floor(err, FLOOR["lamb_oseen64"])
+    e_ok = err["omega_l2"]
     # the stage times matter: far closer to the right ones than to the motion
     # held at each step's start
     assert e_ok < 1e-3 * rel(om_w, om_r, mask=geo.fluid), (e_ok, rel(om_w, om_r, mask=geo.fluid))
@@ -101,6 +118,7 @@ def _accelerating_couette():
 @pytest.mark.parametrize("make", [_oscillating_cylinder, _accelerating_couette])
 def test_translation_rotation_and_enclosure_match_oracle(make):
     w, mot = make()
+    name = make.__name__[1:]
     geo = OG.Geometry(w.grid, w.bodies)
     om = np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, 91, count=5), 0.0)
     G = wl.seeded_gammas(geo.nbc, 92, scale=0.2)
@@ -113,15 +131,16 @@ def test_translation_rotation_and_enclosure_match_oracle(make):
     ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
     d = to_dev(om)
     G1, _ = ctx.rk3_steps_moving(d, G, dt, sched)
+    ctx.set_body_motion(np.array(mot(t0 + n * dt)).ravel())
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    ctx.reconstruct(d, G1, psi, U, V)
     torch.cuda.synchronize()
     got = d.cpu().numpy()
     st.set_motion(mot(t0 + n * dt))
-    a = st.rec.reconstruct(got, G1)
     b = st.rec.reconstruct(om_r, G_r)
-    fl = np.pad(geo.fluid, 1)
-    assert rel(np.stack([a.U[fl], a.V[fl]]), np.stack([b.U[fl], b.V[fl]])) < 1e-11
-    assert rel(got, om_r, mask=geo.fluid) < 2e-9
-    assert np.max(np.abs(G1 - G_r)) < 1e-10 * (1 + np.abs(G_r).max())
+    err = _errors(geo, got, G1, U.cpu().numpy(), V.cpu().numpy(), om_r, G_r, b)
+    print(name, err)
+    assert_within_floor(err, FLOOR[name])
     ctx.close()
 
 
