@@ -224,7 +224,7 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
     lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE), full-size launches",
              "# inside the RK steps of the 1024x512 free-space cylinder workload; bytes = KiB * 1024 * scale, where scale is",
              "# 256 MiB over the counter's reading for one plain 256 MiB device copy in the same run.", "",
-             "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE"),
+             "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE").replace("pmc_w", "pmc_f"),
              "command_write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_f", "pmc_w"),
              "kernel_source_sha256_16: " + _src_hash()]
     for k in sorted(res):

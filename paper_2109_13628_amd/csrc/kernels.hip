@@ -1285,6 +1285,13 @@ __device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict_
 // boundary-kernel nodes (4 lanes each), whose dependent loads take longest,
 // so that they are dispatched first, then the bulk rows.  The three parts
 // read the same inputs and write disjoint outputs.
+//
+// Workgroups go to the eight XCDs in turn (block b to XCD b mod 8), and each
+// XCD has its own L2.  The bulk part therefore starts at a multiple of eight
+// and hands XCD x one contiguous band of rows: the five-row stencils of
+// neighbouring rows then hit the same L2, and only the band edges are read
+// from HBM twice (with consecutive rows on alternating XCDs every row of
+// omega and psi was read twice).
 template <bool P>
 __global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __restrict__ omega,
                                                        const double* __restrict__ psi,
@@ -1307,15 +1314,22 @@ __global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __
     transport_special(g, omega, vel, w4, w3b, w3n, out, Q, a, b, dt, mode, blk);
     return;
   }
-  blk -= nb_sp;
-  transport_bulk(g, omega, vel, out, Q, a, b, dt, mode, blk % nbx, blk / nbx);
+  const int nlead = (g.nbc + nb_sp + 7) & ~7;
+  const int nb = nbx * g.ny, band = (nb + 7) >> 3;
+  const int bb = (int)blockIdx.x - nlead;
+  if (bb < 0) return;   // padding up to the first bulk block
+  const int tile = (bb & 7) * band + (bb >> 3);
+  if (tile >= nb) return;
+  transport_bulk(g, omega, vel, out, Q, a, b, dt, mode, tile % nbx, tile / nbx);
 }
 
 void launch_transport_all(const DGeom& g, const double* omega, const double* psi, const double* U, const double* V,
                           const double* w4, const double* w3b, const double* w3n, double* out, double* Q, double* dG,
                           double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
                           Prof* prof) {
-  const int blocks = ((g.nx + 255) / 256) * g.ny + (4 * g.nsp + 255) / 256 + g.nbc;
+  // leading blocks padded to a multiple of 8; eight bands of bulk tiles
+  const int nb = ((g.nx + 255) / 256) * g.ny;
+  const int blocks = ((g.nbc + (4 * g.nsp + 255) / 256 + 7) & ~7) + 8 * ((nb + 7) / 8);
   const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
                  g.special, g.rects, g.nonfinite};
   if (psi) {
