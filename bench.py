@@ -29,11 +29,14 @@ def _parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--solver", choices=["krylov", "direct"], default="direct")
-    p.add_argument("--krylov-steps", type=int, default=10, help="timed steps of each GMRES path in 'paths' (0: none)")
+    p.add_argument("--krylov-steps", type=int, default=20, help="timed steps of each GMRES path in 'paths' (0: none)")
     p.add_argument("--krylov-tol", type=float, default=1e-10, help="relative residual of the GMRES paths")
-    p.add_argument("--train-runs", type=int, default=10, help="recorded runs for the network (0: no network path)")
-    p.add_argument("--train-steps", type=int, default=600, help="RK3 steps per recorded run")
+    p.add_argument("--train-runs", type=int, default=7,
+                   help="recorded runs at distinct Re for the network, one of them for validation (0: no network path)")
+    p.add_argument("--train-steps", type=int, default=1000, help="RK3 steps per recorded run (3 solves each)")
     p.add_argument("--train-iters", type=int, default=2000)
+    p.add_argument("--eval-start", type=int, default=400,
+                   help="steps of the held-out run (direct solver) before the GMRES paths take over")
     p.add_argument("--batch-sims", type=int, default=64, help="simulations of the batched-serving measurement (0: none)")
     p.add_argument("--batch-steps", type=int, default=20)
     p.add_argument("--no-autotune", action="store_true", help="keep the default FFT tile shapes on the headline path")
@@ -43,9 +46,14 @@ def _parse():
                    help="write the text summary of a rocprofv3 --kernel-trace --stats run and exit")
     p.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                    help="write the HBM traffic summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    p.add_argument("--summarize-mfma", nargs=2, metavar=("PMC_DIR", "OUT"),
+                   help="write the matrix-core counter summary of a --net-only counter run and exit")
     p.add_argument("--command", default="", help="command line recorded in a summary")
     p.add_argument("--copy-probe", action="store_true",
                    help="end with one plain device copy of 256 MiB (scale reference for HBM byte counters)")
+    p.add_argument("--net-only", action="store_true",
+                   help="only the network's matrix-core timing (forward and training steps at the training "
+                        "batch shape); for counter runs")
     p.add_argument("--batch-only", action="store_true",
                    help="run only the batched-serving leg and print its JSON object (the benchmark runs this "
                         "in a child process)")
@@ -64,15 +72,18 @@ def _say(msg):
 
 
 def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profile_kernels=None, tol=1e-13,
-              net=None, per_step=False, tiles=None):
+              net=None, per_step=False, tiles=None, start=None):
     g = w.grid
     ctx = iim.Context(g, w.bodies, precision=precision, tol=tol, guess=guess, solver=solver)
     if net is not None:
         ctx.set_warm_start(iim.GUESS_NETWORK, net)
     if tiles is not None:
         ctx.set_fft_shape(tiles["row_per"], tiles["col_per"])
-    omega = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
-    Gamma = np.zeros(ctx.n_circ)
+    if start is None:
+        omega = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
+        Gamma = np.zeros(ctx.n_circ)
+    else:
+        omega, Gamma = start[0].clone(), np.array(start[1], dtype=np.float64)
     pre = {}
     # warm-up: all but the last two steps with every kernel timed by events (to
     # find the dominant kernel); the last two without instrumentation, so that a
@@ -119,34 +130,139 @@ def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profil
     return ctx, omega, Gamma, res, pre
 
 
+# Re of the recorded runs (the held-out run is the workload's own Re 100);
+# the middle one is the validation run
+TRAIN_RE = (60, 80, 120, 150, 200, 250, 300)
+
+
 def _train_network(iim, w, torch, np, runs, steps, iters):
-    """Record the solves of `runs` perturbed runs of the workload with the
-    dense solver, then train the initial-guess network on them (on the GPU,
-    the library's own kernels)."""
+    """The learned guess's data and training: `runs` runs shaped like the
+    workload (same grid and body) at the Reynolds numbers of TRAIN_RE, each
+    with the cylinder centre moved by a seeded sub-cell offset, impulsively
+    started and advanced `steps` steps with the dense solver while every
+    stage solve is recorded; one run (the middle Re) is held out for
+    validation, the others train one network (on the GPU, the library's own
+    kernels) in chunks, keeping the parameters with the lowest validation
+    loss.  The workload's own run (Re 100, centred body) is never seen."""
     import workloads as wl
-    g = w.grid
-    rec = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
-    rec.record_solves(runs * steps * 3)
+    res = list(TRAIN_RE[:max(2, min(runs, len(TRAIN_RE)))])
+    val_re = res[len(res) // 2]
+    rng = np.random.default_rng(11)
+    g0 = w.grid
+    ctxs, offsets = {}, {}
     t0 = time.perf_counter()
-    for seed in range(1, runs + 1):
-        om = torch.as_tensor(0.5 * wl.seeded_vortices(g, seed, count=8), device="cuda:0")
-        rec.reset_history()
-        rec.rk3_steps(om, np.zeros(rec.n_circ), w.dt, steps)
+    for re in res:
+        dx, dy = (rng.uniform(-0.5, 0.5, 2) * g0.h).tolist()
+        wr = wl.cylinder(nx=g0.nx, ny=g0.ny, h=g0.h, nu=1.0 / re, dt=w.dt, center=(2.0 + dx, dy))
+        c = iim.Context(wr.grid, wr.bodies, solver=iim.SOLVER_DIRECT)
+        c.record_solves(3 * steps)
+        om = torch.zeros((wr.grid.ny, wr.grid.nx), dtype=torch.float64, device="cuda:0")
+        c.rk3_steps(om, np.zeros(c.n_circ), wr.dt, steps)
+        ctxs[re], offsets[re] = c, (dx, dy)
     torch.cuda.synchronize()
     t_rec = time.perf_counter() - t0
+    train = [ctxs[r] for r in res if r != val_re]
     net = iim.Network(bf16=True, seed=0)
+    chunk = max(1, min(iters, 250))
+    best, curve, train_loss = (float("inf"), None, 0), [], []
     t0 = time.perf_counter()
-    losses = rec.warm_start_train(net, iters=iters, batch=64, lr=1e-3, seed=1)
+    done = 0
+    while done < iters:
+        k = min(chunk, iters - done)
+        losses = iim.warm_start_train_multi(train, net, iters=k, batch=64, lr=1e-3, seed=1 + done)
+        done += k
+        vl, nval = ctxs[val_re].warm_start_loss(net)
+        curve.append((done, float(np.mean(losses[-min(50, k):])), vl))
+        train_loss.append(losses)
+        if vl < best[0]:
+            best = (vl, net.get(), done)
+    net.set(best[1])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    info = {"recorded_solves": rec.warm_start_stats()["recorded"], "runs": runs, "steps_per_run": steps,
-            "record_s": t_rec, "train_s": t_train, "adam_steps": iters, "batch": 64,
+    losses = np.concatenate(train_loss)
+    recorded = {re: ctxs[re].warm_start_stats()["recorded"] for re in res}
+    info = {"protocol": "runs shaped like the workload at Re %s (sub-cell seeded centre offsets), %d steps each "
+                        "from rest with every stage solve recorded; %d runs train, the Re %d run validates "
+                        "(the parameters with the lowest validation loss are kept); evaluated on the workload's "
+                        "own Re 100 run, never seen in training" % (list(res), steps, len(train), val_re),
+            "recorded_solves": recorded, "train_re": [r for r in res if r != val_re], "validation_re": val_re,
+            "centre_offsets": {r: offsets[r] for r in res}, "record_s": t_rec, "train_s": t_train,
+            "adam_steps": iters, "batch": 64, "validation_samples": nval,
             "loss_first100": float(losses[:100].mean()), "loss_last100": float(losses[-100:].mean()),
-            "network": "4 circular conv1d layers, kernel 5, width 128, GELU; BF16 matrix-core products, FP32 accumulation",
-            "data": "runs started from mild seeded vortices (0.5 x seeded_vortices, 8 vortices, seeds 1..%d); "
-                    "evaluated on the impulsive start from rest" % runs}
-    rec.close()
+            "curve_step_trainloss_valloss": curve, "kept_step": best[2], "kept_validation_loss": best[0],
+            "network": "4 circular conv1d layers, kernel 5, width 128, GELU; BF16 matrix-core products "
+                       "(16x16x32 MFMA, LDS-staged operands), FP32 accumulation"}
+    for c in ctxs.values():
+        c.close()
     return net, info
+
+
+def _segments_dev(torch, np, lengths):
+    seg0, segl, pos, start = [], [], [], 0
+    for L in lengths:
+        seg0 += [start] * L
+        segl += [L] * L
+        pos += list(range(L))
+        start += L
+    return torch.as_tensor(np.array([seg0, segl, pos], dtype=np.int32), device="cuda:0")
+
+
+def _net_roofline(iim, torch, np, B=64, P=384, reps=50):
+    """The network's matrix-core throughput: forward passes and training
+    steps (forward, backward, Adam) at the training batch shape (B sequences
+    of P control points), and one forward pass at batch 1 (the inference
+    inside a solve), timed with HIP events on the network's stream; FLOPs are
+    the GEMMs' 2 M N K."""
+    net = iim.Network(bf16=True, seed=0)
+    cin, width, layers = net.shape
+    chans = [cin] + [width] * (layers - 1) + [1]
+    gen = torch.Generator(device="cuda:0").manual_seed(5)
+    x = torch.randn((B, P, cin), generator=gen, device="cuda:0", dtype=torch.float32)
+    t = torch.randn((B, P), generator=gen, device="cuda:0", dtype=torch.float32)
+    y = torch.zeros((B, P), device="cuda:0", dtype=torch.float32)
+    seq = _segments_dev(torch, np, [P])
+    taps = 5
+    fwd = sum(2.0 * B * P * taps * a * b for a, b in zip(chans[:-1], chans[1:]))
+    bwd_w = fwd
+    bwd_d = sum(2.0 * B * P * taps * a * b for a, b in zip(chans[1:-1], chans[2:]))
+    out = {}
+    for _ in range(5):
+        net.forward(x, seq, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.forward(x, seq, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["forward"] = {"batch": B, "P": P, "ms": ms, "gflop": fwd / 1e9, "tflops": fwd / (ms * 1e-3) / 1e12}
+    net.train_step(x, seq, t, 1e-4)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.train_step(x, seq, t, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tot = fwd + bwd_w + bwd_d
+    out["train_step"] = {"batch": B, "P": P, "ms": ms, "gflop": tot / 1e9, "tflops": tot / (ms * 1e-3) / 1e12,
+                         "note": "includes the loss copy to the host that every training step returns"}
+    x1, y1 = x[:1].contiguous(), y[:1].contiguous()
+    for _ in range(5):
+        net.forward(x1, seq, y1)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.forward(x1, seq, y1)
+    e1.record()
+    torch.cuda.synchronize()
+    out["inference_batch1_us"] = 1e3 * e0.elapsed_time(e1) / reps
+    best = max(out["forward"]["tflops"], out["train_step"]["tflops"])
+    out["roofline"] = {"bound": "mfma", "achieved": best, "peak": 2500.0, "unit": "TFLOP/s", "frac": best / 2500.0,
+                       "dtype": "bf16 operands, fp32 accumulation"}
+    net.close()
+    return out
 
 
 # library kernel names of the instrumented kernel ids
@@ -233,6 +349,41 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
         f.write("\n".join(lines) + "\n")
 
 
+def _summarize_mfma(pmc_dir, out, command):
+    """Matrix-core counters of the network's GEMM kernels: per kernel
+    instantiation, the mean over its dispatches of the BF16 MFMA FLOPs
+    (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512), the MFMA busy fraction
+    (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE times the 1024 SIMDs) and
+    the fraction of cycles the shader array was busy."""
+    import glob
+    rows = _read_csv(glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)[0])
+    per = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "k_mm" not in name:
+            continue
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "")
+        short = short.split("(")[0].replace("iim::", "")
+        d = per.setdefault((short, int(r["Grid_Size"])), {})
+        d.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = ["# Matrix-core counters of the network's GEMMs (rocprofv3 --pmc), the --net-only leg of bench.py:",
+             "# forward passes and training steps at batch 64 x 384 control points, and batch-1 forward passes.",
+             "# mfma_util = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs); flop = MOPS_BF16 x 512", "",
+             "command: " + command, "",
+             "kernel | grid | dispatches | BF16 GFLOP per dispatch | mfma_util % | busy % (SQ_BUSY_CYCLES / GRBM_GUI_ACTIVE)",
+             "---|---|---|---|---|---"]
+    for (short, grid), disp in sorted(per.items(), key=lambda kv: (-len(kv[1]), kv[0])):
+        vals = [v for v in disp.values() if "GRBM_GUI_ACTIVE" in v and v["GRBM_GUI_ACTIVE"] > 0]
+        if not vals:
+            continue
+        fl = sum(v.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512 for v in vals) / len(vals)
+        ut = sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (v["GRBM_GUI_ACTIVE"] * 1024) for v in vals) / len(vals)
+        bz = sum(v.get("SQ_BUSY_CYCLES", 0.0) / v["GRBM_GUI_ACTIVE"] for v in vals) / len(vals)
+        lines.append("%s | %d | %d | %.4f | %.2f | %.1f" % (short[:90], grid, len(vals), fl / 1e9, 100 * ut, 100 * bz))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def _traffic(kernel):
     """HBM bytes per full-size launch of `kernel` from the committed counter
     summary, or None when it is missing or the kernel source has changed
@@ -263,6 +414,9 @@ def main():
     if args.summarize_pmc:
         _summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2], args.command)
         return
+    if args.summarize_mfma:
+        _summarize_mfma(args.summarize_mfma[0], args.summarize_mfma[1], args.command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -272,6 +426,9 @@ def main():
     import workloads as wl
     import paper_2109_13628_amd as iim
 
+    if args.net_only:
+        print(json.dumps({"network": _net_roofline(iim, torch, np)}), flush=True)
+        return
     if args.batch_only:
         try:
             res = _batch(iim, wl, torch, np, args.batch_sims, args.batch_steps)
@@ -427,29 +584,44 @@ def main():
 
 
 def _krylov_paths(iim, w, torch, np, args, tiles, paths):
-    """The paper's iterative solve (GMRES with the FFT product) in FP64 and in
-    mixed precision, with the previous-stage, extrapolated and network
-    guesses; fills `paths` and returns the trained network and its record."""
-    kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles)
-    for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
-        for g_name, g_mode in (("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)):
-            _say("GMRES path %s, guess %s" % (p_name, g_name))
-            c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode, **kw)
-            paths["%s_krylov_%s" % (p_name, g_name)] = r_
-            c_.close()
+    """The paper's iterative solve (GMRES with the FFT product, to a relative
+    residual of args.krylov_tol) in FP64 and in mixed precision with the
+    zero, previous-stage, extrapolated and learned guesses, every path timed
+    over the same steps of the workload's run: the state after
+    args.eval_start steps from rest (dense solver), then 3 warm-up and
+    args.krylov_steps timed steps (the network's inference inside the timed
+    steps).  Fills `paths`; returns the trained network and its record."""
+    g = w.grid
+    spin = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
+    om0 = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
+    G0, _ = spin.rk3_steps(om0, np.zeros(spin.n_circ), w.dt, args.eval_start)
+    torch.cuda.synchronize()
+    spin.close()
+    start = (om0, G0)
     net, warm = None, {}
     if args.train_runs:
-        _say("warm-start network: %d recorded runs, %d training iterations" % (args.train_runs, args.train_iters))
+        _say("warm-start network: %d recorded runs of %d steps, %d training iterations"
+             % (args.train_runs, args.train_steps, args.train_iters))
         net, warm = _train_network(iim, w, torch, np, args.train_runs, args.train_steps, args.train_iters)
-        for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
-            _say("GMRES path %s, guess network" % p_name)
-            c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, iim.GUESS_NETWORK,
-                                        net=net, **kw)
-            paths["%s_krylov_network" % p_name] = r_
+        _say("network matrix-core timing")
+        warm["network_roofline"] = _net_roofline(iim, torch, np)
+    kw = dict(warmup=3, steps=args.krylov_steps, tol=args.krylov_tol, per_step=True, tiles=tiles, start=start)
+    guesses = [("zero", iim.GUESS_ZERO), ("previous", iim.GUESS_PREVIOUS), ("extrapolate", iim.GUESS_EXTRAPOLATE)]
+    if net is not None:
+        guesses.append(("network", iim.GUESS_NETWORK))
+    for p_name, p_prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+        for g_name, g_mode in guesses:
+            _say("GMRES path %s, guess %s" % (p_name, g_name))
+            c_, _, _, r_, _ = _run_path(iim, w, torch, np, p_prec, iim.SOLVER_KRYLOV, g_mode,
+                                        net=net if g_mode == iim.GUESS_NETWORK else None, **kw)
+            r_["t_start"] = (args.eval_start + 3) * w.dt
+            paths["%s_krylov_%s" % (p_name, g_name)] = r_
             c_.close()
     base = paths["fp64_krylov_previous"]["ms_per_step"]
     warm["speedup_vs_fp64_krylov_previous"] = {k: base / v["ms_per_step"] for k, v in paths.items()
                                               if "krylov" in k and "ms_per_step" in v}
+    warm["iterations_per_solve"] = {k: v["krylov"]["iterations_per_solve"] for k, v in paths.items()
+                                    if "krylov" in k and "krylov" in v}
     return net, warm
 
 

@@ -482,6 +482,18 @@ int iim_record_solves(iim_ctx* ctx, int32_t capacity);
  * every step.  Errors: IIM_EINVAL when no recorded solve qualifies. */
 int iim_warm_start_train(iim_ctx* ctx, iim_net* net, int32_t iters, int32_t batch, float lr, uint64_t seed,
                          float* loss_host);
+/* The same over the records of n_ctx contexts (runs of different geometry or
+ * viscosity; one network for all): each step draws its batch from one
+ * context, chosen with probability proportional to its qualifying records,
+ * so that every qualifying record is equally likely.  Works on the stream of
+ * ctxs[0] after synchronizing every context's stream.  Errors: IIM_EINVAL
+ * when no record of any context qualifies (message on ctxs[0]). */
+int iim_warm_start_train_multi(iim_ctx* const* ctxs, int32_t n_ctx, iim_net* net, int32_t iters, int32_t batch,
+                               float lr, uint64_t seed, float* loss_host);
+/* The training loss of iim_warm_start_train over every qualifying record of
+ * ctx (forward passes only, `batch` records per pass): *loss its mean,
+ * *samples (nullable) the number of records.  For held-out validation. */
+int iim_warm_start_loss(iim_ctx* ctx, iim_net* net, int32_t batch, double* loss, int64_t* samples);
 /* Start a new run: the next solves do not extrapolate from, and recorded
  * samples do not reach back to, the solves made so far (call when the state
  * is replaced by one that does not continue the previous steps). */

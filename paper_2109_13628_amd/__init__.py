@@ -34,7 +34,8 @@ EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_give
            "iim_set_warm_start", "iim_record_solves", "iim_warm_start_train", "iim_warm_start_stats",
            "iim_warm_start_sequences", "iim_reset_history", "iim_autotune", "iim_set_fft_shape",
            "iim_batch_create", "iim_batch_destroy", "iim_batch_last_error", "iim_batch_step", "iim_batch_info",
-           "iim_dt_limit", "iim_set_speed_bound", "iim_net_train_step", "iim_net_forward_noalloc"]
+           "iim_dt_limit", "iim_set_speed_bound", "iim_net_train_step", "iim_net_forward_noalloc",
+           "iim_warm_start_train_multi", "iim_warm_start_loss"]
 KERNEL_NAMES = ["fft_rows_fwd", "fft_cols_conv", "fft_rows_inv", "transport", "arnoldi"]
 
 
@@ -207,6 +208,11 @@ def lib():
     L.iim_record_solves.argtypes = [vp, C.c_int32]
     L.iim_warm_start_train.restype = ip
     L.iim_warm_start_train.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp]
+    L.iim_warm_start_train_multi.restype = ip
+    L.iim_warm_start_train_multi.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_int32, C.c_int32, C.c_float,
+                                             C.c_uint64, vp]
+    L.iim_warm_start_loss.restype = ip
+    L.iim_warm_start_loss.argtypes = [vp, vp, C.c_int32, dp, i64p]
     L.iim_warm_start_stats.restype = ip
     L.iim_warm_start_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
     L.iim_autotune.restype = ip
@@ -495,6 +501,14 @@ class Context:
                                                losses.ctypes.data_as(C.c_void_p)), "iim_warm_start_train")
         return losses
 
+    def warm_start_loss(self, net, batch=64):
+        """Mean training loss of net over this context's qualifying records
+        (forward passes only) and the number of records."""
+        loss, n = C.c_double(), C.c_int64()
+        self._check(lib().iim_warm_start_loss(self._h, net._h, batch, C.byref(loss), C.byref(n)),
+                    "iim_warm_start_loss")
+        return loss.value, n.value
+
     def warm_start_stats(self):
         v = [C.c_int64() for _ in range(4)]
         self._check(lib().iim_warm_start_stats(self._h, *[C.byref(x) for x in v]), "iim_warm_start_stats")
@@ -519,6 +533,19 @@ def _fptr(t, dtype_name="float32"):
     if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
         raise ValueError("expected a contiguous %s CUDA tensor" % dtype_name)
     return C.c_void_p(t.data_ptr())
+
+
+def warm_start_train_multi(contexts, net, iters, batch, lr, seed=0):
+    """Train net on the recorded solves of several contexts (one network for
+    runs of different geometry or viscosity); the loss of every step."""
+    if not contexts:
+        raise ValueError("no contexts")
+    arr = (C.c_void_p * len(contexts))(*[c._h for c in contexts])
+    losses = np.zeros(iters, dtype=np.float32)
+    contexts[0]._check(lib().iim_warm_start_train_multi(arr, len(contexts), net._h, iters, batch, lr, seed,
+                                                        losses.ctypes.data_as(C.c_void_p)),
+                       "iim_warm_start_train_multi")
+    return losses
 
 
 class Network:

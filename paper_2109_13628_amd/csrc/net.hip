@@ -2,15 +2,21 @@
 //
 // Every convolution is one GEMM on the matrix cores.  A workgroup of four
 // 64-wide waves owns a 64 x 64 output tile; each wave computes 32 x 32 of it
-// as 2 x 2 blocks of 16 x 16 MFMA results.  The operands are gathered straight
-// from global memory through accessors (im2col over the circular sequences,
-// transposed weights, ...): the network is a few MFLOP per sample, so the
-// gather costs far less than the launches and no LDS staging is needed.
+// as 2 x 2 blocks of 16 x 16 MFMA results.  The operands are gathered from
+// global memory through accessors (im2col over the circular sequences,
+// transposed weights, ...).  BF16 operands: each 32-deep slice of the A and B
+// tiles is gathered once per workgroup (coalesced, rounded to BF16), staged
+// in LDS (double-buffered: the next slice's loads are in flight while the
+// current one is multiplied) and read back as 16-byte fragments for the
+// gfx950 16x16x32 BF16 MFMA.  FP32 operands: fragments gathered straight from
+// global memory (the 16x16x4 FP32 MFMA).
 //
 // Matrix-core lane layouts (64 lanes, r = lane % 16, g = lane / 16):
-//   16x16x16 bf16: lane holds A[r][4g + q] and B[4g + q][r], q = 0..3
+//   16x16x32 bf16: lane holds A[r][8g + q] and B[8g + q][r], q = 0..7
 //   16x16x4  f32 : lane holds A[r][g] and B[g][r]
 //   result       : lane holds D[4g + q][r], q = 0..3
+// (a GEMM only needs the A and B slots of a lane to hold the same k values;
+// the result layout fixes where D lands)
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -19,8 +25,8 @@
 
 namespace iim {
 
-typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -49,27 +55,53 @@ __device__ __forceinline__ int seq_src(const Seq& s, int p, int off) {
   return s.seg0[p] + q;
 }
 
-// ---- operand accessors: A(m, k), B(k, n)
+// ---- operand accessors: A(m, k), B(k, n).  For the A operand, row(m)
+// gathers what depends on the row alone (the sequence lookups of the
+// circular convolution) once, and at(row, m, k) forms an element from it.
+struct RowIdx {
+  int m;
+};
 struct AConv {               // im2col: A(row, tap*C + c) = X[row shifted by sgn*(tap-2) in its sequence][c]
   const float* X;
   int C;
   Seq s;
   int sgn;
+  struct Row {               // the row's sequence: first row, length, position
+    int first, len, pos;
+  };
   __device__ float operator()(int m, int k) const {
     const int b = m / s.P, p = m - b * s.P;
     const int tap = k / C, c = k - tap * C;
     return X[((size_t)b * s.P + seq_src(s, p, sgn * (tap - 2))) * C + c];
+  }
+  __device__ Row row(int m) const {
+    const int b = m / s.P, p = m - b * s.P;
+    return Row{b * s.P + s.seg0[p], s.segl[p], s.pos[p]};
+  }
+  // arithmetic only (a table of the five source rows would be indexed by the
+  // tap at run time, which the compiler places in private memory)
+  __device__ float at(const Row& r, int, int k) const {
+    const int tap = k / C, c = k - tap * C;
+    int q = r.pos + sgn * (tap - 2);            // |shift| <= 2: two corrections reach [0, len)
+    q += q < 0 ? r.len : 0;
+    q += q < 0 ? r.len : 0;
+    q -= q >= r.len ? r.len : 0;
+    q -= q >= r.len ? r.len : 0;
+    return X[(size_t)(r.first + q) * C + c];
   }
 };
 struct AConvT {              // A(tap*C + c, row) = X[row shifted by (tap-2)][c]  (weight gradient)
   const float* X;
   int C;
   Seq s;
+  using Row = RowIdx;
   __device__ float operator()(int m, int k) const {
     const int tap = m / C, c = m - tap * C;
     const int b = k / s.P, p = k - b * s.P;
     return X[((size_t)b * s.P + seq_src(s, p, tap - 2)) * C + c];
   }
+  __device__ Row row(int m) const { return Row{m}; }
+  __device__ float at(const Row&, int m, int k) const { return (*this)(m, k); }
 };
 struct BRow {                // B(k, n) = P[k*ld + n]
   const float* P;
@@ -114,9 +146,134 @@ struct EPart {
   __device__ void operator()(int m, int n, float v, int z) const { part[z * MN + (size_t)m * N + n] = v; }
 };
 
-// C(M x N) = sum_k A(m, k) B(k, n) over k in [z*kper, min(K, (z+1)*kper)), z = blockIdx.z
-template <bool BF16, class AF, class BF, class EF>
-__global__ void __launch_bounds__(256) k_mm(int M, int N, int K, int kper, AF A, BF B, EF E) {
+// Round eight FP32 values to BF16 (nearest even) and pack them.
+__device__ __forceinline__ uint4 pack_bf16x8(const float (&f)[8]) {
+  unsigned h[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) h[q] = (unsigned short)to_bf16(f[q]);
+  return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+constexpr int MM_KT = 32;               // k depth of one staged slice (one 16x16x32 MFMA)
+constexpr int MM_LD = MM_KT + 8;        // LDS row length in BF16 (16-byte pad against bank conflicts)
+
+// C(M x N) = sum_k A(m, k) B(k, n) over k in [z*kper, min(K, (z+1)*kper)),
+// z = blockIdx.z; BF16 operands staged in LDS, FP32 accumulation.
+//
+// Slice i is gathered into register set i mod MM_D at iteration i - MM_D,
+// staged into LDS buffer i mod 2 at the end of iteration i - 1 and
+// multiplied at iteration i: MM_D - 1 iterations of products hide each
+// gather's latency (with one slice in flight the loop waited a full global
+// round trip per slice, which dominated the small inference products).
+constexpr int MM_D = 3;
+template <class AF, class BF, class EF>
+__global__ void __launch_bounds__(256) k_mm_bf16(int M, int N, int K, int kper, AF A, BF B, EF E) {
+  // slices: A as [m][k], B transposed as [n][k], both k-contiguous
+  __shared__ __align__(16) unsigned short As[2][64 * MM_LD];
+  __shared__ __align__(16) unsigned short Bs[2][64 * MM_LD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  const int mw = (wave & 1) * 32, nw = (wave >> 1) * 32;
+  const int kb = blockIdx.z * kper;
+  const int ke = min(K, kb + kper);
+  const int ns = ke > kb ? (ke - kb + MM_KT - 1) / MM_KT : 0;   // slices of this block
+  // gather roles: A row am, k offset ak (8 consecutive k); B column bn, k offset bk
+  const int am = tid >> 2, ak = (tid & 3) * 8;
+  const int bn = tid & 63, bk = (tid >> 6) * 8;
+  float fa[MM_D][8], fb[MM_D][8];
+  const int ma = min(m0 + am, M - 1);
+  const typename AF::Row arow = A.row(ma);   // the row's lookups, once
+  if (ns == 0) {                             // nothing to multiply: zero result, no loads
+#pragma unroll
+    for (int d = 0; d < MM_D; ++d) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) fa[d][q] = fb[d][q] = 0.f;
+    }
+  }
+  // Loads without branches: indices outside the operands are clamped to a
+  // valid element (kb < ke whenever ns > 0) and the value replaced by zero.
+  const int m = m0 + am, n = n0 + bn;
+  const int nc = min(n, N - 1);
+  // The validity of each loaded value is kept as a bit and applied when the
+  // slice is staged: a select right after the load would wait for it.
+  unsigned va[MM_D] = {}, vbm[MM_D] = {};
+  auto gather = [&](int slot, int i) {
+    const int k0 = kb + i * MM_KT;
+    const bool live = i < ns;
+    unsigned ba = 0, bb = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ka = k0 + ak + q, kbq = k0 + bk + q;
+      fa[slot][q] = A.at(arow, ma, min(ka, ke - 1));
+      fb[slot][q] = B(min(kbq, ke - 1), nc);
+      ba |= (live && m < M && ka < ke) ? (1u << q) : 0u;
+      bb |= (live && n < N && kbq < ke) ? (1u << q) : 0u;
+    }
+    va[slot] = ba;
+    vbm[slot] = bb;
+  };
+  auto stage = [&](int slot, int buf) {
+    float xa[8], xb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      xa[q] = (va[slot] >> q) & 1u ? fa[slot][q] : 0.f;
+      xb[q] = (vbm[slot] >> q) & 1u ? fb[slot][q] : 0.f;
+    }
+    *reinterpret_cast<uint4*>(&As[buf][am * MM_LD + ak]) = pack_bf16x8(xa);
+    *reinterpret_cast<uint4*>(&Bs[buf][bn * MM_LD + bk]) = pack_bf16x8(xb);
+  };
+  f4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  if (ns > 0) {
+#pragma unroll
+    for (int d = 0; d < MM_D; ++d) gather(d, d);
+  }
+  stage(0, 0);
+  __syncthreads();
+  for (int i0 = 0; i0 < ns; i0 += MM_D) {
+#pragma unroll
+    for (int d = 0; d < MM_D; ++d) {
+      const int i = i0 + d;             // slice i sits in register set d
+      if (i < ns) {                     // uniform over the block
+        const int buf = i & 1;
+        bf8v a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          a[u] = *reinterpret_cast<const bf8v*>(&As[buf][(mw + 16 * u + r) * MM_LD + 8 * g]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          b[u] = *reinterpret_cast<const bf8v*>(&Bs[buf][(nw + 16 * u + r) * MM_LD + 8 * g]);
+        gather(d, i + MM_D);            // set d is free: slice i was staged an iteration ago (ns > 0 here)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v)
+            acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[v], acc[u][v], 0, 0, 0);
+        if (i + 1 < ns) stage((d + 1) % MM_D, buf ^ 1);   // the other buffer: last read before the barrier
+        __syncthreads();
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + mw + 16 * i + 4 * g + q, n = n0 + nw + 16 * j + r;
+        if (m < M && n < N) E(m, n, acc[i][j][q], (int)blockIdx.z);
+      }
+}
+
+// The same product with FP32 operands gathered straight into the 16x16x4
+// FP32 MFMA fragments.
+template <class AF, class BF, class EF>
+__global__ void __launch_bounds__(256) k_mm_f32(int M, int N, int K, int kper, AF A, BF B, EF E) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int mw = blockIdx.x * 64 + (wave & 1) * 32;
@@ -128,51 +285,23 @@ __global__ void __launch_bounds__(256) k_mm(int M, int N, int K, int kper, AF A,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-  if constexpr (BF16) {
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-      s4v a[2], b[2];
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const int k = k0 + g;
+    float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = mw + 16 * i + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 4 * g + q;
-          a[i][q] = to_bf16((m < M && k < ke) ? A(m, k) : 0.f);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = nw + 16 * j + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 4 * g + q;
-          b[j][q] = to_bf16((n < N && k < ke) ? B(k, n) : 0.f);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < 2; ++i) {
+      const int m = mw + 16 * i + r;
+      a[i] = (m < M && k < ke) ? A(m, k) : 0.f;
     }
-  } else {
-    for (int k0 = kb; k0 < ke; k0 += 4) {
-      const int k = k0 + g;
-      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = mw + 16 * i + r;
-        a[i] = (m < M && k < ke) ? A(m, k) : 0.f;
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = nw + 16 * j + r;
-        b[j] = (n < N && k < ke) ? B(k, n) : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int j = 0; j < 2; ++j) {
+      const int n = nw + 16 * j + r;
+      b[j] = (n < N && k < ke) ? B(k, n) : 0.f;
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -185,19 +314,24 @@ __global__ void __launch_bounds__(256) k_mm(int M, int N, int K, int kper, AF A,
       }
 }
 
+// Split-K chunks are multiples of MM_KT rows (the BF16 slice depth; a
+// multiple of the FP32 kernel's 4).
+int mm_kper(int K, int splits) {
+  int kper = (K + splits - 1) / splits;
+  kper = ((kper + MM_KT - 1) / MM_KT) * MM_KT;
+  return kper == 0 ? MM_KT : kper;
+}
+
 template <class AF, class BF, class EF>
 void mm(bool bf16, int M, int N, int K, int splits, AF A, BF B, EF E, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
-  const int step = 16;
-  int kper = (K + splits - 1) / splits;
-  kper = ((kper + step - 1) / step) * step;
-  if (kper == 0) kper = step;
+  const int kper = mm_kper(K, splits);
   const int z = (K + kper - 1) / kper;
   dim3 grid((M + 63) / 64, (N + 63) / 64, z < 1 ? 1 : z);
   if (bf16)
-    k_mm<true><<<grid, 256, 0, st>>>(M, N, K, kper, A, B, E);
+    k_mm_bf16<<<grid, 256, 0, st>>>(M, N, K, kper, A, B, E);
   else
-    k_mm<false><<<grid, 256, 0, st>>>(M, N, K, kper, A, B, E);
+    k_mm_f32<<<grid, 256, 0, st>>>(M, N, K, kper, A, B, E);
 }
 
 __global__ void k_reduce_part(const float* __restrict__ part, int splits, size_t MN, float* __restrict__ out) {
@@ -366,9 +500,8 @@ void launch_conv_bwd_w(bool bf16, const Seq& s, int B, const float* H, int cin, 
   const int rows = B * s.P;
   const int M = NET_TAPS * cin;
   const size_t MN = (size_t)M * cout;
-  // the split count the GEMM really uses (its chunks are multiples of 16 rows)
-  int kper = (rows + splits - 1) / splits;
-  kper = ((kper + 15) / 16) * 16;
+  // the split count the GEMM really uses
+  const int kper = mm_kper(rows, splits);
   const int z = (rows + kper - 1) / kper;
   mm(bf16, M, cout, rows, splits, AConvT{H, cin, s}, BRow{dZ, cout}, EPart{part, MN, cout}, st);
   k_reduce_part<<<(unsigned)((MN + 255) / 256), 256, 0, st>>>(part, z, MN, gW);

@@ -573,7 +573,115 @@ int iim_warm_start_stats(const iim_ctx* c, int64_t* recorded, int64_t* net_used,
 
 int iim_warm_start_train(iim_ctx* c, iim_net* net, int32_t iters, int32_t batch, float lr, uint64_t seed,
                          float* loss_host) {
-  if (!c || check_net(net) != IIM_OK || iters < 1 || batch < 1 || !(lr > 0.f)) return IIM_EINVAL;
+  return iim_warm_start_train_multi(&c, 1, net, iters, batch, lr, seed, loss_host);
+}
+
+int iim_warm_start_train_multi(iim_ctx* const* ctxs, int32_t n_ctx, iim_net* net, int32_t iters, int32_t batch,
+                               float lr, uint64_t seed, float* loss_host) {
+  if (!ctxs || n_ctx < 1) return IIM_EINVAL;
+  for (int q = 0; q < n_ctx; ++q)
+    if (!ctxs[q]) return IIM_EINVAL;
+  iim_ctx* c0 = ctxs[0];
+  if (check_net(net) != IIM_OK || iters < 1 || batch < 1 || !(lr > 0.f)) return IIM_EINVAL;
+  for (int q = 0; q < n_ctx; ++q)
+    if (ctxs[q]->host_only) return IIM_EUNSUPPORTED;
+  // the usable records of every context: three predecessors in the same run
+  std::vector<std::vector<int>> valid(n_ctx);
+  size_t total = 0;
+  for (int q = 0; q < n_ctx; ++q) {
+    const iim_ctx* c = ctxs[q];
+    for (int m = 3; m < c->rec_count; ++m)
+      if (c->rec_run[m - 3] == c->rec_run[m]) valid[q].push_back(m);
+    total += valid[q].size();
+  }
+  if (total == 0) {
+    c0->err = "no recorded solve has three predecessors in the same run";
+    return IIM_EINVAL;
+  }
+  iim_ctx* failed = c0;
+  try {
+    // every context's records are complete before the training stream reads them
+    for (int q = 0; q < n_ctx; ++q) {
+      failed = ctxs[q];
+      HIPCHK(hipStreamSynchronize(ctxs[q]->stream));
+      ensure_sequences(ctxs[q]);
+    }
+    failed = c0;
+    hipStream_t st = c0->stream;
+    int Pmax = 1;
+    for (int q = 0; q < n_ctx; ++q) Pmax = std::max(Pmax, ctxs[q]->seq_P);
+    std::vector<void*> tmp;
+    struct Free {
+      std::vector<void*>& l;
+      ~Free() {
+        for (void* p : l) (void)hipFree(p);
+      }
+    } fr{tmp};
+    float* F = net_alloc<float>(tmp, (size_t)batch * Pmax * NET_FEATURES);
+    float* tgt = net_alloc<float>(tmp, (size_t)batch * Pmax);
+    float* scale = net_alloc<float>(tmp, batch);
+    float* losses = net_alloc<float>(tmp, iters);
+    int* hs = net_alloc<int>(tmp, (size_t)iters * batch * 8);
+    // each iteration draws its batch from one context (one boundary
+    // sequence), the context chosen in proportion to its usable records
+    std::vector<int> h_hs((size_t)iters * batch * 8), which(iters);
+    uint64_t s = seed;
+    for (int it = 0; it < iters; ++it) {
+      size_t pick = (size_t)(uniform01(s) * total) % total;
+      int q = 0;
+      while (pick >= valid[q].size()) pick -= valid[q++].size();
+      which[it] = q;
+      const std::vector<int>& vq = valid[q];
+      for (int e = 0; e < batch; ++e) {
+        const int m = vq[(size_t)(uniform01(s) * vq.size()) % vq.size()];
+        int* t = &h_hs[8 * ((size_t)it * batch + e)];
+        t[0] = m;
+        t[1] = m - 1;
+        t[2] = m - 2;
+        t[3] = m - 1;
+        t[4] = m - 2;
+        t[5] = m - 3;
+        t[6] = ctxs[q]->rec_stage[m];
+        t[7] = m;
+      }
+    }
+    HIPCHK(hipMemcpy(hs, h_hs.data(), h_hs.size() * sizeof(int), hipMemcpyHostToDevice));
+    ensure_rows(net, (size_t)batch * Pmax);   // no regrowth (and free) between queued launches
+    for (int it = 0; it < iters; ++it) {
+      const iim_ctx* c = ctxs[which[it]];
+      const Seq sq = ctx_seq(c);
+      NetPrep p{};
+      p.bh = c->rb;
+      p.xh = c->rx;
+      p.hs = hs + (size_t)it * batch * 8;
+      p.perm = c->perm;
+      p.geo = c->seq_geo;
+      p.n = c->dk.n;
+      p.na = c->dg.na;
+      p.P = c->seq_P;
+      p.F = F;
+      p.tgt = tgt;
+      p.scale = scale;
+      launch_net_prep(p, batch, st);
+      net_forward(net, sq, batch, F, true, st);
+      launch_mse(net->H.back(), tgt, (size_t)batch * c->seq_P, net->dY, losses + it, st);
+      net_backward(net, sq, batch, F, net->dY, st);
+      adam(net, lr, st);
+    }
+    std::vector<float> hl(iters);
+    HIPCHK(hipMemcpyAsync(hl.data(), losses, iters * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (loss_host) std::copy(hl.begin(), hl.end(), loss_host);
+  } catch (const HipError& e) {
+    failed->err = e.what();
+    return e.code;
+  }
+  return IIM_OK;
+}
+
+int iim_warm_start_loss(iim_ctx* c, iim_net* net, int32_t batch, double* loss, int64_t* samples) {
+  if (!c || check_net(net) != IIM_OK || batch < 1 || !loss) return IIM_EINVAL;
   if (c->host_only) return IIM_EUNSUPPORTED;
   std::vector<int> valid;
   for (int m = 3; m < c->rec_count; ++m)
@@ -584,9 +692,9 @@ int iim_warm_start_train(iim_ctx* c, iim_net* net, int32_t iters, int32_t batch,
   }
   try {
     hipStream_t st = c->stream;
-    const int n = c->dk.n;
     ensure_sequences(c);
     const int P = c->seq_P;
+    const int nb = (int)((valid.size() + batch - 1) / batch);
     std::vector<void*> tmp;
     struct Free {
       std::vector<void*>& l;
@@ -597,48 +705,52 @@ int iim_warm_start_train(iim_ctx* c, iim_net* net, int32_t iters, int32_t batch,
     float* F = net_alloc<float>(tmp, (size_t)batch * P * NET_FEATURES);
     float* tgt = net_alloc<float>(tmp, (size_t)batch * P);
     float* scale = net_alloc<float>(tmp, batch);
-    float* losses = net_alloc<float>(tmp, iters);
-    int* hs = net_alloc<int>(tmp, (size_t)iters * batch * 8);
-    std::vector<int> h_hs((size_t)iters * batch * 8);
-    uint64_t s = seed;
-    for (size_t q = 0; q < (size_t)iters * batch; ++q) {
-      const int m = valid[(size_t)(uniform01(s) * valid.size()) % valid.size()];
-      int* t = &h_hs[8 * q];
-      t[0] = m;
-      t[1] = m - 1;
-      t[2] = m - 2;
-      t[3] = m - 1;
-      t[4] = m - 2;
-      t[5] = m - 3;
-      t[6] = c->rec_stage[m];
-      t[7] = m;
+    float* losses = net_alloc<float>(tmp, nb);
+    int* hs = net_alloc<int>(tmp, (size_t)nb * batch * 8);
+    std::vector<int> h_hs((size_t)nb * batch * 8), count(nb);
+    for (int bq = 0; bq < nb; ++bq) {
+      count[bq] = (int)std::min<size_t>(batch, valid.size() - (size_t)bq * batch);
+      for (int e = 0; e < count[bq]; ++e) {
+        const int m = valid[(size_t)bq * batch + e];
+        int* t = &h_hs[8 * ((size_t)bq * batch + e)];
+        t[0] = m;
+        t[1] = m - 1;
+        t[2] = m - 2;
+        t[3] = m - 1;
+        t[4] = m - 2;
+        t[5] = m - 3;
+        t[6] = c->rec_stage[m];
+        t[7] = m;
+      }
     }
     HIPCHK(hipMemcpy(hs, h_hs.data(), h_hs.size() * sizeof(int), hipMemcpyHostToDevice));
+    ensure_rows(net, (size_t)batch * P);
     const Seq sq = ctx_seq(c);
-    for (int it = 0; it < iters; ++it) {
+    for (int bq = 0; bq < nb; ++bq) {
       NetPrep p{};
       p.bh = c->rb;
       p.xh = c->rx;
-      p.hs = hs + (size_t)it * batch * 8;
+      p.hs = hs + (size_t)bq * batch * 8;
       p.perm = c->perm;
       p.geo = c->seq_geo;
-      p.n = n;
+      p.n = c->dk.n;
       p.na = c->dg.na;
       p.P = P;
       p.F = F;
       p.tgt = tgt;
       p.scale = scale;
-      launch_net_prep(p, batch, st);
-      net_forward(net, sq, batch, F, true, st);
-      launch_mse(net->H.back(), tgt, (size_t)batch * P, net->dY, losses + it, st);
-      net_backward(net, sq, batch, F, net->dY, st);
-      adam(net, lr, st);
+      launch_net_prep(p, count[bq], st);
+      net_forward(net, sq, count[bq], F, false, st);
+      launch_mse(net->H.back(), tgt, (size_t)count[bq] * P, net->dY, losses + bq, st);
     }
-    std::vector<float> hl(iters);
-    HIPCHK(hipMemcpyAsync(hl.data(), losses, iters * sizeof(float), hipMemcpyDeviceToHost, st));
+    std::vector<float> hl(nb);
+    HIPCHK(hipMemcpyAsync(hl.data(), losses, nb * sizeof(float), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
-    if (loss_host) std::copy(hl.begin(), hl.end(), loss_host);
+    double acc = 0.0;
+    for (int bq = 0; bq < nb; ++bq) acc += (double)hl[bq] * count[bq];
+    *loss = acc / (double)valid.size();
+    if (samples) *samples = (int64_t)valid.size();
   } catch (const HipError& e) {
     c->err = e.what();
     return e.code;

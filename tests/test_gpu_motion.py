@@ -189,6 +189,9 @@ def test_constant_motion_equals_fixed_rotation():
     # on the velocity, the vorticity within its rounding bound)
     fixed = iim.Context(grid, [body], solver=iim.SOLVER_DIRECT)
     d0, G0, U0, V0 = _steps_and_velocity(fixed, grid, om, G, dt, n)
+    print("schedule vs composed forms: omega", rel(d2.cpu().numpy(), d0.cpu().numpy()),
+          linf_rel(d2.cpu().numpy(), d0.cpu().numpy()), "Gamma", abs(G2[0] - G0[0]) / abs(G0[0]), "velocity",
+          rel(np.stack([U2.cpu().numpy()[fl], V2.cpu().numpy()[fl]]), np.stack([U0.cpu().numpy()[fl], V0.cpu().numpy()[fl]])))
     assert rel(d2.cpu().numpy(), d0.cpu().numpy()) < 2e-9
     assert abs(G2[0] - G0[0]) < 1e-12 * abs(G0[0])
     assert rel(np.stack([U2.cpu().numpy()[fl], V2.cpu().numpy()[fl]]),

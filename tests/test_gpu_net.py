@@ -16,10 +16,12 @@ pytestmark = pytest.mark.gpu
 
 # FP32 operands: rounding of FP32 products through a few layers.  BF16
 # operands: each product rounds both operands to 8 significant bits
-# (relative 2^-9 each), about 4e-3 per layer, compounded over 4 layers
-# forward and 4 backward.
+# (relative 2^-9 each); the errors of independent roundings add in
+# quadrature over a K-term sum, so a layer's relative error stays near
+# 2^-9 (measured: forward 3.5e-3 and 5.5e-3, gradients at most 4.7e-3 and
+# 7.3e-3 for widths 16 and 128), below the 2e-2 bound asked of the BF16 path.
 TOL_F32_FWD, TOL_F32_GRAD = 1e-5, 1e-4
-TOL_BF16_FWD, TOL_BF16_GRAD = 3e-2, 6e-2
+TOL_BF16_FWD, TOL_BF16_GRAD = 2e-2, 2e-2
 
 
 def _segments(lengths):
@@ -91,15 +93,16 @@ def test_forward_and_gradients_match_oracle(arch, bf16):
     y_ref, loss_ref, g_ref = _oracle(params, X, T, LENGTHS)
     ey = rel(y.cpu().numpy(), y_ref)
     tf, tg = (TOL_BF16_FWD, TOL_BF16_GRAD) if bf16 else (TOL_F32_FWD, TOL_F32_GRAD)
-    assert ey < tf, ey
-    assert abs(loss - loss_ref) / loss_ref < tf, (loss, loss_ref)
     # every layer's weight and bias gradient
-    off = 0
+    off, eg = 0, []
     for cin, cout in zip(sizes[:-1], sizes[1:]):
         for n in (N.TAPS * cin * cout, cout):
-            e = rel(g[off:off + n], g_ref[off:off + n])
-            assert e < tg, (off, n, e)
+            eg.append(rel(g[off:off + n], g_ref[off:off + n]))
             off += n
+    print(arch, "bf16" if bf16 else "fp32", "forward", ey, "loss", abs(loss - loss_ref) / loss_ref, "gradients", eg)
+    assert ey < tf, ey
+    assert abs(loss - loss_ref) / loss_ref < tf, (loss, loss_ref)
+    assert max(eg) < tg, eg
 
 
 def test_adam_step_matches_oracle():
@@ -121,6 +124,38 @@ def test_adam_step_matches_oracle():
         # the update itself (lr-sized) must agree to FP32 rounding
         assert np.max(np.abs(got - p)) < 1e-5, (step, np.max(np.abs(got - p)))
         p = got
+
+
+def test_training_across_runs_and_validation_loss():
+    """One network trained on the records of two runs of different viscosity
+    and body position (iim_warm_start_train_multi) lowers the loss on both;
+    the validation loss (iim_warm_start_loss) does not depend on how the
+    records are batched and counts every record with three predecessors."""
+    base = wl.cylinder_small()
+    runs = []
+    for re, dx in ((50.0, 0.0), (150.0, 0.3 * base.grid.h)):
+        w = wl.cylinder(nx=base.grid.nx, ny=base.grid.ny, h=base.grid.h, points=128, dt=base.dt,
+                        center=(1.5 + dx, 0.1 * dx), nu=1.0 / re)
+        ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+        ctx.record_solves(200)
+        om = torch.zeros((w.grid.ny, w.grid.nx), dtype=torch.float64, device=DEV)
+        ctx.rk3_steps(om, np.zeros(ctx.n_circ), w.dt, 40)
+        runs.append(ctx)
+    torch.cuda.synchronize()
+    net = iim.Network(bf16=True, seed=0)
+    before = [c.warm_start_loss(net)[0] for c in runs]
+    for c in runs:
+        l1, n1 = c.warm_start_loss(net, batch=1)
+        l64, n64 = c.warm_start_loss(net, batch=64)
+        assert n1 == n64 == 40 * 3 - 3
+        assert abs(l1 - l64) < 1e-5 * l64, (l1, l64)
+    losses = iim.warm_start_train_multi(runs, net, iters=300, batch=32, lr=1e-3, seed=4)
+    assert np.all(np.isfinite(losses))
+    after = [c.warm_start_loss(net)[0] for c in runs]
+    print("validation losses before", before, "after", after)
+    assert all(a < 0.7 * b for a, b in zip(after, before)), (before, after)
+    for c in runs:
+        c.close()
 
 
 def test_sequences_cover_affected_points():
