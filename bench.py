@@ -351,10 +351,9 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
 
 def _summarize_mfma(pmc_dir, out, command):
     """Matrix-core counters of the network's GEMM kernels: per kernel
-    instantiation, the mean over its dispatches of the BF16 MFMA FLOPs
-    (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512), the MFMA busy fraction
-    (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE times the 1024 SIMDs) and
-    the fraction of cycles the shader array was busy."""
+    instantiation and launch size, the mean over its dispatches of the BF16
+    MFMA FLOPs (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512) and of rocprofv3's
+    MfmaUtil (MFMA busy cycles over the active cycles of all SIMDs, %)."""
     import glob
     rows = _read_csv(glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)[0])
     per = {}
@@ -367,19 +366,16 @@ def _summarize_mfma(pmc_dir, out, command):
         d = per.setdefault((short, int(r["Grid_Size"])), {})
         d.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
     lines = ["# Matrix-core counters of the network's GEMMs (rocprofv3 --pmc), the --net-only leg of bench.py:",
-             "# forward passes and training steps at batch 64 x 384 control points, and batch-1 forward passes.",
-             "# mfma_util = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs); flop = MOPS_BF16 x 512", "",
+             "# forward passes and training steps at batch 64 x 384 control points, and batch-1 forward passes",
+             "# (grid = threads of the launch; the small grids are the batch-1 inference layers).", "",
              "command: " + command, "",
-             "kernel | grid | dispatches | BF16 GFLOP per dispatch | mfma_util % | busy % (SQ_BUSY_CYCLES / GRBM_GUI_ACTIVE)",
-             "---|---|---|---|---|---"]
-    for (short, grid), disp in sorted(per.items(), key=lambda kv: (-len(kv[1]), kv[0])):
-        vals = [v for v in disp.values() if "GRBM_GUI_ACTIVE" in v and v["GRBM_GUI_ACTIVE"] > 0]
-        if not vals:
-            continue
+             "kernel | grid | dispatches | BF16 GFLOP per dispatch | MfmaUtil %",
+             "---|---|---|---|---"]
+    for (short, grid), disp in sorted(per.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        vals = list(disp.values())
         fl = sum(v.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512 for v in vals) / len(vals)
-        ut = sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (v["GRBM_GUI_ACTIVE"] * 1024) for v in vals) / len(vals)
-        bz = sum(v.get("SQ_BUSY_CYCLES", 0.0) / v["GRBM_GUI_ACTIVE"] for v in vals) / len(vals)
-        lines.append("%s | %d | %d | %.4f | %.2f | %.1f" % (short[:90], grid, len(vals), fl / 1e9, 100 * ut, 100 * bz))
+        ut = sum(v.get("MfmaUtil", 0.0) for v in vals) / len(vals)
+        lines.append("%s | %d | %d | %.4f | %.2f" % (short[:90], grid, len(vals), fl / 1e9, ut))
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 

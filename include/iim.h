@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IIM_ABI_VERSION 2
+#define IIM_ABI_VERSION 3
 
 enum {
   IIM_OK = 0,
@@ -98,6 +98,17 @@ enum { IIM_GUESS_ZERO = 0, IIM_GUESS_PREVIOUS = 1, IIM_GUESS_EXTRAPOLATE = 2, II
  * iterative solve), or the dense inverse of the Schur matrix built once at
  * create (bodies are fixed, so the matrix is too). */
 enum { IIM_SOLVER_KRYLOV = 0, IIM_SOLVER_DIRECT = 1 };
+/* Lengths of the zero-padded free-space torus (at least 2 nx, or 4 nx with
+ * the outflow mirror, by 2 ny; Sec. 4.2's free-space convolution is exact on
+ * any such torus):
+ *   COMPACT  the smallest length with a register FFT plan: powers of two and,
+ *            for FP64 contexts whose row half-length and column length are
+ *            both 256 or more, 320, 384, 640, 768, 1280 and 1536 points per
+ *            row half and column (radix-3 and radix-5 passes); mixed precision
+ *            uses powers of two;
+ *   POW2     the next powers of two.
+ * The periodic exterior uses the grid itself (powers of two). */
+enum { IIM_FFT_SIZES_COMPACT = 0, IIM_FFT_SIZES_POW2 = 1 };
 
 typedef struct {
   int32_t nx, ny;         /* grid nodes per direction (>= 16) */
@@ -131,6 +142,7 @@ typedef struct {
   int32_t guess;          /* IIM_GUESS_* initial guess of each Schur solve */
   int32_t host_only;      /* 1: build geometry and tables only, allocate nothing on the device */
   int32_t solver;         /* IIM_SOLVER_*; DIRECT stores (|A| + n_circ)^2 doubles on the device */
+  int32_t fft_sizes;      /* IIM_FFT_SIZES_* (free-space tori) */
 } iim_solver_opts;
 
 typedef struct {

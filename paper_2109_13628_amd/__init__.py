@@ -24,6 +24,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 GUESS_ZERO, GUESS_PREVIOUS, GUESS_EXTRAPOLATE, GUESS_NETWORK = 0, 1, 2, 3
 NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
+FFT_SIZES_COMPACT, FFT_SIZES_POW2 = 0, 1
 
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_given_wb", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
@@ -64,7 +65,7 @@ class BodyDesc(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_max_iter", C.c_int32),
                 ("krylov_restart", C.c_int32), ("max_refine", C.c_int32), ("guess", C.c_int32),
-                ("host_only", C.c_int32), ("solver", C.c_int32)]
+                ("host_only", C.c_int32), ("solver", C.c_int32), ("fft_sizes", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -279,7 +280,8 @@ class Context:
     """One IIM problem (grid + bodies) on the current device."""
 
     def __init__(self, grid, bodies, precision=PREC_FP64, tol=1e-13, max_iter=400, restart=40,
-                 guess=GUESS_PREVIOUS, host_only=False, stream=None, solver=SOLVER_KRYLOV):
+                 guess=GUESS_PREVIOUS, host_only=False, stream=None, solver=SOLVER_KRYLOV,
+                 fft_sizes=FFT_SIZES_COMPACT):
         L = lib()
         g = GridDesc(nx=grid.nx, ny=grid.ny, x0=grid.x0, y0=grid.y0, h=grid.h, exterior=EXT[grid.exterior],
                      nu=grid.nu)
@@ -289,7 +291,7 @@ class Context:
         arr = _body_array(bodies, self._pts)
         self.n_bodies = len(bodies)
         o = SolverOpts(precision=precision, krylov_tol=tol, krylov_max_iter=max_iter, krylov_restart=restart,
-                       max_refine=8, guess=guess, host_only=int(host_only), solver=solver)
+                       max_refine=8, guess=guess, host_only=int(host_only), solver=solver, fft_sizes=fft_sizes)
         if stream is None and not host_only:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -668,7 +670,7 @@ class Batch:
     """Independent simulations advanced together, one HIP graph per batch
     step (dense FP64 Schur solver in every simulation)."""
 
-    def __init__(self, workloads, stream=None):
+    def __init__(self, workloads, stream=None, fft_sizes=FFT_SIZES_COMPACT):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -680,7 +682,7 @@ class Batch:
         ptrs = (C.POINTER(BodyDesc) * n)(*[C.cast(a, C.POINTER(BodyDesc)) for a in arrs])
         nb = (C.c_int32 * n)(*[len(w.bodies) for w in workloads])
         o = SolverOpts(precision=PREC_FP64, krylov_tol=1e-13, krylov_max_iter=400, krylov_restart=40,
-                       max_refine=8, guess=GUESS_PREVIOUS, host_only=0, solver=SOLVER_DIRECT)
+                       max_refine=8, guess=GUESS_PREVIOUS, host_only=0, solver=SOLVER_DIRECT, fft_sizes=fft_sizes)
         h = C.c_void_p()
         rc = lib().iim_batch_create(n, grids, nb, ptrs, C.byref(o), C.c_void_p(stream or 0), C.byref(h))
         if rc:

@@ -36,6 +36,15 @@ int next_pow2(int v) {
   return p;
 }
 
+// The smallest length >= v that the register FFTs take: a power of two, or
+// 320, 384, 640, 768, 1280, 1536 (FP64 plans with radix-3 and radix-5 passes)
+int compact_len(int v) {
+  int best = next_pow2(v);
+  for (int n : {320, 384, 640, 768, 1280, 1536})
+    if (n >= v && n < best) best = n;
+  return best;
+}
+
 // Kernel spectrum of the lattice Green's function on an mx x my torus for
 // h = 1 (the spectrum for spacing h is h^2 times it), computed once per torus
 // size in this process: contexts of equal FFT size share it.
@@ -401,7 +410,16 @@ void setup_device(iim_ctx* c) {
       throw ArgError("the periodic exterior needs power-of-two nx, ny >= 32");
     // free space: a zero-padded torus (>= 2 nx, >= 2 ny; 4 nx with the
     // outflow mirror); periodic: the grid itself
-    const int mx = periodic ? nx : next_pow2((outflow ? 4 : 2) * nx), my = periodic ? ny : next_pow2(2 * ny);
+    int mx = periodic ? nx : next_pow2((outflow ? 4 : 2) * nx), my = periodic ? ny : next_pow2(2 * ny);
+    if (!periodic && c->fft_sizes == IIM_FFT_SIZES_COMPACT && c->precision == IIM_PREC_FP64) {
+      const int hxc = compact_len((outflow ? 2 : 1) * nx), myc = compact_len(2 * ny);
+      // the register kernels take every compact length; below 256 points the
+      // LDS kernels run, which take powers of two only
+      if (hxc >= 256 && myc >= 256 && hxc <= 4096 && myc <= 4096) {
+        mx = 2 * hxc;
+        my = myc;
+      }
+    }
     if (mx / 2 > 4096 || my > 4096) throw ArgError("grid too large for the FFT plan (mx/2, my <= 4096)");
     DFft& f = c->df;
     f.mx = mx;
@@ -1080,8 +1098,11 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       c->guess = opts->guess;
       c->host_only = opts->host_only != 0;
       c->solver = opts->solver;
+      c->fft_sizes = opts->fft_sizes;
       c->use_graph = std::getenv("IIM_NO_GRAPH") == nullptr;
     }
+    if (c->fft_sizes != IIM_FFT_SIZES_COMPACT && c->fft_sizes != IIM_FFT_SIZES_POW2)
+      throw ArgError("unknown FFT size policy");
     if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
     if (c->solver != IIM_SOLVER_KRYLOV && c->solver != IIM_SOLVER_DIRECT) throw ArgError("unknown solver");
     if (c->guess < IIM_GUESS_ZERO || c->guess > IIM_GUESS_NETWORK) throw ArgError("unknown initial guess");

@@ -68,8 +68,11 @@ __device__ __forceinline__ CX mkc(A x, B y) {
 // plus the mirrored source at column 2 nx - 1 - i for the outflow exterior.
 // This is what the real row transform of length mx gives for a row that holds
 // only these point values; the column pass adds it directly, so the sparse
-// sources need no row pass.  tw_xr holds W^k for k <= mx / 2 (mx a power of two).
+// sources need no row pass.  tw_xr holds W^k for k <= mx / 2 (mx even).
 // W^r for 0 <= r < mx from the table of W^k, k <= mx / 2 (one load, always in range)
+// v mod m for v >= 0: a mask when m is a power of two (every LDS-kernel torus),
+// a division otherwise (tori with a factor 3 or 5)
+__device__ __forceinline__ int torus_mod(int v, int m) { return (m & (m - 1)) == 0 ? (v & (m - 1)) : v % m; }
 template <class CX>
 __device__ __forceinline__ CX twiddle_r(const CX* __restrict__ tw_xr, int r, int mx) {
   const bool hi = r > mx / 2;
@@ -94,12 +97,12 @@ __device__ __forceinline__ CX sparse_row_dft(const DGeom& g, int mx, bool outflo
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const CX w = twiddle_r(tw_xr, (kx * ii[u]) & (mx - 1), mx);
+      const CX w = twiddle_r(tw_xr, torus_mod(kx * ii[u], mx), mx);
       const S v = (S)val[u];
       acc.x += v * w.x;
       acc.y += v * w.y;
       if (outflow) {
-        const CX w2 = twiddle_r(tw_xr, (kx * (2 * g.nx - 1 - ii[u])) & (mx - 1), mx);
+        const CX w2 = twiddle_r(tw_xr, torus_mod(kx * (2 * g.nx - 1 - ii[u]), mx), mx);
         acc.x += v * w2.x;
         acc.y += v * w2.y;
       }
@@ -1589,6 +1592,14 @@ template <> struct RP<512> { static constexpr int T = 64, E = 8; };
 template <> struct RP<1024> { static constexpr int T = IIM_FFT1024_THREADS, E = 1024 / IIM_FFT1024_THREADS; };
 template <> struct RP<2048> { static constexpr int T = 128, E = 16; };
 template <> struct RP<4096> { static constexpr int T = 256, E = 16; };
+// tori with a factor 3 or 5 (FP64), so that a padded size can follow 2N
+// instead of the next power of two: E divisible by every radix of the plan
+template <> struct RP<320> { static constexpr int T = 16, E = 20; };
+template <> struct RP<384> { static constexpr int T = 32, E = 12; };
+template <> struct RP<640> { static constexpr int T = 32, E = 20; };
+template <> struct RP<768> { static constexpr int T = 64, E = 12; };
+template <> struct RP<1280> { static constexpr int T = 64, E = 20; };
+template <> struct RP<1536> { static constexpr int T = 128, E = 12; };
 // Lanes per FFT of the row passes (ROWS) and of the column pass: the same
 // except at 1024 points, where the row passes run 256 lanes of 4 points
 // (faster there) and the column pass 128 lanes of 8 (faster there).
@@ -1712,7 +1723,35 @@ __device__ __forceinline__ CX w16(int e, bool inv) {
 
 template <int R, bool INV, class CX>
 __device__ __forceinline__ void dftR(CX (&u)[R]) {
-  if constexpr (R == 2) {
+  using S = typename Real<CX>::t;
+  if constexpr (R == 3) {
+    // y1, y2 = x0 - (x1 + x2) / 2 -/+ i (sqrt 3 / 2)(x1 - x2) (forward W = exp(-2 pi i / 3))
+    const S h = (S)0.86602540378443864676;
+    const CX a = cadd(u[1], u[2]), d = csub(u[1], u[2]);
+    const CX m = mkc<CX>(u[0].x - S(0.5) * a.x, u[0].y - S(0.5) * a.y);
+    const CX r = INV ? mkc<CX>(-h * d.y, h * d.x) : mkc<CX>(h * d.y, -h * d.x);   // -/+ i h d
+    u[0] = cadd(u[0], a);
+    u[1] = cadd(m, r);
+    u[2] = csub(m, r);
+  } else if constexpr (R == 5) {
+    // pairs (x1, x4), (x2, x3): y_k = x0 + c(k) sums - i s(k) differences
+    const S c1 = (S)0.30901699437494742410, c2 = (S)-0.80901699437494742410;
+    const S s1 = (S)0.95105651629515357212, s2 = (S)0.58778525229247312917;
+    const CX p1 = cadd(u[1], u[4]), q1 = csub(u[1], u[4]);
+    const CX p2 = cadd(u[2], u[3]), q2 = csub(u[2], u[3]);
+    const CX a1 = mkc<CX>(u[0].x + c1 * p1.x + c2 * p2.x, u[0].y + c1 * p1.y + c2 * p2.y);
+    const CX a2 = mkc<CX>(u[0].x + c2 * p1.x + c1 * p2.x, u[0].y + c2 * p1.y + c1 * p2.y);
+    const CX b1 = mkc<CX>(s1 * q1.x + s2 * q2.x, s1 * q1.y + s2 * q2.y);
+    const CX b2 = mkc<CX>(s2 * q1.x - s1 * q2.x, s2 * q1.y - s1 * q2.y);
+    // -i b = (b.y, -b.x); the inverse transform takes +i b
+    const CX r1 = INV ? mkc<CX>(-b1.y, b1.x) : mkc<CX>(b1.y, -b1.x);
+    const CX r2 = INV ? mkc<CX>(-b2.y, b2.x) : mkc<CX>(b2.y, -b2.x);
+    u[0] = cadd(u[0], cadd(p1, p2));
+    u[1] = cadd(a1, r1);
+    u[4] = csub(a1, r1);
+    u[2] = cadd(a2, r2);
+    u[3] = csub(a2, r2);
+  } else if constexpr (R == 2) {
     const CX a = u[0];
     u[0] = cadd(a, u[1]);
     u[1] = csub(a, u[1]);
@@ -1768,7 +1807,7 @@ struct PassTw {
       constexpr int step = N / (NS * R);
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int k = (t + T * b) & (NS - 1);
+        const int k = (t + T * b) % NS;
 #pragma unroll
         for (int r = 1; r < R; ++r) w[b][r - 1] = tw[r * k * step];
       }
@@ -1813,7 +1852,7 @@ __device__ __forceinline__ void reg_pass(CX (&v)[E], CX* lds, int t, const PassT
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + T * b;
-      const int k = j & (NS - 1);
+      const int k = j % NS;
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[padi(base + r * NS)] = u[b][r];
@@ -1856,6 +1895,30 @@ template <> struct Plan<4096, 16> {
   static constexpr int P = 3;
   static constexpr int R[P] = {16, 16, 16}, NS[P] = {1, 16, 256};
 };
+template <> struct Plan<320, 20> {
+  static constexpr int P = 4;
+  static constexpr int R[P] = {5, 4, 4, 4}, NS[P] = {1, 5, 20, 80};
+};
+template <> struct Plan<384, 12> {
+  static constexpr int P = 5;
+  static constexpr int R[P] = {3, 4, 4, 4, 2}, NS[P] = {1, 3, 12, 48, 192};
+};
+template <> struct Plan<640, 20> {
+  static constexpr int P = 5;
+  static constexpr int R[P] = {5, 4, 4, 4, 2}, NS[P] = {1, 5, 20, 80, 320};
+};
+template <> struct Plan<768, 12> {
+  static constexpr int P = 5;
+  static constexpr int R[P] = {3, 4, 4, 4, 4}, NS[P] = {1, 3, 12, 48, 192};
+};
+template <> struct Plan<1280, 20> {
+  static constexpr int P = 5;
+  static constexpr int R[P] = {5, 4, 4, 4, 4}, NS[P] = {1, 5, 20, 80, 320};
+};
+template <> struct Plan<1536, 12> {
+  static constexpr int P = 6;
+  static constexpr int R[P] = {3, 4, 4, 4, 4, 2}, NS[P] = {1, 3, 12, 48, 192, 768};
+};
 
 template <int N, int E, int I, class CX>
 using PlanTw = PassTw<N, N / E, E, Plan<N, E>::R[I], Plan<N, E>::NS[I], CX>;
@@ -1892,7 +1955,7 @@ struct Tw1 {
       const int R = PL::R[i], NS = PL::NS[i], step = N / (NS * R);
 #pragma unroll
       for (int b = 0; b < E; ++b)
-        if (b < E / R) w[i][b] = tw[((t + T * b) & (NS - 1)) * step];
+        if (b < E / R) w[i][b] = tw[((t + T * b) % NS) * step];
     }
   }
 };
@@ -1926,7 +1989,7 @@ __device__ __forceinline__ void reg_pass_w(CX (&v)[E], CX* lds, int t, const CX*
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + T * b;
-      const int k = j & (NS - 1);
+      const int k = j % NS;
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[padi(base + r * NS)] = u[b][r];
@@ -1957,9 +2020,18 @@ __device__ __forceinline__ void fft_reg_w(CX (&v)[E], CX* lds, int t, const Tw1<
 // between passes.  FP64: base twiddles loaded up front (Tw1); FP32 (the
 // mixed-precision products, whose error budget assumes table twiddles): every
 // power from the table, one pass ahead.
+// Base twiddles up front (Tw1) for FP64 powers of two; tori with a factor 3
+// or 5 hold 12 or 20 points per lane, too many registers to keep every
+// pass's base twiddles live as well, so they load each pass's powers from
+// the table one pass ahead like FP32.
+template <int N, class CX>
+constexpr bool use_tw1() {
+  return std::is_same<CX, double2>::value && (N & (N - 1)) == 0;
+}
+
 template <int N, bool INV, class CX, int E>
 __device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw) {
-  if constexpr (std::is_same<CX, double2>::value) {
+  if constexpr (use_tw1<N, CX>()) {
     Tw1<N, E, CX> tw1;
     tw1.load(t, tw);
     fft_reg_w<N, INV, CX, E>(v, lds, t, tw1);
@@ -2036,8 +2108,8 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
         CX w1[4], w2[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          w1[u] = twiddle_r(ft.tw_xr, (kx * ii[u]) & (mx - 1), mx);
-          w2[u] = f.outflow ? twiddle_r(ft.tw_xr, (kx * (2 * g.nx - 1 - ii[u])) & (mx - 1), mx) : mkc<CX>(0, 0);
+          w1[u] = twiddle_r(ft.tw_xr, torus_mod(kx * ii[u], mx), mx);
+          w2[u] = f.outflow ? twiddle_r(ft.tw_xr, torus_mod(kx * (2 * g.nx - 1 - ii[u]), mx), mx) : mkc<CX>(0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -2065,7 +2137,7 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
     const int n = t + T * m;
     gk[m] = gh[n <= MY / 2 ? n : MY - n];
   }
-  if constexpr (std::is_same<CX, double2>::value) {
+  if constexpr (use_tw1<MY, CX>()) {
     Tw1<MY, E, CX> tw1;   // both FFTs' base twiddles
     tw1.load(t, ft.tw_y);
     fft_reg_w<MY, false>(v, lds[w], t, tw1);
@@ -2158,8 +2230,8 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int co
     const int rr = idx % C::PER, k = idx / C::PER;
     const int jj = j0 + lb * C::PER + rr;
     if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
-    const CX zk = lds[rr][padi(k & (HX - 1))];
-    const CX zc = conj2(lds[rr][padi((HX - k) & (HX - 1))]);
+    const CX zk = lds[rr][padi(k == HX ? 0 : k)];
+    const CX zc = conj2(lds[rr][padi(k == 0 ? 0 : HX - k)]);
     const CX E2 = mkc<CX>(S(0.5) * (zk.x + zc.x), S(0.5) * (zk.y + zc.y));
     const CX Od = csub(zk, zc);
     const CX O = mkc<CX>(S(0.5) * Od.y, S(-0.5) * Od.x);
@@ -2287,16 +2359,37 @@ void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, doubl
   IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_inv_go, g, f, j0, count, psi, done, s, prof, bytes);
 }
 
-#define IIM_REG_SWITCH(VAL, FN, CXT, ...)           \
-  switch (VAL) {                                    \
-    case 256: FN<256, CXT>(__VA_ARGS__); break;     \
-    case 512: FN<512, CXT>(__VA_ARGS__); break;     \
-    case 1024: FN<1024, CXT>(__VA_ARGS__); break;   \
-    case 2048: FN<2048, CXT>(__VA_ARGS__); break;   \
-    case 4096: FN<4096, CXT>(__VA_ARGS__); break;   \
-    default: break;                                 \
+// Register FFT sizes: powers of two 256 .. 4096 (FP64 and FP32) and, FP64
+// only, 320, 384, 640, 768, 1280, 1536 (factors 3 and 5)
+#define IIM_REG_SWITCH(VAL, FN, CXT, ...)                                              \
+  switch (VAL) {                                                                       \
+    case 256: FN<256, CXT>(__VA_ARGS__); break;                                        \
+    case 512: FN<512, CXT>(__VA_ARGS__); break;                                        \
+    case 1024: FN<1024, CXT>(__VA_ARGS__); break;                                      \
+    case 2048: FN<2048, CXT>(__VA_ARGS__); break;                                      \
+    case 4096: FN<4096, CXT>(__VA_ARGS__); break;                                      \
+    default:                                                                           \
+      if constexpr (std::is_same<CXT, double2>::value) {                               \
+        switch (VAL) {                                                                 \
+          case 320: FN<320, CXT>(__VA_ARGS__); break;                                  \
+          case 384: FN<384, CXT>(__VA_ARGS__); break;                                  \
+          case 640: FN<640, CXT>(__VA_ARGS__); break;                                  \
+          case 768: FN<768, CXT>(__VA_ARGS__); break;                                  \
+          case 1280: FN<1280, CXT>(__VA_ARGS__); break;                                \
+          case 1536: FN<1536, CXT>(__VA_ARGS__); break;                                \
+          default: break;                                                              \
+        }                                                                              \
+      }                                                                                \
+      break;                                                                           \
   }
 
+bool reg_fft_size(int n, bool fp32) {
+  switch (n) {
+    case 256: case 512: case 1024: case 2048: case 4096: return true;
+    case 320: case 384: case 640: case 768: case 1280: case 1536: return !fp32;
+    default: return false;
+  }
+}
 bool conv_reg_supported(int hx, int my) { return hx >= 256 && my >= 256; }
 
 // ---- launch-resource check of the register FFT instantiations that a tile

@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(iim.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.iim_abi_version() == 2
+    assert L.iim_abi_version() == 3
 
 
 def test_lgf_matches_closed_forms_and_oracle():

@@ -1,0 +1,94 @@
+"""Free-space tori with a factor 3 or 5 (radix-3 and radix-5 register FFT
+passes): the padded lengths follow 2 nx and 2 ny instead of the next powers
+of two.  The zero-padded convolution is the same operator on any torus of at
+least 2 nx by 2 ny (Sec. 4.2), so the library on the compact torus is checked
+against the oracle's convolution on the 2 nx x 2 ny torus, and against the
+library on the power-of-two torus; then the reconstruction and one RK3 step
+of a cylinder on a compact torus against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+import paper_2109_13628_amd as iim
+from oracle import geometry as OG
+from oracle import poisson as OP
+from oracle import ns as ONS
+from gpu_util import to_dev, ring_zeros, seeded_state, rel
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, exterior) -> compact (mx, my); every plan 320 ... 1536 appears as a
+# row half-length and as a column length
+CASES = [
+    ((300, 150, "free"), (640, 320)),
+    ((350, 170, "free"), (768, 384)),
+    ((600, 300, "free"), (1280, 640)),
+    ((700, 350, "free"), (1536, 768)),
+    ((1100, 600, "free"), (2560, 1280)),
+    ((1400, 700, "free"), (3072, 1536)),
+    ((300, 170, "outflow"), (1280, 384)),
+    ((170, 600, "outflow"), (768, 1280)),
+]
+
+
+def _grid(nx, ny, ext):
+    h = 1.0 / 64
+    return wl.GridDesc(nx=nx, ny=ny, x0=0.5 * h, y0=-0.5 * ny * h, h=h, exterior=ext, u_inf=(1.0, 0.0), nu=0.01)
+
+
+@pytest.mark.parametrize("case", CASES, ids=["%dx%d_%s" % c[0] for c in CASES])
+def test_poisson_on_compact_torus(case):
+    (nx, ny, ext), (mx, my) = case
+    g = _grid(nx, ny, ext)
+    rng = np.random.default_rng(nx + ny)
+    src = rng.standard_normal((ny, nx))
+    ref = OP.FreeSpace(nx, ny, g.h, outflow=(ext == "outflow"))(src)
+    out = {}
+    for pol in (iim.FFT_SIZES_COMPACT, iim.FFT_SIZES_POW2):
+        ctx = iim.Context(g, [], fft_sizes=pol)
+        psi = ring_zeros(g)
+        ctx.poisson(to_dev(src), psi)
+        torch.cuda.synchronize()
+        out[pol] = (psi.cpu().numpy(), (ctx.info["fft_mx"], ctx.info["fft_my"]))
+        ctx.close()
+    assert out[iim.FFT_SIZES_COMPACT][1] == (mx, my), out[iim.FFT_SIZES_COMPACT][1]
+    e_c = rel(out[iim.FFT_SIZES_COMPACT][0], ref)
+    e_p = rel(out[iim.FFT_SIZES_POW2][0], ref)
+    print(case, "compact", e_c, "pow2", out[iim.FFT_SIZES_POW2][1], e_p)
+    assert e_c < 1e-13 and e_p < 1e-13, (e_c, e_p)
+    assert rel(out[iim.FFT_SIZES_COMPACT][0], out[iim.FFT_SIZES_POW2][0]) < 1e-13
+
+
+def test_mixed_precision_keeps_powers_of_two():
+    g = _grid(350, 170, "free")
+    ctx = iim.Context(g, [], precision=iim.PREC_MIXED)
+    assert (ctx.info["fft_mx"], ctx.info["fft_my"]) == (1024, 512)
+    ctx.close()
+
+
+@pytest.mark.parametrize("solver", [iim.SOLVER_DIRECT, iim.SOLVER_KRYLOV])
+@pytest.mark.parametrize("ext", ["free", "outflow"])
+def test_step_on_compact_torus(ext, solver):
+    w = wl.cylinder(nx=350, ny=170, h=1.0 / 32, points=128, dt=0.005, center=(2.0, 0.0))
+    if ext == "outflow":
+        w.grid.exterior = wl.EXT_OUTFLOW
+    geo = OG.Geometry(w.grid, w.bodies)
+    om, G = seeded_state(w, geo, 5, body_scale=1.0)
+    st = ONS.Stepper(geo)
+    om_ref, G_ref = st.step(om, G, w.dt)
+    ctx = iim.Context(w.grid, w.bodies, solver=solver, tol=1e-13)
+    assert ctx.info["fft_my"] == 384 and ctx.info["fft_mx"] == (768 if ext == "free" else 1536)
+    d = to_dev(om)
+    G1, stats = ctx.rk3_steps(d, G.copy(), w.dt, 1)
+    psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
+    ctx.reconstruct(d, G1, psi, U, V)
+    torch.cuda.synchronize()
+    b = st.rec.reconstruct(om_ref, G_ref)
+    fl = np.pad(geo.fluid, 1)
+    ev = rel(np.stack([U.cpu().numpy()[fl], V.cpu().numpy()[fl]]), np.stack([b.U[fl], b.V[fl]]))
+    ew = rel(d.cpu().numpy(), om_ref, mask=geo.fluid)
+    print(ext, solver, "velocity", ev, "vorticity", ew, stats)
+    assert ev < 1e-11 and ew < 1e-11, (ev, ew)
+    assert np.max(np.abs(G1 - G_ref)) < 1e-13 * (1 + np.abs(G_ref).max())
+    ctx.close()
