@@ -101,6 +101,9 @@ enum { IIM_SOLVER_KRYLOV = 0, IIM_SOLVER_DIRECT = 1 };
 /* Lengths of the zero-padded free-space torus (at least 2 nx, or 4 nx with
  * the outflow mirror, by 2 ny; Sec. 4.2's free-space convolution is exact on
  * any such torus):
+ *   TUNED    (default) times one full convolution on the COMPACT torus and
+ *            on the POW2 torus at create (scratch tables, zero source) and
+ *            keeps the faster; the same as COMPACT when the two coincide;
  *   COMPACT  the smallest length with a register FFT plan: powers of two and,
  *            for FP64 contexts whose row half-length and column length are
  *            both 256 or more, 320, 384, 640, 768, 1280 and 1536 points per
@@ -108,7 +111,7 @@ enum { IIM_SOLVER_KRYLOV = 0, IIM_SOLVER_DIRECT = 1 };
  *            uses powers of two;
  *   POW2     the next powers of two.
  * The periodic exterior uses the grid itself (powers of two). */
-enum { IIM_FFT_SIZES_COMPACT = 0, IIM_FFT_SIZES_POW2 = 1 };
+enum { IIM_FFT_SIZES_TUNED = 0, IIM_FFT_SIZES_COMPACT = 1, IIM_FFT_SIZES_POW2 = 2 };
 
 typedef struct {
   int32_t nx, ny;         /* grid nodes per direction (>= 16) */

@@ -24,7 +24,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 GUESS_ZERO, GUESS_PREVIOUS, GUESS_EXTRAPOLATE, GUESS_NETWORK = 0, 1, 2, 3
 NET_FEATURES = 10
 SOLVER_KRYLOV, SOLVER_DIRECT = 0, 1
-FFT_SIZES_COMPACT, FFT_SIZES_POW2 = 0, 1
+FFT_SIZES_TUNED, FFT_SIZES_COMPACT, FFT_SIZES_POW2 = 0, 1, 2
 
 # every symbol declared in include/iim.h
 EXPORTS = ["iim_abi_version", "iim_surface_loads", "iim_cv_terms", "iim_rhs_given_wb", "iim_set_body_motion", "iim_rk3_steps_moving", "iim_status_string", "iim_create", "iim_destroy", "iim_last_error", "iim_query",
@@ -281,7 +281,7 @@ class Context:
 
     def __init__(self, grid, bodies, precision=PREC_FP64, tol=1e-13, max_iter=400, restart=40,
                  guess=GUESS_PREVIOUS, host_only=False, stream=None, solver=SOLVER_KRYLOV,
-                 fft_sizes=FFT_SIZES_COMPACT):
+                 fft_sizes=FFT_SIZES_TUNED):
         L = lib()
         g = GridDesc(nx=grid.nx, ny=grid.ny, x0=grid.x0, y0=grid.y0, h=grid.h, exterior=EXT[grid.exterior],
                      nu=grid.nu)
@@ -670,7 +670,7 @@ class Batch:
     """Independent simulations advanced together, one HIP graph per batch
     step (dense FP64 Schur solver in every simulation)."""
 
-    def __init__(self, workloads, stream=None, fft_sizes=FFT_SIZES_COMPACT):
+    def __init__(self, workloads, stream=None, fft_sizes=FFT_SIZES_TUNED):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream

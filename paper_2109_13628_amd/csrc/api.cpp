@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -248,6 +249,65 @@ bool build_boundary_forms(iim_ctx* c, const std::vector<double>& psibt, const st
   return true;
 }
 
+// Time of one dense free-space convolution (row pass, column pass, inverse
+// row pass over the whole grid, default tile shapes) on an mx x my torus,
+// with scratch tables and a zero source: the torus-size tuner's measure.
+// Microseconds, the median of five after two warm-up runs.
+double time_torus(iim_ctx* c, int mx, int my) {
+  const DGeom& d = c->dg;
+  const int nx = d.nx, ny = d.ny;
+  DFft f{};
+  f.mx = mx;
+  f.my = my;
+  f.hx = mx / 2;
+  f.ld = ny + 2;
+  f.outflow = d.outflow != 0;
+  f.use_reg = true;
+  if (!reg_shapes_fit(f, false, nullptr)) return std::numeric_limits<double>::infinity();
+  std::vector<void*> tmp;
+  struct Free {
+    std::vector<void*>& l;
+    ~Free() {
+      for (void* p : l) (void)hipFree(p);
+    }
+  } fr{tmp};
+  auto alloc = [&](size_t bytes) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, bytes ? bytes : 1));
+    tmp.push_back(p);
+    HIPCHK(hipMemsetAsync(p, 0, bytes ? bytes : 1, c->stream));
+    return p;
+  };
+  f.ghat = (double*)alloc(sizeof(double) * (size_t)(f.hx + 1) * (my / 2 + 1));
+  f.tw_x = (double2*)alloc(sizeof(double2) * (size_t)f.hx);
+  f.tw_xr = (double2*)alloc(sizeof(double2) * (size_t)(f.hx + 1));
+  f.tw_y = (double2*)alloc(sizeof(double2) * (size_t)my);
+  f.spec = (double2*)alloc(sizeof(double2) * (size_t)(f.hx + 1) * f.ld);
+  f.spec_out = (double2*)alloc(sizeof(double2) * (size_t)(f.hx + 1) * f.ld);
+  double* om = (double*)alloc(sizeof(double) * (size_t)nx * ny);
+  double* psi = (double*)alloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<float> ms;
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < 7 && err == hipSuccess; ++r) {
+    err = hipEventRecord(e0, c->stream);
+    launch_conv(d, f, om, nullptr, 0.0, 0, ny - 1, -1, ny, psi, nullptr, c->stream, nullptr, false, false);
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (r >= 2) ms.push_back(t);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  HIPCHK(hipGetLastError());
+  std::sort(ms.begin(), ms.end());
+  return 1e3 * ms[ms.size() / 2];
+}
+
 void setup_device(iim_ctx* c) {
   const Geometry& g = c->geo;
   const int nx = g.grid.nx, ny = g.grid.ny, nxr = nx + 2;
@@ -411,13 +471,21 @@ void setup_device(iim_ctx* c) {
     // free space: a zero-padded torus (>= 2 nx, >= 2 ny; 4 nx with the
     // outflow mirror); periodic: the grid itself
     int mx = periodic ? nx : next_pow2((outflow ? 4 : 2) * nx), my = periodic ? ny : next_pow2(2 * ny);
-    if (!periodic && c->fft_sizes == IIM_FFT_SIZES_COMPACT && c->precision == IIM_PREC_FP64) {
+    if (!periodic && c->fft_sizes != IIM_FFT_SIZES_POW2 && c->precision == IIM_PREC_FP64) {
       const int hxc = compact_len((outflow ? 2 : 1) * nx), myc = compact_len(2 * ny);
       // the register kernels take every compact length; below 256 points the
       // LDS kernels run, which take powers of two only
-      if (hxc >= 256 && myc >= 256 && hxc <= 4096 && myc <= 4096) {
-        mx = 2 * hxc;
-        my = myc;
+      if (hxc >= 256 && myc >= 256 && hxc <= 4096 && myc <= 4096 && (2 * hxc != mx || myc != my)) {
+        bool take = true;
+        if (c->fft_sizes == IIM_FFT_SIZES_TUNED) {
+          c->torus_us[0] = time_torus(c, 2 * hxc, myc);
+          c->torus_us[1] = time_torus(c, mx, my);
+          take = c->torus_us[0] < c->torus_us[1];
+        }
+        if (take) {
+          mx = 2 * hxc;
+          my = myc;
+        }
       }
     }
     if (mx / 2 > 4096 || my > 4096) throw ArgError("grid too large for the FFT plan (mx/2, my <= 4096)");
@@ -1101,7 +1169,8 @@ int iim_create(const iim_grid_desc* grid, int32_t n_bodies, const iim_body_desc*
       c->fft_sizes = opts->fft_sizes;
       c->use_graph = std::getenv("IIM_NO_GRAPH") == nullptr;
     }
-    if (c->fft_sizes != IIM_FFT_SIZES_COMPACT && c->fft_sizes != IIM_FFT_SIZES_POW2)
+    if (c->fft_sizes != IIM_FFT_SIZES_TUNED && c->fft_sizes != IIM_FFT_SIZES_COMPACT &&
+        c->fft_sizes != IIM_FFT_SIZES_POW2)
       throw ArgError("unknown FFT size policy");
     if (c->precision != IIM_PREC_FP64 && c->precision != IIM_PREC_MIXED) throw ArgError("unknown precision");
     if (c->solver != IIM_SOLVER_KRYLOV && c->solver != IIM_SOLVER_DIRECT) throw ArgError("unknown solver");

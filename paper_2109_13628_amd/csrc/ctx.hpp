@@ -64,7 +64,8 @@ struct iim_ctx {
   int precision = IIM_PREC_FP64;
   double tol = 1e-13;
   int max_iter = 400, restart = 40, guess = IIM_GUESS_PREVIOUS, chunk = 4;
-  int fft_sizes = IIM_FFT_SIZES_COMPACT;
+  int fft_sizes = IIM_FFT_SIZES_TUNED;
+  double torus_us[2] = {0.0, 0.0};   // TUNED: convolution time on the compact and the power-of-two torus
   double eps32 = 2e-6;            // mixed precision: FP32 operator error (measured ~2e-7) x 10
   long n_fp32_products = 0;       // Arnoldi products applied in FP32
   int max_refine = 8;             // mixed precision: FP64 residual evaluations per solve

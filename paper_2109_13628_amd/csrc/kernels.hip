@@ -2020,13 +2020,42 @@ __device__ __forceinline__ void fft_reg_w(CX (&v)[E], CX* lds, int t, const Tw1<
 // between passes.  FP64: base twiddles loaded up front (Tw1); FP32 (the
 // mixed-precision products, whose error budget assumes table twiddles): every
 // power from the table, one pass ahead.
-// Base twiddles up front (Tw1) for FP64 powers of two; tori with a factor 3
+// Base twiddles up front (Tw1) for FP64 powers of two.  Tori with a factor 3
 // or 5 hold 12 or 20 points per lane, too many registers to keep every
-// pass's base twiddles live as well, so they load each pass's powers from
-// the table one pass ahead like FP32.
+// pass's base twiddles live as well: they load one pass's base twiddles one
+// pass ahead (BaseTw) and form the powers by products, as Tw1 does.
 template <int N, class CX>
 constexpr bool use_tw1() {
   return std::is_same<CX, double2>::value && (N & (N - 1)) == 0;
+}
+
+template <int N, int E, int I, class CX>
+struct BaseTw {
+  using PL = Plan<N, E>;
+  static constexpr int R = PL::R[I], NS = PL::NS[I], B = E / R, T = N / E;
+  CX w[B];
+  __device__ __forceinline__ void load(int t, const CX* __restrict__ tw) {
+    if constexpr (NS > 1) {
+      constexpr int step = N / (NS * R);
+#pragma unroll
+      for (int b = 0; b < B; ++b) w[b] = tw[((t + T * b) % NS) * step];
+    }
+  }
+};
+
+template <int N, bool INV, class CX, int E, int I>
+__device__ __forceinline__ void fft_passes_b(CX (&v)[E], CX* lds, int t, const CX* __restrict__ tw,
+                                             const BaseTw<N, E, I, CX>& cur) {
+  using PL = Plan<N, E>;
+  constexpr int T = N / E;
+  if constexpr (I + 1 < PL::P) {
+    BaseTw<N, E, I + 1, CX> nxt;
+    nxt.load(t, tw);   // the next pass's base twiddles, in flight during this pass
+    reg_pass_w<N, T, E, PL::R[I], PL::NS[I], INV, false>(v, lds, t, cur.w);
+    fft_passes_b<N, INV, CX, E, I + 1>(v, lds, t, tw, nxt);
+  } else {
+    reg_pass_w<N, T, E, PL::R[I], PL::NS[I], INV, true>(v, lds, t, cur.w);
+  }
 }
 
 template <int N, bool INV, class CX, int E>
@@ -2035,6 +2064,9 @@ __device__ __forceinline__ void fft_reg(CX (&v)[E], CX* lds, int t, const CX* __
     Tw1<N, E, CX> tw1;
     tw1.load(t, tw);
     fft_reg_w<N, INV, CX, E>(v, lds, t, tw1);
+  } else if constexpr (std::is_same<CX, double2>::value) {
+    BaseTw<N, E, 0, CX> first;   // the first pass has no twiddles
+    fft_passes_b<N, INV, CX, E, 0>(v, lds, t, tw, first);
   } else {
     PlanTw<N, E, 0, CX> first;   // the first pass has no twiddles
     fft_passes<N, INV, CX, E, 0>(v, lds, t, tw, first);

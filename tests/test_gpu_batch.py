@@ -1,7 +1,7 @@
 """Batched serving: independent simulations advanced by one HIP graph per
 batch step.  Each simulation must come out exactly as it does alone (the
 batch changes the launch structure and the FFT tile shapes, not the
-arithmetic), and one of them is checked against the FP64 oracle."""
+arithmetic), and every one is checked against the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -51,15 +51,18 @@ def test_batch_equals_single_simulations_and_oracle():
         scale = np.max(np.abs(omd.cpu().numpy()))
         assert d <= 1e-14 * scale, (k, d, scale)
         assert np.max(np.abs(G1 - G_b[k])) <= 1e-14 * (np.abs(G1).max() + 1.0)
-    # the smallest one against the oracle
-    k = int(np.argmin([w.grid.nx * w.grid.ny for w in ws]))
-    geo, om, G = states[k]
-    ref = ONS.Stepper(geo)
-    om_r, G_r = np.where(geo.fluid, om, 0.0), np.array(G, dtype=np.float64)
-    for _ in range(steps):
-        om_r, G_r = ref.step(om_r, G_r, ws[k].dt)
-    e = rel(om_b[k].cpu().numpy(), om_r, mask=geo.fluid)
-    assert e < 1e-11, e
+    # every simulation against the oracle (tori of powers of two and of
+    # compact lengths with a factor 3 or 5 among them)
+    print("tori", [(t["fft_mx"], t["fft_my"]) for t in info["tuning"]])
+    for k, (w, (geo, om, G)) in enumerate(zip(ws, states)):
+        ref = ONS.Stepper(geo)
+        om_r, G_r = np.where(geo.fluid, om, 0.0), np.array(G, dtype=np.float64)
+        for _ in range(steps):
+            om_r, G_r = ref.step(om_r, G_r, w.dt)
+        e = rel(om_b[k].cpu().numpy(), om_r, mask=geo.fluid)
+        eg = np.max(np.abs(G_b[k] - G_r)) / (1.0 + np.abs(G_r).max())
+        print("simulation", k, w.grid.nx, "x", w.grid.ny, "omega", e, "Gamma", eg)
+        assert e < 1e-11 and eg < 1e-13, (k, e, eg)
     # a second call continues the same graph from the updated states
     st2 = batch.step(om_b, G_b, [w.dt for w in ws], 1)
     assert st2["steps"] == 1

@@ -60,6 +60,24 @@ def test_poisson_on_compact_torus(case):
     assert rel(out[iim.FFT_SIZES_COMPACT][0], out[iim.FFT_SIZES_POW2][0]) < 1e-13
 
 
+def test_tuned_policy_takes_one_of_the_two_tori():
+    """The default policy times a convolution on both tori at create and
+    keeps the faster; either way the operator is the same."""
+    for (nx, ny, ext), (mx, my) in CASES[:4]:
+        g = _grid(nx, ny, ext)
+        ctx = iim.Context(g, [])
+        got = (ctx.info["fft_mx"], ctx.info["fft_my"])
+        pow2 = (1 << (2 * nx - 1).bit_length(), 1 << (2 * ny - 1).bit_length())
+        print((nx, ny), "tuned", got, "compact", (mx, my), "pow2", pow2)
+        assert got in ((mx, my), pow2)
+        src = np.random.default_rng(1).standard_normal((ny, nx))
+        psi = ring_zeros(g)
+        ctx.poisson(to_dev(src), psi)
+        torch.cuda.synchronize()
+        assert rel(psi.cpu().numpy(), OP.FreeSpace(nx, ny, g.h)(src)) < 1e-13
+        ctx.close()
+
+
 def test_mixed_precision_keeps_powers_of_two():
     g = _grid(350, 170, "free")
     ctx = iim.Context(g, [], precision=iim.PREC_MIXED)
@@ -77,7 +95,7 @@ def test_step_on_compact_torus(ext, solver):
     om, G = seeded_state(w, geo, 5, body_scale=1.0)
     st = ONS.Stepper(geo)
     om_ref, G_ref = st.step(om, G, w.dt)
-    ctx = iim.Context(w.grid, w.bodies, solver=solver, tol=1e-13)
+    ctx = iim.Context(w.grid, w.bodies, solver=solver, tol=1e-13, fft_sizes=iim.FFT_SIZES_COMPACT)
     assert ctx.info["fft_my"] == 384 and ctx.info["fft_mx"] == (768 if ext == "free" else 1536)
     d = to_dev(om)
     G1, stats = ctx.rk3_steps(d, G.copy(), w.dt, 1)
