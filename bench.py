@@ -502,6 +502,12 @@ def main():
         except Exception as e:   # recorded; the other legs still run
             failed.append("krylov_paths")
             paths["krylov_error"] = repr(e)
+        if not args.no_extra_workloads:
+            try:
+                paths.update(_krylov_large(iim, wl, torch, np, args.krylov_tol))
+            except Exception as e:   # recorded; the other legs still run
+                failed.append("krylov_large")
+                paths["krylov_large_error"] = repr(e)
 
     out = {
         "metric": "RK3 step cell-updates/s at 1e-8 rel. error; FP64 plain vs mixed+learned warm-start",
@@ -636,6 +642,30 @@ def _batch_child(args):
     res = json.loads(lines[-1]) if lines else {}
     if r.returncode != 0 and "error" not in res:
         res["error"] = "exit status %d" % r.returncode
+    return res
+
+
+def _krylov_large(iim, wl, torch, np, tol, steps=3):
+    """FP64 against mixed-precision GMRES (extrapolated guess, to tol) on the
+    four-body 2048 x 2048 outflow configuration, where each product moves
+    more bytes than at the headline size: 2 warm-up and `steps` timed steps
+    from the state after 20 dense-solver steps."""
+    w = wl.multi_body(2048)
+    g = w.grid
+    spin = iim.Context(g, w.bodies, solver=iim.SOLVER_DIRECT)
+    om0 = torch.zeros((g.ny, g.nx), dtype=torch.float64, device="cuda:0")
+    G0, _ = spin.rk3_steps(om0, np.zeros(spin.n_circ), w.dt, 20)
+    torch.cuda.synchronize()
+    spin.close()
+    res = {}
+    for name, prec in (("fp64", iim.PREC_FP64), ("mixed", iim.PREC_MIXED)):
+        _say("multi_body_2048 GMRES %s" % name)
+        c_, _, _, r_, _ = _run_path(iim, w, torch, np, prec, iim.SOLVER_KRYLOV, iim.GUESS_EXTRAPOLATE, warmup=2,
+                                    steps=steps, tol=tol, per_step=True, start=(om0, G0))
+        r_["fft"] = [c_.info["fft_mx"], c_.info["fft_my"]]
+        r_["schur_unknowns"] = c_.info["n_affected"] + c_.info["n_circ"]
+        res["multi_body_2048_outflow_krylov_%s_extrapolate" % name] = r_
+        c_.close()
     return res
 
 

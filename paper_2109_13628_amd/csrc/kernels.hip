@@ -473,8 +473,36 @@ __global__ void k_ring_reflect(DGeom g, double* __restrict__ psi, const double* 
   }
 }
 
+// The same product for small boxes: one output per thread (64 columns x 4
+// rows per block), the k loop over operands that stay in L2, eight products
+// in flight.  A 128 x 128 box gives 64 blocks instead of the tiled kernel's
+// 16, and no barrier per k tile: its latency, not its bytes, set the time.
+__global__ void __launch_bounds__(256)
+k_gemm_small(int M, int N, int K, const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+             double* __restrict__ Cm, int ldc, const double* __restrict__ S, const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (r >= M || c >= N) return;
+  const double* a = A + (size_t)r * lda;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int k = 0;
+  for (; k + 8 <= K; k += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += a[k + u] * B[(size_t)(k + u) * ldb + c];
+  }
+  for (; k < K; ++k) acc[0] += a[k] * B[(size_t)k * ldb + c];
+  const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  Cm[(size_t)r * ldc + c] = S ? v * S[(size_t)r * N + c] : v;
+}
+
 static void gemm(int M, int N, int K, const double* A, int lda, bool tA, const double* B, int ldb, double* Cm,
                  int ldc, const double* S, const double* done, hipStream_t s) {
+  if (!tA && (size_t)M * N <= (size_t)512 * 512 && K <= 1024) {
+    dim3 grid((N + 63) / 64, (M + 3) / 4);
+    k_gemm_small<<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, Cm, ldc, S, done);
+    return;
+  }
   constexpr int TS = 32;
   dim3 grid((N + TS - 1) / TS, (M + TS - 1) / TS);
   k_gemm<TS><<<grid, TS * TS / 4, 0, s>>>(M, N, K, A, lda, tA, B, ldb, Cm, ldc, S, done);
