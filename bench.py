@@ -51,6 +51,9 @@ def _parse():
     p.add_argument("--command", default="", help="command line recorded in a summary")
     p.add_argument("--copy-probe", action="store_true",
                    help="end with one plain device copy of 256 MiB (scale reference for HBM byte counters)")
+    p.add_argument("--workload", choices=sorted(WORKLOADS), default="cylinder_1024x512",
+                   help="the headline workload; multi_body_2048 serves the kernel profiles at the 2048 x 2048 "
+                        "four-body configuration")
     p.add_argument("--net-only", action="store_true",
                    help="only the network's matrix-core timing (forward and training steps at the training "
                         "batch shape); for counter runs")
@@ -270,7 +273,13 @@ HIP_NAMES = {"fft_rows_fwd": "k_rows_fwd_reg", "fft_cols_conv": "k_cols_reg", "f
              "transport": "k_transport_all", "arnoldi": "k_arnoldi"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "paper_2109_13628_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_cylinder_1024x512.txt")
+# headline workloads: name -> (title of the profile summaries, generator)
+WORKLOADS = {"cylinder_1024x512": "the 1024x512 free-space cylinder workload",
+             "multi_body_2048": "the 2048x2048 four-body outflow workload"}
+
+
+def _traffic_file(workload):
+    return os.path.join(HERE, "profiles", "hbm_traffic_%s.txt" % workload)
 
 
 def _src_hash():
@@ -285,14 +294,14 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
-def _summarize_trace(trace_dir, out, command):
+def _summarize_trace(trace_dir, out, command, workload):
     """Top kernels of a --kernel-trace --stats run, and for the instrumented
     kernels the average duration per launch shape (the full-size launches of
     the RK3 steps are the largest grid)."""
     import glob
     stats = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0])
     trace = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0])
-    lines = ["# rocprofv3 kernel trace: RK3 steps of the 1024x512 free-space cylinder workload", "",
+    lines = ["# rocprofv3 kernel trace: RK3 steps of " + WORKLOADS[workload], "",
              "command: " + command, "", "kernel | calls | avg us | total ms | share %", "---|---|---|---|---"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
         name = r["Name"].split("(")[0].replace("void ", "")
@@ -314,7 +323,7 @@ def _summarize_trace(trace_dir, out, command):
         f.write("\n".join(lines) + "\n")
 
 
-def _summarize_pmc(fetch_dir, write_dir, out, command):
+def _summarize_pmc(fetch_dir, write_dir, out, command, workload):
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the full-size
     launches of every instrumented kernel, and the scale that turns each
     counter into bytes: the counter reading of one plain 256 MiB device copy
@@ -338,7 +347,7 @@ def _summarize_pmc(fetch_dir, write_dir, out, command):
             res["%s_%s_kib" % (short, tag)] = sum(v) / len(v)
             res["%s_grid" % short] = gmax
     lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE), full-size launches",
-             "# inside the RK steps of the 1024x512 free-space cylinder workload; bytes = KiB * 1024 * scale, where scale is",
+             "# inside the RK steps of " + WORKLOADS[workload] + "; bytes = KiB * 1024 * scale, where scale is",
              "# 256 MiB over the counter's reading for one plain 256 MiB device copy in the same run.", "",
              "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE").replace("pmc_w", "pmc_f"),
              "command_write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_f", "pmc_w"),
@@ -380,14 +389,15 @@ def _summarize_mfma(pmc_dir, out, command):
         f.write("\n".join(lines) + "\n")
 
 
-def _traffic(kernel):
+def _traffic(kernel, workload):
     """HBM bytes per full-size launch of `kernel` from the committed counter
-    summary, or None when it is missing or the kernel source has changed
-    since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary of the workload, or None when it is missing or the kernel source
+    has changed since the counters were taken."""
+    path = _traffic_file(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -399,16 +409,17 @@ def _traffic(kernel):
         wb = float(kv[kernel + "_write_kib"]) * 1024 * float(kv["write_scale"])
     except KeyError:
         return None
-    return {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb, "source": os.path.relpath(TRAFFIC_FILE, HERE)}
+    return {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb, "source": os.path.relpath(path, HERE)}
 
 
 def main():
     args = _parse()
     if args.summarize_trace:
-        _summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        _summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command, args.workload)
         return
     if args.summarize_pmc:
-        _summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2], args.command)
+        _summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2], args.command,
+                       args.workload)
         return
     if args.summarize_mfma:
         _summarize_mfma(args.summarize_mfma[0], args.summarize_mfma[1], args.command)
@@ -434,7 +445,7 @@ def main():
         sys.exit(3 if "error" in res else 0)
     failed = []
 
-    w = wl.cylinder()
+    w = wl.cylinder() if args.workload == "cylinder_1024x512" else wl.multi_body(2048)
     g = w.grid
     prec = iim.PREC_FP64 if args.precision == "fp64" else iim.PREC_MIXED
     solver = iim.SOLVER_KRYLOV if args.solver == "krylov" else iim.SOLVER_DIRECT
@@ -474,7 +485,7 @@ def main():
         torch.cuda.synchronize()
     ctx.profile(0)
     achieved = rep["GBps"] if rep else prof.get("GBps")
-    tr = _traffic(dominant)
+    tr = _traffic(dominant, args.workload)
     roof = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
             "frac": (achieved / 8000.0) if achieved else None,
             "traffic": tr["bytes_per_launch"] if tr else None, "traffic_detail": tr,
@@ -523,7 +534,7 @@ def main():
         "dtype": "f64" if prec == iim.PREC_FP64 else "f32+f64",
         "data": "synthetic (impulsively started flow from rest)",
         "config": {"workload": w.name, "nx": g.nx, "ny": g.ny, "h": g.h,
-                   "fft": [ctx.info["fft_mx"], ctx.info["fft_my"]], "Re": 100, "dt": w.dt,
+                   "fft": [ctx.info["fft_mx"], ctx.info["fft_my"]], "Re": (w.extra or {}).get("Re", 100), "dt": w.dt,
                    "precision": args.precision, "solver": args.solver, "krylov_tol_headline": 1e-13,
                    "fft_tiles": tiles,
                    "t_start": args.warmup * w.dt},
