@@ -454,10 +454,11 @@ int iim_net_forward(iim_net* net, const float* x_dev, int32_t batch, int32_t P, 
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  iim_net_forward grows the network's activation
  * buffers with hipMalloc when batch * P exceeds what it holds; this call
- * keeps the hidden activations in a 16 MiB device array of the library
+ * keeps the hidden activations (16 MiB) and the partial sums of split
+ * one-sample products (4 MiB) in a 20 MiB device array of the library
  * instead (one per GPU, held until the process ends) and writes the last
- * layer straight into y_dev, with the same kernels: its outputs are
- * identical.  Limit: batch * P <= 2^21 / max hidden width (16384 positions
+ * layer straight into y_dev, with the same kernels and the same splits: its
+ * outputs are identical.  Limit: batch * P <= 2^21 / max hidden width (16384 positions
  * at width 128), else IIM_EINVAL naming the limit.  Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (two streams, or
  * two threads) race and must be serialised by the caller.  IIM_EINVAL as

@@ -49,6 +49,7 @@ struct iim_net {
   std::vector<float*> Z, H;
   float *dA = nullptr, *dB = nullptr;  // [rows][max width]
   float* part = nullptr;               // weight-gradient partial sums
+  float* fwd_part = nullptr;           // split forward products' partial sums (CONV_FWD_PART_MAX floats)
   size_t part_cap = 0;
   float* dY = nullptr;                 // [rows]
   float* lossbuf = nullptr;            // [1]

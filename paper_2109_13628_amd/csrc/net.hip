@@ -19,6 +19,7 @@
 // the result layout fixes where D lands)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "net_dev.hpp"
@@ -479,9 +480,46 @@ void launch_mse(const float* Y, const float* T, size_t n, float* dY, float* loss
   k_mse<<<1, 1024, 0, st>>>(Y, T, n, dY, loss);
 }
 
+// Split count of a forward product: enough workgroups to occupy the device
+// when the output has few 64 x 64 tiles (the k chain of one workgroup, not
+// bandwidth, sets the time of a one-sample product), at least two 32-deep
+// slices per split, and the workspace within CONV_FWD_PART_MAX floats.
+int conv_fwd_splits(int rows, int cin, int cout) {
+  const int tiles = ((rows + 63) / 64) * ((cout + 63) / 64);
+  const int slices = (NET_TAPS * cin + MM_KT - 1) / MM_KT;
+  int sp = (128 + tiles - 1) / tiles;
+  sp = std::min(sp, slices / 2);
+  while (sp > 1 && (size_t)sp * rows * cout > CONV_FWD_PART_MAX) --sp;
+  if (sp < 1) sp = 1;
+  // the count the GEMM really uses (its chunks are whole slices)
+  const int K = NET_TAPS * cin;
+  const int kper = mm_kper(K, sp);
+  return (K + kper - 1) / kper;
+}
+
+// out = sum over splits of part (in split order) + bias; Z keeps it, H its GELU
+__global__ void k_reduce_fwd(const float* __restrict__ part, int splits, size_t MN, int N,
+                             const float* __restrict__ bias, float* __restrict__ Z, float* __restrict__ H, int act) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += part[z * MN + i];
+  const float zv = v + bias[i % N];
+  if (Z) Z[i] = zv;
+  H[i] = act ? gelu(zv) : zv;
+}
+
 void launch_conv_fwd(bool bf16, const Seq& s, int B, const float* X, int cin, const float* W, const float* bias,
-                     int cout, float* Z, float* H, int act, hipStream_t st) {
-  mm(bf16, B * s.P, cout, NET_TAPS * cin, 1, AConv{X, cin, s, 1}, BRow{W, cout}, EFwd{bias, Z, H, cout, act}, st);
+                     int cout, float* Z, float* H, int act, float* part, hipStream_t st) {
+  const int rows = B * s.P;
+  const int sp = bf16 && part ? conv_fwd_splits(rows, cin, cout) : 1;
+  if (sp <= 1) {
+    mm(bf16, rows, cout, NET_TAPS * cin, 1, AConv{X, cin, s, 1}, BRow{W, cout}, EFwd{bias, Z, H, cout, act}, st);
+    return;
+  }
+  const size_t MN = (size_t)rows * cout;
+  mm(bf16, rows, cout, NET_TAPS * cin, sp, AConv{X, cin, s, 1}, BRow{W, cout}, EPart{part, MN, cout}, st);
+  k_reduce_fwd<<<(unsigned)((MN + 255) / 256), 256, 0, st>>>(part, sp, MN, cout, bias, Z, H, act);
 }
 
 void launch_conv_bwd_data(bool bf16, const Seq& s, int B, const float* dZ, int cout, const float* W, int cin,

@@ -22,9 +22,15 @@ struct Seq {
   int P;
 };
 
-// forward: Z = conv(X) + bias; H = gelu(Z) (act = 1) or H = Z (act = 0)
+// forward: Z = conv(X) + bias; H = gelu(Z) (act = 1) or H = Z (act = 0).
+// Small products (few output tiles, e.g. one sample at inference) split the
+// k range over conv_fwd_splits(...) workgroups whose partial sums go to
+// `part` (conv_fwd_splits * rows * cout floats) and are added in a fixed
+// order by a second kernel; part may be null when the count is 1.
+int conv_fwd_splits(int rows, int cin, int cout);
+constexpr size_t CONV_FWD_PART_MAX = (size_t)1 << 20;   // floats: the largest split workspace used
 void launch_conv_fwd(bool bf16, const Seq& s, int B, const float* X, int cin, const float* W, const float* bias,
-                     int cout, float* Z, float* H, int act, hipStream_t st);
+                     int cout, float* Z, float* H, int act, float* part, hipStream_t st);
 // backward data: dX = conv^T(dZ); written as dX * gelu'(Zprev) when Zprev != null
 void launch_conv_bwd_data(bool bf16, const Seq& s, int B, const float* dZ, int cout, const float* W, int cin,
                           const float* Zprev, float* dXout, hipStream_t st);

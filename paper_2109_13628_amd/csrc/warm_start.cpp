@@ -29,12 +29,13 @@
 
 using namespace iim;
 
-// Activation scratch of the allocation-free forward pass
-// (iim_net_forward_noalloc): the hidden layers' outputs alternate between the
-// two halves of this file-scope array, which every GPU the library runs on
-// holds for the life of the process.
-constexpr size_t NET_SCRATCH_FLOATS = (size_t)4 << 20;   // 16 MiB
-static __device__ __align__(256) float scratch[NET_SCRATCH_FLOATS];
+// Scratch of the allocation-free forward pass (iim_net_forward_noalloc): the
+// hidden layers' outputs alternate between the two halves of the first
+// NET_SCRATCH_FLOATS floats, and the split products' partial sums use the
+// CONV_FWD_PART_MAX floats after them; every GPU the library runs on holds
+// this file-scope array for the life of the process.
+constexpr size_t NET_SCRATCH_FLOATS = (size_t)4 << 20;   // 16 MiB of activations
+static __device__ __align__(256) float scratch[NET_SCRATCH_FLOATS + CONV_FWD_PART_MAX];
 
 namespace {
 
@@ -101,6 +102,7 @@ void ensure_rows(iim_net* net, size_t rows) {
   net->dA = net_alloc<float>(net->act_allocs, cap * wmax);
   net->dB = net_alloc<float>(net->act_allocs, cap * wmax);
   net->dY = net_alloc<float>(net->act_allocs, cap);
+  net->fwd_part = net_alloc<float>(net->act_allocs, CONV_FWD_PART_MAX);
   size_t kn = 0;
   for (int l = 0; l < L; ++l) kn = std::max(kn, (size_t)NET_TAPS * net->lin[l] * net->lout[l]);
   net->part_cap = (size_t)conv_bwd_w_splits((int)std::min(cap, (size_t)1 << 30)) * kn;
@@ -233,7 +235,8 @@ void iim::net_forward(iim_net* net, const Seq& s, int B, const float* X, bool ke
   for (int l = 0; l < net->layers; ++l) {
     const bool last = l == net->layers - 1;
     launch_conv_fwd(net->bf16, s, B, in, net->lin[l], net->params + net->offW[l], net->params + net->offb[l],
-                    net->lout[l], (keep_pre && !last) ? net->Z[l] : nullptr, net->H[l], last ? 0 : 1, st);
+                    net->lout[l], (keep_pre && !last) ? net->Z[l] : nullptr, net->H[l], last ? 0 : 1, net->fwd_part,
+                    st);
     in = net->H[l];
   }
 }
@@ -429,7 +432,7 @@ int iim_net_forward_noalloc(iim_net* net, const float* x_dev, int32_t batch, int
       // hidden layers alternate between the scratch halves; the last writes y
       float* out = last ? y_dev : buf + (size_t)(l & 1) * rows * wmax;
       launch_conv_fwd(net->bf16, s, batch, in, net->lin[l], net->params + net->offW[l], net->params + net->offb[l],
-                      net->lout[l], nullptr, out, last ? 0 : 1, net->stream);
+                      net->lout[l], nullptr, out, last ? 0 : 1, buf + NET_SCRATCH_FLOATS, net->stream);
       in = out;
     }
     HIPCHK(hipGetLastError());
