@@ -103,7 +103,8 @@ enum { IIM_SOLVER_KRYLOV = 0, IIM_SOLVER_DIRECT = 1 };
  * any such torus):
  *   TUNED    (default) times one full convolution on the COMPACT torus and
  *            on the POW2 torus at create (scratch tables, zero source) and
- *            keeps the faster; the same as COMPACT when the two coincide;
+ *            keeps COMPACT only if it is at least 5 % faster; the same as
+ *            COMPACT when the two coincide;
  *   COMPACT  the smallest length with a register FFT plan: powers of two and,
  *            for FP64 contexts whose row half-length and column length are
  *            both 256 or more, 320, 384, 640, 768, 1280 and 1536 points per

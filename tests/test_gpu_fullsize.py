@@ -63,11 +63,14 @@ FLOOR = {
     "cyl512": (3.2e-13, 3.4e-13, 2.7e-13, 7.2e-13, 2.4e-17),
     "cyl1024": (1.0e-12, 1.7e-12, 8.6e-13, 4.3e-12, 0.0),
     "multi512": (4.1e-11, 3.3e-11, 1.8e-11, 6.8e-11, 3.9e-17),
+    # four nonconvex bodies, outflow, 1024 x 1024 (FFT torus 4096 x 2048);
+    # floors (1) and (3) only: the GMRES-to-1e-15 floor takes too long here
+    "multi1024": (1.3e-10, 1.4e-10, 8.0e-11, 3.8e-10, 1.2e-16),
 }
 
 
 @pytest.mark.parametrize("solver", [iim.SOLVER_DIRECT, iim.SOLVER_KRYLOV])
-@pytest.mark.parametrize("name", ["cyl512", "cyl1024", "multi512"])
+@pytest.mark.parametrize("name", ["cyl512", "cyl1024", "multi512", "multi1024"])
 def test_step_fullsize(name, solver):
     """One RK3 step from a seeded wake-like state, library against oracle:
     omega, Gamma and the library's own reconstructed velocity, each in L2

@@ -31,7 +31,9 @@ CASES = [
 @pytest.mark.parametrize("nx,ny,ext,torus", CASES)
 def test_poisson_large_torus(nx, ny, ext, torus):
     g = wl.GridDesc(nx=nx, ny=ny, x0=0.0, y0=0.0, h=1.0 / 64, exterior=ext, u_inf=(1.0, 0.0), nu=0.01)
-    ctx = iim.Context(g, [])
+    # powers of two: these cases exercise the 2048- and 4096-point plans (the
+    # default tuner may prefer a compact torus for some of these grids)
+    ctx = iim.Context(g, [], fft_sizes=iim.FFT_SIZES_POW2)
     assert (ctx.info["fft_mx"], ctx.info["fft_my"]) == torus
     src = np.random.default_rng(nx + ny).standard_normal((ny, nx))
     psi = ring_zeros(g)
@@ -50,7 +52,7 @@ def test_step_on_the_widest_torus():
     om = np.where(geo.fluid, 0.5 * wl.seeded_vortices(w.grid, 71, count=8, box=(0.5, 30.0, -1.4, 1.4)), 0.0)
     G = np.array([0.2])
     ref = Reconstructor(geo).reconstruct(om, G)
-    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT, fft_sizes=iim.FFT_SIZES_POW2)
     assert ctx.info["fft_mx"] == 8192
     psi, U, V = ring_zeros(w.grid), ring_zeros(w.grid), ring_zeros(w.grid)
     ctx.reconstruct(to_dev(om), G, psi, U, V)
