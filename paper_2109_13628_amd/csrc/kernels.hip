@@ -1048,31 +1048,45 @@ struct Vel {
     else
       return V[t];
   }
-  // any node (ii, jj); axis 0: u, 1: v.  The axis may differ between lanes:
-  // no pointer is selected by it (both arrays are read and the value
-  // selected), which keeps the pointers out of private (scratch) memory.
-  __device__ __forceinline__ double node(const TGeom& g, int axis, int ii, int jj) const {
-    const int nxr = g.nx + 2;
-    if (ii < -1 || jj < -1 || ii > g.nx || jj > g.ny) return 0.0;
-    const int t = (jj + 1) * nxr + ii + 1;
+  // component `axis` (0: u, 1: v) at ring index t of a node whose stencil
+  // value is that component's central difference (or the stored value); the
+  // axis may differ between lanes
+  __device__ __forceinline__ double comp_at(const TGeom& g, int axis, int t) const {
     if constexpr (FROM_PSI) {
-      const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
-      const bool side = (ii == -1 || ii == g.nx) && jj >= 0 && jj < g.ny;
-      const bool topbot = (jj == -1 || jj == g.ny) && ii >= 0 && ii < g.nx;
-      if (!in && (axis == 0 ? !side : !topbot)) return 0.0;
-      // psi at t +- o lies in the ring for every node that gets here
-      const int o = axis == 0 ? nxr : 1;
+      const int o = axis == 0 ? g.nx + 2 : 1;
       const double d = psi[t + o] - psi[t - o];
-      const double val = axis == 0 ? g.uinf_x + 0.5 * g.inv_h * d : g.uinf_y - 0.5 * g.inv_h * d;
-      if (!in) return val;
-      // class, difference and extension value loaded together, then selected
-      const int8_t cl = g.cls[jj * g.nx + ii];
-      const double ue = U[t], ve = V[t];
-      const double e = axis == 0 ? ue : ve;
-      return cl == 2 ? e : (cl > 2 ? 0.0 : val);
+      return axis == 0 ? g.uinf_x + 0.5 * g.inv_h * d : g.uinf_y - 0.5 * g.inv_h * d;
     } else {
       const double ue = U[t], ve = V[t];
       return axis == 0 ? ue : ve;
+    }
+  }
+  // any node (ii, jj); axis 0: u, 1: v.  Straight-line code: every address is
+  // clamped into its array and the value selected afterwards, so that the
+  // loads of all the nodes of a stencil are in flight together (branches
+  // around them put one memory round trip per branch on the critical path).
+  // No pointer is selected by the axis either, which keeps the pointers out
+  // of private (scratch) memory.
+  __device__ __forceinline__ double node(const TGeom& g, int axis, int ii, int jj) const {
+    const int nx = g.nx, ny = g.ny, nxr = nx + 2;
+    const int t = (min(max(jj, -1), ny) + 1) * nxr + min(max(ii, -1), nx) + 1;
+    const double ue = U[t], ve = V[t];
+    const double e = axis == 0 ? ue : ve;
+    if constexpr (FROM_PSI) {
+      const bool in = ii >= 0 && jj >= 0 && ii < nx && jj < ny;
+      const bool side = (ii == -1 || ii == nx) && jj >= 0 && jj < ny;
+      const bool topbot = (jj == -1 || jj == ny) && ii >= 0 && ii < nx;
+      const int o = axis == 0 ? nxr : 1;
+      const double d = psi[min(t + o, nxr * (ny + 2) - 1)] - psi[max(t - o, 0)];
+      const double val = axis == 0 ? g.uinf_x + 0.5 * g.inv_h * d : g.uinf_y - 0.5 * g.inv_h * d;
+      // in the grid: the class picks the extension (ghost), zero (solid) or val
+      const int8_t cl = g.cls[min(max(jj, 0), ny - 1) * nx + min(max(ii, 0), nx - 1)];
+      const double v_in = cl == 2 ? e : (cl > 2 ? 0.0 : val);
+      // on the ring only the component normal to the grid edge; zero beyond
+      return in ? v_in : ((axis == 0 ? side : topbot) ? val : 0.0);
+    } else {
+      const bool ring = ii >= -1 && jj >= -1 && ii <= nx && jj <= ny;
+      return ring ? e : 0.0;
     }
   }
 };
@@ -1083,37 +1097,35 @@ __device__ double flux_general(const TGeom& g, const double* __restrict__ omega,
                                const double* __restrict__ w4, const double* __restrict__ w3b,
                                const double* __restrict__ w3n, int i, int j, int axis) {
   const int di = axis == 0 ? 1 : 0, dj = axis == 0 ? 0 : 1;
+  const int nx = g.nx, ny = g.ny;
   int kind[4];
   double u[4], w[4], w4v[4], wb[4], wn[4];
+  // straight-line: every load at a clamped address, values selected afterwards
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     int ii = i + (t - 1) * di, jj = j + (t - 1) * dj;
     if (g.periodic) {   // the node a periodic edge repeats
-      ii = (ii + g.nx) % g.nx;
-      jj = (jj + g.ny) % g.ny;
+      ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+      jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
     }
-    const bool in = ii >= 0 && jj >= 0 && ii < g.nx && jj < g.ny;
-    u[t] = vel.node(g, axis, ii, jj);
-    if (!in) {
-      kind[t] = NK_OUT;
-      w[t] = w4v[t] = wb[t] = wn[t] = 0.0;
-      if (g.outflow && ii >= g.nx && ii <= g.nx + 1 && jj >= 0 && jj < g.ny) {
-        const int im = 2 * g.nx - 1 - ii;   // mirror across the outflow face
-        w[t] = w4v[t] = wb[t] = wn[t] = omega[jj * g.nx + im];
-        if (axis == 0 && ii == g.nx + 1) u[t] = vel.node(g, 0, im, jj);
-      }
-    } else {
-      const int q = jj * g.nx + ii;
-      const int c = g.cls[q];
-      const double oq = omega[q];
-      const double e4 = w4 ? w4[q] : 0.0, eb = w3b ? w3b[q] : 0.0, en = w3n ? w3n[q] : 0.0;
-      kind[t] = c < 2 ? NK_FLUID : (c == 2 ? NK_GHOST : NK_SOLID);
-      const bool fl = kind[t] == NK_FLUID, gh = kind[t] == NK_GHOST;
-      w[t] = fl ? oq : 0.0;
-      w4v[t] = fl ? oq : (gh ? e4 : 0.0);
-      wb[t] = fl ? oq : (gh ? eb : 0.0);
-      wn[t] = fl ? oq : (gh ? en : 0.0);
-    }
+    const bool in = ii >= 0 && jj >= 0 && ii < nx && jj < ny;
+    // past the outflow face, nodes nx, nx + 1 repeat the vorticity of nx - 1,
+    // nx - 2, and node nx + 1 the x-velocity of nx - 2
+    const bool mirrored = g.outflow && ii >= nx && ii <= nx + 1 && jj >= 0 && jj < ny;
+    const int iw = mirrored ? 2 * nx - 1 - ii : ii;
+    const int iu = (mirrored && axis == 0 && ii == nx + 1) ? nx - 2 : ii;
+    const int qc = min(max(jj, 0), ny - 1) * nx + min(max(iw, 0), nx - 1);
+    const int c = g.cls[qc];
+    const double oq = omega[qc];
+    const double e4 = w4 ? w4[qc] : 0.0, eb = w3b ? w3b[qc] : 0.0, en = w3n ? w3n[qc] : 0.0;
+    u[t] = vel.node(g, axis, iu, jj);
+    kind[t] = in ? (c < 2 ? NK_FLUID : (c == 2 ? NK_GHOST : NK_SOLID)) : NK_OUT;
+    const bool fl = in && c < 2, gh = in && c == 2;
+    const double base = (fl || mirrored) ? oq : 0.0;   // zero outside the grid and at solid nodes
+    w[t] = base;
+    w4v[t] = gh ? e4 : base;
+    wb[t] = gh ? eb : base;
+    wn[t] = gh ? en : base;
   }
   const bool fl0 = kind[1] == NK_FLUID || kind[1] == NK_OUT;
   const bool fl1 = kind[2] == NK_FLUID || kind[2] == NK_OUT;
@@ -1148,84 +1160,80 @@ __device__ __forceinline__ double flux_interior(const TGeom& g, const double* __
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     w[t] = omega[q + (t - 1) * dq];
-    const int rt = r + (t - 1) * dr;
-    u[t] = axis == 0 ? vel.u_at(g, rt) : vel.v_at(g, rt);
+    u[t] = vel.comp_at(g, axis, r + (t - 1) * dr);
   }
   return flux_std(u[0], u[1], u[2], u[3], w[0], w[1], w[2], w[3], g.nu * g.inv_h);
 }
 
-// Bulk nodes (cls 0): all stencil nodes are fluid and inside the grid.
-// Bulk part: one thread per node of grid row j, 256 nodes per block.
+// Bulk nodes (cls 0): every stencil node inside the grid is fluid (bodies keep
+// three cells from the grid edge, so this also holds for stencils that wrap
+// across a periodic edge).  Bulk part: one thread per node of grid row j, 256
+// nodes per block.
+//
+// Every lane takes the same straight-line path: the ten stencil positions are
+// mapped onto the grid first (periodic edges wrap, the outflow plane mirrors
+// omega and u_x), positions that carry no value (omega outside the grid, a
+// velocity outside the ring) are read at a clamped address and masked to zero,
+// and the node's class, the stencil values and the RK register are all in
+// flight together.  A lane near the grid edge thus costs one memory round
+// trip like any other, instead of a chain of dependent loads that set the
+// duration of the whole launch.
 template <bool P>
 __device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
                                                double* __restrict__ out, double* __restrict__ Q, double a, double b,
                                                double dt, int mode, int bx, int j) {
   const int i = bx * 256 + threadIdx.x;
   if (i >= g.nx) return;
-  const int q = j * g.nx + i;
   const int nx = g.nx, ny = g.ny, nxr = nx + 2;
-  const int r = (j + 1) * nxr + i + 1;
-  const double nih = g.nu * g.inv_h;
-  double fxr, fxl, fyt, fyb, wc;
-  if (i >= 2 && i < nx - 2 && j >= 2 && j < ny - 2) {
-    // interior: every stencil address is valid, so the node class is loaded
-    // together with the stencil values instead of in front of them
-    const int8_t c = g.cls[q];
-    wc = omega[q];
-    const double wxm2 = omega[q - 2], wxm1 = omega[q - 1], wxp1 = omega[q + 1], wxp2 = omega[q + 2];
-    const double uxm2 = vel.u_at(g, r - 2), uxm1 = vel.u_at(g, r - 1), uc = vel.u_at(g, r);
-    const double uxp1 = vel.u_at(g, r + 1), uxp2 = vel.u_at(g, r + 2);
-    const double wym2 = omega[q - 2 * nx], wym1 = omega[q - nx], wyp1 = omega[q + nx], wyp2 = omega[q + 2 * nx];
-    const double vym2 = vel.v_at(g, r - 2 * nxr), vym1 = vel.v_at(g, r - nxr), vc = vel.v_at(g, r);
-    const double vyp1 = vel.v_at(g, r + nxr), vyp2 = vel.v_at(g, r + 2 * nxr);
-    if (c == 1) return;   // boundary kernel
-    if (c >= 2) {         // solid: vorticity stays zero
-      out[q] = 0.0;
-      if (mode == 1) Q[q] = 0.0;
-      return;
+  const int q = j * nx + i;
+  const bool per = g.periodic != 0, mir = g.outflow != 0;
+  const int8_t c = g.cls[q];
+  const double qp = (mode == 1 && a != 0.0) ? Q[q] : 0.0;   // the first stage (a = 0) overwrites the register
+  const double wc = omega[q];
+  double wx[5], ux[5], wy[5], vy[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    // row j, column i + d - 2
+    int iw = i + d - 2, iu = iw;
+    if (per) {
+      iw = iw < 0 ? iw + nx : (iw >= nx ? iw - nx : iw);
+      iu = iw;
+    } else if (mir && iw >= nx) {   // nodes nx, nx + 1 repeat nx - 1, nx - 2
+      iu = iw == nx + 1 ? nx - 2 : iw;
+      iw = 2 * nx - 1 - iw;
     }
-    fxr = flux_std(uxm1, uc, uxp1, uxp2, wxm1, wc, wxp1, wxp2, nih);
-    fxl = flux_std(uxm2, uxm1, uc, uxp1, wxm2, wxm1, wc, wxp1, nih);
-    fyt = flux_std(vym1, vc, vyp1, vyp2, wym1, wc, wyp1, wyp2, nih);
-    fyb = flux_std(vym2, vym1, vc, vyp1, wym2, wym1, wc, wyp1, nih);
-  } else {
-    const int8_t c = g.cls[q];
-    if (c == 1) return;
-    if (c >= 2) {
-      out[q] = 0.0;
-      if (mode == 1) Q[q] = 0.0;
-      return;
-    }
-    wc = omega[q];
-    // near the grid edge: nodes outside carry omega = 0; velocities come from the ring
-    // with an outflow plane at x_{nx-1/2}, nodes nx, nx+1 mirror nx-1, nx-2 (omega and u_x even);
-    // periodic: the nodes past an edge are the nodes they repeat
-    const bool mir = g.outflow != 0, per = g.periodic != 0;
-    auto wx = [&](int ii) { return per ? (ii + nx) % nx : ii; };
-    auto wy = [&](int jj) { return per ? (jj + ny) % ny : jj; };
-    auto W = [&](int ii, int jj) {
-      ii = wx(ii);
-      jj = wy(jj);
-      if (mir && ii >= nx && ii <= nx + 1 && jj >= 0 && jj < ny) ii = 2 * nx - 1 - ii;
-      return (ii >= 0 && jj >= 0 && ii < nx && jj < ny) ? omega[jj * nx + ii] : 0.0;
-    };
-    auto UU = [&](int ii, int jj) {
-      ii = wx(ii);
-      jj = wy(jj);
-      if (mir && ii == nx + 1) ii = nx - 2;
-      return vel.node(g, 0, ii, jj);
-    };
-    auto VV = [&](int ii, int jj) { return vel.node(g, 1, wx(ii), wy(jj)); };
-    fxr = flux_std(UU(i - 1, j), UU(i, j), UU(i + 1, j), UU(i + 2, j), W(i - 1, j), wc, W(i + 1, j), W(i + 2, j), nih);
-    fxl = flux_std(UU(i - 2, j), UU(i - 1, j), UU(i, j), UU(i + 1, j), W(i - 2, j), W(i - 1, j), wc, W(i + 1, j), nih);
-    fyt = flux_std(VV(i, j - 1), VV(i, j), VV(i, j + 1), VV(i, j + 2), W(i, j - 1), wc, W(i, j + 1), W(i, j + 2), nih);
-    fyb = flux_std(VV(i, j - 2), VV(i, j - 1), VV(i, j), VV(i, j + 1), W(i, j - 2), W(i, j - 1), wc, W(i, j + 1), nih);
+    const bool wok = iw >= 0 && iw < nx, uok = iu >= -1 && iu <= nx;
+    const double wv = omega[j * nx + min(max(iw, 0), nx - 1)];
+    const double uv = vel.u_at(g, (j + 1) * nxr + min(max(iu, -1), nx) + 1);
+    wx[d] = d == 2 ? wc : (wok ? wv : 0.0);
+    ux[d] = uok ? uv : 0.0;
+    // column i, row j + d - 2
+    int jw = j + d - 2;
+    if (per) jw = jw < 0 ? jw + ny : (jw >= ny ? jw - ny : jw);
+    const bool wyok = jw >= 0 && jw < ny, vok = jw >= -1 && jw <= ny;
+    const double wyv = omega[min(max(jw, 0), ny - 1) * nx + i];
+    const double vv = vel.v_at(g, (min(max(jw, -1), ny) + 1) * nxr + i + 1);
+    wy[d] = d == 2 ? wc : (wyok ? wyv : 0.0);
+    vy[d] = vok ? vv : 0.0;
   }
-  const double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
+  const double nih = g.nu * g.inv_h;
+  const double fxr = flux_std(ux[1], ux[2], ux[3], ux[4], wx[1], wx[2], wx[3], wx[4], nih);
+  const double fxl = flux_std(ux[0], ux[1], ux[2], ux[3], wx[0], wx[1], wx[2], wx[3], nih);
+  const double fyt = flux_std(vy[1], vy[2], vy[3], vy[4], wy[1], wy[2], wy[3], wy[4], nih);
+  const double fyb = flux_std(vy[0], vy[1], vy[2], vy[3], wy[0], wy[1], wy[2], wy[3], nih);
+  double rhs = -((fxr - fxl) + (fyt - fyb)) * g.inv_h;
+  // pins the arithmetic (and so every load) above the class test: the
+  // compiler would otherwise sink the stencil loads below the wait for c
+  asm volatile("" : "+v"(rhs));
+  if (c == 1) return;   // boundary-kernel node: the lanes of the special part write it
+  if (c >= 2) {         // solid: vorticity stays zero
+    out[q] = 0.0;
+    if (mode == 1) Q[q] = 0.0;
+    return;
+  }
   if (mode == 0) {
     out[q] = rhs;
   } else {
-    const double qp = a == 0.0 ? 0.0 : Q[q];   // the first stage (a = 0) overwrites the register
     const double qn = a * qp + dt * rhs;
     Q[q] = qn;
     const double wn = wc + b * qn;
@@ -1284,11 +1292,15 @@ __device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict_
   const int nv = j1 - j0 + 1, nh = i1 - i0 + 1;
   double acc = 0.0;
   const int nf = 2 * (nv + nh);
+  // face t: right (+), left (-), top (+), bottom (-) faces in turn; the face
+  // is selected arithmetically, so that every lane runs one flux evaluation
   auto face = [&](int t) {
-    if (t < nv) return flux_interior(g, omega, vel, i1, j0 + t, 0);                 // right (+)
-    if (t < 2 * nv) return -flux_interior(g, omega, vel, i0 - 1, j0 + t - nv, 0);   // left (-)
-    if (t < 2 * nv + nh) return flux_interior(g, omega, vel, i0 + t - 2 * nv, j1, 1);  // top (+)
-    return -flux_interior(g, omega, vel, i0 + t - 2 * nv - nh, j0 - 1, 1);            // bottom (-)
+    const bool vert = t < 2 * nv, first = vert ? t < nv : t < 2 * nv + nh;
+    const int s = vert ? (first ? t : t - nv) : (first ? t - 2 * nv : t - 2 * nv - nh);
+    const int fi = vert ? (first ? i1 : i0 - 1) : i0 + s;
+    const int fj = vert ? j0 + s : (first ? j1 : j0 - 1);
+    const double f = flux_interior(g, omega, vel, fi, fj, vert ? 0 : 1);
+    return first ? f : -f;
   };
   for (int t = threadIdx.x; t < nf; t += 2 * blockDim.x) {
     const int t2 = t + blockDim.x;
