@@ -911,31 +911,41 @@ __global__ void __launch_bounds__(256) k_boundary_forms(DGeom g, DBnd b, const d
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = tid / L, l = tid % L;
   constexpr int M = (1 << 28) - 1;
+  // the row's constant and destination, requested with its entries (the
+  // launch has at least one row)
+  const int rr = min(r, b.rows - 1);
+  const double kc = b.kc[rr];
+  const int d = b.dst[rr];
   double acc = 0.0;
   if (r < b.rows) {
+    // straight-line loads: entries at clamped indices (those past the row's
+    // end repeat its last entry with weight zero), the source array chosen
+    // by a pointer select rather than a branch per array (a branch around a
+    // load waits for it inside the branch, one round trip per entry)
     const int e1 = b.ptr[r + 1];
     for (int e0 = b.ptr[r] + l; e0 < e1; e0 += 4 * L) {
       int id[4];
       double wv[4], val[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const bool ok = e0 + u * L < e1;
-        id[u] = ok ? b.idx[e0 + u * L] : -1;
-        wv[u] = ok ? b.w[e0 + u * L] : 0.0;
+        const int e = min(e0 + u * L, e1 - 1);
+        id[u] = b.idx[e];
+        wv[u] = b.w[e];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kind = id[u] >> 28, i = id[u] & M;
-        val[u] = id[u] < 0 ? 0.0 : (kind == 0 ? psi[i] : (kind == 1 ? omega[i] : x[g.na + i]));
+        const double* src = kind == 0 ? psi : (kind == 1 ? omega : x + g.na);
+        val[u] = src[i];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc += wv[u] * val[u];
+      for (int u = 0; u < 4; ++u) acc += (e0 + u * L < e1 ? wv[u] : 0.0) * val[u];
     }
   }
   for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (r >= b.rows || l != 0) return;
-  acc += b.kc[r];
-  const int d = b.dst[r], kind = d >> 28, i = d & M;
+  acc += kc;
+  const int kind = d >> 28, i = d & M;
   double* out = kind == 0 ? psi : kind == 1 ? U : kind == 2 ? V : kind == 3 ? wb : kind == 4 ? w4 : kind == 5 ? w3b : w3n;
   out[i] = acc;
 }
@@ -1515,7 +1525,7 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
                                                    const double* __restrict__ Gamma,
                                                    const double* __restrict__ Mt, int n, double* __restrict__ b,
                                                    double* __restrict__ x) {
-  extern __shared__ double bs[];   // b [n], then the entry products [nnz]
+  extern __shared__ double bs[];   // b [n], then the entry products [nnz] and a spare slot
   __shared__ double red[16];
   __shared__ double part[64][17];
   const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;   // 16 outputs, 64 slices of each sum
@@ -1534,12 +1544,15 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
   double* terms = bs + n;
   const int nnz = g.aop.nnz;
   for (int e0 = threadIdx.x; e0 < nnz; e0 += 2 * blockDim.x) {
-    const int e1 = e0 + blockDim.x;
-    const int r0 = g.aop.ridx[e0], r1 = e1 < nnz ? g.aop.ridx[e1] : 0;
-    const double w0 = g.aop.w[e0], w1 = e1 < nnz ? g.aop.w[e1] : 0.0;
-    const double p0 = psi[r0], p1 = e1 < nnz ? psi[r1] : 0.0;
+    // the second entry at a clamped index and stored unconditionally (past
+    // the end into the spare slot terms[nnz]): under a per-lane branch its
+    // loads would be issued, and waited for, after the first entry's
+    const int e1 = e0 + blockDim.x, e1c = min(e1, nnz - 1);
+    const int r0 = g.aop.ridx[e0], r1 = g.aop.ridx[e1c];
+    const double w0 = g.aop.w[e0], w1 = g.aop.w[e1c];
+    const double p0 = psi[r0], p1 = psi[r1];
     terms[e0] = w0 * p0;
-    if (e1 < nnz) terms[e1] = w1 * p1;
+    terms[min(e1, nnz)] = w1 * p1;
   }
   for (int k = 0; k < g.nbc; ++k) {
     const int i0 = g.rects[4 * k], i1 = g.rects[4 * k + 1], j0 = g.rects[4 * k + 2], j1 = g.rects[4 * k + 3];
@@ -1596,10 +1609,10 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
 
 bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
                       const double* Mt, int n, double* b, double* x, hipStream_t s) {
-  if (n != g.na + g.nbc || n + g.aop.nnz > RHS_SOLVE_MAX_LDS) return false;
+  if (n != g.na + g.nbc || n + g.aop.nnz + 1 > RHS_SOLVE_MAX_LDS) return false;
   if (n == 0) return true;
-  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)(n + g.aop.nnz) * sizeof(double), s>>>(g, psi_ring, omega, Gamma, Mt,
-                                                                                   n, b, x);
+  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)(n + g.aop.nnz + 1) * sizeof(double), s>>>(g, psi_ring, omega, Gamma,
+                                                                                       Mt, n, b, x);
   return true;
 }
 
@@ -2321,8 +2334,13 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
   __shared__ CX lds[C::PER][C::LDSN];
   if (done && done[KS_DONE] != 0.0) return;
   const int lb = xcd_block();
+  const int w = threadIdx.x / T, t = threadIdx.x % T;
+  CX twk[E];                 // split twiddles of this thread's bins
+  Tw1<HX, E, CX> tw1;        // the FFT's base twiddles (FP64 powers of two)
   {
-    // all loads of this thread in flight before the LDS stores
+    // all loads of this thread in flight before the LDS stores: the
+    // spectrum, then the twiddles (which would otherwise be requested after
+    // the barrier, one more round trip)
     constexpr int IT = ((HX + 1) * C::PER + C::THREADS - 1) / C::THREADS;
     CX tmp[IT];
 #pragma unroll
@@ -2334,13 +2352,15 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
                                                              : mkc<CX>(0, 0);
     }
 #pragma unroll
+    for (int m = 0; m < E; ++m) twk[m] = conj2(ft.tw_xr[t + T * m]);
+    if constexpr (use_tw1<HX, CX>()) tw1.load(t, ft.tw_x);
+#pragma unroll
     for (int q = 0; q < IT; ++q) {
       const int idx = threadIdx.x + q * C::THREADS;
       if (idx < (HX + 1) * C::PER) lds[idx % C::PER][padi(idx / C::PER)] = tmp[q];
     }
   }
   __syncthreads();
-  const int w = threadIdx.x / T, t = threadIdx.x % T;
   CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -2348,11 +2368,14 @@ k_rows_inv_reg(DGeom g, DFft f, int j0, int count, double* __restrict__ psi, con
     const CX xk = lds[w][padi(k)];
     const CX xc = conj2(lds[w][padi(HX - k)]);
     const CX Ev = cadd(xk, xc);
-    const CX Ov = cmul(csub(xk, xc), conj2(ft.tw_xr[k]));
+    const CX Ov = cmul(csub(xk, xc), twk[m]);
     v[m] = mkc<CX>(Ev.x - Ov.y, Ev.y + Ov.x);
   }
   __syncthreads();
-  fft_reg<HX, true>(v, lds[w], t, ft.tw_x);
+  if constexpr (use_tw1<HX, CX>())
+    fft_reg_w<HX, true>(v, lds[w], t, tw1);
+  else
+    fft_reg<HX, true>(v, lds[w], t, ft.tw_x);
   const int jo = j0 + lb * C::PER + w;
   if (jo >= j0 + count) return;
   const int nxr = g.nx + 2;
