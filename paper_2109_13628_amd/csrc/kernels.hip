@@ -2180,27 +2180,31 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
     for (int c0 = eb; c0 < ee; c0 += C::LDSN) {
       const int c1 = min(ee, c0 + C::LDSN);
       for (int e0 = c0 + t; e0 < c1; e0 += 4 * T) {
-        int ii[4];
-        double val[4];
+        // every load unconditional, at a clamped index (lanes past c1 repeat
+        // entry c1 - 1 and write nothing): a load under a per-lane branch,
+        // or feeding a per-lane select, is waited for inside a branch, one
+        // round trip per entry
         int2 ia[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) ia[u] = e0 + u * T < c1 ? g.row_ia[e0 + u * T] : make_int2(0, -1);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ii[u] = ia[u].x;
-          val[u] = ia[u].y >= 0 ? sgn * gam[ia[u].y] : 0.0;
-        }
+        for (int u = 0; u < 4; ++u) ia[u] = g.row_ia[min(e0 + u * T, c1 - 1)];
+        // twiddles and circulation values of the entries, all in flight
+        // together; the mirror source's twiddle (outflow) is loaded on every
+        // torus and weighted by 0 or 1, for the same reason
         CX w1[4], w2[4];
+        double gv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          w1[u] = twiddle_r(ft.tw_xr, torus_mod(kx * ii[u], mx), mx);
-          w2[u] = f.outflow ? twiddle_r(ft.tw_xr, torus_mod(kx * (2 * g.nx - 1 - ii[u]), mx), mx) : mkc<CX>(0, 0);
+          const int ii = ia[u].x;
+          w1[u] = twiddle_r(ft.tw_xr, torus_mod(kx * ii, mx), mx);
+          w2[u] = twiddle_r(ft.tw_xr, torus_mod(kx * (2 * g.nx - 1 - ii), mx), mx);
+          gv[u] = gam[ia[u].y];
         }
+        const S mir = f.outflow ? (S)1 : (S)0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (e0 + u * T >= c1) break;
-          const S vv = (S)val[u];
-          lds[w][e0 + u * T - c0] = mkc<CX>(vv * (w1[u].x + w2[u].x), vv * (w1[u].y + w2[u].y));
+          const S vv = (S)(sgn * gv[u]);
+          lds[w][e0 + u * T - c0] = mkc<CX>(vv * (w1[u].x + mir * w2[u].x), vv * (w1[u].y + mir * w2[u].y));
         }
       }
       __syncthreads();
