@@ -1020,6 +1020,7 @@ enum { NK_FLUID = 0, NK_GHOST = 1, NK_SOLID = 2, NK_OUT = 3 };
 // this large kernel (they spilled to scratch memory).
 struct TGeom {
   int nx, ny, nsp, nbc, outflow, periodic;
+  int vec;                     // bulk pairs may use 16-byte loads (nx even, arrays aligned, psi given)
   double h, inv_h, nu, uinf_x, uinf_y;
   const int8_t* __restrict__ cls;
   const int* __restrict__ special;
@@ -1043,18 +1044,26 @@ struct Vel {
   const double* __restrict__ psi;
   const double* __restrict__ U;
   const double* __restrict__ V;
+  // central differences of psi: u from the nodes above (pp) and below (pm),
+  // v from the nodes right (pp) and left (pm)
+  __device__ static __forceinline__ double u_of(const TGeom& g, double pp, double pm) {
+    return g.uinf_x + 0.5 * g.inv_h * (pp - pm);
+  }
+  __device__ static __forceinline__ double v_of(const TGeom& g, double pp, double pm) {
+    return g.uinf_y - 0.5 * g.inv_h * (pp - pm);
+  }
   // ring index t of a fluid node (or of a ring node with that component)
   __device__ __forceinline__ double u_at(const TGeom& g, int t) const {
     if constexpr (FROM_PSI) {
       const int nxr = g.nx + 2;
-      return g.uinf_x + 0.5 * g.inv_h * (psi[t + nxr] - psi[t - nxr]);
+      return u_of(g, psi[t + nxr], psi[t - nxr]);
     } else {
       return U[t];
     }
   }
   __device__ __forceinline__ double v_at(const TGeom& g, int t) const {
     if constexpr (FROM_PSI)
-      return g.uinf_y - 0.5 * g.inv_h * (psi[t + 1] - psi[t - 1]);
+      return v_of(g, psi[t + 1], psi[t - 1]);
     else
       return V[t];
   }
@@ -1177,10 +1186,10 @@ __device__ __forceinline__ double flux_interior(const TGeom& g, const double* __
 
 // Bulk nodes (cls 0): every stencil node inside the grid is fluid (bodies keep
 // three cells from the grid edge, so this also holds for stencils that wrap
-// across a periodic edge).  Bulk part: one thread per node of grid row j, 256
-// nodes per block.
+// across a periodic edge).  Bulk part: one thread per pair of nodes of grid
+// row j, 512 nodes per block.
 //
-// Every lane takes the same straight-line path: the ten stencil positions are
+// One node, any position.  Every lane takes the same straight-line path: the ten stencil positions are
 // mapped onto the grid first (periodic edges wrap, the outflow plane mirrors
 // omega and u_x), positions that carry no value (omega outside the grid, a
 // velocity outside the ring) are read at a clamped address and masked to zero,
@@ -1189,10 +1198,9 @@ __device__ __forceinline__ double flux_interior(const TGeom& g, const double* __
 // trip like any other, instead of a chain of dependent loads that set the
 // duration of the whole launch.
 template <bool P>
-__device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
-                                               double* __restrict__ out, double* __restrict__ Q, double a, double b,
-                                               double dt, int mode, int bx, int j) {
-  const int i = bx * 256 + threadIdx.x;
+__device__ __forceinline__ void bulk_cell(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                          double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                          double dt, int mode, int i, int j) {
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nxr = nx + 2;
   const int q = j * nx + i;
@@ -1250,6 +1258,113 @@ __device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __r
     out[q] = wn;
     mark_nonfinite(g, wn);
   }
+}
+
+// The RK update (or the right-hand side) of one bulk-part node from its
+// class: boundary-kernel nodes are left to the lanes of the special part,
+// solid nodes keep zero vorticity.
+__device__ __forceinline__ void bulk_store(const TGeom& g, double* __restrict__ out, double* __restrict__ Q, int8_t c,
+                                           int q, double rhs, double wc, double qp, double a, double b, double dt,
+                                           int mode) {
+  if (c == 1) return;
+  if (c >= 2) {
+    out[q] = 0.0;
+    if (mode == 1) Q[q] = 0.0;
+    return;
+  }
+  if (mode == 0) {
+    out[q] = rhs;
+  } else {
+    const double qn = a * qp + dt * rhs;
+    Q[q] = qn;
+    const double wn = wc + b * qn;
+    out[q] = wn;
+    mark_nonfinite(g, wn);
+  }
+}
+
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+
+// Two interior nodes i0, i0 + 1 (i0 even, every stencil position inside the
+// grid, nx even, arrays 16-byte aligned) with 16-byte loads: the bulk part
+// is bound by the number of load instructions (its bytes come from L2), and
+// a pair needs 27 loads instead of 62.  The face between the two nodes is
+// evaluated once.  Each node takes the formulas of bulk_cell (the results
+// agree to rounding: the compiler may fuse other multiply-adds).
+template <bool P>
+__device__ __forceinline__ void bulk_pair(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                          double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                          double dt, int mode, int i0, int j) {
+  const int nx = g.nx, nxr = nx + 2;
+  const double* __restrict__ psi = vel.psi;
+  const int q = j * nx + i0;                 // even
+  const int r = (j + 1) * nxr + i0 + 1;      // ring index of node i0 (odd)
+  const unsigned short cc = *reinterpret_cast<const unsigned short*>(g.cls + q);
+  const double2 qp = (mode == 1 && a != 0.0) ? ld2(Q + q) : make_double2(0.0, 0.0);
+  // row j: omega and u at nodes i0 - 2 + m, m = 0 .. 5 (u from ring rows j + 2
+  // and j, ring indices r - 3 + k, k = 0 .. 7)
+  double wx[6], up[8], dn[8];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double2 w2 = ld2(omega + q - 2 + 2 * k);
+    wx[2 * k] = w2.x;
+    wx[2 * k + 1] = w2.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 u2 = ld2(psi + r + nxr - 3 + 2 * k), d2 = ld2(psi + r - nxr - 3 + 2 * k);
+    up[2 * k] = u2.x;
+    up[2 * k + 1] = u2.y;
+    dn[2 * k] = d2.x;
+    dn[2 * k + 1] = d2.y;
+  }
+  double ux[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) ux[m] = Vel<P>::u_of(g, up[m + 1], dn[m + 1]);
+  // columns i0, i0 + 1: omega and v at rows j - 2 + d, d = 0 .. 4 (v from ring
+  // columns i0 .. i0 + 3 of ring row j - 1 + d)
+  double wya[5], wyb[5], vya[5], vyb[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    const double2 w2 = d == 2 ? make_double2(wx[2], wx[3]) : ld2(omega + q + (d - 2) * nx);
+    wya[d] = w2.x;
+    wyb[d] = w2.y;
+    const int rr = (j - 1 + d) * nxr + i0;   // ring column i0 of ring row j - 1 + d
+    const double2 p0 = ld2(psi + rr), p1 = ld2(psi + rr + 2);
+    vya[d] = Vel<P>::v_of(g, p1.x, p0.x);
+    vyb[d] = Vel<P>::v_of(g, p1.y, p0.y);
+  }
+  const double nih = g.nu * g.inv_h;
+  const double fmid = flux_std(ux[1], ux[2], ux[3], ux[4], wx[1], wx[2], wx[3], wx[4], nih);   // face i0 + 1/2
+  const double fxla = flux_std(ux[0], ux[1], ux[2], ux[3], wx[0], wx[1], wx[2], wx[3], nih);
+  const double fxrb = flux_std(ux[2], ux[3], ux[4], ux[5], wx[2], wx[3], wx[4], wx[5], nih);
+  const double fyta = flux_std(vya[1], vya[2], vya[3], vya[4], wya[1], wya[2], wya[3], wya[4], nih);
+  const double fyba = flux_std(vya[0], vya[1], vya[2], vya[3], wya[0], wya[1], wya[2], wya[3], nih);
+  const double fytb = flux_std(vyb[1], vyb[2], vyb[3], vyb[4], wyb[1], wyb[2], wyb[3], wyb[4], nih);
+  const double fybb = flux_std(vyb[0], vyb[1], vyb[2], vyb[3], wyb[0], wyb[1], wyb[2], wyb[3], nih);
+  double rha = -((fmid - fxla) + (fyta - fyba)) * g.inv_h;
+  double rhb = -((fxrb - fmid) + (fytb - fybb)) * g.inv_h;
+  // keeps every load above the class tests (see bulk_cell)
+  asm volatile("" : "+v"(rha), "+v"(rhb));
+  const int8_t ca = (int8_t)(cc & 0xff), cb = (int8_t)(cc >> 8);
+  bulk_store(g, out, Q, ca, q, rha, wx[2], qp.x, a, b, dt, mode);
+  bulk_store(g, out, Q, cb, q + 1, rhb, wx[3], qp.y, a, b, dt, mode);
+}
+
+template <bool P>
+__device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                               double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                               double dt, int mode, int bx, int j) {
+  const int i0 = 2 * (bx * 256 + threadIdx.x);
+  if (i0 >= g.nx) return;
+  if constexpr (P) {
+    if (g.vec && i0 >= 2 && i0 + 4 <= g.nx && j >= 2 && j + 2 < g.ny) {
+      bulk_pair(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
+      return;
+    }
+  }
+  bulk_cell(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
+  bulk_cell(g, omega, vel, out, Q, a, b, dt, mode, i0 + 1, j);
 }
 
 // One group of 4 lanes per boundary-kernel node: lane f computes the flux on
@@ -1356,7 +1471,7 @@ __global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __
                                                        double b, double dt, int mode) {
   __shared__ double red[16];
   const Vel<P> vel{psi, U, V};
-  const int nbx = (g.nx + 255) / 256, nb_sp = (4 * g.nsp + 255) / 256;
+  const int nbx = (g.nx + 511) / 512, nb_sp = (4 * g.nsp + 255) / 256;
   int blk = blockIdx.x;
   if (blk < g.nbc) {
     kelvin(g, omega, vel, dG, Gamma, QG, a, b, dt, mode, blk, red);
@@ -1381,9 +1496,13 @@ void launch_transport_all(const DGeom& g, const double* omega, const double* psi
                           double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
                           Prof* prof) {
   // leading blocks padded to a multiple of 8; eight bands of bulk tiles
-  const int nb = ((g.nx + 255) / 256) * g.ny;
+  // (512 nodes each)
+  const int nb = ((g.nx + 511) / 512) * g.ny;
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const int vec = psi && g.nx % 2 == 0 && al16(omega) && al16(psi) && al16(out) && al16(Q) &&
+                  ((uintptr_t)g.cls & 1) == 0;
   const int blocks = ((g.nbc + (4 * g.nsp + 255) / 256 + 7) & ~7) + 8 * ((nb + 7) / 8);
-  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
+  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, vec, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
                  g.special, g.rects, g.nonfinite};
   if (psi) {
     // algorithmic bytes per cell: omega, psi, Q read; out, Q written
