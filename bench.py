@@ -346,11 +346,13 @@ def _summarize_pmc(fetch_dir, write_dir, out, command, workload):
             v = [float(r["Counter_Value"]) for r in ks if int(r["Grid_Size"]) == gmax]
             res["%s_%s_kib" % (short, tag)] = sum(v) / len(v)
             res["%s_grid" % short] = gmax
+    # the two runs differ in the counter and in the output folder
+    fname, wname = os.path.basename(fetch_dir.rstrip("/")), os.path.basename(write_dir.rstrip("/"))
     lines = ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE), full-size launches",
              "# inside the RK steps of " + WORKLOADS[workload] + "; bytes = KiB * 1024 * scale, where scale is",
              "# 256 MiB over the counter's reading for one plain 256 MiB device copy in the same run.", "",
-             "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE").replace("pmc_w", "pmc_f"),
-             "command_write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_f", "pmc_w"),
+             "command_fetch: " + command.replace("WRITE_SIZE", "FETCH_SIZE").replace(wname, fname),
+             "command_write: " + command.replace("FETCH_SIZE", "WRITE_SIZE").replace(fname, wname),
              "kernel_source_sha256_16: " + _src_hash()]
     for k in sorted(res):
         lines.append("%s: %s" % (k, res[k]))

@@ -22,6 +22,8 @@ SMALL = {
     "cyl_small": wl.cylinder_small,
     "two_c_128": lambda: wl.two_c_shapes_lamb_oseen(128),
     "cyl_outflow": wl.cylinder_outflow_small,
+    # odd nx and ny: the transport's bulk part takes its per-node path everywhere
+    "cyl_odd": lambda: wl.cylinder(nx=127, ny=97, h=1.0 / 32, points=128, dt=0.005, steps=5, center=(1.5, 0.011)),
 }
 
 
@@ -83,7 +85,7 @@ def test_rhs(name):
 
 
 @pytest.mark.parametrize("solver", [iim.SOLVER_KRYLOV, iim.SOLVER_DIRECT])
-@pytest.mark.parametrize("name", ["tc128", "cyl_small", "two_c_128", "cyl_outflow"])
+@pytest.mark.parametrize("name", ["tc128", "cyl_small", "two_c_128", "cyl_outflow", "cyl_odd"])
 def test_rk3_step(name, solver):
     w = SMALL[name]()
     geo = OG.Geometry(w.grid, w.bodies)
