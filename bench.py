@@ -133,21 +133,23 @@ def _run_path(iim, w, torch, np, precision, solver, guess, warmup, steps, profil
     return ctx, omega, Gamma, res, pre
 
 
-# Re of the recorded runs (the held-out run is the workload's own Re 100);
-# the middle one is the validation run
+# Reynolds numbers of the recorded runs, in hundredths of the workload's own
+# (the held-out evaluation run is the workload itself, 100); the middle one is
+# the validation run
 TRAIN_RE = (60, 80, 120, 150, 200, 250, 300)
 
 
 def _train_network(iim, w, torch, np, runs, steps, iters):
     """The learned guess's data and training: `runs` runs shaped like the
-    workload (same grid and body) at the Reynolds numbers of TRAIN_RE, each
-    with the cylinder centre moved by a seeded sub-cell offset, impulsively
-    started and advanced `steps` steps with the dense solver while every
-    stage solve is recorded; one run (the middle Re) is held out for
-    validation, the others train one network (on the GPU, the library's own
-    kernels) in chunks, keeping the parameters with the lowest validation
-    loss.  The workload's own run (Re 100, centred body) is never seen."""
-    import workloads as wl
+    workload (same grid, its bodies moved by a seeded sub-cell offset) at
+    Reynolds numbers re / 100 times the workload's, re from TRAIN_RE (the
+    viscosity scaled), impulsively started and advanced `steps` steps with
+    the dense solver while every stage solve is recorded; one run (the middle
+    re) is held out for validation, the others train one network (on the
+    GPU, the library's own kernels) in chunks, keeping the parameters with the
+    lowest validation loss.  The workload's own run (re 100, bodies in place)
+    is never seen."""
+    import dataclasses
     res = list(TRAIN_RE[:max(2, min(runs, len(TRAIN_RE)))])
     val_re = res[len(res) // 2]
     rng = np.random.default_rng(11)
@@ -156,11 +158,13 @@ def _train_network(iim, w, torch, np, runs, steps, iters):
     t0 = time.perf_counter()
     for re in res:
         dx, dy = (rng.uniform(-0.5, 0.5, 2) * g0.h).tolist()
-        wr = wl.cylinder(nx=g0.nx, ny=g0.ny, h=g0.h, nu=1.0 / re, dt=w.dt, center=(2.0 + dx, dy))
-        c = iim.Context(wr.grid, wr.bodies, solver=iim.SOLVER_DIRECT)
+        bodies = [dataclasses.replace(b, points=b.points + np.array([dx, dy]),
+                                      center=(b.center[0] + dx, b.center[1] + dy)) for b in w.bodies]
+        grid = dataclasses.replace(g0, nu=g0.nu * 100.0 / re)
+        c = iim.Context(grid, bodies, solver=iim.SOLVER_DIRECT)
         c.record_solves(3 * steps)
-        om = torch.zeros((wr.grid.ny, wr.grid.nx), dtype=torch.float64, device="cuda:0")
-        c.rk3_steps(om, np.zeros(c.n_circ), wr.dt, steps)
+        om = torch.zeros((grid.ny, grid.nx), dtype=torch.float64, device="cuda:0")
+        c.rk3_steps(om, np.zeros(c.n_circ), w.dt, steps)
         ctxs[re], offsets[re] = c, (dx, dy)
     torch.cuda.synchronize()
     t_rec = time.perf_counter() - t0
@@ -184,10 +188,11 @@ def _train_network(iim, w, torch, np, runs, steps, iters):
     t_train = time.perf_counter() - t0
     losses = np.concatenate(train_loss)
     recorded = {re: ctxs[re].warm_start_stats()["recorded"] for re in res}
-    info = {"protocol": "runs shaped like the workload at Re %s (sub-cell seeded centre offsets), %d steps each "
-                        "from rest with every stage solve recorded; %d runs train, the Re %d run validates "
-                        "(the parameters with the lowest validation loss are kept); evaluated on the workload's "
-                        "own Re 100 run, never seen in training" % (list(res), steps, len(train), val_re),
+    info = {"protocol": "runs shaped like the workload (its bodies moved by seeded sub-cell offsets) at re/100 "
+                        "times its Reynolds number, re in %s, %d steps each from rest with every stage solve "
+                        "recorded; %d runs train, the re %d run validates (the parameters with the lowest "
+                        "validation loss are kept); evaluated on the workload's own run (re 100), never seen in "
+                        "training" % (list(res), steps, len(train), val_re),
             "recorded_solves": recorded, "train_re": [r for r in res if r != val_re], "validation_re": val_re,
             "centre_offsets": {r: offsets[r] for r in res}, "record_s": t_rec, "train_s": t_train,
             "adam_steps": iters, "batch": 64, "validation_samples": nval,
