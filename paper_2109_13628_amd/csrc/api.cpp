@@ -626,6 +626,7 @@ void build_direct(iim_ctx* c) {
   const int n = c->dk.n;
   if (n == 0) return;
   c->Sinv_t = c->dalloc<double>((size_t)n * n);
+  c->gemv_part = c->dalloc<double>((size_t)gemv_t_parts(n) * n);
   build_schur_t(c, c->Sinv_t);
   // the buffer holds S^T; its inverse is (S^-1)^T
   int* perm = c->dalloc<int>(n);
@@ -655,7 +656,7 @@ int reconstruct_stage(iim_ctx* c, const double* omega, const double* Gamma_dev, 
   if (c->solver == IIM_SOLVER_DIRECT) {
     if (!launch_rhs_solve(dg, c->psi, omega, Gamma_dev, c->Sinv_t, k.n, k.b, k.x, c->stream)) {
       launch_rhs_vector(dg, c->psi, omega, Gamma_dev, k.b, c->stream);
-      launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->stream);
+      launch_gemv_t(c->Sinv_t, k.n, k.b, k.x, c->gemv_part, c->stream);
     }
     iters = 0;
     res0 = res = 0.0;

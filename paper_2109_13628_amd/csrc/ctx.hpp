@@ -114,6 +114,7 @@ struct iim_ctx {
   bool have_prev = false;
   int solver = IIM_SOLVER_KRYLOV;
   double* Sinv_t = nullptr;       // transpose of the dense Schur inverse (row-major)
+  double* gemv_part = nullptr;    // partial sums of the solve's product (gemv_t_parts(n) x n)
   // one RK3 step captured as a HIP graph (direct solver): replayed while the
   // omega buffer and dt stay the same
   hipStream_t gstream = nullptr;

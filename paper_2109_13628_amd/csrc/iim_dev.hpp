@@ -301,7 +301,9 @@ void launch_fill(double* p, double v, size_t n, hipStream_t s);
 void launch_fill_int(int* p, int v, size_t n, hipStream_t s);
 // dense Schur complement: in-place Gauss-Jordan inverse, transposed GEMV, unit vector
 void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, hipStream_t s);
-void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s);
+// x = Mt^T b (Mt row-major n x n); `part` holds gemv_t_parts(n) x n doubles
+int gemv_t_parts(int n);
+void launch_gemv_t(const double* Mt, int n, const double* b, double* x, double* part, hipStream_t s);
 // b (right-hand side, as launch_rhs_vector) and x = Mt^T b in one launch; b is
 // stored too.  Returns false, launching nothing, when n differs from
 // na + nbc or exceeds the kernel's LDS capacity.

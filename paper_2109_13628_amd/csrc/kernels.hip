@@ -1600,35 +1600,59 @@ void launch_gj_invert(double* M, int n, int* perm, double* fcol, double* info, h
 }
 
 // x[p] = sum_q Mt[q][p] b[q]   (Mt = transpose of the inverse, row-major)
-__global__ void __launch_bounds__(256) k_gemv_t(const double* __restrict__ Mt, int n, const double* __restrict__ b,
-                                                double* __restrict__ x) {
-  // 16 outputs per block, 16 slices of the sum per output, reduced through LDS
-  __shared__ double part[16][17];
-  const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;
-  const int p = blockIdx.x * 16 + lo;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (p < n) {
-    int q = sl;
-    for (; q + 48 < n; q += 64) {
-      a0 += Mt[(size_t)q * n + p] * b[q];
-      a1 += Mt[(size_t)(q + 16) * n + p] * b[q + 16];
-      a2 += Mt[(size_t)(q + 32) * n + p] * b[q + 32];
-      a3 += Mt[(size_t)(q + 48) * n + p] * b[q + 48];
-    }
-    for (; q < n; q += 16) a0 += Mt[(size_t)q * n + p] * b[q];
-  }
-  part[sl][lo] = (a0 + a1) + (a2 + a3);
-  __syncthreads();
-  if (sl == 0 && p < n) {
-    double t = 0.0;
+// x = Mt^T b for a dense n x n row-major Mt (the transposed Schur inverse):
+// a bandwidth-bound product of n^2 doubles.  The rows of Mt are split into
+// segments of GEMV_ROWS: block (tile, segment) gives each of its 256 lanes one
+// output p of the tile and sums its segment's rows in order, sixteen loads in
+// flight at a time (coalesced along p); a second launch adds the segments'
+// partial sums of each output in segment order (deterministic).  Enough
+// blocks to fill the chip even for n of a few thousand.
+constexpr int GEMV_ROWS = 64;
+int gemv_t_parts(int n) { return (n + GEMV_ROWS - 1) / GEMV_ROWS; }
+
+__global__ void __launch_bounds__(256) k_gemv_t_part(const double* __restrict__ Mt, int n,
+                                                     const double* __restrict__ b, double* __restrict__ part) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int q0 = blockIdx.y * GEMV_ROWS, q1 = min(q0 + GEMV_ROWS, n);
+  if (p >= n) return;
+  double acc = 0.0;
+  int q = q0;
+  for (; q + 16 <= q1; q += 16) {
+    double m[16], bb[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) t += part[k][lo];
-    x[p] = t;
+    for (int u = 0; u < 16; ++u) {
+      m[u] = Mt[(size_t)(q + u) * n + p];
+      bb[u] = b[q + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += m[u] * bb[u];
   }
+  for (; q < q1; ++q) acc += Mt[(size_t)q * n + p] * b[q];
+  part[(size_t)blockIdx.y * n + p] = acc;
 }
 
-void launch_gemv_t(const double* Mt, int n, const double* b, double* x, hipStream_t s) {
-  if (n > 0) k_gemv_t<<<(n + 15) / 16, 256, 0, s>>>(Mt, n, b, x);
+__global__ void __launch_bounds__(256) k_gemv_t_sum(const double* __restrict__ part, int parts, int n,
+                                                    double* __restrict__ x) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  double t = 0.0;
+  int s = 0;
+  for (; s + 8 <= parts; s += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(s + u) * n + p];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += v[u];
+  }
+  for (; s < parts; ++s) t += part[(size_t)s * n + p];
+  x[p] = t;
+}
+
+void launch_gemv_t(const double* Mt, int n, const double* b, double* x, double* part, hipStream_t s) {
+  if (n <= 0) return;
+  const int tiles = (n + 255) / 256, parts = gemv_t_parts(n);
+  k_gemv_t_part<<<dim3(tiles, parts), 256, 0, s>>>(Mt, n, b, part);
+  k_gemv_t_sum<<<tiles, 256, 0, s>>>(part, parts, n, x);
 }
 
 // Right-hand side and direct solve in one launch: every block builds all of b
