@@ -369,6 +369,17 @@ void setup_device(iim_ctx* c) {
     }
   }
   d.row_ptr = c->upload(rp);
+  {
+    std::vector<int> rows, slot(ny, -1);
+    for (int j = 0; j < ny; ++j)
+      if (rp[j + 1] > rp[j]) {
+        slot[j] = (int)rows.size();
+        rows.push_back(j);
+      }
+    d.n_corr_rows = (int)rows.size();
+    d.corr_rows = c->upload(rows);
+    d.row_slot = c->upload(slot);
+  }
   d.row_i = c->upload(ri);
   d.row_a = c->upload(ra);
   {
@@ -514,6 +525,10 @@ void setup_device(iim_ctx* c) {
     f.tw_y = c->upload(twid(my, my));
     f.spec = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
     f.spec_out = c->dalloc<double2>((size_t)(f.hx + 1) * f.ld);
+    // many affected points: their row transforms come from a pre-pass (one
+    // value per row and column) instead of each column summing all of them
+    if (d.na > CORR_PREPASS_MIN && conv_reg_supported(f.hx, f.my))
+      f.corr = c->dalloc<double2>((size_t)d.n_corr_rows * (f.hx + 1));
     if (c->precision == IIM_PREC_MIXED && conv_reg_supported(f.hx, f.my)) {
       // FP32 tables for the inner matrix-vector products
       auto to32 = [](const std::vector<double2>& t) {

@@ -47,6 +47,9 @@ struct DGeom {
   const int* row_a;            //   affected index
   const int2* row_ia;          //   (column i, affected index) packed, same order
   int a_j0, a_j1;              // first and last grid row holding affected points (a_j0 > a_j1: none)
+  const int* corr_rows;        // the grid rows holding affected points, ascending [n_corr_rows]
+  const int* row_slot;         // per grid row: its index in corr_rows, or -1 [ny]
+  int n_corr_rows;
   const int* special;          // boundary-kernel fluid nodes (grid index)
   const int* c_col;            // control point -> circulation column (-1: none)
   const double* c_psibt;       // psi_b - psi_inf at control points
@@ -101,6 +104,10 @@ struct DFft {
   const float2* tw_y32 = nullptr;
   float2* spec32 = nullptr;
   float2* spec32_out = nullptr;
+  // row transforms of the correction sources, [mx/2+1][n_corr_rows] (complex
+  // of the pass's precision), formed by a pre-pass when there are many
+  // affected points (null: the column pass forms them itself)
+  void* corr = nullptr;
   bool outflow;
   bool periodic = false;       // unpadded torus of the grid itself: every row and column carries data
   bool use_reg = true;         // register-resident FFT kernels (sizes >= 256)
@@ -260,6 +267,9 @@ bool conv_reg_supported(int hx, int my);
 // col_per; FP64 or the FP32 copies) can be launched on the current device;
 // why (nullable) names the failing kernel and its limits
 bool reg_shapes_fit(const DFft& f, bool fp32, std::string* why);
+// affected points above which the correction sources' row transforms are
+// formed by a pre-pass (DFft::corr)
+constexpr int CORR_PREPASS_MIN = 1024;
 void launch_conv(const DGeom& g, const DFft& f, const double* omega, const double* gam, double sgn,
                  int rj0, int rj1, int oj0, int oj1, double* psi_ring, const double* done_flag,
                  hipStream_t s, Prof* prof = nullptr, bool fp32 = false, bool rows_ready = false);

@@ -2298,7 +2298,29 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
     const bool row_ok = pad_y ? (m < E / 2) : true;
     v[m] = (row_ok && valid && dense && n >= rj0 && n <= rj1) ? col[n + 1] : mkc<CX>(0, 0);
   }
-  if (gam) {
+  if (gam && f.corr) {
+    // Correction sources from the pre-pass: this column's value of each
+    // affected row (slot loads and value loads unconditional, at clamped
+    // indices, and the value weighted by 0 or 1: under a per-lane branch
+    // each would be waited for inside it)
+    const CX* corr = reinterpret_cast<const CX*>(f.corr) + (size_t)(valid ? kx : 0) * g.n_corr_rows;
+    const int jb = max(rj0, 0), je = min(rj1, g.ny - 1);
+    int sl[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      const int q = g.row_slot[min(n, g.ny - 1)];
+      sl[m] = ((!pad_y || m < E / 2) && n >= jb && n <= je) ? q : -1;   // padded: sources lie below MY / 2
+    }
+    CX cv[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) cv[m] = corr[max(sl[m], 0)];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const S w = sl[m] >= 0 ? (S)1 : (S)0;
+      v[m] = mkc<CX>(v[m].x + w * cv[m].x, v[m].y + w * cv[m].y);
+    }
+  } else if (gam) {
     // Correction sources: the column's T lanes compute the terms
     // sgn gam[a_e] W^(kx i_e) of all entries e of rows [rj0, rj1] (a few per
     // lane, loads batched), stage them in this FFT's LDS buffer (free until
@@ -2407,20 +2429,32 @@ k_cols_reg(DGeom g, DFft f, bool dense, const double* __restrict__ gam, double s
 }
 
 // ---- forward rows: real FFT of length 2 HX (half-length complex FFT + split)
-template <int HX, class CX, int PER>
-__global__ void __launch_bounds__((RegCfg<HX, PER, true>::THREADS))
-k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int count,
-               const double* __restrict__ done) {
+// CORR = false: rows j0 .. j0 + count - 1 of the masked vorticity -> spec
+// (row jj at slot jj + 1).  CORR = true: the correction sources sgn gam[a]
+// placed at the affected points of the grid rows corr_rows[slot], slot <
+// count (rows outside [j0, jb_end] carry none) -> f.corr[k][slot]: the
+// row transforms that the column pass adds for those rows.  Both follow
+// the same even mirror past the outflow plane.
+template <int HX, class CX, int PER, bool CORR>
+__device__ __forceinline__ void rows_fwd_body(const DGeom& g, const DFft& f, const double* __restrict__ omega,
+                                              const double* __restrict__ gam, double sgn, int j0, int j1, int count) {
   using C = RegCfg<HX, PER, true>;
   using S = typename Real<CX>::t;
   const FftT<CX> ft = fft_view<CX>(f);
   constexpr int T = RPX<HX, true>::T, E = RPX<HX, true>::E;
   __shared__ CX lds[C::PER][C::LDSN];
-  if (done && done[KS_DONE] != 0.0) return;
   const int w = threadIdx.x / T, t = threadIdx.x % T;
   const int lb = xcd_block();
-  const int jrow = j0 + lb * C::PER + w;
-  const bool valid = (jrow < j0 + count) && jrow >= 0 && jrow < g.ny;
+  const int r0 = lb * C::PER + w;   // this FFT's row (CORR: its slot)
+  int jrow;
+  bool valid;
+  if constexpr (CORR) {
+    jrow = r0 < count ? g.corr_rows[r0] : 0;
+    valid = r0 < count && jrow >= j0 && jrow <= j1;
+  } else {
+    jrow = j0 + r0;
+    valid = (r0 < count) && jrow >= 0 && jrow < g.ny;
+  }
   CX v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -2434,12 +2468,21 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int co
         m1 = i1 < g.nx ? i1 : 2 * g.nx - 1 - i1;
       }
       const size_t rb = (size_t)jrow * g.nx;
-      // class and vorticity loaded together (both addresses are valid), then selected
       const bool in0 = m0 >= 0 && m0 < g.nx, in1 = m1 >= 0 && m1 < g.nx;
-      const int8_t c0 = in0 ? g.cls[rb + m0] : (int8_t)3, c1 = in1 ? g.cls[rb + m1] : (int8_t)3;
-      const double o0 = in0 ? omega[rb + m0] : 0.0, o1 = in1 ? omega[rb + m1] : 0.0;
-      z.x = c0 < 2 ? (S)o0 : (S)0;
-      z.y = c1 < 2 ? (S)o1 : (S)0;
+      if constexpr (CORR) {
+        // the affected index of the node, then its circulation value (both
+        // loads unconditional at valid addresses, the value weighted by 0 or 1)
+        const int a0 = g.a_id[rb + (in0 ? m0 : 0)], a1 = g.a_id[rb + (in1 ? m1 : 0)];
+        const double v0 = gam[max(a0, 0)], v1 = gam[max(a1, 0)];
+        z.x = (S)(sgn * v0 * ((in0 && a0 >= 0) ? 1.0 : 0.0));
+        z.y = (S)(sgn * v1 * ((in1 && a1 >= 0) ? 1.0 : 0.0));
+      } else {
+        // class and vorticity loaded together (both addresses are valid), then selected
+        const int8_t c0 = in0 ? g.cls[rb + m0] : (int8_t)3, c1 = in1 ? g.cls[rb + m1] : (int8_t)3;
+        const double o0 = in0 ? omega[rb + m0] : 0.0, o1 = in1 ? omega[rb + m1] : 0.0;
+        z.x = c0 < 2 ? (S)o0 : (S)0;
+        z.y = c1 < 2 ? (S)o1 : (S)0;
+      }
     }
     v[m] = z;
   }
@@ -2460,15 +2503,41 @@ k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int co
     const int idx = threadIdx.x + q * C::THREADS;
     if (idx >= (HX + 1) * C::PER) break;
     const int rr = idx % C::PER, k = idx / C::PER;
-    const int jj = j0 + lb * C::PER + rr;
-    if (jj >= j0 + count || jj < 0 || jj >= g.ny) continue;
+    const int slot = lb * C::PER + rr;
+    if constexpr (CORR) {
+      if (slot >= count) continue;
+    } else {
+      const int jj = j0 + slot;
+      if (slot >= count || jj < 0 || jj >= g.ny) continue;
+    }
     const CX zk = lds[rr][padi(k == HX ? 0 : k)];
     const CX zc = conj2(lds[rr][padi(k == 0 ? 0 : HX - k)]);
     const CX E2 = mkc<CX>(S(0.5) * (zk.x + zc.x), S(0.5) * (zk.y + zc.y));
     const CX Od = csub(zk, zc);
     const CX O = mkc<CX>(S(0.5) * Od.y, S(-0.5) * Od.x);
-    ft.spec[(size_t)k * f.ld + jj + 1] = cadd(E2, cmul(wk[q], O));
+    const CX val = cadd(E2, cmul(wk[q], O));
+    if constexpr (CORR)
+      reinterpret_cast<CX*>(f.corr)[(size_t)k * count + slot] = val;
+    else
+      ft.spec[(size_t)k * f.ld + j0 + slot + 1] = val;
   }
+}
+
+template <int HX, class CX, int PER>
+__global__ void __launch_bounds__((RegCfg<HX, PER, true>::THREADS))
+k_rows_fwd_reg(DGeom g, DFft f, const double* __restrict__ omega, int j0, int count,
+               const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  rows_fwd_body<HX, CX, PER, false>(g, f, omega, nullptr, 0.0, j0, 0, count);
+}
+
+// the correction sources' row transforms of rows [jb, je] (slots 0 .. R - 1)
+template <int HX, class CX, int PER>
+__global__ void __launch_bounds__((RegCfg<HX, PER, true>::THREADS))
+k_rows_fwd_corr(DGeom g, DFft f, const double* __restrict__ gam, double sgn, int jb, int je,
+                const double* __restrict__ done) {
+  if (done && done[KS_DONE] != 0.0) return;
+  rows_fwd_body<HX, CX, PER, true>(g, f, nullptr, gam, sgn, jb, je, g.n_corr_rows);
 }
 
 // ---- inverse rows: complex-to-real of length 2 HX; rows jo in [j0, j0 + count) of the ring
@@ -2583,6 +2652,20 @@ void rows_inv_go(const DGeom& g, const DFft& f, int j0, int count, double* psi, 
     }                                                                                  \
     GO<N, CX, D_>(__VA_ARGS__);                                                        \
   } while (0)
+
+// The correction sources' row transforms (DFft::corr), for the column pass
+// of a product with many affected points: a forward row pass over the rows
+// holding affected points, with the sources placed at those points.
+template <int HX, class CX>
+void corr_rows_launch(const DGeom& g, const DFft& f, const double* gam, double sgn, int rj0, int rj1,
+                      const double* done, hipStream_t s) {
+  constexpr int PER = RegDef<HX, true>::PER;
+  using C = RegCfg<HX, PER, true>;
+  const int blocks = (g.n_corr_rows + C::PER - 1) / C::PER;
+  if (blocks > 0)
+    k_rows_fwd_corr<HX, CX, PER><<<blocks, C::THREADS, 0, s>>>(g, f, gam, sgn, max(rj0, 0), min(rj1, g.ny - 1),
+                                                                done);
+}
 
 template <int HX, class CX>
 void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, int j0, int count, const double* done,
@@ -2715,10 +2798,12 @@ void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const d
   const double b_inv = (double)nout * (cb * (f.hx + 1) + 8.0 * (g.nx + 2));
   if (fp32) {
     if (rows) IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, rj0, nin, done, s, prof, b_fwd);
+    if (gam && f.corr) IIM_REG_SWITCH(f.hx, corr_rows_launch, float2, g, f, gam, sgn, rj0, rj1, done, s);
     IIM_REG_SWITCH(f.my, cols_reg_launch, float2, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, float2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   } else {
     if (rows) IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, double2, g, f, omega, rj0, nin, done, s, prof, b_fwd);
+    if (gam && f.corr) IIM_REG_SWITCH(f.hx, corr_rows_launch, double2, g, f, gam, sgn, rj0, rj1, done, s);
     IIM_REG_SWITCH(f.my, cols_reg_launch, double2, g, f, dense, gam, sgn, rj0, rj1, oj0, oj1, done, s, prof, b_col);
     IIM_REG_SWITCH(f.hx, rows_inv_reg_launch, double2, g, f, oj0, nout, psi_ring, done, s, prof, b_inv);
   }

@@ -19,6 +19,12 @@ from gpu_util import to_dev, ring_zeros, seeded_state, rel
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-11
 CASES = {"cyl_mid": wl.cylinder_mid, "cyl_outflow": wl.cylinder_outflow_small}
+# four bodies, outflow, 512 x 512: more than 1024 affected points, so the
+# correction sources' row transforms come from the pre-pass (FP32 and FP64)
+STEP_CASES = dict(CASES, multi512=lambda: wl.multi_body(512))
+# its FP64 rounding floor (vorticity, L2) is 4.1e-11 (test_gpu_fullsize.py):
+# the gate there is ten times the floor, and so it is here
+STEP_TOL = {"multi512": 4.1e-10}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -62,9 +68,9 @@ def test_mixed_reconstruct_meets_fp64_tolerance(name):
     assert st["res"][0] <= 1e-13, st
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", list(STEP_CASES))
 def test_mixed_rk3_step(name):
-    w = CASES[name]()
+    w = STEP_CASES[name]()
     geo = OG.Geometry(w.grid, w.bodies)
     om, G = seeded_state(w, geo, 3)
     st = ONS.Stepper(geo)
@@ -75,8 +81,9 @@ def test_mixed_rk3_step(name):
     torch.cuda.synchronize()
     e = rel(omd.cpu().numpy(), om_ref)
     print("mixed rk3 step", name, "vorticity error", e, stats)
-    assert e < TOL64, (e, stats)
-    assert np.max(np.abs(G_gpu - G_ref)) < TOL64 * (np.abs(G_ref).max() + 1.0)
+    tol = STEP_TOL.get(name, TOL64)
+    assert e < tol, (e, stats)
+    assert np.max(np.abs(G_gpu - G_ref)) < tol * (np.abs(G_ref).max() + 1.0)
 
 
 def test_mixed_matches_fp64_path_over_steps():
