@@ -2667,10 +2667,15 @@ void corr_rows_launch(const DGeom& g, const DFft& f, const double* gam, double s
                                                                 done);
 }
 
+// Fewer rows than the chip has compute units (the band a product's
+// right-hand side reads): one row per workgroup whatever the tuned shape,
+// so that the rows spread over as many CUs as possible.
+constexpr int ROWS_FEW = 256;
 template <int HX, class CX>
 void rows_fwd_reg_launch(const DGeom& g, const DFft& f, const double* omega, int j0, int count, const double* done,
                          hipStream_t s, Prof* prof, double bytes) {
-  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_fwd_go, g, f, omega, j0, count, done, s, prof, bytes);
+  IIM_PER_DISPATCH(HX, CX, count < ROWS_FEW ? 1 : f.row_per, true, rows_fwd_go, g, f, omega, j0, count, done, s,
+                   prof, bytes);
 }
 template <int MY, class CX>
 void cols_reg_launch(const DGeom& g, const DFft& f, bool dense, const double* gam, double sgn, int rj0, int rj1,
@@ -2681,7 +2686,8 @@ void cols_reg_launch(const DGeom& g, const DFft& f, bool dense, const double* ga
 template <int HX, class CX>
 void rows_inv_reg_launch(const DGeom& g, const DFft& f, int j0, int count, double* psi, const double* done,
                          hipStream_t s, Prof* prof, double bytes) {
-  IIM_PER_DISPATCH(HX, CX, f.row_per, true, rows_inv_go, g, f, j0, count, psi, done, s, prof, bytes);
+  IIM_PER_DISPATCH(HX, CX, count < ROWS_FEW ? 1 : f.row_per, true, rows_inv_go, g, f, j0, count, psi, done, s, prof,
+                   bytes);
 }
 
 // Register FFT sizes: powers of two 256 .. 4096 (FP64 and FP32) and, FP64
@@ -2794,7 +2800,9 @@ void launch_conv_reg(const DGeom& g, const DFft& f, const double* omega, const d
   // spectrum in + ring rows out
   const double cb = fp32 ? 8.0 : 16.0, rb = fp32 ? 4.0 : 8.0;
   const double b_fwd = (double)nin * (8.0 * g.nx + cb * (f.hx + 1));
-  const double b_col = (double)(f.hx + 1) * ((dense ? cb * nin : 0.0) + rb * (f.my / 2 + 1) + cb * nout);
+  // (with the correction pre-pass the column pass also reads its rows)
+  const double b_col = (double)(f.hx + 1) * ((dense ? cb * nin : 0.0) + rb * (f.my / 2 + 1) + cb * nout +
+                                             ((gam && f.corr) ? cb * g.n_corr_rows : 0.0));
   const double b_inv = (double)nout * (cb * (f.hx + 1) + 8.0 * (g.nx + 2));
   if (fp32) {
     if (rows) IIM_REG_SWITCH(f.hx, rows_fwd_reg_launch, float2, g, f, omega, rj0, nin, done, s, prof, b_fwd);
