@@ -246,11 +246,13 @@ def surface_driven_cylinder(nx=128, ny=96, h=1.0 / 32, points=128, center=(1.5, 
     return dataclasses.replace(w, name="surface_driven_cylinder_%dx%d" % (nx, ny), bodies=[body])
 
 
-def periodic_cylinder(nx=128, ny=64, h=1.0 / 16, points=128, dt=0.01, center=(2.0, 0.0), mean=(1.0, 0.0)):
-    """A D = 1 cylinder in a box periodic in both directions (a row-and-column
-    array of cylinders) with the mean velocity `mean`; cell-centred grid on
-    [0, nx*h) x [-ny*h/2, ny*h/2); nx, ny powers of two."""
-    w = cylinder(nx=nx, ny=ny, h=h, points=points, dt=dt, steps=5, center=center)
+def periodic_cylinder(nx=128, ny=64, h=1.0 / 16, points=128, dt=0.01, center=(2.0, 0.0), mean=(1.0, 0.0),
+                      diameter=1.0):
+    """A cylinder (diameter D, 1 by default) in a box periodic in both
+    directions (a row-and-column array of cylinders) with the mean velocity
+    `mean`; cell-centred grid on [0, nx*h) x [-ny*h/2, ny*h/2); nx, ny powers
+    of two."""
+    w = cylinder(nx=nx, ny=ny, h=h, points=points, dt=dt, steps=5, center=center, diameter=diameter)
     w.grid.exterior = EXT_PERIODIC
     w.grid.u_inf = tuple(mean)
     w.name = "periodic_cylinder_%dx%d" % (nx, ny)
