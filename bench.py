@@ -307,7 +307,13 @@ def _summarize_trace(trace_dir, out, command, workload):
     stats = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0])
     trace = _read_csv(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0])
     lines = ["# rocprofv3 kernel trace: RK3 steps of " + WORKLOADS[workload], "",
-             "command: " + command, "", "kernel | calls | avg us | total ms | share %", "---|---|---|---|---"]
+             "command: " + command, ""]
+    if "--no-autotune" in command:
+        # a profiler's own overhead shifts the tuner's timings, so a profiled
+        # run states its tile shapes instead of tuning them
+        lines += ["FFT tile shapes: the defaults, which the autotuner keeps for this workload when bench.py "
+                  "runs unprofiled (fft_tiles row_per 0, col_per 0 in its JSON line)", ""]
+    lines += ["kernel | calls | avg us | total ms | share %", "---|---|---|---|---"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
         name = r["Name"].split("(")[0].replace("void ", "")
         lines.append("%s | %s | %.2f | %.3f | %.2f" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,

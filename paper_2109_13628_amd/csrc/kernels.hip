@@ -1021,6 +1021,7 @@ enum { NK_FLUID = 0, NK_GHOST = 1, NK_SOLID = 2, NK_OUT = 3 };
 struct TGeom {
   int nx, ny, nsp, nbc, outflow, periodic;
   int vec;                     // bulk pairs may use 16-byte loads (nx even, arrays aligned, psi given)
+  int quad;                    // bulk tiles of two rows, a 2 x 2 block of nodes per lane (needs vec)
   double h, inv_h, nu, uinf_x, uinf_y;
   const int8_t* __restrict__ cls;
   const int* __restrict__ special;
@@ -1186,8 +1187,8 @@ __device__ __forceinline__ double flux_interior(const TGeom& g, const double* __
 
 // Bulk nodes (cls 0): every stencil node inside the grid is fluid (bodies keep
 // three cells from the grid edge, so this also holds for stencils that wrap
-// across a periodic edge).  Bulk part: one thread per pair of nodes of grid
-// row j, 512 nodes per block.
+// across a periodic edge).  Bulk part: one thread per 2 x 2 block of nodes,
+// two grid rows of 512 nodes per workgroup.
 //
 // One node, any position.  Every lane takes the same straight-line path: the ten stencil positions are
 // mapped onto the grid first (periodic edges wrap, the outflow plane mirrors
@@ -1283,6 +1284,28 @@ __device__ __forceinline__ void bulk_store(const TGeom& g, double* __restrict__ 
   }
 }
 
+// Nodes q, q + 1 of one row (q even): one 16-byte store per array when both
+// are bulk fluid nodes, else bulk_store for each.
+__device__ __forceinline__ void bulk_store2(const TGeom& g, double* __restrict__ out, double* __restrict__ Q,
+                                            unsigned short cc, int q, double ra, double rb, double wa, double wb,
+                                            double2 qp, double a, double b, double dt, int mode) {
+  if (cc == 0) {
+    if (mode == 0) {
+      *reinterpret_cast<double2*>(out + q) = make_double2(ra, rb);
+    } else {
+      const double qa = a * qp.x + dt * ra, qb = a * qp.y + dt * rb;
+      *reinterpret_cast<double2*>(Q + q) = make_double2(qa, qb);
+      const double wna = wa + b * qa, wnb = wb + b * qb;
+      *reinterpret_cast<double2*>(out + q) = make_double2(wna, wnb);
+      mark_nonfinite(g, wna);
+      mark_nonfinite(g, wnb);
+    }
+    return;
+  }
+  bulk_store(g, out, Q, (int8_t)(cc & 0xff), q, ra, wa, qp.x, a, b, dt, mode);
+  bulk_store(g, out, Q, (int8_t)(cc >> 8), q + 1, rb, wb, qp.y, a, b, dt, mode);
+}
+
 __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
 
 // Two interior nodes i0, i0 + 1 (i0 even, every stencil position inside the
@@ -1346,17 +1369,115 @@ __device__ __forceinline__ void bulk_pair(const TGeom& g, const double* __restri
   double rhb = -((fxrb - fmid) + (fytb - fybb)) * g.inv_h;
   // keeps every load above the class tests (see bulk_cell)
   asm volatile("" : "+v"(rha), "+v"(rhb));
-  const int8_t ca = (int8_t)(cc & 0xff), cb = (int8_t)(cc >> 8);
-  bulk_store(g, out, Q, ca, q, rha, wx[2], qp.x, a, b, dt, mode);
-  bulk_store(g, out, Q, cb, q + 1, rhb, wx[3], qp.y, a, b, dt, mode);
+  bulk_store2(g, out, Q, cc, q, rha, rhb, wx[2], wx[3], qp, a, b, dt, mode);
 }
 
+// A 2 x 2 block of interior nodes: rows j, j + 1 and columns i0, i0 + 1 (the
+// conditions of bulk_pair, with the stencils of both rows inside the grid).
+// The two rows share the omega and psi rows their stencils overlap on, each
+// row its middle x face and each column its middle y face, so the block takes
+// 34 loads instead of the 54 of two pairs.  Every node takes the formulas of
+// bulk_cell (the results agree to rounding).
 template <bool P>
-__device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
-                                               double* __restrict__ out, double* __restrict__ Q, double a, double b,
-                                               double dt, int mode, int bx, int j) {
-  const int i0 = 2 * (bx * 256 + threadIdx.x);
-  if (i0 >= g.nx) return;
+__device__ __forceinline__ void bulk_quad(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                          double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                          double dt, int mode, int i0, int j) {
+  const int nx = g.nx, nxr = nx + 2;
+  const double* __restrict__ psi = vel.psi;
+  const int q = j * nx + i0;                 // even, as is q + nx
+  const unsigned short c0 = *reinterpret_cast<const unsigned short*>(g.cls + q);
+  const unsigned short c1 = *reinterpret_cast<const unsigned short*>(g.cls + q + nx);
+  const bool rq = mode == 1 && a != 0.0;
+  const double2 q0 = rq ? ld2(Q + q) : make_double2(0.0, 0.0);
+  const double2 q1 = rq ? ld2(Q + q + nx) : make_double2(0.0, 0.0);
+  // omega of rows j - 2 + d, d = 0 .. 5: columns i0 - 2 .. i0 + 3 on rows j
+  // and j + 1, columns i0 and i0 + 1 on the other four
+  double wr[2][6];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double2 w2 = ld2(omega + q + s * nx - 2 + 2 * k);
+      wr[s][2 * k] = w2.x;
+      wr[s][2 * k + 1] = w2.y;
+    }
+  double2 wo[4];   // rows j - 2, j - 1, j + 2, j + 3
+#pragma unroll
+  for (int d = 0; d < 4; ++d) wo[d] = ld2(omega + q + (d < 2 ? d - 2 : d) * nx);
+  // psi of ring rows j + e, e = 0 .. 3 (grid rows j - 1 .. j + 2), ring
+  // columns i0 - 2 .. i0 + 5: u of rows j and j + 1 and v of the middle rows;
+  // ring rows j - 1 and j + 4, ring columns i0 .. i0 + 3: v of the outer rows
+  const int r0 = j * nxr + i0;               // ring row j, ring column i0 (even)
+  double pr[4][8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 p2 = ld2(psi + r0 + e * nxr - 2 + 2 * k);
+      pr[e][2 * k] = p2.x;
+      pr[e][2 * k + 1] = p2.y;
+    }
+  double2 po[4];   // ring row j - 1 then j + 4, ring columns i0, i0 + 1 then i0 + 2, i0 + 3
+#pragma unroll
+  for (int t = 0; t < 4; ++t) po[t] = ld2(psi + r0 + (t < 2 ? -nxr : 4 * nxr) + 2 * (t & 1));
+  // all 30 loads are issued before any of them is used: left alone, the
+  // compiler holds the last ones back until most others have returned (to
+  // save registers), which costs each wave a second memory round trip
+  asm volatile("" : "+v"(wo[0].x), "+v"(wo[0].y), "+v"(wo[1].x), "+v"(wo[1].y), "+v"(wo[2].x), "+v"(wo[2].y),
+               "+v"(wo[3].x), "+v"(wo[3].y), "+v"(po[0].x), "+v"(po[0].y), "+v"(po[1].x), "+v"(po[1].y),
+               "+v"(po[2].x), "+v"(po[2].y), "+v"(po[3].x), "+v"(po[3].y));
+  double ux[2][6];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) ux[s][m] = Vel<P>::u_of(g, pr[s + 2][m + 1], pr[s][m + 1]);
+  // columns i0 (a) and i0 + 1 (b) on grid rows j - 2 + d (ring row j - 1 + d,
+  // ring columns i0 .. i0 + 3)
+  double wya[6], wyb[6], vya[6], vyb[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const double2 w2 = (d == 2 || d == 3) ? make_double2(wr[d - 2][2], wr[d - 2][3]) : wo[d < 2 ? d : d - 2];
+    wya[d] = w2.x;
+    wyb[d] = w2.y;
+    double p[4];
+    if (d == 0 || d == 5) {
+      const int o = d == 0 ? 0 : 2;
+      p[0] = po[o].x; p[1] = po[o].y; p[2] = po[o + 1].x; p[3] = po[o + 1].y;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) p[t] = pr[d - 1][2 + t];
+    }
+    vya[d] = Vel<P>::v_of(g, p[2], p[0]);
+    vyb[d] = Vel<P>::v_of(g, p[3], p[1]);
+  }
+  const double nih = g.nu * g.inv_h;
+  double fx[2][3], fya[3], fyb[3];   // x faces i0 - 1/2, i0 + 1/2, i0 + 3/2; y faces j - 1/2, j + 1/2, j + 3/2
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      fx[s][k] = flux_std(ux[s][k], ux[s][k + 1], ux[s][k + 2], ux[s][k + 3], wr[s][k], wr[s][k + 1], wr[s][k + 2],
+                          wr[s][k + 3], nih);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    fya[k] = flux_std(vya[k], vya[k + 1], vya[k + 2], vya[k + 3], wya[k], wya[k + 1], wya[k + 2], wya[k + 3], nih);
+    fyb[k] = flux_std(vyb[k], vyb[k + 1], vyb[k + 2], vyb[k + 3], wyb[k], wyb[k + 1], wyb[k + 2], wyb[k + 3], nih);
+  }
+  double r00 = -((fx[0][1] - fx[0][0]) + (fya[1] - fya[0])) * g.inv_h;
+  double r01 = -((fx[0][2] - fx[0][1]) + (fyb[1] - fyb[0])) * g.inv_h;
+  double r10 = -((fx[1][1] - fx[1][0]) + (fya[2] - fya[1])) * g.inv_h;
+  double r11 = -((fx[1][2] - fx[1][1]) + (fyb[2] - fyb[1])) * g.inv_h;
+  // keeps every load above the class tests (see bulk_cell)
+  asm volatile("" : "+v"(r00), "+v"(r01), "+v"(r10), "+v"(r11));
+  bulk_store2(g, out, Q, c0, q, r00, r01, wr[0][2], wr[0][3], q0, a, b, dt, mode);
+  bulk_store2(g, out, Q, c1, q + nx, r10, r11, wr[1][2], wr[1][3], q1, a, b, dt, mode);
+}
+
+// Nodes i0, i0 + 1 of row j.
+template <bool P>
+__device__ __forceinline__ void bulk_two(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                         double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                         double dt, int mode, int i0, int j) {
   if constexpr (P) {
     if (g.vec && i0 >= 2 && i0 + 4 <= g.nx && j >= 2 && j + 2 < g.ny) {
       bulk_pair(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
@@ -1365,6 +1486,30 @@ __device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __r
   }
   bulk_cell(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
   bulk_cell(g, omega, vel, out, Q, a, b, dt, mode, i0 + 1, j);
+}
+
+// Bulk tile (bx, jt), columns 512 bx .. 512 bx + 511: row jt, a pair of
+// nodes per lane, or (g.quad) rows 2 jt and 2 jt + 1, a 2 x 2 block of nodes
+// per lane.
+template <bool P>
+__device__ __forceinline__ void transport_bulk(const TGeom& g, const double* __restrict__ omega, const Vel<P>& vel,
+                                               double* __restrict__ out, double* __restrict__ Q, double a, double b,
+                                               double dt, int mode, int bx, int jt) {
+  const int i0 = 2 * (bx * 256 + threadIdx.x);
+  if (i0 >= g.nx) return;
+  if (!g.quad) {
+    bulk_two(g, omega, vel, out, Q, a, b, dt, mode, i0, jt);
+    return;
+  }
+  const int j = 2 * jt;
+  if constexpr (P) {
+    if (i0 >= 2 && i0 + 4 <= g.nx && j >= 2 && j + 3 < g.ny) {
+      bulk_quad(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
+      return;
+    }
+  }
+  bulk_two(g, omega, vel, out, Q, a, b, dt, mode, i0, j);
+  if (j + 1 < g.ny) bulk_two(g, omega, vel, out, Q, a, b, dt, mode, i0, j + 1);
 }
 
 // One group of 4 lanes per boundary-kernel node: lane f computes the flux on
@@ -1460,6 +1605,10 @@ __device__ __forceinline__ void kelvin(const TGeom& g, const double* __restrict_
 // neighbouring rows then hit the same L2, and only the band edges are read
 // from HBM twice (with consecutive rows on alternating XCDs every row of
 // omega and psi was read twice).
+// Grid size (nodes) from which the bulk part takes 2 x 2 blocks per lane:
+// about where the pair tiles need two rounds of waves to cover the grid.
+constexpr long TRANSPORT_QUAD_MIN = 1L << 20;
+
 template <bool P>
 __global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __restrict__ omega,
                                                        const double* __restrict__ psi,
@@ -1483,7 +1632,7 @@ __global__ void __launch_bounds__(256) k_transport_all(TGeom g, const double* __
     return;
   }
   const int nlead = (g.nbc + nb_sp + 7) & ~7;
-  const int nb = nbx * g.ny, band = (nb + 7) >> 3;
+  const int nb = nbx * (g.quad ? (g.ny + 1) >> 1 : g.ny), band = (nb + 7) >> 3;
   const int bb = (int)blockIdx.x - nlead;
   if (bb < 0) return;   // padding up to the first bulk block
   const int tile = (bb & 7) * band + (bb >> 3);
@@ -1495,14 +1644,17 @@ void launch_transport_all(const DGeom& g, const double* omega, const double* psi
                           const double* w4, const double* w3b, const double* w3n, double* out, double* Q, double* dG,
                           double* Gamma, double* QG, double a, double b, double dt, int mode, hipStream_t s,
                           Prof* prof) {
-  // leading blocks padded to a multiple of 8; eight bands of bulk tiles
-  // (512 nodes each)
-  const int nb = ((g.nx + 511) / 512) * g.ny;
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   const int vec = psi && g.nx % 2 == 0 && al16(omega) && al16(psi) && al16(out) && al16(Q) &&
                   ((uintptr_t)g.cls & 1) == 0;
+  // 2 x 2 blocks per lane take fewer loads per node but give half as many
+  // waves: they pay once the grid fills the chip several times over
+  const int quad = vec && (long)g.nx * g.ny >= TRANSPORT_QUAD_MIN;
+  // leading blocks padded to a multiple of 8; eight bands of bulk tiles
+  // (one or two rows of 512 nodes each)
+  const int nb = ((g.nx + 511) / 512) * (quad ? (g.ny + 1) / 2 : g.ny);
   const int blocks = ((g.nbc + (4 * g.nsp + 255) / 256 + 7) & ~7) + 8 * ((nb + 7) / 8);
-  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, vec, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
+  const TGeom tg{g.nx, g.ny, g.nsp, g.nbc, g.outflow, g.periodic, vec, quad, g.h, g.inv_h, g.nu, g.uinf_x, g.uinf_y, g.cls,
                  g.special, g.rects, g.nonfinite};
   if (psi) {
     // algorithmic bytes per cell: omega, psi, Q read; out, Q written
