@@ -85,3 +85,21 @@ def test_step_fullsize(name, solver):
     print(name, solver, {k: v for k, v in err.items() if k != "stats"}, err["stats"])
     assert_within_floor(err, FLOOR[name])
     ctx.close()
+
+
+def test_step_repeatable_multi1024():
+    """The same RK3 steps run twice from the same state agree bit for bit:
+    every sum of the step (block reductions, the dense product's ordered
+    partial sums) adds its terms in a fixed order."""
+    w, geo, st = _setup("multi1024")
+    om, G = seeded_state(w, geo, 21, body_scale=0.1)
+    ctx = iim.Context(w.grid, w.bodies, solver=iim.SOLVER_DIRECT)
+    out = []
+    for _ in range(2):
+        d = to_dev(om)
+        G1, _ = ctx.rk3_steps(d, np.array(G, dtype=np.float64), w.dt, 3)
+        torch.cuda.synchronize()
+        out.append((d.cpu().numpy(), np.array(G1)))
+    ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
