@@ -241,9 +241,33 @@ bool build_boundary_forms(iim_ctx* c, const std::vector<double>& psibt, const st
   // kinds take the top bits above 28-bit indices (ring indices < 2^28)
   if ((size_t)(nx + 2) * (ny + 2) >= ((size_t)1 << 28)) return false;
   c->bnd.rows = (int)kc.size();
-  c->bnd.ptr = c->upload(ptr);
-  c->bnd.idx = c->upload(idx);
-  c->bnd.w = c->upload(w);
+  // rows of at most 64 entries padded to a multiple of 32 (the kernel's eight
+  // lanes times four entries): the kernel then requests a row's entries
+  // without reading its bounds first
+  int longest = 0;
+  for (size_t r = 0; r + 1 < ptr.size(); ++r) longest = std::max(longest, ptr[r + 1] - ptr[r]);
+  const int stride = std::max(32, (longest + 31) / 32 * 32);
+  if (stride <= 64) {
+    std::vector<int> pidx((size_t)stride * kc.size());
+    std::vector<double> pw(pidx.size(), 0.0);
+    for (size_t r = 0; r < kc.size(); ++r) {
+      const int e0 = ptr[r], n = ptr[r + 1] - ptr[r];
+      for (int e = 0; e < stride; ++e) {
+        // pads: the row's last entry (the ring's first node for an empty row)
+        pidx[r * stride + e] = n > 0 ? idx[e0 + std::min(e, n - 1)] : 0;
+        if (e < n) pw[r * stride + e] = w[e0 + e];
+      }
+    }
+    c->bnd.stride = stride;
+    c->bnd.ptr = nullptr;
+    c->bnd.idx = c->upload(pidx);
+    c->bnd.w = c->upload(pw);
+  } else {
+    c->bnd.stride = 0;
+    c->bnd.ptr = c->upload(ptr);
+    c->bnd.idx = c->upload(idx);
+    c->bnd.w = c->upload(w);
+  }
   c->bnd.kc = c->upload(kc);
   c->bnd.dst = c->upload(dst);
   return true;

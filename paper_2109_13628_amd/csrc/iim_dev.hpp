@@ -78,6 +78,10 @@ struct DGeom {
 // 5 E3b, 6 E3n (grid)).  Indices stay below 2^28, kinds below 8.
 struct DBnd {
   int rows = 0;
+  // > 0: every row holds exactly `stride` entries from row * stride on (the
+  // pads repeat the row's last entry with weight zero) and ptr is unused;
+  // 0: rows delimited by ptr
+  int stride = 0;
   const int* ptr = nullptr;
   const int* idx = nullptr;
   const double* w = nullptr;

@@ -917,7 +917,28 @@ __global__ void __launch_bounds__(256) k_boundary_forms(DGeom g, DBnd b, const d
   const double kc = b.kc[rr];
   const int d = b.dst[rr];
   double acc = 0.0;
-  if (r < b.rows) {
+  if (b.stride > 0) {
+    // rows padded to a fixed stride: the entries are requested at once,
+    // without the round trip for the row's bounds (lanes past the last row
+    // read that row's entries and write nothing)
+    for (int e0 = rr * b.stride + l; e0 < (rr + 1) * b.stride; e0 += 4 * L) {
+      int id[4];
+      double wv[4], val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        id[u] = b.idx[e0 + u * L];
+        wv[u] = b.w[e0 + u * L];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kind = id[u] >> 28, i = id[u] & M;
+        const double* src = kind == 0 ? psi : (kind == 1 ? omega : x + g.na);
+        val[u] = src[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += wv[u] * val[u];
+    }
+  } else if (r < b.rows) {
     // straight-line loads: entries at clamped indices (those past the row's
     // end repeat its last entry with weight zero), the source array chosen
     // by a pointer select rather than a branch per array (a branch around a
