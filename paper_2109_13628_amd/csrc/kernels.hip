@@ -1834,15 +1834,16 @@ void launch_gemv_t(const double* Mt, int n, const double* b, double* x, double* 
 // x = Mt^T b, its matrix entries loaded before b is ready.  The correction
 // rows are formed entry-parallel: each lane stores the products w psi of a
 // few entries in LDS (all their loads in flight together), then the lane
-// owning a row sums its entries in order.  Block 0 also stores b.
-constexpr int RHS_SOLVE_MAX_LDS = 6144;   // b and the entry products in dynamic LDS (48 KiB)
+// owning a row sums its entries in order.  The circulation rows' wave sums
+// go to LDS and are added, in wave order, in the phase after the next
+// barrier (no block reduction of their own).  Block 0 also stores b.
+constexpr int RHS_SOLVE_MAX_LDS = 6144;   // b, the entry products and the wave sums in dynamic LDS (48 KiB)
 __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __restrict__ psi,
                                                    const double* __restrict__ omega,
                                                    const double* __restrict__ Gamma,
                                                    const double* __restrict__ Mt, int n, double* __restrict__ b,
                                                    double* __restrict__ x) {
-  extern __shared__ double bs[];   // b [n], then the entry products [nnz] and a spare slot
-  __shared__ double red[16];
+  extern __shared__ double bs[];   // b [n], the entry products [nnz], a spare slot, the wave sums [nbc][16]
   __shared__ double part[64][17];
   const int lo = threadIdx.x & 15, sl = threadIdx.x >> 4;   // 16 outputs, 64 slices of each sum
   const int p = blockIdx.x * 16 + lo;
@@ -1857,8 +1858,11 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
   const bool own = a_own < g.na;
   const int pb = own ? g.aop.ptr[a_own] : 0, pe = own ? g.aop.ptr[a_own + 1] : 0;
   const double bconst = own ? g.bpsi[a_own] : 0.0;
+  const double gam_own = (int)threadIdx.x < g.nbc ? Gamma[threadIdx.x] : 0.0;
   double* terms = bs + n;
   const int nnz = g.aop.nnz;
+  constexpr int NW = 16;   // waves of the 1024-lane block
+  double* wsum = terms + nnz + 1;
   for (int e0 = threadIdx.x; e0 < nnz; e0 += 2 * blockDim.x) {
     // the second entry at a clamped index and stored unconditionally (past
     // the end into the spare slot terms[nnz]): under a per-lane branch its
@@ -1892,10 +1896,15 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
       for (int u = 0; u < 8; ++u)
         if (cl[u] < 2) acc += v[u];
     }
-    const double sum = block_sum(acc, red);
-    if (threadIdx.x == 0) bs[g.na + k] = sum - Gamma[k] * g.inv_h * g.inv_h;
+    const double ws = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) wsum[k * NW + (threadIdx.x >> 6)] = ws;
   }
   __syncthreads();
+  for (int k = threadIdx.x; k < g.nbc; k += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < NW; ++q) t += wsum[k * NW + q];
+    bs[g.na + k] = t - (k == (int)threadIdx.x ? gam_own : Gamma[k]) * g.inv_h * g.inv_h;
+  }
   for (int a = threadIdx.x; a < g.na; a += blockDim.x) {
     const bool first = a == a_own;
     const int e1 = first ? pe : g.aop.ptr[a + 1];
@@ -1925,10 +1934,10 @@ __global__ void __launch_bounds__(1024) k_rhs_solve(DGeom g, const double* __res
 
 bool launch_rhs_solve(const DGeom& g, const double* psi_ring, const double* omega, const double* Gamma,
                       const double* Mt, int n, double* b, double* x, hipStream_t s) {
-  if (n != g.na + g.nbc || n + g.aop.nnz + 1 > RHS_SOLVE_MAX_LDS) return false;
+  const size_t lds = (size_t)n + g.aop.nnz + 1 + 16 * (size_t)g.nbc;
+  if (n != g.na + g.nbc || lds > RHS_SOLVE_MAX_LDS) return false;
   if (n == 0) return true;
-  k_rhs_solve<<<(n + 15) / 16, 1024, (size_t)(n + g.aop.nnz + 1) * sizeof(double), s>>>(g, psi_ring, omega, Gamma,
-                                                                                       Mt, n, b, x);
+  k_rhs_solve<<<(n + 15) / 16, 1024, lds * sizeof(double), s>>>(g, psi_ring, omega, Gamma, Mt, n, b, x);
   return true;
 }
 
